@@ -1,0 +1,167 @@
+/*
+ * gkr.h -- C ABI of the MI355X GKR prover / verifier over F_p, p = 2^61 - 1.
+ *
+ * Method: Thaler, Roberts, Mitzenmacher, Pfister, "Verifiable Computation
+ * with Massively Parallel Interactive Proofs" (GKR protocol, Sec. 3.1;
+ * parallel prover, Sec. 4.1.1; verifier, Sec. 4.1.2; field, Sec. 5.1).
+ *
+ * Conventions shared by every entry point
+ *   - Field elements are uint64_t in canonical form, 0 <= x < p.
+ *   - Layers are numbered 0 = output ... d = input (the reverse of the
+ *     paper's numbering).  Layer i < d has S_i gates; gate g has a type
+ *     (GKR_ADD or GKR_MUL) and two wires in1[g], in2[g] into layer i+1.
+ *     s_i = ceil(log2 S_i) (0 when S_i = 1); a wire may name a padding slot
+ *     of layer i+1 (index < 2^{s_{i+1}}), whose value is 0.
+ *   - Transcript layout ("msgs"): V_0[0..S_0) (the claimed outputs), then per
+ *     layer i = 0..d-1: G_j(0), G_j(1), G_j(2) for each of the
+ *     n_i = s_i + 2 s_{i+1} sum-check rounds (variables a, then b, then c,
+ *     least significant bit first), then v1 = ~V_{i+1}(b*), v2 = ~V_{i+1}(c*),
+ *     then h(t) = ~V_{i+1}(b* + t (c* - b*)) for t = 2 .. s_{i+1}.
+ *     Challenges ("chals"): z_0 (s_0 values), then per layer r_1..r_{n_i}, tau.
+ *   - Challenges come from SplitMix64 (Steele, Lea, Flood 2014) seeded with
+ *     (seed << 8) | 2 (GKR) or (seed << 8) | 4 (F2 sum-check); a draw keeps
+ *     the low 61 bits of an output and redraws on 2^61 - 1.  The prover reads
+ *     challenge j only after message j is complete.
+ *   - Buffers: every pointer is owned by the caller and is neither freed nor
+ *     retained after the call returns.  "on_device" flags say whether a
+ *     pointer is a device (HBM) address or host memory.  Transcript outputs
+ *     are host memory.
+ *   - Streams: hip_stream is a hipStream_t or NULL (the library's own
+ *     stream on the current device).  Calls return after their work on that
+ *     stream has finished.
+ *   - Errors: every function returns GKR_OK (0) or a negative code;
+ *     gkr_last_error() gives a message for the calling thread.  Rejection
+ *     of a proof is not an error: gkr_verify returns GKR_OK, *accepted = 0.
+ */
+#ifndef GKR_H
+#define GKR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GKR_OK = 0,
+    GKR_ERR_INVALID = -1, /* malformed circuit, size or argument            */
+    GKR_ERR_RANGE = -2,   /* an input value is not below p                  */
+    GKR_ERR_NOMEM = -3,   /* host or device allocation failed               */
+    GKR_ERR_DEVICE = -4,  /* a HIP runtime error                            */
+    GKR_ERR_BUFSIZE = -5  /* a transcript buffer has the wrong length       */
+};
+
+enum { GKR_ADD = 0, GKR_MUL = 1 };
+
+/* Reasons for rejection (gkr_reject_info.check). */
+enum {
+    GKR_CHECK_MALFORMED = 1, /* wrong length, or a value not below p          */
+    GKR_CHECK_ROUND = 2,     /* G_j(0) + G_j(1) differs from the claim        */
+    GKR_CHECK_WIRING = 3,    /* last claim of a layer differs from
+                                beta(z,a*) [add~ (v1+v2) + mult~ v1 v2]        */
+    GKR_CHECK_LINE = 4,      /* v1 != v2 although layer i+1 has one gate      */
+    GKR_CHECK_INPUT = 5      /* final claim differs from the input's
+                                multilinear extension at the last point       */
+};
+
+typedef struct gkr_circuit gkr_circuit; /* opaque; immutable after creation */
+
+typedef struct {
+    int32_t layer; /* layer whose check failed (-1: whole transcript)       */
+    int32_t round; /* sum-check round within the layer, or -1               */
+    int32_t check; /* GKR_CHECK_*                                           */
+} gkr_reject_info;
+
+/* Create a circuit (Sec. 3.1: layered, fan-in 2, ADD and MUL gates).
+ *   num_layers   d + 1 >= 2, including the input layer.
+ *   layer_sizes  [d+1] host array, S_0 (output) .. S_d (input), each >= 1
+ *                and < 2^31.
+ *   gate_type, in1, in2   [d] host arrays of host pointers; layer i's arrays
+ *                have S_i entries (types GKR_ADD / GKR_MUL, wires
+ *                < 2^{s_{i+1}}).
+ * The arrays are validated and copied to device memory (struct-of-arrays
+ * per layer); the caller may free them afterwards.
+ * Errors: GKR_ERR_INVALID, GKR_ERR_NOMEM, GKR_ERR_DEVICE. */
+int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_sizes,
+                       const uint8_t *const *gate_type, const uint32_t *const *in1,
+                       const uint32_t *const *in2, gkr_circuit **out);
+
+/* Release a circuit and the device memory it holds (NULL is ignored).
+ * No proof on the circuit may be running. */
+void gkr_circuit_destroy(gkr_circuit *c);
+
+/* Transcript lengths for the layout above. */
+int gkr_transcript_size(const gkr_circuit *c, uint64_t *n_msgs, uint64_t *n_chals);
+
+/* Shape summary: total gates including inputs (as Table 2 counts them),
+ * total sum-check rounds, and the number of layers d + 1. */
+int gkr_circuit_info(const gkr_circuit *c, uint64_t *gates, uint64_t *rounds,
+                     uint32_t *num_layers);
+
+/* Prove (Sec. 3.1, 4.1.1): evaluate the circuit on `inputs` (S_d values,
+ * each < p; device or host memory), then run one sum-check per layer.
+ *   msgs   host array of exactly n_msgs values (gkr_transcript_size).
+ *   chals  host array of n_chals values, or NULL.
+ * Device scratch is allocated on the first call for a circuit and reused.
+ * Errors: GKR_ERR_INVALID (NULL arguments), GKR_ERR_RANGE (an input >= p;
+ * the transcript is then unspecified), GKR_ERR_NOMEM, GKR_ERR_DEVICE. */
+int gkr_prove(const gkr_circuit *c, const uint64_t *inputs, int inputs_on_device, uint64_t seed,
+              uint64_t *msgs, uint64_t *chals, void *hip_stream);
+
+/* Verify (Sec. 2.2, 4.1.2): replay every round check, the per-layer wiring
+ * identity (add~ and mult~ evaluated on the device from the circuit), the
+ * line step, and compare the last claim with the inputs' multilinear
+ * extension, computed on the device in one pass over the inputs.
+ *   msgs/n_msgs   host transcript.  accepted: 1 or 0.  why: NULL or filled
+ *   on rejection (layer/round/check as in gkr_reject_info).
+ * Errors: GKR_ERR_INVALID, GKR_ERR_RANGE (an input >= p), GKR_ERR_NOMEM,
+ * GKR_ERR_DEVICE.  A wrong-length or non-canonical transcript is a
+ * rejection (GKR_CHECK_MALFORMED), not an error. */
+int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inputs_on_device, uint64_t seed,
+               const uint64_t *msgs, uint64_t n_msgs, int *accepted, gkr_reject_info *why,
+               void *hip_stream);
+
+/* Sum-check for F2 = sum_x ~a(x)^2 over {0,1}^l, n = 2^l (the sum-check
+ * primitive, Sec. 6, on the second frequency moment of Sec. 2.3).
+ *   freq   n uint32 values (device or host); n a power of two, n <= 2^32.
+ *   msgs   host array of 1 + 3 l values: F2, then G_j(0), G_j(1), G_j(2)
+ *          for rounds j = 1..l (G_j(t) = sum_m ((1-t) A[2m] + t A[2m+1])^2
+ *          over the table A folded by the earlier challenges).
+ *   chals  host array of l values, or NULL.
+ * Errors: GKR_ERR_INVALID, GKR_ERR_NOMEM, GKR_ERR_DEVICE. */
+int f2_sumcheck_prove(const uint32_t *freq, uint64_t n, int on_device, uint64_t seed,
+                      uint64_t *msgs, uint64_t *chals, void *hip_stream);
+
+/* Verify an F2 sum-check transcript: round checks, then the last claim
+ * against ~a(r)^2 with ~a(r) computed on the device from freq.
+ * Rejections: GKR_CHECK_MALFORMED, GKR_CHECK_ROUND, GKR_CHECK_INPUT. */
+int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_device, uint64_t seed,
+                       const uint64_t *msgs, uint64_t n_msgs, int *accepted,
+                       gkr_reject_info *why, void *hip_stream);
+
+/* Elementwise F_p arithmetic on the device field module (Sec. 5.1), for
+ * checking it: out[k] = a[k] op b[k], op 0 = add, 1 = sub, 2 = mul;
+ * a, b, out are device arrays of n canonical values.  Errors:
+ * GKR_ERR_INVALID, GKR_ERR_DEVICE. */
+int gkr_field_op(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
+                 void *hip_stream);
+
+/* Per-kernel timing.  While enabled (flag 1), every launch of the prover's
+ * kernels is bracketed by HIP events on its stream.  gkr_profile_read
+ * synchronises, then reports for each kernel class k < *n_classes: total
+ * milliseconds, launch count and algorithmic bytes moved (the per-unit
+ * figures of each kernel times the units processed), and resets the
+ * totals.  names may be NULL; otherwise it receives static strings.
+ * Errors: GKR_ERR_INVALID, GKR_ERR_DEVICE. */
+int gkr_profile_enable(int flag);
+int gkr_profile_read(uint32_t *n_classes, const char **names, double *ms, uint64_t *launches,
+                     double *bytes);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char *gkr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GKR_H */

@@ -1,0 +1,219 @@
+"""MI355X GKR prover / verifier over F_p, p = 2^61 - 1.
+
+Thin ctypes binding of libgkr.so (include/gkr.h): argument marshalling only,
+every step of the proof runs in the library's HIP kernels.  Device buffers
+are torch tensors on a ROCm device; host buffers are numpy arrays.  The
+binding raises if the library is missing -- there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgkr.so")
+P = (1 << 61) - 1
+
+GKR_OK, GKR_ERR_INVALID, GKR_ERR_RANGE, GKR_ERR_NOMEM, GKR_ERR_DEVICE, GKR_ERR_BUFSIZE = \
+    0, -1, -2, -3, -4, -5
+CHECKS = {1: "malformed", 2: "round", 3: "wiring", 4: "line", 5: "input"}
+
+
+class GkrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gkr error {code}: {msg}")
+        self.code = code
+
+
+class RejectInfo(C.Structure):
+    _fields_ = [("layer", C.c_int32), ("round", C.c_int32), ("check", C.c_int32)]
+
+
+_lib = None
+
+# (name, restype, argtypes) for every entry point of include/gkr.h
+_SIGS = [
+    ("gkr_circuit_create", C.c_int, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
+    ("gkr_circuit_destroy", None, [C.c_void_p]),
+    ("gkr_transcript_size", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    ("gkr_circuit_info", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                   C.POINTER(C.c_uint32)]),
+    ("gkr_prove", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_uint64, C.c_void_p, C.c_void_p,
+                            C.c_void_p]),
+    ("gkr_verify", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_uint64, C.c_void_p, C.c_uint64,
+                             C.POINTER(C.c_int), C.POINTER(RejectInfo), C.c_void_p]),
+    ("f2_sumcheck_prove", C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_uint64, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
+    ("f2_sumcheck_verify", C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_uint64, C.c_void_p,
+                                     C.c_uint64, C.POINTER(C.c_int), C.POINTER(RejectInfo),
+                                     C.c_void_p]),
+    ("gkr_field_op", C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                               C.c_void_p]),
+    ("gkr_profile_enable", C.c_int, [C.c_int]),
+    ("gkr_profile_read", C.c_int, [C.POINTER(C.c_uint32), C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
+    ("gkr_last_error", C.c_char_p, []),
+]
+EXPORTS = [s[0] for s in _SIGS]
+
+
+def lib():
+    """Load libgkr.so (built by paper_1202_1350_amd/build.py); raise if absent."""
+    global _lib
+    if _lib is None:
+        # torch's bundled HIP runtime carries the same soname as ROCm's
+        # (libamdhip64.so.7): loading torch first makes libgkr.so bind to that
+        # one copy, so torch tensors and this library share one runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python paper_1202_1350_amd/build.py` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != GKR_OK:
+        raise GkrError(rc, lib().gkr_last_error().decode())
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype):
+    """(pointer, on_device, keepalive) for a numpy array or torch tensor."""
+    if _is_torch(x):
+        import torch
+        want = {np.uint64: torch.uint64, np.uint32: torch.uint32}[dtype]
+        if x.dtype != want or not x.is_contiguous():
+            raise TypeError(f"expected a contiguous {want} tensor")
+        return x.data_ptr(), int(x.is_cuda), x
+    a = np.ascontiguousarray(x, dtype)
+    return a.ctypes.data, 0, a
+
+
+def _stream(dev, stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    if dev:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return None
+
+
+class Circuit:
+    """Device-resident layered circuit (gkr_circuit_create)."""
+
+    def __init__(self, sizes, types, in1, in2):
+        sizes = np.ascontiguousarray(sizes, np.uint32)
+        d = len(sizes) - 1
+        self._keep = [np.ascontiguousarray(t, np.uint8) for t in types] + \
+                     [np.ascontiguousarray(a, np.uint32) for a in in1] + \
+                     [np.ascontiguousarray(b, np.uint32) for b in in2]
+        tp = (C.c_void_p * max(d, 1))(*[a.ctypes.data for a in self._keep[:d]])
+        ap = (C.c_void_p * max(d, 1))(*[a.ctypes.data for a in self._keep[d:2 * d]])
+        bp = (C.c_void_p * max(d, 1))(*[a.ctypes.data for a in self._keep[2 * d:]])
+        h = C.c_void_p()
+        _check(lib().gkr_circuit_create(len(sizes), sizes.ctypes.data, C.cast(tp, C.c_void_p),
+                                        C.cast(ap, C.c_void_p), C.cast(bp, C.c_void_p),
+                                        C.byref(h)))
+        self._keep = None
+        self.handle = h
+        self.sizes = sizes
+        m, c = C.c_uint64(), C.c_uint64()
+        _check(lib().gkr_transcript_size(h, C.byref(m), C.byref(c)))
+        self.n_msgs, self.n_chals = m.value, c.value
+        g, r, nl = C.c_uint64(), C.c_uint64(), C.c_uint32()
+        _check(lib().gkr_circuit_info(h, C.byref(g), C.byref(r), C.byref(nl)))
+        self.gates, self.rounds = g.value, r.value
+
+    @classmethod
+    def from_workload(cls, circ):
+        return cls(circ.sizes, circ.types, circ.in1, circ.in2)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.gkr_circuit_destroy(h)
+            self.handle = None
+
+
+def gkr_circuit_create(sizes, types, in1, in2) -> Circuit:
+    return Circuit(sizes, types, in1, in2)
+
+
+def gkr_prove(circ: Circuit, inputs, seed: int, want_chals: bool = True, stream=None):
+    """(msgs, chals) as uint64 numpy arrays."""
+    p, dev, keep = _ptr(inputs, np.uint64)
+    msgs = np.zeros(max(circ.n_msgs, 1), np.uint64)
+    chals = np.zeros(max(circ.n_chals, 1), np.uint64) if want_chals else None
+    _check(lib().gkr_prove(circ.handle, p, dev, seed, msgs.ctypes.data,
+                           chals.ctypes.data if want_chals else None, _stream(dev, stream)))
+    return msgs[:circ.n_msgs], (chals[:circ.n_chals] if want_chals else None)
+
+
+def gkr_verify(circ: Circuit, inputs, seed: int, msgs, stream=None):
+    """(accepted, layer, round, check)."""
+    p, dev, keep = _ptr(inputs, np.uint64)
+    m = np.ascontiguousarray(msgs, np.uint64)
+    acc = C.c_int()
+    why = RejectInfo()
+    _check(lib().gkr_verify(circ.handle, p, dev, seed, m.ctypes.data if len(m) else None, len(m),
+                            C.byref(acc), C.byref(why), _stream(dev, stream)))
+    return bool(acc.value), why.layer, why.round, why.check
+
+
+def f2_sumcheck_prove(freq, seed: int, stream=None):
+    p, dev, keep = _ptr(freq, np.uint32)
+    n = freq.numel() if _is_torch(freq) else len(keep)
+    l = int(n).bit_length() - 1
+    msgs = np.zeros(1 + 3 * l, np.uint64)
+    chals = np.zeros(max(l, 1), np.uint64)
+    _check(lib().f2_sumcheck_prove(p, n, dev, seed, msgs.ctypes.data, chals.ctypes.data,
+                                   _stream(dev, stream)))
+    return msgs, chals[:l]
+
+
+def f2_sumcheck_verify(freq, seed: int, msgs, stream=None):
+    p, dev, keep = _ptr(freq, np.uint32)
+    n = freq.numel() if _is_torch(freq) else len(keep)
+    m = np.ascontiguousarray(msgs, np.uint64)
+    acc = C.c_int()
+    why = RejectInfo()
+    _check(lib().f2_sumcheck_verify(p, n, dev, seed, m.ctypes.data if len(m) else None, len(m),
+                                    C.byref(acc), C.byref(why), _stream(dev, stream)))
+    return bool(acc.value), why.round, why.check
+
+
+def gkr_field_op(op: int, a, b, out, stream=None):
+    """Elementwise field op on device tensors (0 add, 1 sub, 2 mul)."""
+    pa, _, _ = _ptr(a, np.uint64)
+    pb, _, _ = _ptr(b, np.uint64)
+    po, dev, _ = _ptr(out, np.uint64)
+    _check(lib().gkr_field_op(op, pa, pb, po, out.numel(), _stream(dev, stream)))
+
+
+def gkr_profile_enable(flag: bool):
+    _check(lib().gkr_profile_enable(int(bool(flag))))
+
+
+def gkr_profile_read():
+    """{kernel class: (ms, launches, algorithmic bytes)}; resets the totals."""
+    n = C.c_uint32(32)
+    names = (C.c_char_p * 32)()
+    ms = (C.c_double * 32)()
+    cnt = (C.c_uint64 * 32)()
+    by = (C.c_double * 32)()
+    _check(lib().gkr_profile_read(C.byref(n), C.cast(names, C.c_void_p), C.cast(ms, C.c_void_p),
+                                  C.cast(cnt, C.c_void_p), C.cast(by, C.c_void_p)))
+    return {names[k].decode(): (ms[k], cnt[k], by[k]) for k in range(n.value)}

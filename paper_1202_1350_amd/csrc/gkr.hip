@@ -1,0 +1,1001 @@
+// gkr.hip -- host driver of the GKR prover / verifier and the C ABI (gkr.h).
+//
+// The prover is a fixed sequence of kernel launches on one stream: load the
+// inputs, evaluate the layers (output last), then per layer the p-phase
+// rounds (a-variables), the two omega-phases (b- then c-variables) and the
+// line step.  Challenges are drawn on the device right after each message
+// is reduced, so the host never waits inside a proof; it copies the
+// transcript back once at the end.  Device scratch is allocated on the
+// first proof of a circuit and kept with it (Sec. 5.1 does not count
+// scratch allocation in prover time).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gkr.h"
+#include "fp61.hpp"
+#include "kernels.hpp"
+
+using namespace gkr;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? GKR_ERR_NOMEM : GKR_ERR_DEVICE,          \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+extern "C" const char *gkr_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------- profiling
+
+namespace {
+
+enum ProfClass {
+    PC_EVAL, PC_PPHASE, PC_OMEGA, PC_FOLD, PC_FINAL, PC_LINE, PC_TABLES, PC_WIRING, PC_MLE,
+    PC_F2SC, PC_MISC, PC_COUNT
+};
+const char *kProfNames[PC_COUNT] = {"eval", "pphase", "omega", "fold", "final", "line",
+                                    "eq_tables", "wiring", "mle", "f2sc_round", "misc"};
+
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    double ms[PC_COUNT] = {0};
+    uint64_t n[PC_COUNT] = {0};
+    double bytes[PC_COUNT] = {0};
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+} g_prof;
+
+// Brackets one launch with events when profiling is on.
+struct Scope {
+    int cls;
+    double bytes;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Scope(int c, hipStream_t s, double b) : cls(c), bytes(b), st(s) {
+        if (!g_prof.on) return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        a = g_prof.get();
+        if (a) (void)hipEventRecord(a, st);
+    }
+    ~Scope() {
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        hipEvent_t b = g_prof.get();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        g_prof.recs.push_back({cls, a, b, bytes});
+    }
+};
+
+}  // namespace
+
+extern "C" int gkr_profile_enable(int flag) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = flag != 0;
+    return GKR_OK;
+}
+
+extern "C" int gkr_profile_read(uint32_t *n_classes, const char **names, double *ms,
+                                uint64_t *launches, double *bytes) {
+    if (!n_classes) return fail(GKR_ERR_INVALID, "n_classes is NULL");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (auto &r : g_prof.recs) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+        g_prof.ms[r.cls] += t;
+        g_prof.n[r.cls] += 1;
+        g_prof.bytes[r.cls] += r.bytes;
+        g_prof.pool.push_back(r.a);
+        g_prof.pool.push_back(r.b);
+    }
+    g_prof.recs.clear();
+    uint32_t cap = *n_classes;
+    *n_classes = PC_COUNT;
+    for (uint32_t k = 0; k < PC_COUNT && k < cap; k++) {
+        if (names) names[k] = kProfNames[k];
+        if (ms) ms[k] = g_prof.ms[k];
+        if (launches) launches[k] = g_prof.n[k];
+        if (bytes) bytes[k] = g_prof.bytes[k];
+        g_prof.ms[k] = 0;
+        g_prof.n[k] = 0;
+        g_prof.bytes[k] = 0;
+    }
+    return GKR_OK;
+}
+
+// ------------------------------------------------------------------ helpers
+
+namespace {
+
+u32 log2ceil(u64 n) {
+    u32 s = 0;
+    while ((1ull << s) < n) s++;
+    return s;
+}
+
+// The library's own stream per device, used when the caller passes NULL.
+hipStream_t default_stream() {
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev]) {
+        if (hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+            return nullptr;
+    }
+    return streams[dev];
+}
+
+hipStream_t pick_stream(void *s) { return s ? (hipStream_t)s : default_stream(); }
+
+// Bump allocator over one device allocation; every piece 256-byte aligned.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    template <class T>
+    T *take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        if (base == nullptr) {  // sizing pass
+            used += bytes;
+            return nullptr;
+        }
+        T *p = reinterpret_cast<T *>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+constexpr u32 HALF_MAX = 1u << 16;  // eq half tables: at most 2^16 entries
+
+void split_half(u32 s, u32 *L) { *L = s / 2; }
+
+// Line-step shape for s' variables: lanes 2^L, waves 2^M, steps 2^H.
+void line_shape(u32 sp, u32 *L, u32 *M, u32 *H) {
+    *L = std::min<u32>(6, sp);
+    *M = std::min<u32>(sp - *L, 13);
+    *H = sp - *L - *M;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ circuit
+
+struct Workspace {
+    void *mem = nullptr;
+    std::vector<u64 *> V;  // per layer, 2^{s_i}
+    u64 *pA, *pB, *bA, *bB, *fA, *fB;
+    u64 *w, *off;
+    u64 *zbuf;
+    u64 *zlo, *zhi, *alo, *ahi, *blo, *bhi;
+    u64 *llo, *lhl, *lhh;
+    u64 *partials;
+    u64 *msgs, *chals;
+    ProofState *ps;
+    u32 *flag;
+    u64 *h_msgs = nullptr, *h_chals = nullptr;  // pinned staging
+    u32 *h_flag = nullptr;
+};
+
+struct gkr_circuit {
+    int device = 0;
+    u32 L = 0;  // layers incl. input
+    std::vector<u32> S, s;
+    std::vector<int> kind;
+    std::vector<u8 *> type;
+    std::vector<u32 *> in1, in2;
+    void *soa = nullptr;
+    u64 n_msgs = 0, n_chals = 0, gates = 0, rounds = 0;
+    std::vector<u64> mo, co;  // per layer: offset of its round messages / challenges
+    u32 smax = 0, spmax = 0;
+    u64 gmax = 0;
+    u64 line_lo = 1, line_hl = 1, line_hh = 1;  // table sizes (entries)
+    std::mutex mu;
+    Workspace *ws = nullptr;
+};
+
+extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_sizes,
+                                  const uint8_t *const *gate_type, const uint32_t *const *in1,
+                                  const uint32_t *const *in2, gkr_circuit **out) {
+    if (!out) return fail(GKR_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (num_layers < 2) return fail(GKR_ERR_INVALID, "need at least 2 layers");
+    if (!layer_sizes || !gate_type || !in1 || !in2) return fail(GKR_ERR_INVALID, "NULL array");
+    for (u32 i = 0; i < num_layers; i++) {
+        if (layer_sizes[i] == 0 || layer_sizes[i] >= (1u << 31))
+            return fail(GKR_ERR_INVALID, "layer size must be in [1, 2^31)");
+    }
+    std::unique_ptr<gkr_circuit> c(new gkr_circuit());
+    HIP_TRY(hipGetDevice(&c->device));
+    c->L = num_layers;
+    c->S.assign(layer_sizes, layer_sizes + num_layers);
+    c->s.resize(num_layers);
+    for (u32 i = 0; i < num_layers; i++) {
+        c->s[i] = log2ceil(c->S[i]);
+        c->gates += c->S[i];
+        c->smax = std::max(c->smax, c->s[i]);
+        c->gmax = std::max<u64>(c->gmax, c->S[i]);
+    }
+    const u32 d = num_layers - 1;
+    c->kind.resize(d);
+    size_t soa_bytes = 0;
+    for (u32 i = 0; i < d; i++) {
+        if (!gate_type[i] || !in1[i] || !in2[i]) return fail(GKR_ERR_INVALID, "NULL layer array");
+        const u64 lim = 1ull << c->s[i + 1];
+        bool any_add = false, any_mul = false;
+        for (u32 g = 0; g < c->S[i]; g++) {
+            if (gate_type[i][g] > 1) return fail(GKR_ERR_INVALID, "gate type must be 0 or 1");
+            if (in1[i][g] >= lim || in2[i][g] >= lim)
+                return fail(GKR_ERR_INVALID, "wire beyond the padded next layer");
+            (gate_type[i][g] ? any_mul : any_add) = true;
+        }
+        c->kind[i] = any_add && any_mul ? KIND_MIXED : (any_mul ? KIND_MUL : KIND_ADD);
+        size_t n = c->S[i];
+        soa_bytes += ((n * 4 + 255) & ~size_t(255)) * 2;
+        if (c->kind[i] == KIND_MIXED) soa_bytes += (n + 255) & ~size_t(255);
+    }
+    // transcript layout
+    c->n_msgs = c->S[0];
+    c->n_chals = c->s[0];
+    c->mo.resize(d);
+    c->co.resize(d);
+    for (u32 i = 0; i < d; i++) {
+        const u64 n = c->s[i] + 2ull * c->s[i + 1];
+        const u32 sp = c->s[i + 1];
+        c->mo[i] = c->n_msgs;
+        c->co[i] = c->n_chals;
+        c->n_msgs += 3 * n + 2 + (sp >= 2 ? sp - 1 : 0);
+        c->n_chals += n + 1;
+        c->rounds += n;
+        c->spmax = std::max(c->spmax, sp);
+        if (sp >= 2) {
+            u32 Ll, M, H;
+            line_shape(sp, &Ll, &M, &H);
+            c->line_lo = std::max<u64>(c->line_lo, (u64)(sp - 1) << Ll);
+            c->line_hl = std::max<u64>(c->line_hl, (u64)(sp - 1) << M);
+            c->line_hh = std::max<u64>(c->line_hh, (u64)(sp - 1) << H);
+        }
+    }
+    // struct-of-arrays upload
+    HIP_TRY(hipMalloc(&c->soa, std::max<size_t>(soa_bytes, 256)));
+    char *p = (char *)c->soa;
+    c->type.assign(d, nullptr);
+    c->in1.assign(d, nullptr);
+    c->in2.assign(d, nullptr);
+    for (u32 i = 0; i < d; i++) {
+        size_t n = c->S[i];
+        c->in1[i] = (u32 *)p;
+        p += (n * 4 + 255) & ~size_t(255);
+        c->in2[i] = (u32 *)p;
+        p += (n * 4 + 255) & ~size_t(255);
+        HIP_TRY(hipMemcpy(c->in1[i], in1[i], n * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->in2[i], in2[i], n * 4, hipMemcpyHostToDevice));
+        if (c->kind[i] == KIND_MIXED) {
+            c->type[i] = (u8 *)p;
+            p += (n + 255) & ~size_t(255);
+            HIP_TRY(hipMemcpy(c->type[i], gate_type[i], n, hipMemcpyHostToDevice));
+        }
+    }
+    *out = c.release();
+    return GKR_OK;
+}
+
+static void free_workspace(Workspace *ws) {
+    if (!ws) return;
+    if (ws->mem) (void)hipFree(ws->mem);
+    if (ws->h_msgs) (void)hipHostFree(ws->h_msgs);
+    if (ws->h_chals) (void)hipHostFree(ws->h_chals);
+    if (ws->h_flag) (void)hipHostFree(ws->h_flag);
+    delete ws;
+}
+
+extern "C" void gkr_circuit_destroy(gkr_circuit *c) {
+    if (!c) return;
+    free_workspace(c->ws);
+    if (c->soa) (void)hipFree(c->soa);
+    delete c;
+}
+
+extern "C" int gkr_transcript_size(const gkr_circuit *c, uint64_t *n_msgs, uint64_t *n_chals) {
+    if (!c) return fail(GKR_ERR_INVALID, "circuit is NULL");
+    if (n_msgs) *n_msgs = c->n_msgs;
+    if (n_chals) *n_chals = c->n_chals;
+    return GKR_OK;
+}
+
+extern "C" int gkr_circuit_info(const gkr_circuit *c, uint64_t *gates, uint64_t *rounds,
+                                uint32_t *num_layers) {
+    if (!c) return fail(GKR_ERR_INVALID, "circuit is NULL");
+    if (gates) *gates = c->gates;
+    if (rounds) *rounds = c->rounds;
+    if (num_layers) *num_layers = c->L;
+    return GKR_OK;
+}
+
+// Lay out (or size, when a.base is NULL) the prover's scratch.
+static void carve(const gkr_circuit *c, Arena &a, Workspace &w) {
+    w.V.assign(c->L, nullptr);
+    for (u32 i = 0; i < c->L; i++) w.V[i] = a.take<u64>(1ull << c->s[i]);
+    const u64 half = std::max<u64>(1ull << (c->smax ? c->smax - 1 : 0), 2);
+    w.pA = a.take<u64>(half);
+    w.pB = a.take<u64>(half);
+    w.bA = a.take<u64>(half);
+    w.bB = a.take<u64>(half);
+    w.fA = a.take<u64>(half);
+    w.fB = a.take<u64>(half);
+    w.w = a.take<u64>(c->gmax);
+    w.off = a.take<u64>(c->gmax);
+    w.zbuf = a.take<u64>(64);
+    w.zlo = a.take<u64>(HALF_MAX);
+    w.zhi = a.take<u64>(HALF_MAX);
+    w.alo = a.take<u64>(HALF_MAX);
+    w.ahi = a.take<u64>(HALF_MAX);
+    w.blo = a.take<u64>(HALF_MAX);
+    w.bhi = a.take<u64>(HALF_MAX);
+    w.llo = a.take<u64>(c->line_lo);
+    w.lhl = a.take<u64>(c->line_hl);
+    w.lhh = a.take<u64>(c->line_hh);
+    w.partials = a.take<u64>((u64)MAX_BLOCKS * MAX_LINE);
+    w.msgs = a.take<u64>(c->n_msgs);
+    w.chals = a.take<u64>(std::max<u64>(c->n_chals, 1));
+    w.ps = a.take<ProofState>(1);
+    w.flag = a.take<u32>(1);
+}
+
+static int ensure_workspace(gkr_circuit *c) {
+    if (c->ws) return GKR_OK;
+    Workspace probe;
+    Arena sz;
+    carve(c, sz, probe);
+    std::unique_ptr<Workspace> ws(new Workspace());
+    HIP_TRY(hipMalloc(&ws->mem, sz.used));
+    Arena a;
+    a.base = (char *)ws->mem;
+    a.cap = sz.used;
+    carve(c, a, *ws);
+    HIP_TRY(hipHostMalloc((void **)&ws->h_msgs, c->n_msgs * 8));
+    HIP_TRY(hipHostMalloc((void **)&ws->h_chals, std::max<u64>(c->n_chals, 1) * 8));
+    HIP_TRY(hipHostMalloc((void **)&ws->h_flag, 4));
+    c->ws = ws.release();
+    return GKR_OK;
+}
+
+// ------------------------------------------------------------------- prover
+
+#define LAUNCH(cls, bytes, expr)                                  \
+    do {                                                          \
+        Scope sc_(cls, st, (double)(bytes));                      \
+        HIP_TRY(expr);                                            \
+    } while (0)
+
+// Enqueue one whole proof; inputs already in ws.V[d].
+static int enqueue_proof(const gkr_circuit *c, Workspace &w, u64 seed, hipStream_t st) {
+    const u32 d = c->L - 1;
+    int nb = 0;
+    // circuit evaluation, layer d-1 down to 0 (a3)
+    for (int i = (int)d - 1; i >= 0; i--) {
+        const u64 S = c->S[i], npad = 1ull << c->s[i];
+        const double bytes = S * (8.0 + 16 + 8 + (c->kind[i] == KIND_MIXED ? 1 : 0)) + (npad - S) * 8.0;
+        LAUNCH(PC_EVAL, bytes,
+               launch_eval(st, c->kind[i], c->S[i], npad, c->type[i], c->in1[i], c->in2[i],
+                           w.V[i + 1], w.V[i]));
+    }
+    LAUNCH(PC_MISC, c->S[0] * 16.0,
+           launch_init_proof(st, w.ps, seed, c->s[0], w.V[0], c->S[0], w.msgs, w.chals, w.zbuf));
+
+    for (u32 i = 0; i < d; i++) {
+        const u32 s = c->s[i], sp = c->s[i + 1], S = c->S[i];
+        const u32 n = s + 2 * sp;
+        const int kind = c->kind[i];
+        u64 *msg = w.msgs + c->mo[i];
+        u64 *chal = w.chals + c->co[i];
+        // ---- p-phase (a5): rounds over the a-variables
+        if (s > 0) {
+            u32 Lz;
+            split_half(s - 1, &Lz);
+            LAUNCH(PC_TABLES, 8.0 * ((1ull << Lz) + (1ull << (s - 1 - Lz))),
+                   launch_eq_halves(st, w.zbuf + 1, s - 1, Lz, w.zlo, w.zhi));
+            const u64 *Vsrc = w.V[i];
+            u64 *vbuf[2] = {w.pA, w.pB};
+            u64 *bbuf[2] = {w.bA, w.bB};
+            const u64 *Bprev = nullptr;
+            for (u32 j = 0; j < s; j++) {
+                const u64 nm = 1ull << (s - j - 1);
+                const bool first = j == 0;
+                u64 *Vout = first ? nullptr : vbuf[j & 1];
+                u64 *Bout = (j + 1 < s) ? bbuf[j & 1] : nullptr;
+                const double bytes = first ? nm * (16.0 + 8) : nm * (32.0 + 16 + 16 + 8);
+                LAUNCH(PC_PPHASE, bytes,
+                       launch_pphase(st, first, nm, Vsrc, Vout, Bprev, Bout, w.zlo, w.zhi, Lz,
+                                     first ? nullptr : chal + j - 1, w.partials, &nb));
+                LAUNCH(PC_FINAL, nb * 16.0,
+                       launch_pfinal(st, nb, w.partials, w.ps, w.zbuf + j, msg + 3 * j, chal + j));
+                if (!first) Vsrc = Vout;
+                Bprev = Bout;
+            }
+        }
+        u64 *vslot = msg + 3ull * n;  // v1, v2, then h(2..s')
+        if (sp == 0) {
+            LAUNCH(PC_MISC, 8.0, launch_single_gate_end(st, w.V[i + 1], w.ps, vslot));
+        } else {
+            // ---- omega-phases (a6, a7, a8)
+            u32 La, Lb;
+            split_half(s, &La);
+            split_half(sp, &Lb);
+            LAUNCH(PC_TABLES, 8.0 * ((1ull << La) + (1ull << (s - La))),
+                   launch_eq_halves(st, chal, s, La, w.alo, w.ahi));
+            for (int ph = 1; ph <= 2; ph++) {
+                if (ph == 2)
+                    LAUNCH(PC_TABLES, 8.0 * ((1ull << Lb) + (1ull << (sp - Lb))),
+                           launch_eq_halves(st, chal + s, sp, Lb, w.blo, w.bhi));
+                const u64 *F = w.V[i + 1];
+                u64 *fbuf[2] = {w.fA, w.fB};
+                const u32 rbase = s + (ph == 2 ? sp : 0);
+                for (u32 k = 0; k < sp; k++) {
+                    if (k > 0) {
+                        const u64 nh = 1ull << (sp - k);
+                        u64 *dst = fbuf[k & 1];
+                        LAUNCH(PC_FOLD, nh * 24.0, launch_fold(st, nh, F, dst, chal + rbase + k - 1));
+                        F = dst;
+                    }
+                    OmegaArgs a;
+                    a.kind = kind;
+                    a.ph = ph;
+                    a.init = k == 0;
+                    a.write_w = k + 1 < sp;
+                    a.S = S;
+                    a.k = k;
+                    a.idx = ph == 1 ? c->in1[i] : c->in2[i];
+                    a.oth = ph == 1 ? c->in2[i] : c->in1[i];
+                    a.type = c->type[i];
+                    a.F = F;
+                    a.Vn = w.V[i + 1];
+                    a.alo = w.alo;
+                    a.ahi = w.ahi;
+                    a.La = La;
+                    a.blo = w.blo;
+                    a.bhi = w.bhi;
+                    a.Lb = Lb;
+                    a.ps = w.ps;
+                    a.rptr = k > 0 ? chal + rbase + k - 1 : nullptr;
+                    a.w = w.w;
+                    a.off = w.off;
+                    a.partials = w.partials;
+                    // algorithmic bytes per gate: index 4, weight read 8 (not at
+                    // init) and write 8 (not in the last round), the additive
+                    // operand 8 (phase 1 with ADD gates), type 1 (mixed),
+                    // init: other index 4 + operand gather 8 (phase 1);
+                    // plus one pass over the fold table.
+                    double per = 4.0 + (a.init ? 0 : 8) + (a.write_w ? 8 : 0) +
+                                 (ph == 1 && kind != KIND_MUL ? 8 : 0) + (kind == KIND_MIXED ? 1 : 0) +
+                                 (a.init ? 4.0 + (ph == 1 ? 8 : 0) : 0);
+                    const double bytes = S * per + 8.0 * (1ull << (sp - k));
+                    LAUNCH(PC_OMEGA, bytes, launch_omega(st, a, &nb));
+                    const int last = k + 1 == sp ? ph : 0;
+                    LAUNCH(PC_FINAL, nb * 32.0,
+                           launch_wfinal(st, nb, w.partials, w.ps, msg + 3ull * (rbase + k),
+                                         chal + rbase + k, last, F, vslot + (ph - 1)));
+                }
+            }
+        }
+        // ---- line step (a9)
+        const u64 *bstar = chal + s, *cstar = chal + s + sp;
+        int nparts = 0;
+        if (sp >= 2) {
+            u32 Ll, M, H;
+            line_shape(sp, &Ll, &M, &H);
+            LAUNCH(PC_TABLES, 8.0 * (sp - 1) * ((1ull << Ll) + (1ull << M) + (1ull << H)),
+                   launch_line_tables(st, bstar, cstar, sp, Ll, M, w.llo, w.lhl, w.lhh));
+            LAUNCH(PC_LINE, 8.0 * (1ull << sp),
+                   launch_line(st, sp, Ll, M, w.V[i + 1], w.llo, w.lhl, w.lhh, w.partials, &nparts));
+        }
+        LAUNCH(PC_FINAL, nparts * 8.0 * MAX_LINE,
+               launch_line_final(st, nparts, w.partials, sp, w.ps, bstar, cstar, vslot + 2,
+                                 chal + n, w.zbuf));
+    }
+    return GKR_OK;
+}
+
+extern "C" int gkr_prove(const gkr_circuit *cc, const uint64_t *inputs, int inputs_on_device,
+                         uint64_t seed, uint64_t *msgs, uint64_t *chals, void *hip_stream) {
+    if (!cc || !inputs || !msgs) return fail(GKR_ERR_INVALID, "NULL argument");
+    gkr_circuit *c = const_cast<gkr_circuit *>(cc);
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    std::lock_guard<std::mutex> lk(c->mu);
+    int rc = ensure_workspace(c);
+    if (rc) return rc;
+    Workspace &w = *c->ws;
+    const u32 d = c->L - 1;
+    const u64 Sd = c->S[d], npad = 1ull << c->s[d];
+    if (inputs_on_device) {
+        HIP_TRY(hipMemsetAsync(w.flag, 0, 4, st));
+        LAUNCH(PC_MISC, Sd * 8.0 + npad * 8.0, launch_load_inputs(st, inputs, Sd, npad, w.V[d], w.flag));
+    } else {
+        for (u64 g = 0; g < Sd; g++)
+            if (inputs[g] >= fp::P) return fail(GKR_ERR_RANGE, "input value not below p");
+        HIP_TRY(hipMemcpyAsync(w.V[d], inputs, Sd * 8, hipMemcpyHostToDevice, st));
+        if (npad > Sd) HIP_TRY(hipMemsetAsync(w.V[d] + Sd, 0, (npad - Sd) * 8, st));
+    }
+    rc = enqueue_proof(c, w, seed, st);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(w.h_msgs, w.msgs, c->n_msgs * 8, hipMemcpyDeviceToHost, st));
+    if (chals) HIP_TRY(hipMemcpyAsync(w.h_chals, w.chals, c->n_chals * 8, hipMemcpyDeviceToHost, st));
+    if (inputs_on_device) HIP_TRY(hipMemcpyAsync(w.h_flag, w.flag, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (inputs_on_device && *w.h_flag) return fail(GKR_ERR_RANGE, "input value not below p");
+    memcpy(msgs, w.h_msgs, c->n_msgs * 8);
+    if (chals) memcpy(chals, w.h_chals, c->n_chals * 8);
+    return GKR_OK;
+}
+
+// ----------------------------------------------------------------- verifier
+
+namespace {
+
+// Lagrange interpolation of y[0..D] at nodes 0..D, evaluated at x.
+u64 lagrange_host(const u64 *y, u32 D, u64 x) {
+    using namespace fp;
+    u64 acc = 0;
+    for (u32 i = 0; i <= D; i++) {
+        u64 num = 1, den = 1;
+        for (u32 j = 0; j <= D; j++) {
+            if (j == i) continue;
+            num = mul(num, sub(x, j));
+            den = mul(den, sub(i, j));
+        }
+        acc = add(acc, mul(y[i], mul(num, inv(den))));
+    }
+    return acc;
+}
+
+// G(r) for a degree-2 message given at 0, 1, 2.
+u64 quad_at(const u64 *G, u64 r) {
+    using namespace fp;
+    const u64 inv2 = 1ull << 60;  // 2 * 2^60 = 2^61 = 1
+    const u64 r1 = sub(r, 1), r2 = sub(r, 2);
+    u64 t0 = mul(mul(G[0], mul(r1, r2)), inv2);
+    u64 t1 = mul(G[1], mul(r, r2));
+    u64 t2 = mul(mul(G[2], mul(r, r1)), inv2);
+    return add(sub(t0, t1), t2);
+}
+
+// ~T(pt) on the host by binding variables one at a time (small tables).
+u64 mle_host(std::vector<u64> T, const u64 *pt, u32 s) {
+    using namespace fp;
+    for (u32 k = 0; k < s; k++) {
+        const u64 h = 1ull << (s - k - 1);
+        for (u64 m = 0; m < h; m++) T[m] = add(T[2 * m], mul(pt[k], sub(T[2 * m + 1], T[2 * m])));
+    }
+    return T[0];
+}
+
+struct VerifyScratch {
+    std::mutex mu;
+    int device = -1;
+    void *mem = nullptr;
+    size_t cap = 0;
+    u64 *h_res = nullptr;
+    size_t h_cap = 0;
+};
+VerifyScratch g_vs;
+
+int vs_reserve(size_t bytes, size_t host_words) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (g_vs.device != dev || g_vs.cap < bytes) {
+        if (g_vs.mem) (void)hipFree(g_vs.mem);
+        g_vs.mem = nullptr;
+        g_vs.cap = 0;
+        HIP_TRY(hipMalloc(&g_vs.mem, bytes));
+        g_vs.cap = bytes;
+        g_vs.device = dev;
+    }
+    if (g_vs.h_cap < host_words) {
+        if (g_vs.h_res) (void)hipHostFree(g_vs.h_res);
+        g_vs.h_res = nullptr;
+        HIP_TRY(hipHostMalloc((void **)&g_vs.h_res, host_words * 8));
+        g_vs.h_cap = host_words;
+    }
+    return GKR_OK;
+}
+
+void reject(int *accepted, gkr_reject_info *why, int layer, int round, int check) {
+    *accepted = 0;
+    if (why) {
+        why->layer = layer;
+        why->round = round;
+        why->check = check;
+    }
+}
+
+}  // namespace
+
+extern "C" int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inputs_on_device,
+                          uint64_t seed, const uint64_t *msgs, uint64_t n_msgs, int *accepted,
+                          gkr_reject_info *why, void *hip_stream) {
+    using namespace fp;
+    if (!c || !inputs || !accepted || (!msgs && n_msgs)) return fail(GKR_ERR_INVALID, "NULL argument");
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    *accepted = 0;
+    if (why) *why = {-1, -1, 0};
+    const u32 d = c->L - 1;
+    const u64 Sd = c->S[d];
+    if (!inputs_on_device) {
+        for (u64 g = 0; g < Sd; g++)
+            if (inputs[g] >= P) return fail(GKR_ERR_RANGE, "input value not below p");
+    }
+    if (n_msgs != c->n_msgs) {
+        reject(accepted, why, -1, -1, GKR_CHECK_MALFORMED);
+        return GKR_OK;
+    }
+    for (u64 k = 0; k < n_msgs; k++)
+        if (msgs[k] >= P) {
+            reject(accepted, why, -1, -1, GKR_CHECK_MALFORMED);
+            return GKR_OK;
+        }
+    // The verifier's own coins: same stream as the prover's challenges.
+    std::vector<u64> ch(c->n_chals);
+    u64 rs = sm_state(seed, PURPOSE_GKR);
+    for (auto &x : ch) x = sm_field(rs);
+    // z_{i} for every layer; z_{i+1} = l(tau) of layer i.
+    std::vector<std::vector<u64>> z(c->L);
+    z[0].assign(ch.begin(), ch.begin() + c->s[0]);
+    for (u32 i = 0; i < d; i++) {
+        const u32 s = c->s[i], sp = c->s[i + 1], n = s + 2 * sp;
+        const u64 *r = ch.data() + c->co[i];
+        const u64 tau = r[n];
+        z[i + 1].resize(sp);
+        for (u32 k = 0; k < sp; k++) z[i + 1][k] = add(r[s + k], mul(tau, sub(r[s + sp + k], r[s + k])));
+    }
+    // Device part: add~ / mult~ per layer, and the inputs' extension at z_d.
+    std::lock_guard<std::mutex> lk(g_vs.mu);
+    Arena sz;
+    const u64 npts = c->n_chals + c->s[d] + 8;
+    struct {
+        u64 *pts, *tab, *partials, *res, *in;
+        u32 *flag;
+    } v;
+    auto lay = [&](Arena &a) {
+        v.pts = a.take<u64>(npts);
+        v.tab = a.take<u64>(6ull * HALF_MAX);
+        v.partials = a.take<u64>((u64)MAX_BLOCKS * 4);
+        v.res = a.take<u64>(2ull * d + 2);
+        v.in = a.take<u64>(inputs_on_device ? 1 : Sd);
+        v.flag = a.take<u32>(1);
+    };
+    lay(sz);
+    int rc = vs_reserve(sz.used, 2ull * d + 3);
+    if (rc) return rc;
+    Arena a;
+    a.base = (char *)g_vs.mem;
+    lay(a);
+    // points: chals as drawn, then z_d
+    std::vector<u64> pts(npts, 0);
+    std::copy(ch.begin(), ch.end(), pts.begin());
+    std::copy(z[d].begin(), z[d].end(), pts.begin() + c->n_chals);
+    HIP_TRY(hipMemcpyAsync(v.pts, pts.data(), npts * 8, hipMemcpyHostToDevice, st));
+    const u64 *in_dev = inputs;
+    if (!inputs_on_device) {
+        HIP_TRY(hipMemcpyAsync(v.in, inputs, Sd * 8, hipMemcpyHostToDevice, st));
+        in_dev = v.in;
+    } else {
+        HIP_TRY(hipMemsetAsync(v.flag, 0, 4, st));
+        LAUNCH(PC_MISC, Sd * 8.0, launch_check_range(st, inputs, Sd, v.flag));
+    }
+    u64 *T = v.tab;
+    int nb = 0;
+    for (u32 i = 0; i < d; i++) {
+        const u32 s = c->s[i], sp = c->s[i + 1];
+        const u64 *r = v.pts + c->co[i];
+        u32 La, Lb;
+        split_half(s, &La);
+        split_half(sp, &Lb);
+        LAUNCH(PC_TABLES, 0, launch_eq_halves(st, r, s, La, T, T + HALF_MAX));
+        LAUNCH(PC_TABLES, 0, launch_eq_halves(st, r + s, sp, Lb, T + 2 * HALF_MAX, T + 3 * HALF_MAX));
+        LAUNCH(PC_TABLES, 0,
+               launch_eq_halves(st, r + s + sp, sp, Lb, T + 4 * HALF_MAX, T + 5 * HALF_MAX));
+        WiringArgs wa;
+        wa.kind = c->kind[i];
+        wa.S = c->S[i];
+        wa.type = c->type[i];
+        wa.in1 = c->in1[i];
+        wa.in2 = c->in2[i];
+        wa.alo = T;
+        wa.ahi = T + HALF_MAX;
+        wa.La = La;
+        wa.blo = T + 2 * HALF_MAX;
+        wa.bhi = T + 3 * HALF_MAX;
+        wa.Lb = Lb;
+        wa.clo = T + 4 * HALF_MAX;
+        wa.chi = T + 5 * HALF_MAX;
+        wa.Lc = Lb;
+        wa.partials = v.partials;
+        LAUNCH(PC_WIRING, c->S[i] * 8.0, launch_wiring(st, wa, &nb));
+        LAUNCH(PC_MISC, 0, launch_reduce_rows(st, nb, 2, v.partials, v.res + 2 * i));
+    }
+    {
+        const u32 sd = c->s[d];
+        u32 Ld;
+        split_half(sd, &Ld);
+        LAUNCH(PC_TABLES, 0, launch_eq_halves(st, v.pts + c->n_chals, sd, Ld, T, T + HALF_MAX));
+        LAUNCH(PC_MLE, Sd * 8.0, launch_mle(st, Sd, in_dev, nullptr, T, T + HALF_MAX, Ld, v.partials, &nb));
+        LAUNCH(PC_MISC, 0, launch_reduce_rows(st, nb, 1, v.partials, v.res + 2 * d));
+    }
+    HIP_TRY(hipMemcpyAsync(g_vs.h_res, v.res, (2ull * d + 1) * 8, hipMemcpyDeviceToHost, st));
+    if (inputs_on_device)
+        HIP_TRY(hipMemcpyAsync(g_vs.h_res + 2ull * d + 1, v.flag, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (inputs_on_device && (uint32_t)g_vs.h_res[2ull * d + 1])
+        return fail(GKR_ERR_RANGE, "input value not below p");
+    const u64 *res = g_vs.h_res;
+    // Host replay of the protocol (a10).
+    u64 mi = 0;
+    std::vector<u64> outs(1ull << c->s[0], 0);
+    for (u32 g = 0; g < c->S[0]; g++) outs[g] = msgs[mi++];
+    u64 claim = mle_host(outs, z[0].data(), c->s[0]);
+    for (u32 i = 0; i < d; i++) {
+        const u32 s = c->s[i], sp = c->s[i + 1], n = s + 2 * sp;
+        const u64 *r = ch.data() + c->co[i];
+        for (u32 j = 0; j < n; j++) {
+            const u64 *G = msgs + mi;
+            mi += 3;
+            if (add(G[0], G[1]) != claim) {
+                reject(accepted, why, (int)i, (int)j, GKR_CHECK_ROUND);
+                return GKR_OK;
+            }
+            claim = quad_at(G, r[j]);
+        }
+        const u64 v1 = msgs[mi++], v2 = msgs[mi++];
+        u64 beta = 1;
+        for (u32 k = 0; k < s; k++) beta = mul(beta, eq(z[i][k], r[k]));
+        const u64 addv = res[2 * i], mulv = res[2 * i + 1];
+        const u64 rhs = mul(beta, add(mul(addv, add(v1, v2)), mul(mulv, mul(v1, v2))));
+        if (rhs != claim) {
+            reject(accepted, why, (int)i, (int)n, GKR_CHECK_WIRING);
+            return GKR_OK;
+        }
+        if (sp == 0 && v1 != v2) {
+            reject(accepted, why, (int)i, -1, GKR_CHECK_LINE);
+            return GKR_OK;
+        }
+        std::vector<u64> y(std::max<u32>(sp, 1) + 1);
+        y[0] = v1;
+        y[1] = v2;
+        for (u32 t = 2; t <= sp; t++) y[t] = msgs[mi++];
+        claim = lagrange_host(y.data(), std::max<u32>(sp, 1), r[n]);
+    }
+    if (res[2 * d] != claim) {
+        reject(accepted, why, (int)d, -1, GKR_CHECK_INPUT);
+        return GKR_OK;
+    }
+    *accepted = 1;
+    return GKR_OK;
+}
+
+// --------------------------------------------------------- F2 sum-check
+
+namespace {
+
+struct F2Scratch {
+    std::mutex mu;
+    int device = -1;
+    void *mem = nullptr;
+    size_t cap = 0;
+    u64 *h = nullptr;
+    size_t h_cap = 0;
+} g_f2;
+
+int f2_reserve(size_t bytes, size_t host_words) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (g_f2.device != dev || g_f2.cap < bytes) {
+        if (g_f2.mem) (void)hipFree(g_f2.mem);
+        g_f2.mem = nullptr;
+        g_f2.cap = 0;
+        HIP_TRY(hipMalloc(&g_f2.mem, bytes));
+        g_f2.cap = bytes;
+        g_f2.device = dev;
+    }
+    if (g_f2.h_cap < host_words) {
+        if (g_f2.h) (void)hipHostFree(g_f2.h);
+        g_f2.h = nullptr;
+        HIP_TRY(hipHostMalloc((void **)&g_f2.h, host_words * 8));
+        g_f2.h_cap = host_words;
+    }
+    return GKR_OK;
+}
+
+bool pow2(u64 n) { return n && !(n & (n - 1)); }
+
+}  // namespace
+
+extern "C" int f2_sumcheck_prove(const uint32_t *freq, uint64_t n, int on_device, uint64_t seed,
+                                 uint64_t *msgs, uint64_t *chals, void *hip_stream) {
+    if (!freq || !msgs) return fail(GKR_ERR_INVALID, "NULL argument");
+    if (!pow2(n) || n > (1ull << 32)) return fail(GKR_ERR_INVALID, "n must be a power of two <= 2^32");
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    const u32 l = log2ceil(n);
+    const u64 nm = 1 + 3ull * l;
+    std::lock_guard<std::mutex> lk(g_f2.mu);
+    struct {
+        u64 *A0, *A1, *partials, *msgs, *chals;
+        ProofState *ps;
+        u32 *in;
+    } v;
+    auto lay = [&](Arena &a) {
+        v.A0 = a.take<u64>(std::max<u64>(n / 2, 2));
+        v.A1 = a.take<u64>(std::max<u64>(n / 4, 2));
+        v.partials = a.take<u64>((u64)MAX_BLOCKS * 3);
+        v.msgs = a.take<u64>(nm);
+        v.chals = a.take<u64>(std::max<u32>(l, 1));
+        v.ps = a.take<ProofState>(1);
+        v.in = a.take<u32>(on_device ? 1 : n);
+    };
+    Arena sz;
+    lay(sz);
+    int rc = f2_reserve(sz.used, nm + l + 1);
+    if (rc) return rc;
+    Arena a;
+    a.base = (char *)g_f2.mem;
+    lay(a);
+    const u32 *a32 = freq;
+    if (!on_device) {
+        HIP_TRY(hipMemcpyAsync(v.in, freq, n * 4, hipMemcpyHostToDevice, st));
+        a32 = v.in;
+    }
+    int nb = 0;
+    if (l == 0) {
+        LAUNCH(PC_MISC, 4, launch_f2sc_single(st, a32, v.msgs));
+    } else {
+        LAUNCH(PC_MISC, 0, launch_f2sc_init(st, v.ps, seed));
+        u64 *bufs[2] = {v.A0, v.A1};
+        const u64 *src = nullptr;
+        for (u32 j = 0; j < l; j++) {
+            const u64 pairs = n >> (j + 1);
+            u64 *dst = j == 0 ? nullptr : bufs[(j + 1) & 1];
+            const double bytes = j == 0 ? pairs * 8.0 : (j == 1 ? pairs * 32.0 : pairs * 48.0);
+            LAUNCH(PC_F2SC, bytes,
+                   launch_f2sc_round(st, (int)std::min<u32>(j, 2), pairs, a32, src, dst,
+                                     j ? v.chals + j - 1 : nullptr, v.partials, &nb));
+            LAUNCH(PC_FINAL, nb * 24.0,
+                   launch_f2sc_final(st, nb, v.partials, v.ps, v.msgs + 1 + 3 * j, v.chals + j,
+                                     j == 0 ? v.msgs : nullptr));
+            if (j > 0) src = dst;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(g_f2.h, v.msgs, nm * 8, hipMemcpyDeviceToHost, st));
+    if (chals && l) HIP_TRY(hipMemcpyAsync(g_f2.h + nm, v.chals, l * 8ull, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    memcpy(msgs, g_f2.h, nm * 8);
+    if (chals && l) memcpy(chals, g_f2.h + nm, l * 8ull);
+    return GKR_OK;
+}
+
+extern "C" int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_device, uint64_t seed,
+                                  const uint64_t *msgs, uint64_t n_msgs, int *accepted,
+                                  gkr_reject_info *why, void *hip_stream) {
+    using namespace fp;
+    if (!freq || !accepted || (!msgs && n_msgs)) return fail(GKR_ERR_INVALID, "NULL argument");
+    if (!pow2(n) || n > (1ull << 32)) return fail(GKR_ERR_INVALID, "n must be a power of two <= 2^32");
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    *accepted = 0;
+    if (why) *why = {-1, -1, 0};
+    const u32 l = log2ceil(n);
+    if (n_msgs != 1 + 3ull * l) {
+        reject(accepted, why, -1, -1, GKR_CHECK_MALFORMED);
+        return GKR_OK;
+    }
+    for (u64 k = 0; k < n_msgs; k++)
+        if (msgs[k] >= P) {
+            reject(accepted, why, -1, -1, GKR_CHECK_MALFORMED);
+            return GKR_OK;
+        }
+    std::vector<u64> r(l);
+    u64 rs = sm_state(seed, PURPOSE_F2SC);
+    for (auto &x : r) x = sm_field(rs);
+    u64 claim = msgs[0];
+    for (u32 j = 0; j < l; j++) {
+        const u64 *G = msgs + 1 + 3 * j;
+        if (add(G[0], G[1]) != claim) {
+            reject(accepted, why, -1, (int)j, GKR_CHECK_ROUND);
+            return GKR_OK;
+        }
+        claim = quad_at(G, r[j]);
+    }
+    // ~a(r) on the device, one pass over the vector (Sec. 4.1.2)
+    std::lock_guard<std::mutex> lk(g_f2.mu);
+    struct {
+        u64 *pts, *tab, *partials, *res;
+        u32 *in;
+    } v;
+    auto lay = [&](Arena &a) {
+        v.pts = a.take<u64>(l + 1);
+        v.tab = a.take<u64>(2ull * HALF_MAX);
+        v.partials = a.take<u64>((u64)MAX_BLOCKS);
+        v.res = a.take<u64>(1);
+        v.in = a.take<u32>(on_device ? 1 : n);
+    };
+    Arena sz;
+    lay(sz);
+    int rc = f2_reserve(sz.used, 2);
+    if (rc) return rc;
+    Arena a;
+    a.base = (char *)g_f2.mem;
+    lay(a);
+    const u32 *a32 = freq;
+    if (!on_device) {
+        HIP_TRY(hipMemcpyAsync(v.in, freq, n * 4, hipMemcpyHostToDevice, st));
+        a32 = v.in;
+    }
+    if (l) HIP_TRY(hipMemcpyAsync(v.pts, r.data(), l * 8ull, hipMemcpyHostToDevice, st));
+    u32 L;
+    split_half(l, &L);
+    int nb = 0;
+    LAUNCH(PC_TABLES, 0, launch_eq_halves(st, v.pts, l, L, v.tab, v.tab + HALF_MAX));
+    LAUNCH(PC_MLE, n * 4.0, launch_mle(st, n, nullptr, a32, v.tab, v.tab + HALF_MAX, L, v.partials, &nb));
+    LAUNCH(PC_MISC, 0, launch_reduce_rows(st, nb, 1, v.partials, v.res));
+    HIP_TRY(hipMemcpyAsync(g_f2.h, v.res, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const u64 ar = g_f2.h[0];
+    if (mul(ar, ar) != claim) {
+        reject(accepted, why, -1, -1, GKR_CHECK_INPUT);
+        return GKR_OK;
+    }
+    *accepted = 1;
+    return GKR_OK;
+}
+
+// -------------------------------------------------------------- field check
+
+extern "C" int gkr_field_op(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
+                            void *hip_stream) {
+    if (op < 0 || op > 2 || (n && (!a || !b || !out))) return fail(GKR_ERR_INVALID, "bad argument");
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    if (n == 0) return GKR_OK;
+    HIP_TRY(launch_field_op(st, op, a, b, out, n));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GKR_OK;
+}

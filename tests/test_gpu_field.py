@@ -1,0 +1,29 @@
+"""Device field module (Sec. 5.1) against Python big integers."""
+import random
+
+import numpy as np
+import pytest
+
+from gpu_util import say, device_tensor
+
+P = (1 << 61) - 1
+pytestmark = pytest.mark.gpu
+
+
+def test_field_ops_match_integers():
+    import torch
+    import paper_1202_1350_amd as G
+    rng = random.Random(3)
+    edge = [0, 1, 2, P - 1, P - 2, 1 << 60, (1 << 32) - 1, 1 << 32, (1 << 32) + 1, (1 << 61) - 3]
+    a = [x for x in edge for _ in edge] + [rng.randrange(P) for _ in range(100000)]
+    b = [y for _ in edge for y in edge] + [rng.randrange(P) for _ in range(100000)]
+    ta = device_tensor(np.array(a, np.uint64))
+    tb = device_tensor(np.array(b, np.uint64))
+    out = torch.zeros_like(ta)
+    for op, f in ((0, lambda x, y: (x + y) % P), (1, lambda x, y: (x - y) % P),
+                  (2, lambda x, y: x * y % P)):
+        say("field op", op, len(a))
+        G.gkr_field_op(op, ta, tb, out)
+        got = out.cpu().view(torch.int64).numpy().view(np.uint64)
+        want = np.array([f(x, y) for x, y in zip(a, b)], np.uint64)
+        assert np.array_equal(got, want), op
