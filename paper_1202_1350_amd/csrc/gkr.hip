@@ -21,6 +21,7 @@
 #include "../../include/gkr.h"
 #include "fp61.hpp"
 #include "kernels.hpp"
+#include "steps.hpp"
 
 using namespace gkr;
 
@@ -185,13 +186,16 @@ struct Arena {
 };
 
 constexpr u32 HALF_MAX = 1u << 16;  // eq half tables: at most 2^16 entries
+// Up to this many gates an omega round folds its table itself (two extra
+// products per gate) instead of a separate fold step.
+constexpr u32 INLINE_FOLD_MAX_GATES = 1u << 19;
 
 void split_half(u32 s, u32 *L) { *L = s / 2; }
 
 // Line-step shape for s' variables: lanes 2^L, waves 2^M, steps 2^H.
 void line_shape(u32 sp, u32 *L, u32 *M, u32 *H) {
     *L = std::min<u32>(6, sp);
-    *M = std::min<u32>(sp - *L, 13);
+    *M = std::min<u32>(sp - *L, 11);
     *H = sp - *L - *M;
 }
 
@@ -199,19 +203,25 @@ void line_shape(u32 sp, u32 *L, u32 *M, u32 *H) {
 
 // ------------------------------------------------------------------ circuit
 
+// Scratch of one proof on a circuit: the layer tables, the per-round tables
+// of the sum-checks, the transcript, and the step program (descriptors and
+// one-job launch entries) with every pointer bound to this scratch.
 struct Workspace {
     void *mem = nullptr;
-    std::vector<u64 *> V;  // per layer, 2^{s_i}
+    std::vector<u64 *> V;  // per layer, 2^{s_i} values
     u64 *pA, *pB, *bA, *bB, *fA, *fB;
     u64 *w, *off;
-    u64 *zbuf;
     u64 *zlo, *zhi, *alo, *ahi, *blo, *bhi;
     u64 *llo, *lhl, *lhh;
-    u64 *partials;
-    u64 *msgs, *chals;
-    ProofState *ps;
+    u64 *rows[2];
+    u64 *msgs, *chals, *rngst, *zbuf, *state;
     u32 *flag;
-    u64 *h_msgs = nullptr, *h_chals = nullptr;  // pinned staging
+    StepDesc *d_steps;
+    JobEntry *d_jobs;
+    std::vector<StepDesc> steps;  // host copy of the program
+    std::vector<int> pclass;      // profiling class of each step
+    std::vector<double> pbytes;   // algorithmic bytes of each step
+    u64 *h_msgs = nullptr, *h_chals = nullptr, *h_seed = nullptr;  // pinned staging
     u32 *h_flag = nullptr;
 };
 
@@ -323,6 +333,7 @@ static void free_workspace(Workspace *ws) {
     if (ws->mem) (void)hipFree(ws->mem);
     if (ws->h_msgs) (void)hipHostFree(ws->h_msgs);
     if (ws->h_chals) (void)hipHostFree(ws->h_chals);
+    if (ws->h_seed) (void)hipHostFree(ws->h_seed);
     if (ws->h_flag) (void)hipHostFree(ws->h_flag);
     delete ws;
 }
@@ -350,8 +361,8 @@ extern "C" int gkr_circuit_info(const gkr_circuit *c, uint64_t *gates, uint64_t 
     return GKR_OK;
 }
 
-// Lay out (or size, when a.base is NULL) the prover's scratch.
-static void carve(const gkr_circuit *c, Arena &a, Workspace &w) {
+// Lay out (or size, when a.base is NULL) a proof's scratch.
+static void carve(const gkr_circuit *c, Arena &a, Workspace &w, size_t nsteps) {
     w.V.assign(c->L, nullptr);
     for (u32 i = 0; i < c->L; i++) w.V[i] = a.take<u64>(1ull << c->s[i]);
     const u64 half = std::max<u64>(1ull << (c->smax ? c->smax - 1 : 0), 2);
@@ -363,7 +374,6 @@ static void carve(const gkr_circuit *c, Arena &a, Workspace &w) {
     w.fB = a.take<u64>(half);
     w.w = a.take<u64>(c->gmax);
     w.off = a.take<u64>(c->gmax);
-    w.zbuf = a.take<u64>(64);
     w.zlo = a.take<u64>(HALF_MAX);
     w.zhi = a.take<u64>(HALF_MAX);
     w.alo = a.take<u64>(HALF_MAX);
@@ -373,26 +383,318 @@ static void carve(const gkr_circuit *c, Arena &a, Workspace &w) {
     w.llo = a.take<u64>(c->line_lo);
     w.lhl = a.take<u64>(c->line_hl);
     w.lhh = a.take<u64>(c->line_hh);
-    w.partials = a.take<u64>((u64)MAX_BLOCKS * MAX_LINE);
+    w.rows[0] = a.take<u64>((u64)SMAX_BLOCKS * ROW_STRIDE);
+    w.rows[1] = a.take<u64>((u64)SMAX_BLOCKS * ROW_STRIDE);
     w.msgs = a.take<u64>(c->n_msgs);
     w.chals = a.take<u64>(std::max<u64>(c->n_chals, 1));
-    w.ps = a.take<ProofState>(1);
+    w.rngst = a.take<u64>(c->n_chals + 1);
+    w.zbuf = a.take<u64>(64);
+    w.state = a.take<u64>(4);
     w.flag = a.take<u32>(1);
+    w.d_steps = a.take<StepDesc>(nsteps);
+    w.d_jobs = a.take<JobEntry>(2 * nsteps);
 }
+
+// Workgroups of the step kernel for n items at `per` items per thread.
+static u32 sblocks(u64 n, u64 per = 1) {
+    u64 t = (n + per - 1) / per;
+    u64 b = (t + SBLOCK - 1) / SBLOCK;
+    return (u32)std::max<u64>(1, std::min<u64>(b, SMAX_BLOCKS));
+}
+
+// Builds a proof's step program.  With `ws` NULL it only counts the steps.
+struct Planner {
+    const gkr_circuit *c;
+    Workspace *w;
+    std::vector<StepDesc> out;
+    std::vector<int> cls;
+    std::vector<double> bytes;
+    ProofPtrs pp{};
+
+    StepDesc &add(u32 kind, u32 nblocks, int pclass, double nbytes) {
+        StepDesc s;
+        memset(&s, 0, sizeof s);
+        s.kind = kind;
+        s.nblocks = nblocks;
+        s.fin.kind = FIN_NONE;
+        s.fin.draw = -1;
+        s.pp = pp;
+        out.push_back(s);
+        cls.push_back(pclass);
+        bytes.push_back(nbytes);
+        return out.back();
+    }
+    // The step just added writes K-value rows into the buffer of its parity.
+    void reduces(u32 K) {
+        StepDesc &s = out.back();
+        s.reduces = 1;
+        s.K = K;
+        s.rows = w ? w->rows[(out.size() - 1) & 1] : nullptr;
+    }
+    // Finalize info for a step that follows a reducing step.
+    Fin fin_of_prev(u32 kind) const {
+        Fin f;
+        memset(&f, 0, sizeof f);
+        f.kind = kind;
+        f.draw = -1;
+        const StepDesc &p = out.back();
+        f.rows = p.rows;
+        f.nrows = p.nblocks;
+        return f;
+    }
+
+    void build() {
+        const u32 d = c->L - 1;
+        if (w) pp = ProofPtrs{w->msgs, w->chals, w->rngst, w->zbuf, w->state};
+        auto V = [&](u32 i) -> u64 * { return w ? w->V[i] : nullptr; };
+        auto P_ = [&](u64 *p) -> u64 * { return w ? p : nullptr; };
+        // circuit evaluation (a3), layer d-1 down to 0
+        for (int i = (int)d - 1; i >= 0; i--) {
+            const u64 S = c->S[i], npad = 1ull << c->s[i];
+            StepDesc &s = add(ST_EVAL, sblocks(npad, 4), PC_EVAL,
+                              S * (8.0 + 16 + 8 + (c->kind[i] == KIND_MIXED)) + (npad - S) * 8.0);
+            s.u.eval = EvalArgs{(u32)c->kind[i], c->S[i], npad, c->type[i], c->in1[i], c->in2[i],
+                                V(i + 1), V(i)};
+        }
+        {
+            StepDesc &s = add(ST_START, sblocks(c->S[0]), PC_MISC, c->S[0] * 16.0);
+            s.u.start = StartArgs{c->s[0], c->S[0], V(0)};
+        }
+        Fin layer_end;  // how the previous layer is finished (line values, tau)
+        memset(&layer_end, 0, sizeof layer_end);
+        layer_end.kind = FIN_NONE;
+        layer_end.draw = -1;
+        for (u32 i = 0; i < d; i++) {
+            const u32 s = c->s[i], sp = c->s[i + 1], S = c->S[i];
+            const u32 n = s + 2 * sp;
+            const int kind = c->kind[i];
+            const u32 co = (u32)c->co[i];
+            u64 *msg = w ? w->msgs + c->mo[i] : nullptr;
+            u64 *chals = w ? w->chals : nullptr;
+            u64 *vslot = w ? msg + 3ull * n : nullptr;  // v1, v2, then h(2..s')
+            // ---- eq tables of z_i[1..s) for the p-phase's first round
+            {
+                const u32 nz = s ? s - 1 : 0;
+                StepDesc &e = add(ST_EQ, sblocks((1ull << (nz / 2)) + (1ull << (nz - nz / 2))), PC_TABLES, 0);
+                e.fin = layer_end;
+                e.u.eq = EqArgs{PT_Z, nz, nz / 2, 1, P_(w ? w->zlo : nullptr), P_(w ? w->zhi : nullptr)};
+            }
+            // ---- p-phase (a5)
+            for (u32 j = 0; j < s; j++) {
+                const u64 nm = 1ull << (s - j - 1);
+                Fin f = fin_of_prev(FIN_P);
+                const bool first = j == 0;
+                u64 *vbuf[2] = {w ? w->pA : nullptr, w ? w->pB : nullptr};
+                u64 *bbuf[2] = {w ? w->bA : nullptr, w ? w->bB : nullptr};
+                PArgs pa;
+                pa.first = first;
+                pa.nm = nm;
+                pa.Vsrc = j <= 1 ? V(i) : vbuf[(j - 1) & 1];
+                pa.Vout = first ? nullptr : vbuf[j & 1];
+                pa.Bprev = first ? nullptr : bbuf[(j - 1) & 1];
+                pa.Bout = j + 1 < s ? bbuf[j & 1] : nullptr;
+                pa.zlo = w ? w->zlo : nullptr;
+                pa.zhi = w ? w->zhi : nullptr;
+                const u32 nz = s - 1;
+                pa.L = nz / 2;
+                StepDesc &st = add(ST_P, sblocks(nm, 2), PC_PPHASE,
+                                   first ? nm * (16.0 + 8) : nm * (32.0 + 16 + 16 + 8));
+                if (!first) {
+                    f.j = j - 1;
+                    f.draw = (i32)(co + j - 1);
+                    f.msg = w ? msg + 3ull * (j - 1) : nullptr;
+                    st.fin = f;
+                }
+                st.u.p = pa;
+                reduces(2);
+            }
+            // ---- eq tables of a*
+            {
+                const u32 La = s / 2;
+                Fin f;
+                memset(&f, 0, sizeof f);
+                f.kind = FIN_NONE;
+                f.draw = -1;
+                if (s > 0) {
+                    f = fin_of_prev(FIN_P);
+                    f.j = s - 1;
+                    f.draw = (i32)(co + s - 1);
+                    f.msg = w ? msg + 3ull * (s - 1) : nullptr;
+                }
+                StepDesc &e = add(ST_EQ, sblocks((1ull << La) + (1ull << (s - La))), PC_TABLES, 0);
+                e.fin = f;
+                e.u.eq = EqArgs{PT_CHAL, s, La, co, w ? w->alo : nullptr, w ? w->ahi : nullptr};
+            }
+            if (sp == 0) {
+                StepDesc &e = add(ST_SGE, 1, PC_MISC, 8);
+                e.u.sge = SgeArgs{V(i + 1), vslot};
+                memset(&layer_end, 0, sizeof layer_end);
+                layer_end.kind = FIN_LINE;
+                layer_end.draw = (i32)(co + n);
+                layer_end.T = 0;
+                layer_end.sp = 0;
+                layer_end.bstar = chals ? chals + co + s : nullptr;
+                layer_end.cstar = chals ? chals + co + s : nullptr;
+                continue;
+            }
+            // ---- omega-phases (a6, a7, a8)
+            const u64 *Fend = nullptr;  // table of the phase's last round
+            for (u32 ph = 1; ph <= 2; ph++) {
+                const u32 rbase = s + (ph == 2 ? sp : 0);
+                const u32 Lb = sp / 2;
+                if (ph == 2) {
+                    Fin f = fin_of_prev(FIN_W);
+                    f.draw = (i32)(co + s + sp - 1);
+                    f.msg = w ? msg + 3ull * (s + sp - 1) : nullptr;
+                    f.last = 1;
+                    f.F = Fend;
+                    f.vout = vslot;
+                    StepDesc &e = add(ST_EQ, sblocks((1ull << Lb) + (1ull << (sp - Lb))), PC_TABLES, 0);
+                    e.fin = f;
+                    e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
+                }
+                const u64 *F = V(i + 1);
+                u64 *fbuf[2] = {w ? w->fA : nullptr, w ? w->fB : nullptr};
+                for (u32 k = 0; k < sp; k++) {
+                    WArgs a;
+                    memset(&a, 0, sizeof a);
+                    a.kind = kind;
+                    a.ph = ph;
+                    a.init = k == 0;
+                    a.write_w = k + 1 < sp;
+                    a.inline_fold = k > 0 && S <= INLINE_FOLD_MAX_GATES;
+                    a.S = S;
+                    a.k = k;
+                    a.nfold = 1ull << (sp - k);
+                    a.idx = ph == 1 ? c->in1[i] : c->in2[i];
+                    a.oth = ph == 1 ? c->in2[i] : c->in1[i];
+                    a.type = c->type[i];
+                    a.Vn = V(i + 1);
+                    a.alo = w ? w->alo : nullptr;
+                    a.ahi = w ? w->ahi : nullptr;
+                    a.La = s / 2;
+                    a.blo = w ? w->blo : nullptr;
+                    a.bhi = w ? w->bhi : nullptr;
+                    a.Lb = Lb;
+                    a.rchal = -1;
+                    a.w = w ? w->w : nullptr;
+                    a.off = w ? w->off : nullptr;
+                    Fin f;
+                    memset(&f, 0, sizeof f);
+                    f.kind = FIN_NONE;
+                    f.draw = -1;
+                    if (k > 0) {
+                        f = fin_of_prev(FIN_W);
+                        f.draw = (i32)(co + rbase + k - 1);
+                        f.msg = w ? msg + 3ull * (rbase + k - 1) : nullptr;
+                        u64 *dst = fbuf[k & 1];
+                        if (a.inline_fold) {
+                            a.F = F;       // F^(k-1): the kernel folds it into dst
+                            a.Fout = dst;
+                        } else {
+                            StepDesc &fs = add(ST_FOLD, sblocks(a.nfold, 4), PC_FOLD, a.nfold * 24.0);
+                            fs.fin = f;
+                            fs.u.fold = FoldArgs{a.nfold, F, dst};
+                            memset(&f, 0, sizeof f);
+                            f.kind = FIN_NONE;
+                            f.draw = -1;
+                            a.F = dst;
+                            a.rchal = (i32)(co + rbase + k - 1);
+                        }
+                        F = dst;
+                    } else {
+                        a.F = F;
+                    }
+                    // algorithmic bytes per gate: index 4, weight read 8 (not at
+                    // init) and write 8 (not in the last round), the additive
+                    // operand 8 (phase 1 with ADD gates), type 1 (mixed), init:
+                    // other index 4 + operand gather 8 (phase 1); plus one pass
+                    // over the fold table (and its folded half when inline).
+                    const double per = 4.0 + (a.init ? 0 : 8) + (a.write_w ? 8 : 0) +
+                                       (ph == 1 && kind != KIND_MUL ? 8 : 0) +
+                                       (kind == KIND_MIXED ? 1 : 0) + (a.init ? 4.0 + (ph == 1 ? 8 : 0) : 0);
+                    const double nb = S * per + (a.inline_fold ? 24.0 : 8.0) * a.nfold;
+                    StepDesc &ws = add(ST_W, sblocks(std::max<u64>(S, a.inline_fold ? a.nfold : 0), 4),
+                                       PC_OMEGA, nb);
+                    ws.fin = f;
+                    ws.u.w = a;
+                    reduces(4);
+                }
+                Fend = F;
+            }
+            // ---- line step (a9): finish the last round, then the line tables
+            {
+                Fin f = fin_of_prev(FIN_W);
+                f.draw = (i32)(co + n - 1);
+                f.msg = w ? msg + 3ull * (n - 1) : nullptr;
+                f.last = 2;
+                f.F = Fend;
+                f.vout = vslot ? vslot + 1 : nullptr;
+                u32 Ll = 0, M = 0, H = 0;
+                if (sp >= 2) line_shape(sp, &Ll, &M, &H);
+                const u64 ntab = sp >= 2 ? (u64)(sp - 1) * ((1ull << Ll) + (1ull << M) + (1ull << H)) : 1;
+                StepDesc &e = add(ST_LT, sblocks(ntab), PC_TABLES, 0);
+                e.fin = f;
+                e.u.lt = LtArgs{sp >= 2 ? sp : 1, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
+                                w ? w->lhl : nullptr, w ? w->lhh : nullptr};
+                if (sp < 2) e.u.lt.sp = 0;  // nothing to tabulate
+                memset(&layer_end, 0, sizeof layer_end);
+                layer_end.kind = FIN_LINE;
+                layer_end.draw = (i32)(co + n);
+                layer_end.sp = sp;
+                layer_end.bstar = chals ? chals + co + s : nullptr;
+                layer_end.cstar = chals ? chals + co + s + sp : nullptr;
+                layer_end.msg = vslot ? vslot + 2 : nullptr;
+                if (sp >= 2) {
+                    const u32 T = sp - 1;
+                    const u32 chunks = (T + LINE_CHUNK - 1) / LINE_CHUNK;
+                    const u32 cb = (u32)(((1ull << M) + (SBLOCK / 64) - 1) / (SBLOCK / 64));
+                    StepDesc &ls = add(ST_LINE, chunks * cb, PC_LINE, 8.0 * (1ull << sp) * chunks);
+                    ls.u.line = LineArgs{sp, Ll, M, T, cb, V(i + 1), w ? w->llo : nullptr,
+                                         w ? w->lhl : nullptr, w ? w->lhh : nullptr};
+                    reduces(LINE_CHUNK);
+                    layer_end.T = T;
+                    layer_end.rows = ls.rows;
+                    layer_end.nrows = ls.nblocks;
+                    layer_end.chunk_blocks = cb;
+                }
+            }
+        }
+        StepDesc &e = add(ST_END, 1, PC_MISC, 0);
+        e.fin = layer_end;
+    }
+};
 
 static int ensure_workspace(gkr_circuit *c) {
     if (c->ws) return GKR_OK;
+    Planner count{c, nullptr};
+    count.build();
+    const size_t nsteps = count.out.size();
     Workspace probe;
     Arena sz;
-    carve(c, sz, probe);
+    carve(c, sz, probe, nsteps);
     std::unique_ptr<Workspace> ws(new Workspace());
     HIP_TRY(hipMalloc(&ws->mem, sz.used));
     Arena a;
     a.base = (char *)ws->mem;
     a.cap = sz.used;
-    carve(c, a, *ws);
+    carve(c, a, *ws, nsteps);
+    Planner plan{c, ws.get()};
+    plan.build();
+    if (plan.out.size() != nsteps) return fail(GKR_ERR_INVALID, "step program changed size");
+    ws->steps = plan.out;
+    ws->pclass = plan.cls;
+    ws->pbytes = plan.bytes;
+    std::vector<JobEntry> jobs(2 * nsteps);
+    for (size_t t = 0; t < nsteps; t++) {
+        jobs[2 * t] = JobEntry{ws->d_steps + t, 0, 0};
+        jobs[2 * t + 1] = JobEntry{nullptr, step_grid(plan.out[t]), 0};
+    }
+    HIP_TRY(hipMemcpy(ws->d_steps, plan.out.data(), nsteps * sizeof(StepDesc), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ws->d_jobs, jobs.data(), jobs.size() * sizeof(JobEntry), hipMemcpyHostToDevice));
     HIP_TRY(hipHostMalloc((void **)&ws->h_msgs, c->n_msgs * 8));
     HIP_TRY(hipHostMalloc((void **)&ws->h_chals, std::max<u64>(c->n_chals, 1) * 8));
+    HIP_TRY(hipHostMalloc((void **)&ws->h_seed, 8));
     HIP_TRY(hipHostMalloc((void **)&ws->h_flag, 4));
     c->ws = ws.release();
     return GKR_OK;
@@ -406,131 +708,12 @@ static int ensure_workspace(gkr_circuit *c) {
         HIP_TRY(expr);                                            \
     } while (0)
 
-// Enqueue one whole proof; inputs already in ws.V[d].
-static int enqueue_proof(const gkr_circuit *c, Workspace &w, u64 seed, hipStream_t st) {
-    const u32 d = c->L - 1;
-    int nb = 0;
-    // circuit evaluation, layer d-1 down to 0 (a3)
-    for (int i = (int)d - 1; i >= 0; i--) {
-        const u64 S = c->S[i], npad = 1ull << c->s[i];
-        const double bytes = S * (8.0 + 16 + 8 + (c->kind[i] == KIND_MIXED ? 1 : 0)) + (npad - S) * 8.0;
-        LAUNCH(PC_EVAL, bytes,
-               launch_eval(st, c->kind[i], c->S[i], npad, c->type[i], c->in1[i], c->in2[i],
-                           w.V[i + 1], w.V[i]));
-    }
-    LAUNCH(PC_MISC, c->S[0] * 16.0,
-           launch_init_proof(st, w.ps, seed, c->s[0], w.V[0], c->S[0], w.msgs, w.chals, w.zbuf));
-
-    for (u32 i = 0; i < d; i++) {
-        const u32 s = c->s[i], sp = c->s[i + 1], S = c->S[i];
-        const u32 n = s + 2 * sp;
-        const int kind = c->kind[i];
-        u64 *msg = w.msgs + c->mo[i];
-        u64 *chal = w.chals + c->co[i];
-        // ---- p-phase (a5): rounds over the a-variables
-        if (s > 0) {
-            u32 Lz;
-            split_half(s - 1, &Lz);
-            LAUNCH(PC_TABLES, 8.0 * ((1ull << Lz) + (1ull << (s - 1 - Lz))),
-                   launch_eq_halves(st, w.zbuf + 1, s - 1, Lz, w.zlo, w.zhi));
-            const u64 *Vsrc = w.V[i];
-            u64 *vbuf[2] = {w.pA, w.pB};
-            u64 *bbuf[2] = {w.bA, w.bB};
-            const u64 *Bprev = nullptr;
-            for (u32 j = 0; j < s; j++) {
-                const u64 nm = 1ull << (s - j - 1);
-                const bool first = j == 0;
-                u64 *Vout = first ? nullptr : vbuf[j & 1];
-                u64 *Bout = (j + 1 < s) ? bbuf[j & 1] : nullptr;
-                const double bytes = first ? nm * (16.0 + 8) : nm * (32.0 + 16 + 16 + 8);
-                LAUNCH(PC_PPHASE, bytes,
-                       launch_pphase(st, first, nm, Vsrc, Vout, Bprev, Bout, w.zlo, w.zhi, Lz,
-                                     first ? nullptr : chal + j - 1, w.partials, &nb));
-                LAUNCH(PC_FINAL, nb * 16.0,
-                       launch_pfinal(st, nb, w.partials, w.ps, w.zbuf + j, msg + 3 * j, chal + j));
-                if (!first) Vsrc = Vout;
-                Bprev = Bout;
-            }
-        }
-        u64 *vslot = msg + 3ull * n;  // v1, v2, then h(2..s')
-        if (sp == 0) {
-            LAUNCH(PC_MISC, 8.0, launch_single_gate_end(st, w.V[i + 1], w.ps, vslot));
-        } else {
-            // ---- omega-phases (a6, a7, a8)
-            u32 La, Lb;
-            split_half(s, &La);
-            split_half(sp, &Lb);
-            LAUNCH(PC_TABLES, 8.0 * ((1ull << La) + (1ull << (s - La))),
-                   launch_eq_halves(st, chal, s, La, w.alo, w.ahi));
-            for (int ph = 1; ph <= 2; ph++) {
-                if (ph == 2)
-                    LAUNCH(PC_TABLES, 8.0 * ((1ull << Lb) + (1ull << (sp - Lb))),
-                           launch_eq_halves(st, chal + s, sp, Lb, w.blo, w.bhi));
-                const u64 *F = w.V[i + 1];
-                u64 *fbuf[2] = {w.fA, w.fB};
-                const u32 rbase = s + (ph == 2 ? sp : 0);
-                for (u32 k = 0; k < sp; k++) {
-                    if (k > 0) {
-                        const u64 nh = 1ull << (sp - k);
-                        u64 *dst = fbuf[k & 1];
-                        LAUNCH(PC_FOLD, nh * 24.0, launch_fold(st, nh, F, dst, chal + rbase + k - 1));
-                        F = dst;
-                    }
-                    OmegaArgs a;
-                    a.kind = kind;
-                    a.ph = ph;
-                    a.init = k == 0;
-                    a.write_w = k + 1 < sp;
-                    a.S = S;
-                    a.k = k;
-                    a.idx = ph == 1 ? c->in1[i] : c->in2[i];
-                    a.oth = ph == 1 ? c->in2[i] : c->in1[i];
-                    a.type = c->type[i];
-                    a.F = F;
-                    a.Vn = w.V[i + 1];
-                    a.alo = w.alo;
-                    a.ahi = w.ahi;
-                    a.La = La;
-                    a.blo = w.blo;
-                    a.bhi = w.bhi;
-                    a.Lb = Lb;
-                    a.ps = w.ps;
-                    a.rptr = k > 0 ? chal + rbase + k - 1 : nullptr;
-                    a.w = w.w;
-                    a.off = w.off;
-                    a.partials = w.partials;
-                    // algorithmic bytes per gate: index 4, weight read 8 (not at
-                    // init) and write 8 (not in the last round), the additive
-                    // operand 8 (phase 1 with ADD gates), type 1 (mixed),
-                    // init: other index 4 + operand gather 8 (phase 1);
-                    // plus one pass over the fold table.
-                    double per = 4.0 + (a.init ? 0 : 8) + (a.write_w ? 8 : 0) +
-                                 (ph == 1 && kind != KIND_MUL ? 8 : 0) + (kind == KIND_MIXED ? 1 : 0) +
-                                 (a.init ? 4.0 + (ph == 1 ? 8 : 0) : 0);
-                    const double bytes = S * per + 8.0 * (1ull << (sp - k));
-                    LAUNCH(PC_OMEGA, bytes, launch_omega(st, a, &nb));
-                    const int last = k + 1 == sp ? ph : 0;
-                    LAUNCH(PC_FINAL, nb * 32.0,
-                           launch_wfinal(st, nb, w.partials, w.ps, msg + 3ull * (rbase + k),
-                                         chal + rbase + k, last, F, vslot + (ph - 1)));
-                }
-            }
-        }
-        // ---- line step (a9)
-        const u64 *bstar = chal + s, *cstar = chal + s + sp;
-        int nparts = 0;
-        if (sp >= 2) {
-            u32 Ll, M, H;
-            line_shape(sp, &Ll, &M, &H);
-            LAUNCH(PC_TABLES, 8.0 * (sp - 1) * ((1ull << Ll) + (1ull << M) + (1ull << H)),
-                   launch_line_tables(st, bstar, cstar, sp, Ll, M, w.llo, w.lhl, w.lhh));
-            LAUNCH(PC_LINE, 8.0 * (1ull << sp),
-                   launch_line(st, sp, Ll, M, w.V[i + 1], w.llo, w.lhl, w.lhh, w.partials, &nparts));
-        }
-        LAUNCH(PC_FINAL, nparts * 8.0 * MAX_LINE,
-               launch_line_final(st, nparts, w.partials, sp, w.ps, bstar, cstar, vslot + 2,
-                                 chal + n, w.zbuf));
-    }
+// Enqueue one whole proof (inputs already in w.V[d], seed in w.state[2]):
+// one launch per step.
+static int enqueue_proof(Workspace &w, hipStream_t st) {
+    const size_t n = w.steps.size();
+    for (size_t t = 0; t < n; t++)
+        LAUNCH(w.pclass[t], w.pbytes[t], launch_step(st, w.steps[t]));
     return GKR_OK;
 }
 
@@ -555,7 +738,9 @@ extern "C" int gkr_prove(const gkr_circuit *cc, const uint64_t *inputs, int inpu
         HIP_TRY(hipMemcpyAsync(w.V[d], inputs, Sd * 8, hipMemcpyHostToDevice, st));
         if (npad > Sd) HIP_TRY(hipMemsetAsync(w.V[d] + Sd, 0, (npad - Sd) * 8, st));
     }
-    rc = enqueue_proof(c, w, seed, st);
+    *w.h_seed = seed;
+    HIP_TRY(hipMemcpyAsync(w.state + 2, w.h_seed, 8, hipMemcpyHostToDevice, st));
+    rc = enqueue_proof(w, st);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(w.h_msgs, w.msgs, c->n_msgs * 8, hipMemcpyDeviceToHost, st));
     if (chals) HIP_TRY(hipMemcpyAsync(w.h_chals, w.chals, c->n_chals * 8, hipMemcpyDeviceToHost, st));

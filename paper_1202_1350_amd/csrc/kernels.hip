@@ -124,55 +124,7 @@ hipError_t launch_check_range(hipStream_t st, const u64 *src, u64 n, u32 *bad_fl
     return hipGetLastError();
 }
 
-template <int KIND>
-__global__ void __launch_bounds__(BLOCK) k_eval(u32 S, u64 npad, const u8 *type, const u32 *in1,
-                                                const u32 *in2, const u64 *Vn, u64 *V) {
-    for (u64 g = GTID; g < npad; g += GSTRIDE) {
-        u64 v = 0;
-        if (g < S) {
-            u64 x = Vn[in1[g]], y = Vn[in2[g]];
-            bool ismul = KIND == KIND_MUL || (KIND == KIND_MIXED && type[g]);
-            v = ismul ? mul(x, y) : add(x, y);
-        }
-        V[g] = v;
-    }
-}
-
-hipError_t launch_eval(hipStream_t st, int kind, u32 S, u64 npad, const u8 *type, const u32 *in1,
-                       const u32 *in2, const u64 *Vn, u64 *V) {
-    dim3 g(blocks_for(npad, 4)), b(BLOCK);
-    switch (kind) {
-        case KIND_ADD: hipLaunchKernelGGL(k_eval<KIND_ADD>, g, b, 0, st, S, npad, type, in1, in2, Vn, V); break;
-        case KIND_MUL: hipLaunchKernelGGL(k_eval<KIND_MUL>, g, b, 0, st, S, npad, type, in1, in2, Vn, V); break;
-        default: hipLaunchKernelGGL(k_eval<KIND_MIXED>, g, b, 0, st, S, npad, type, in1, in2, Vn, V); break;
-    }
-    return hipGetLastError();
-}
-
 // --------------------------------------------------------- proof bookkeeping
-
-__global__ void __launch_bounds__(BLOCK) k_init_proof(ProofState *ps, u64 seed, u32 s0, const u64 *V0,
-                                                      u32 S0, u64 *msgs, u64 *chals, u64 *zbuf) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        u64 s = fp::sm_state(seed, fp::PURPOSE_GKR);
-        for (u32 k = 0; k < s0; k++) {
-            u64 z = fp::sm_field(s);
-            chals[k] = z;
-            zbuf[k] = z;
-        }
-        ps->rng = s;
-        ps->betaC = 1;
-        ps->v1 = 0;
-    }
-    for (u64 g = GTID; g < S0; g += GSTRIDE) msgs[g] = V0[g];
-}
-
-hipError_t launch_init_proof(hipStream_t st, ProofState *ps, u64 seed, u32 s0, const u64 *V0,
-                             u32 S0, u64 *msgs, u64 *chals, u64 *zbuf) {
-    hipLaunchKernelGGL(k_init_proof, dim3(blocks_for(S0, 4)), dim3(BLOCK), 0, st, ps, seed, s0, V0,
-                       S0, msgs, chals, zbuf);
-    return hipGetLastError();
-}
 
 // chi over the bits of x of the coordinates pt[0..n)
 __device__ __forceinline__ u64 chi_bits(u64 x, const u64 *pt, u32 n) {
@@ -194,335 +146,6 @@ __global__ void __launch_bounds__(BLOCK) k_eq_halves(const u64 *pt, u32 s, u32 L
 hipError_t launch_eq_halves(hipStream_t st, const u64 *pt, u32 s, u32 L, u64 *lo, u64 *hi) {
     u64 n = (1ull << L) + (1ull << (s - L));
     hipLaunchKernelGGL(k_eq_halves, dim3(blocks_for(n)), dim3(BLOCK), 0, st, pt, s, L, lo, hi);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------- p-phase (a5, a7, a8)
-
-template <bool FIRST>
-__global__ void __launch_bounds__(BLOCK) k_pphase(u64 nm, const u64 *Vsrc, u64 *Vout,
-                                                  const u64 *Bprev, u64 *Bout, const u64 *zlo,
-                                                  const u64 *zhi, u32 L, const u64 *rptr,
-                                                  u64 *partials) {
-    u64 r = 0;
-    if (!FIRST) r = *rptr;
-    const u64 mask = (1ull << L) - 1;
-    u64 acc[2] = {0, 0};
-    for (u64 m = GTID; m < nm; m += GSTRIDE) {
-        u64 v0, v1, b;
-        if (FIRST) {
-            u64x2 p = ld2(Vsrc, 2 * m);
-            v0 = p.x;
-            v1 = p.y;
-            b = mul(zlo[m & mask], zhi[m >> L]);
-        } else {
-            u64x2 p = ld2(Vsrc, 4 * m), q = ld2(Vsrc, 4 * m + 2);
-            v0 = add(p.x, mul(r, sub(p.y, p.x)));
-            v1 = add(q.x, mul(r, sub(q.y, q.x)));
-            if (Vout) st2(Vout, 2 * m, v0, v1);
-            u64x2 bb = ld2(Bprev, 2 * m);
-            b = add(bb.x, bb.y);
-        }
-        if (Bout) Bout[m] = b;
-        acc[0] = add(acc[0], mul(b, v0));
-        acc[1] = add(acc[1], mul(b, v1));
-    }
-    block_store<2>(acc, partials + 2 * (u64)blockIdx.x);
-}
-
-hipError_t launch_pphase(hipStream_t st, bool first, u64 nm, const u64 *Vsrc, u64 *Vout,
-                         const u64 *Bprev, u64 *Bout, const u64 *zlo, const u64 *zhi, u32 L,
-                         const u64 *rptr, u64 *partials, int *nblocks) {
-    int nb = blocks_for(nm, 2);
-    *nblocks = nb;
-    if (first)
-        hipLaunchKernelGGL(k_pphase<true>, dim3(nb), dim3(BLOCK), 0, st, nm, Vsrc, Vout, Bprev, Bout,
-                           zlo, zhi, L, rptr, partials);
-    else
-        hipLaunchKernelGGL(k_pphase<false>, dim3(nb), dim3(BLOCK), 0, st, nm, Vsrc, Vout, Bprev,
-                           Bout, zlo, zhi, L, rptr, partials);
-    return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(BLOCK) k_pfinal(int nparts, const u64 *partials, ProofState *ps,
-                                                  const u64 *zj, u64 *msg, u64 *chal) {
-    u64 t[2];
-    rows_total<2>(nparts, partials, t);
-    if (threadIdx.x == 0) {
-        const u64 z = *zj, C = ps->betaC, S0 = t[0], S1 = t[1];
-        msg[0] = mul(mul(C, sub(1, z)), S0);
-        msg[1] = mul(mul(C, z), S1);
-        const u64 c3 = sub(add(add(z, z), z), 1);  // eq(z, 2) = 3z - 1
-        msg[2] = mul(mul(C, c3), sub(add(S1, S1), S0));
-        const u64 r = draw(ps);
-        *chal = r;
-        ps->betaC = mul(C, fp::eq(z, r));
-    }
-}
-
-hipError_t launch_pfinal(hipStream_t st, int nparts, const u64 *partials, ProofState *ps,
-                         const u64 *zj, u64 *msg, u64 *chal) {
-    hipLaunchKernelGGL(k_pfinal, dim3(1), dim3(BLOCK), 0, st, nparts, partials, ps, zj, msg, chal);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------- omega-phases (a6, a7, a8)
-//
-// Gate g with bound-wire index idx, at round k of its phase:
-//   term_g(t) = w_g eq(bit_k(idx), t) (F(t) + off_g)
-// with F(t) = (1-t) F[2m] + t F[2m+1], m = idx >> (k+1), the extension of
-// V_{i+1} at the partially bound point.  MUL gates carry their fixed
-// operand inside w (off = 0), ADD gates in off.  With P0 = w (F[2m] + off),
-// P1 = w (F[2m+1] + off):  bit 0 adds P0 at t=0 and P0 - 2 P1 at t=2;
-// bit 1 adds P1 at t=1 and 4 P1 - 2 P0 at t=2.
-
-template <int KIND, int PH, bool INIT, bool WRITE_W>
-__global__ void __launch_bounds__(BLOCK) k_omega(OmegaArgs a) {
-    u64 r = 0, omr = 0;
-    if (!INIT) {
-        r = *a.rptr;
-        omr = sub(1, r);
-    }
-    u64 wbase = 0, v1 = 0;
-    if (INIT) wbase = a.ps->betaC;  // beta(z, a*) once the a-variables are bound
-    if (PH == 2) v1 = a.ps->v1;
-    const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
-    const u32 k = a.k;
-    u64 acc[4] = {0, 0, 0, 0};
-    for (u64 g = GTID; g < a.S; g += GSTRIDE) {
-        const u32 idx = a.idx[g];
-        const bool ismul = KIND == KIND_MUL || (KIND == KIND_MIXED && a.type[g]);
-        u64 wt, of;
-        if (INIT) {
-            u64 wg = mul(wbase, mul(a.alo[g & amask], a.ahi[g >> a.La]));
-            if (PH == 1) {
-                const u64 y = a.Vn[a.oth[g]];
-                wt = ismul ? mul(wg, y) : wg;
-                of = ismul ? 0 : y;
-                if (KIND != KIND_MUL) a.off[g] = of;
-            } else {
-                const u32 i1 = a.oth[g];
-                wg = mul(wg, mul(a.blo[i1 & bmask], a.bhi[i1 >> a.Lb]));
-                wt = ismul ? mul(wg, v1) : wg;
-                of = ismul ? 0 : v1;
-            }
-        } else {
-            wt = mul(a.w[g], ((idx >> (k - 1)) & 1) ? r : omr);
-            if (PH == 1)
-                of = KIND == KIND_MUL ? 0 : a.off[g];
-            else
-                of = ismul ? 0 : v1;
-        }
-        const u64x2 f = ld2(a.F, ((u64)idx >> (k + 1)) << 1);
-        const u64 P0 = mul(wt, add(f.x, of)), P1 = mul(wt, add(f.y, of));
-        if ((idx >> k) & 1) {
-            acc[2] = add(acc[2], P0);
-            acc[3] = add(acc[3], P1);
-        } else {
-            acc[0] = add(acc[0], P0);
-            acc[1] = add(acc[1], P1);
-        }
-        if (WRITE_W) a.w[g] = wt;
-    }
-    block_store<4>(acc, a.partials + 4 * (u64)blockIdx.x);
-}
-
-template <int KIND, int PH>
-static void launch_omega_k(hipStream_t st, const OmegaArgs &a, int nb) {
-    dim3 g(nb), b(BLOCK);
-    if (a.init) {
-        if (a.write_w)
-            hipLaunchKernelGGL((k_omega<KIND, PH, true, true>), g, b, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_omega<KIND, PH, true, false>), g, b, 0, st, a);
-    } else {
-        if (a.write_w)
-            hipLaunchKernelGGL((k_omega<KIND, PH, false, true>), g, b, 0, st, a);
-        else
-            hipLaunchKernelGGL((k_omega<KIND, PH, false, false>), g, b, 0, st, a);
-    }
-}
-
-hipError_t launch_omega(hipStream_t st, const OmegaArgs &a, int *nblocks) {
-    int nb = blocks_for(a.S, 4);
-    *nblocks = nb;
-    if (a.ph == 1) {
-        if (a.kind == KIND_ADD) launch_omega_k<KIND_ADD, 1>(st, a, nb);
-        else if (a.kind == KIND_MUL) launch_omega_k<KIND_MUL, 1>(st, a, nb);
-        else launch_omega_k<KIND_MIXED, 1>(st, a, nb);
-    } else {
-        if (a.kind == KIND_ADD) launch_omega_k<KIND_ADD, 2>(st, a, nb);
-        else if (a.kind == KIND_MUL) launch_omega_k<KIND_MUL, 2>(st, a, nb);
-        else launch_omega_k<KIND_MIXED, 2>(st, a, nb);
-    }
-    return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(BLOCK) k_wfinal(int nparts, const u64 *partials, ProofState *ps,
-                                                  u64 *msg, u64 *chal, int last, const u64 *Flast,
-                                                  u64 *vout) {
-    u64 t[4];
-    rows_total<4>(nparts, partials, t);
-    if (threadIdx.x == 0) {
-        const u64 E0 = t[0], E1 = t[1], O0 = t[2], O1 = t[3];
-        msg[0] = E0;
-        msg[1] = O1;
-        u64 o4 = add(O1, O1);
-        o4 = add(o4, o4);
-        msg[2] = sub(add(sub(E0, add(E1, E1)), o4), add(O0, O0));
-        const u64 r = draw(ps);
-        *chal = r;
-        if (last) {
-            const u64 f0 = Flast[0], f1 = Flast[1];
-            const u64 v = add(f0, mul(r, sub(f1, f0)));
-            *vout = v;
-            if (last == 1) ps->v1 = v;
-        }
-    }
-}
-
-hipError_t launch_wfinal(hipStream_t st, int nparts, const u64 *partials, ProofState *ps, u64 *msg,
-                         u64 *chal, int last, const u64 *Flast, u64 *vout) {
-    hipLaunchKernelGGL(k_wfinal, dim3(1), dim3(BLOCK), 0, st, nparts, partials, ps, msg, chal, last,
-                       Flast, vout);
-    return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(BLOCK) k_fold(u64 nh, const u64 *src, u64 *dst, const u64 *rptr) {
-    const u64 r = *rptr;
-    for (u64 m = GTID; m < nh; m += GSTRIDE) {
-        const u64x2 p = ld2(src, 2 * m);
-        dst[m] = add(p.x, mul(r, sub(p.y, p.x)));
-    }
-}
-
-hipError_t launch_fold(hipStream_t st, u64 nh, const u64 *src, u64 *dst, const u64 *rptr) {
-    hipLaunchKernelGGL(k_fold, dim3(blocks_for(nh, 4)), dim3(BLOCK), 0, st, nh, src, dst, rptr);
-    return hipGetLastError();
-}
-
-__global__ void k_single_gate_end(const u64 *Vn, ProofState *ps, u64 *msg_v) {
-    if (threadIdx.x == 0) {
-        const u64 v = Vn[0];
-        msg_v[0] = v;
-        msg_v[1] = v;
-        ps->v1 = v;
-    }
-}
-
-hipError_t launch_single_gate_end(hipStream_t st, const u64 *Vn, ProofState *ps, u64 *msg_v) {
-    hipLaunchKernelGGL(k_single_gate_end, dim3(1), dim3(64), 0, st, Vn, ps, msg_v);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------ line step (a9)
-//
-// h(t) = ~V_{i+1}(l(t)) for t = 2..s', l(t) = b* + t (c* - b*), T = s' - 1
-// points.  The index splits as x = (hh 2^M + mid) 2^L + lane with L <= 6
-// and 2^M the number of waves: chi_x(l(t)) = Hh_t[hh] Hl_t[mid] lo_t[lane].
-// Wave `mid` walks hh accumulating Hh_t[hh] V[x] for each t (one product
-// per element and point), and multiplies by Hl_t[mid] lo_t[lane] once.
-// Tables: lo [T][2^L], Hl [T][2^M], Hh [2^{s'-L-M}][T] (a step's T weights
-// contiguous).
-
-__global__ void __launch_bounds__(BLOCK) k_line_tables(const u64 *bstar, const u64 *cstar, u32 sp,
-                                                       u32 L, u32 M, u64 *lo, u64 *hl, u64 *hh) {
-    const u32 T = sp - 1, H = sp - L - M;
-    const u64 nlo = 1ull << L, nhl = 1ull << M, nhh = 1ull << H;
-    const u64 per = nlo + nhl + nhh;
-    for (u64 e = GTID; e < (u64)T * per; e += GSTRIDE) {
-        const u32 tp = (u32)(e / per);
-        const u64 x = e % per;
-        const u64 t = tp + 2;
-        u32 base, n;
-        u64 bits;
-        if (x < nlo) {
-            base = 0; n = L; bits = x;
-        } else if (x < nlo + nhl) {
-            base = L; n = M; bits = x - nlo;
-        } else {
-            base = L + M; n = H; bits = x - nlo - nhl;
-        }
-        u64 v = 1;
-        for (u32 k = 0; k < n; k++) {
-            const u64 b = bstar[base + k], c = cstar[base + k];
-            const u64 l = add(b, mul(t, sub(c, b)));
-            v = mul(v, fp::eqbit((u32)((bits >> k) & 1), l));
-        }
-        if (x < nlo)
-            lo[(u64)tp * nlo + bits] = v;
-        else if (x < nlo + nhl)
-            hl[(u64)tp * nhl + bits] = v;
-        else
-            hh[bits * T + tp] = v;
-    }
-}
-
-hipError_t launch_line_tables(hipStream_t st, const u64 *bstar, const u64 *cstar, u32 sp, u32 L,
-                              u32 M, u64 *lo, u64 *hl, u64 *hh) {
-    const u64 n = (u64)(sp - 1) * ((1ull << L) + (1ull << M) + (1ull << (sp - L - M)));
-    hipLaunchKernelGGL(k_line_tables, dim3(blocks_for(n)), dim3(BLOCK), 0, st, bstar, cstar, sp, L,
-                       M, lo, hl, hh);
-    return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(BLOCK) k_line(u32 sp, u32 L, u32 M, const u64 *V, const u64 *lo,
-                                                const u64 *hl, const u64 *hh, u64 *partials) {
-    const u32 T = sp - 1, H = sp - L - M;
-    const u64 nlo = 1ull << L, nhl = 1ull << M, nhh = 1ull << H;
-    const u32 lane = threadIdx.x & 63;
-    const u64 mid = (u64)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
-    u64 acc[MAX_LINE];
-#pragma unroll
-    for (int t = 0; t < MAX_LINE; t++) acc[t] = 0;
-    if (lane < nlo && mid < nhl) {
-        for (u64 h = 0; h < nhh; h++) {
-            const u64 v = V[(((h << M) + mid) << L) + lane];
-            const u64 *w = hh + h * T;
-#pragma unroll
-            for (int t = 0; t < MAX_LINE; t++)
-                if (t < (int)T) acc[t] = add(acc[t], mul(w[t], v));
-        }
-#pragma unroll
-        for (int t = 0; t < MAX_LINE; t++)
-            if (t < (int)T)
-                acc[t] = mul(acc[t], mul(hl[(u64)t * nhl + mid], lo[(u64)t * nlo + lane]));
-    }
-    block_store<MAX_LINE>(acc, partials + (u64)blockIdx.x * MAX_LINE);
-}
-
-hipError_t launch_line(hipStream_t st, u32 sp, u32 L, u32 M, const u64 *V, const u64 *lo,
-                       const u64 *hl, const u64 *hh, u64 *partials, int *nblocks) {
-    const u64 nwaves = 1ull << M;
-    int nb = (int)((nwaves + (BLOCK / 64) - 1) / (BLOCK / 64));
-    *nblocks = nb;
-    hipLaunchKernelGGL(k_line, dim3(nb), dim3(BLOCK), 0, st, sp, L, M, V, lo, hl, hh, partials);
-    return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(BLOCK) k_line_final(int nparts, const u64 *partials, u32 sp,
-                                                      ProofState *ps, const u64 *bstar,
-                                                      const u64 *cstar, u64 *msg, u64 *chal,
-                                                      u64 *zbuf) {
-    u64 t[MAX_LINE];
-    rows_total<MAX_LINE>(nparts, partials, t);
-    if (threadIdx.x == 0) {
-        for (u32 k = 2; k <= sp; k++) msg[k - 2] = t[k - 2];
-        const u64 tau = draw(ps);
-        *chal = tau;
-        for (u32 k = 0; k < sp; k++) {
-            const u64 b = bstar[k], c = cstar[k];
-            zbuf[k] = add(b, mul(tau, sub(c, b)));
-        }
-        ps->betaC = 1;  // the next layer's a-variables start unbound
-    }
-}
-
-hipError_t launch_line_final(hipStream_t st, int nparts, const u64 *partials, u32 sp,
-                             ProofState *ps, const u64 *bstar, const u64 *cstar, u64 *msg,
-                             u64 *chal, u64 *zbuf) {
-    hipLaunchKernelGGL(k_line_final, dim3(1), dim3(BLOCK), 0, st, nparts, partials, sp, ps, bstar,
-                       cstar, msg, chal, zbuf);
     return hipGetLastError();
 }
 
@@ -662,8 +285,6 @@ hipError_t launch_f2sc_final(hipStream_t st, int nparts, const u64 *partials, Pr
 __global__ void k_f2sc_init(ProofState *ps, u64 seed) {
     if (threadIdx.x == 0) {
         ps->rng = fp::sm_state(seed, fp::PURPOSE_F2SC);
-        ps->betaC = 1;
-        ps->v1 = 0;
     }
 }
 

@@ -1,0 +1,511 @@
+// steps.hip -- the step kernel: one launch runs one step of each job.
+//
+// Sec. 4.1.1 of the paper: every gate (or table entry) contributes
+// independently to the prover's message, so a step is a grid-stride pass in
+// which each workgroup sums its share (wave64 shuffles, then LDS) into one
+// row of partial sums.  All arithmetic is exact in F_p (Sec. 5.1), so the
+// result does not depend on the summation order.
+#include "fp61.hpp"
+#include "steps.hpp"
+
+namespace gkr {
+
+using fp::add;
+using fp::mul;
+using fp::P;
+using fp::sub;
+
+struct alignas(16) u64x2 {
+    u64 x, y;
+};
+__device__ __forceinline__ u64x2 ld2(const u64 *p, u64 i) { return *reinterpret_cast<const u64x2 *>(p + i); }
+__device__ __forceinline__ void st2(u64 *p, u64 i, u64 a, u64 b) {
+    u64x2 v;
+    v.x = a;
+    v.y = b;
+    *reinterpret_cast<u64x2 *>(p + i) = v;
+}
+
+constexpr int NWAVES = SBLOCK / 64;
+
+template <int K>
+__device__ __forceinline__ void wave_reduce(u64 (&v)[K]) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] = add(v[k], __shfl_xor(v[k], o));
+    }
+}
+
+// Workgroup sum of v; thread k < K writes total k to out[k].
+template <int K>
+__device__ __forceinline__ void block_store(u64 (&v)[K], u64 *out) {
+    __shared__ u64 sm[K][NWAVES];
+    wave_reduce<K>(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) sm[k][wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        u64 a = 0;
+#pragma unroll
+        for (int w = 0; w < NWAVES; w++) a = add(a, sm[threadIdx.x][w]);
+        out[threadIdx.x] = a;
+    }
+    __syncthreads();
+}
+
+// Sum rows [first, first + n) of K values (row stride ROW_STRIDE); every
+// thread of the workgroup receives the totals.
+template <int K>
+__device__ __forceinline__ void rows_total(const u64 *rows, u32 first, u32 n, u64 (&tot)[K]) {
+    __shared__ u64 res[K];
+    u64 v[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = 0;
+    for (u32 r = threadIdx.x; r < n; r += SBLOCK) {
+        const u64 *row = rows + (u64)(first + r) * ROW_STRIDE;
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] = add(v[k], row[k]);
+    }
+    block_store<K>(v, res);
+#pragma unroll
+    for (int k = 0; k < K; k++) tot[k] = res[k];
+}
+
+// chi of the bits of x over coordinates pt[0..n)
+__device__ __forceinline__ u64 chi_bits(u64 x, const u64 *pt, u32 n) {
+    u64 e = 1;
+    for (u32 k = 0; k < n; k++) e = mul(e, fp::eqbit((u32)((x >> k) & 1), pt[k]));
+    return e;
+}
+
+struct Ctx {
+    u32 lb, nb;      // this workgroup within the step, workgroups of the step
+    u64 gtid, gstride;
+    u64 r;           // challenge drawn in the prologue
+};
+
+// ------------------------------------------------------------- prologue
+
+__device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
+    const Fin &f = sd.fin;
+    const ProofPtrs &pp = sd.pp;
+    if (f.kind == FIN_P) {
+        u64 t[2];
+        rows_total<2>(f.rows, 0, f.nrows, t);
+        if (threadIdx.x == 0) {
+            const u64 z = pp.zbuf[f.j], C = pp.state[0], S0 = t[0], S1 = t[1];
+            f.msg[0] = mul(mul(C, sub(1, z)), S0);
+            f.msg[1] = mul(mul(C, z), S1);
+            const u64 c3 = sub(add(add(z, z), z), 1);  // eq(z, 2) = 3z - 1
+            f.msg[2] = mul(mul(C, c3), sub(add(S1, S1), S0));
+            pp.state[0] = mul(C, fp::eq(z, c.r));     // beta prefix over r_0..r_j
+        }
+    } else if (f.kind == FIN_W) {
+        u64 t[4];
+        rows_total<4>(f.rows, 0, f.nrows, t);
+        if (threadIdx.x == 0) {
+            const u64 E0 = t[0], E1 = t[1], O0 = t[2], O1 = t[3];
+            f.msg[0] = E0;
+            f.msg[1] = O1;
+            u64 o4 = add(O1, O1);
+            o4 = add(o4, o4);
+            f.msg[2] = sub(add(sub(E0, add(E1, E1)), o4), add(O0, O0));
+            if (f.last) {
+                const u64 f0 = f.F[0], f1 = f.F[1];
+                const u64 v = add(f0, mul(c.r, sub(f1, f0)));
+                *f.vout = v;
+                if (f.last == 1) pp.state[1] = v;
+            }
+        }
+    } else if (f.kind == FIN_LINE) {
+        if (f.T > 0) {
+            u64 t[LINE_CHUNK];
+            rows_total<LINE_CHUNK>(f.rows, 0, f.chunk_blocks, t);
+            if (threadIdx.x == 0)
+                for (u32 q = 0; q < LINE_CHUNK && q < f.T; q++) f.msg[q] = t[q];
+            if (f.T > LINE_CHUNK) {
+                rows_total<LINE_CHUNK>(f.rows, f.chunk_blocks, f.chunk_blocks, t);
+                if (threadIdx.x == 0)
+                    for (u32 q = 0; q + LINE_CHUNK < f.T; q++) f.msg[LINE_CHUNK + q] = t[q];
+            }
+        }
+        if (threadIdx.x < f.sp) pp.zbuf[threadIdx.x] = s_pt[threadIdx.x];
+        if (threadIdx.x == 0) pp.state[0] = 1;  // the next layer's a-variables start unbound
+    }
+}
+
+// ------------------------------------------------------------ step bodies
+
+__device__ void step_eval(const EvalArgs &a, const Ctx &c) {
+    for (u64 g = c.gtid; g < a.npad; g += c.gstride) {
+        u64 v = 0;
+        if (g < a.S) {
+            const u64 x = a.Vn[a.in1[g]], y = a.Vn[a.in2[g]];
+            const bool ismul = a.kind == 1 || (a.kind == 2 && a.type[g]);
+            v = ismul ? mul(x, y) : add(x, y);
+        }
+        a.V[g] = v;
+    }
+}
+
+__device__ void step_start(const StartArgs &a, const ProofPtrs &pp, const Ctx &c) {
+    if (c.lb == 0 && threadIdx.x == 0) {
+        u64 st = fp::sm_state(pp.state[2], fp::PURPOSE_GKR);  // state[2] = seed
+        pp.rngst[0] = st;
+        for (u32 k = 0; k < a.s0; k++) {
+            const u64 z = fp::sm_field(st);
+            pp.chals[k] = z;
+            pp.zbuf[k] = z;
+            pp.rngst[k + 1] = st;
+        }
+        pp.state[0] = 1;
+        pp.state[1] = 0;
+    }
+    for (u64 g = c.gtid; g < a.S0; g += c.gstride) pp.msgs[g] = a.V0[g];
+}
+
+__device__ void step_eq(const EqArgs &a, const Ctx &c, const u64 *pt) {
+    const u64 nlo = 1ull << a.L, nhi = 1ull << (a.n - a.L);
+    for (u64 x = c.gtid; x < nlo + nhi; x += c.gstride) {
+        if (x < nlo)
+            a.lo[x] = chi_bits(x, pt, a.L);
+        else
+            a.hi[x - nlo] = chi_bits(x - nlo, pt + a.L, a.n - a.L);
+    }
+}
+
+__device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
+    const u64 r = c.r;
+    const u64 mask = (1ull << a.L) - 1;
+    u64 acc[2] = {0, 0};
+    for (u64 m = c.gtid; m < a.nm; m += c.gstride) {
+        u64 v0, v1, b;
+        if (a.first) {
+            const u64x2 p = ld2(a.Vsrc, 2 * m);
+            v0 = p.x;
+            v1 = p.y;
+            b = mul(a.zlo[m & mask], a.zhi[m >> a.L]);
+        } else {
+            const u64x2 p = ld2(a.Vsrc, 4 * m), q = ld2(a.Vsrc, 4 * m + 2);
+            v0 = add(p.x, mul(r, sub(p.y, p.x)));
+            v1 = add(q.x, mul(r, sub(q.y, q.x)));
+            if (a.Vout) st2(a.Vout, 2 * m, v0, v1);
+            const u64x2 bb = ld2(a.Bprev, 2 * m);
+            b = add(bb.x, bb.y);
+        }
+        if (a.Bout) a.Bout[m] = b;
+        acc[0] = add(acc[0], mul(b, v0));
+        acc[1] = add(acc[1], mul(b, v1));
+    }
+    block_store<2>(acc, row);
+}
+
+// Gate g with bound-wire index idx, at round k of its phase:
+//   term_g(t) = w_g eq(bit_k(idx), t) (F(t) + off_g)
+// with F(t) = (1-t) F[2m] + t F[2m+1], m = idx >> (k+1), the extension of
+// V_{i+1} at the partially bound point.  MUL gates carry their fixed
+// operand inside w (off = 0), ADD gates in off.  With P0 = w (F[2m] + off),
+// P1 = w (F[2m+1] + off):  bit 0 adds P0 at t=0 and P0 - 2 P1 at t=2;
+// bit 1 adds P1 at t=1 and 4 P1 - 2 P0 at t=2.  The row holds (E0, E1)
+// = sums of (P0, P1) over bit-0 gates and (O0, O1) over bit-1 gates.
+template <int KIND, int PH>
+__device__ void step_w(const WArgs &a, const Ctx &c, const ProofPtrs &pp, u64 *row) {
+    const bool init = a.init, inl = a.inline_fold, wr = a.write_w;
+    u64 r = 0, omr = 0;
+    if (!init) {
+        r = inl ? c.r : pp.chals[a.rchal];
+        omr = sub(1, r);
+    }
+    const u64 wbase = init ? pp.state[0] : 0;  // beta(z, a*)
+    const u64 v1 = PH == 2 ? pp.state[1] : 0;
+    const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
+    const u32 k = a.k;
+    if (inl) {
+        // this round's table F^(k) = F^(k-1) folded by r, for the next round
+        for (u64 m = c.gtid; m < a.nfold; m += c.gstride) {
+            const u64x2 p = ld2(a.F, 2 * m);
+            a.Fout[m] = add(p.x, mul(r, sub(p.y, p.x)));
+        }
+    }
+    u64 acc[4] = {0, 0, 0, 0};
+    for (u64 g = c.gtid; g < a.S; g += c.gstride) {
+        const u32 idx = a.idx[g];
+        const bool ismul = KIND == 1 || (KIND == 2 && a.type[g]);
+        u64 wt, of;
+        if (init) {
+            u64 wg = mul(wbase, mul(a.alo[g & amask], a.ahi[g >> a.La]));
+            if (PH == 1) {
+                const u64 y = a.Vn[a.oth[g]];
+                wt = ismul ? mul(wg, y) : wg;
+                of = ismul ? 0 : y;
+                if (KIND != 1) a.off[g] = of;
+            } else {
+                const u32 i1 = a.oth[g];
+                wg = mul(wg, mul(a.blo[i1 & bmask], a.bhi[i1 >> a.Lb]));
+                wt = ismul ? mul(wg, v1) : wg;
+                of = ismul ? 0 : v1;
+            }
+        } else {
+            wt = mul(a.w[g], ((idx >> (k - 1)) & 1) ? r : omr);
+            if (PH == 1)
+                of = KIND == 1 ? 0 : a.off[g];
+            else
+                of = ismul ? 0 : v1;
+        }
+        u64 f0, f1;
+        if (inl) {
+            const u64 q = ((u64)idx >> (k + 1)) << 2;
+            const u64x2 p0 = ld2(a.F, q), p1 = ld2(a.F, q + 2);
+            f0 = add(p0.x, mul(r, sub(p0.y, p0.x)));
+            f1 = add(p1.x, mul(r, sub(p1.y, p1.x)));
+        } else {
+            const u64x2 f = ld2(a.F, ((u64)idx >> (k + 1)) << 1);
+            f0 = f.x;
+            f1 = f.y;
+        }
+        const u64 P0 = mul(wt, add(f0, of)), P1 = mul(wt, add(f1, of));
+        if ((idx >> k) & 1) {
+            acc[2] = add(acc[2], P0);
+            acc[3] = add(acc[3], P1);
+        } else {
+            acc[0] = add(acc[0], P0);
+            acc[1] = add(acc[1], P1);
+        }
+        if (wr) a.w[g] = wt;
+    }
+    block_store<4>(acc, row);
+}
+
+__device__ void step_fold(const FoldArgs &a, const Ctx &c) {
+    const u64 r = c.r;
+    for (u64 m = c.gtid; m < a.nh; m += c.gstride) {
+        const u64x2 p = ld2(a.src, 2 * m);
+        a.dst[m] = add(p.x, mul(r, sub(p.y, p.x)));
+    }
+}
+
+// Line step (a9).  h(t) = ~V_{i+1}(l(t)) for t = 2..s', l(t) = b* + t (c* - b*).
+// x = (hh 2^M + mid) 2^L + lane: chi_x(l(t)) = Hh_t[hh] Hl_t[mid] lo_t[lane].
+// Tables: lo [T][2^L], hl [T][2^M], hh [2^H][T].
+__device__ void step_lt(const LtArgs &a, const Ctx &c, const u64 *bstar, const u64 *cstar) {
+    if (a.sp < 2) return;  // no line points
+    const u32 T = a.sp - 1, H = a.sp - a.L - a.M;
+    const u64 nlo = 1ull << a.L, nhl = 1ull << a.M, nhh = 1ull << H;
+    const u64 per = nlo + nhl + nhh;
+    for (u64 e = c.gtid; e < (u64)T * per; e += c.gstride) {
+        const u32 tp = (u32)(e / per);
+        const u64 x = e % per;
+        const u64 t = tp + 2;
+        u32 base, n;
+        u64 bits;
+        if (x < nlo) {
+            base = 0; n = a.L; bits = x;
+        } else if (x < nlo + nhl) {
+            base = a.L; n = a.M; bits = x - nlo;
+        } else {
+            base = a.L + a.M; n = H; bits = x - nlo - nhl;
+        }
+        u64 v = 1;
+        for (u32 k = 0; k < n; k++) {
+            const u64 b = bstar[base + k], cc = cstar[base + k];
+            const u64 l = add(b, mul(t, sub(cc, b)));
+            v = mul(v, fp::eqbit((u32)((bits >> k) & 1), l));
+        }
+        if (x < nlo)
+            a.lo[(u64)tp * nlo + bits] = v;
+        else if (x < nlo + nhl)
+            a.hl[(u64)tp * nhl + bits] = v;
+        else
+            a.hh[bits * T + tp] = v;
+    }
+}
+
+// Workgroups [q * chunk_blocks, (q+1) * chunk_blocks) sum line points
+// t' = 16 q .. 16 q + 15; within a chunk, wave `mid` walks hh.
+__device__ void step_line(const LineArgs &a, const Ctx &c, u64 *row) {
+    const u32 T = a.T, H = a.sp - a.L - a.M;
+    const u64 nlo = 1ull << a.L, nhl = 1ull << a.M, nhh = 1ull << H;
+    const u32 chunk = c.lb / a.chunk_blocks;
+    const u32 t0 = chunk * LINE_CHUNK;
+    const u32 lane = threadIdx.x & 63;
+    const u64 mid = (u64)(c.lb - chunk * a.chunk_blocks) * NWAVES + (threadIdx.x >> 6);
+    u64 acc[LINE_CHUNK];
+#pragma unroll
+    for (int t = 0; t < LINE_CHUNK; t++) acc[t] = 0;
+    if (lane < nlo && mid < nhl) {
+        for (u64 h = 0; h < nhh; h++) {
+            const u64 v = a.V[(((h << a.M) + mid) << a.L) + lane];
+            const u64 *w = a.hh + h * T + t0;
+#pragma unroll
+            for (int t = 0; t < LINE_CHUNK; t++)
+                if (t0 + t < T) acc[t] = add(acc[t], mul(w[t], v));
+        }
+#pragma unroll
+        for (int t = 0; t < LINE_CHUNK; t++)
+            if (t0 + t < T)
+                acc[t] = mul(acc[t], mul(a.hl[(u64)(t0 + t) * nhl + mid], a.lo[(u64)(t0 + t) * nlo + lane]));
+    }
+    block_store<LINE_CHUNK>(acc, row);
+}
+
+// ---------------------------------------------------------------- kernel
+
+// One step on workgroup lb.  Workgroups [0, nblocks) run the body; a step
+// that finishes the previous round has one more workgroup, lb == nblocks,
+// which only folds the previous rows into the message (so that work runs
+// beside the body instead of ahead of it) and records the drawn challenge.
+constexpr u32 KALL = 0xFFFF;  // kind resolved at run time (mixed batches)
+
+template <u32 KIND, int GK, int PH>
+__device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
+    __shared__ u64 s_r;
+    __shared__ u64 s_pt[64];  // a point (EQ), or b* and c* (LT), or z_{i+1} (FIN_LINE)
+    Ctx c;
+    c.lb = lb;
+    c.nb = sd.nblocks;
+    c.gtid = (u64)c.lb * SBLOCK + threadIdx.x;
+    c.gstride = (u64)c.nb * SBLOCK;
+    const Fin &f = sd.fin;
+    const ProofPtrs &pp = sd.pp;
+    const bool has_fin = f.kind != FIN_NONE;
+    const bool fin_block = has_fin && lb == sd.nblocks;
+    const bool recorder = has_fin ? fin_block : lb == 0;
+
+    // --- prologue: the challenge (every workgroup draws the same value)
+    if (threadIdx.x == 0) {
+        u64 r = 0;
+        if (f.draw >= 0) {
+            u64 st = pp.rngst[f.draw];
+            r = fp::sm_field(st);
+            if (recorder) {
+                pp.chals[f.draw] = r;
+                pp.rngst[f.draw + 1] = st;
+            }
+        }
+        s_r = r;
+    }
+    __syncthreads();
+    c.r = s_r;
+    // points assembled in LDS (challenges drawn by earlier launches are in
+    // chals; the one drawn just now is c.r)
+    if (f.kind == FIN_LINE && threadIdx.x < f.sp) {
+        const u64 bb = f.bstar[threadIdx.x], cc = f.cstar[threadIdx.x];
+        s_pt[threadIdx.x] = add(bb, mul(c.r, sub(cc, bb)));  // z_{i+1} = l(tau)
+    }
+    const u32 kind = KIND == KALL ? sd.kind : KIND;
+    if (kind == ST_EQ && sd.u.eq.point == PT_Z && f.kind != FIN_LINE &&
+        threadIdx.x < sd.u.eq.base + sd.u.eq.n)
+        s_pt[threadIdx.x] = pp.zbuf[threadIdx.x];  // z of the layer, already recorded
+    if (kind == ST_EQ && sd.u.eq.point == PT_CHAL && threadIdx.x < sd.u.eq.n) {
+        const i32 ci = (i32)(sd.u.eq.base + threadIdx.x);
+        s_pt[threadIdx.x] = ci == f.draw ? c.r : pp.chals[ci];
+    }
+    if (kind == ST_LT && threadIdx.x < 2 * sd.u.lt.sp) {
+        const u32 sp = sd.u.lt.sp;
+        const i32 ci = (i32)(threadIdx.x < sp ? sd.u.lt.bbase + threadIdx.x
+                                              : sd.u.lt.cbase + threadIdx.x - sp);
+        s_pt[threadIdx.x] = ci == f.draw ? c.r : pp.chals[ci];
+    }
+    __syncthreads();
+    if (fin_block) {
+        finalize(sd, c, s_pt);
+        return;
+    }
+
+    // --- body
+    u64 *row = sd.rows ? sd.rows + (u64)c.lb * ROW_STRIDE : nullptr;
+    switch (kind) {
+        case ST_EVAL: step_eval(sd.u.eval, c); break;
+        case ST_START: step_start(sd.u.start, pp, c); break;
+        case ST_EQ:
+            step_eq(sd.u.eq, c, sd.u.eq.point == PT_Z ? s_pt + sd.u.eq.base : s_pt);
+            break;
+        case ST_P: step_p(sd.u.p, c, row); break;
+        case ST_W: {
+            const WArgs &a = sd.u.w;
+            if (GK >= 0) {
+                step_w<GK < 0 ? 0 : GK, PH < 1 ? 1 : PH>(a, c, pp, row);
+            } else if (a.ph == 1) {
+                if (a.kind == 0) step_w<0, 1>(a, c, pp, row);
+                else if (a.kind == 1) step_w<1, 1>(a, c, pp, row);
+                else step_w<2, 1>(a, c, pp, row);
+            } else {
+                if (a.kind == 0) step_w<0, 2>(a, c, pp, row);
+                else if (a.kind == 1) step_w<1, 2>(a, c, pp, row);
+                else step_w<2, 2>(a, c, pp, row);
+            }
+            break;
+        }
+        case ST_FOLD: step_fold(sd.u.fold, c); break;
+        case ST_LT: step_lt(sd.u.lt, c, s_pt, s_pt + sd.u.lt.sp); break;
+        case ST_LINE: step_line(sd.u.line, c, row); break;
+        case ST_SGE:
+            if (c.lb == 0 && threadIdx.x == 0) {
+                const u64 v = sd.u.sge.Vn[0];
+                sd.u.sge.vslot[0] = v;
+                sd.u.sge.vslot[1] = v;
+                pp.state[1] = v;
+            }
+            break;
+        default: break;
+    }
+}
+
+// A single proof's step, its descriptor passed by value as kernel argument;
+// one instantiation per step kind (and per gate mix and phase for omega
+// rounds) keeps each kernel's code and registers to what the kind needs.
+template <u32 KIND, int GK, int PH>
+__global__ void __launch_bounds__(SBLOCK) k_step_one(const StepDesc sd) {
+    run_step<KIND, GK, PH>(sd, blockIdx.x);
+}
+
+// One step of each of several proofs.
+__global__ void __launch_bounds__(SBLOCK) k_step_jobs(const JobEntry *__restrict__ jobs, u32 njobs) {
+    u32 lo = 0, hi = njobs;
+    const u32 b = blockIdx.x;
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (jobs[mid].block0 <= b) lo = mid; else hi = mid;
+    }
+    run_step<KALL, -1, 0>(*jobs[lo].step, b - jobs[lo].block0);
+}
+
+u32 step_grid(const StepDesc &sd) { return sd.nblocks + (sd.fin.kind != FIN_NONE ? 1 : 0); }
+
+hipError_t launch_step(hipStream_t st, const StepDesc &sd) {
+    const dim3 g(step_grid(sd)), b(SBLOCK);
+#define L1(K) hipLaunchKernelGGL((k_step_one<K, -1, 0>), g, b, 0, st, sd)
+#define LW(G, PH) hipLaunchKernelGGL((k_step_one<ST_W, G, PH>), g, b, 0, st, sd)
+    switch (sd.kind) {
+        case ST_EVAL: L1(ST_EVAL); break;
+        case ST_START: L1(ST_START); break;
+        case ST_EQ: L1(ST_EQ); break;
+        case ST_P: L1(ST_P); break;
+        case ST_W:
+            if (sd.u.w.ph == 1) {
+                if (sd.u.w.kind == 0) LW(0, 1); else if (sd.u.w.kind == 1) LW(1, 1); else LW(2, 1);
+            } else {
+                if (sd.u.w.kind == 0) LW(0, 2); else if (sd.u.w.kind == 1) LW(1, 2); else LW(2, 2);
+            }
+            break;
+        case ST_FOLD: L1(ST_FOLD); break;
+        case ST_LT: L1(ST_LT); break;
+        case ST_LINE: L1(ST_LINE); break;
+        case ST_SGE: L1(ST_SGE); break;
+        default: L1(ST_END); break;
+    }
+#undef L1
+#undef LW
+    return hipGetLastError();
+}
+
+hipError_t launch_steps(hipStream_t st, const JobEntry *jobs, u32 njobs, u32 total_blocks) {
+    hipLaunchKernelGGL(k_step_jobs, dim3(total_blocks), dim3(SBLOCK), 0, st, jobs, njobs);
+    return hipGetLastError();
+}
+
+}  // namespace gkr

@@ -1,0 +1,188 @@
+// steps.hpp -- the prover as a program of steps, executed by one kernel.
+//
+// A proof is a fixed sequence of steps (evaluation of each layer, then per
+// layer: the eq table of z, the p-phase rounds, the eq table of a*, the two
+// omega-phases, the eq table of b*, the line tables and the line sums).
+// Every step is one grid pass; a step that ends a sum-check round leaves one
+// row of partial sums per workgroup.
+//
+// The next step finishes that round in its prologue: workgroup 0 of the
+// step folds the rows into the round's message and writes it, and every
+// workgroup draws the round's challenge from the same SplitMix64 state
+// (the verifier's coins do not depend on the messages), so no step ever
+// synchronises workgroups inside a kernel.  The challenge of round j is
+// drawn only in a launch that starts after the launch computing message j
+// has completed.
+//
+// One launch runs one step of each of several proofs (a job table maps
+// workgroups to (proof, step)); a single proof is the one-job case.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gkr {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int32_t i32;
+typedef uint8_t u8;
+
+constexpr int SBLOCK = 512;      // threads per workgroup of the step kernel
+constexpr int SMAX_BLOCKS = 512; // workgroups per step (2 per CU)
+constexpr int LINE_CHUNK = 16;   // line points summed per workgroup
+constexpr int ROW_STRIDE = 16;   // u64 per partial-sum row
+
+enum StepKind : u32 {
+    ST_EVAL = 0,   // V_i[g] = V_{i+1}[in1] op V_{i+1}[in2]
+    ST_START,      // outputs into the transcript, z_0 drawn
+    ST_EQ,         // eq half tables of a point (z_i suffix, a*, or b*)
+    ST_P,          // one p-phase round (a-variables)
+    ST_W,          // one omega round (b- or c-variables)
+    ST_FOLD,       // fold of V_{i+1}'s table by the last challenge
+    ST_LT,         // eq tables of the line points
+    ST_LINE,       // line sums h(t), t = 2..s'
+    ST_SGE,        // next layer has one gate: v1 = v2 = V_{i+1}[0]
+    ST_END,        // nothing but the prologue
+};
+
+enum FinKind : u32 {
+    FIN_NONE = 0,
+    FIN_P,     // p-phase message from rows of (S0, S1)
+    FIN_W,     // omega message from rows of (E0, E1, O0, O1)
+    FIN_LINE,  // h(t) values from rows of line sums; then tau and z_{i+1}
+};
+
+// The point the ST_EQ step expands, assembled in LDS by each workgroup.
+enum PointKind : u32 {
+    PT_Z = 0,  // z_i[1..s): computed from the previous layer's line and tau
+    PT_CHAL,   // challenges chals[base .. base+n) (the last may be drawn now)
+};
+
+// Per-proof device state shared by all steps of a proof.
+struct ProofPtrs {
+    u64 *msgs;   // transcript
+    u64 *chals;  // challenges
+    u64 *rngst;  // rngst[c] = SplitMix64 state before challenge c
+    u64 *zbuf;   // z of the current layer
+    u64 *state;  // [0] beta prefix C, [1] v1, [2] the proof's seed
+};
+
+// Prologue: finish the previous round and/or draw challenge `draw`.
+struct Fin {
+    u32 kind;          // FinKind
+    i32 draw;          // challenge index drawn here (-1: none)
+    const u64 *rows;   // partial rows of the previous step
+    u32 nrows;
+    u32 j;             // FIN_P: round index (z_j)
+    u32 last;          // FIN_W: 1 / 2 = end of phase 1 / 2 (v1 / v2)
+    u32 T;             // FIN_LINE: number of line values
+    u32 sp;            // FIN_LINE: coordinates of z_{i+1}
+    u32 chunk_blocks;  // FIN_LINE: workgroups per chunk of line points
+    const u64 *F;      // FIN_W last: the 2-entry table
+    u64 *msg;          // where the message goes
+    u64 *vout;         // FIN_W last: transcript slot of v1 / v2
+    const u64 *bstar, *cstar;  // FIN_LINE: line endpoints (chals)
+};
+
+struct EvalArgs {
+    u32 kind, S;
+    u64 npad;
+    const u8 *type;
+    const u32 *in1, *in2;
+    const u64 *Vn;
+    u64 *V;
+};
+struct StartArgs {
+    u32 s0, S0;
+    const u64 *V0;
+};
+struct EqArgs {
+    u32 point;  // PointKind
+    u32 n;      // coordinates
+    u32 L;      // lo table covers coordinates [0, L)
+    u32 base;   // PT_CHAL: first challenge index; PT_Z: first coordinate of z
+    u64 *lo, *hi;
+};
+struct PArgs {
+    u32 first;
+    u64 nm;
+    const u64 *Vsrc;
+    u64 *Vout;
+    const u64 *Bprev;
+    u64 *Bout;
+    const u64 *zlo, *zhi;
+    u32 L;
+};
+struct WArgs {
+    u32 kind, ph, init, write_w, inline_fold;
+    u32 S, k;
+    u64 nfold;
+    const u32 *idx, *oth;
+    const u8 *type;
+    const u64 *F, *Vn;
+    u64 *Fout;
+    const u64 *alo, *ahi;
+    u32 La;
+    const u64 *blo, *bhi;
+    u32 Lb;
+    i32 rchal;  // non-inline rounds k > 0: index of r_{k-1} in chals
+    u64 *w, *off;
+};
+struct FoldArgs {
+    u64 nh;
+    const u64 *src;
+    u64 *dst;
+};
+struct LtArgs {
+    u32 sp, L, M;
+    u32 bbase, cbase;  // challenge indices of b* and c*
+    u64 *lo, *hl, *hh;
+};
+struct LineArgs {
+    u32 sp, L, M, T, chunk_blocks;
+    const u64 *V, *lo, *hl, *hh;
+};
+struct SgeArgs {
+    const u64 *Vn;
+    u64 *vslot;
+};
+
+struct StepDesc {
+    u32 kind;
+    u32 nblocks;
+    u32 reduces;   // 1 if the step writes partial rows
+    u32 K;         // values per row
+    u64 *rows;     // this step's partial rows
+    Fin fin;
+    ProofPtrs pp;
+    union {
+        EvalArgs eval;
+        StartArgs start;
+        EqArgs eq;
+        PArgs p;
+        WArgs w;
+        FoldArgs fold;
+        LtArgs lt;
+        LineArgs line;
+        SgeArgs sge;
+    } u;
+};
+
+// One (proof, step) of a launch; workgroups [block0, next block0) run it.
+struct JobEntry {
+    const StepDesc *step;
+    u32 block0;
+    u32 pad;
+};
+
+// Workgroups a step needs: its body's plus one that finishes the previous
+// round when the step has a prologue.
+u32 step_grid(const StepDesc &sd);
+// One step of one proof (descriptor passed by value).
+hipError_t launch_step(hipStream_t st, const StepDesc &sd);
+// One step of each of njobs proofs (entries in device memory, sorted by
+// block0, followed by a sentinel whose block0 is the total; each job spans
+// step_grid(*step) workgroups).
+hipError_t launch_steps(hipStream_t st, const JobEntry *jobs, u32 njobs, u32 total_blocks);
+
+}  // namespace gkr
