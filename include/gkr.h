@@ -53,6 +53,15 @@ enum {
 
 enum { GKR_ADD = 0, GKR_MUL = 1 };
 
+/* How the prover computes the rounds over the wire variables (b, c):
+ *   GKR_OMEGA_GATES   every round is a pass over the layer's gates, each gate
+ *                     contributing its term (Sec. 4.1.1), O(S log S) per layer;
+ *   GKR_OMEGA_TABLES  the gates' weights are summed once per phase into
+ *                     tables indexed by the bound wire, and every round folds
+ *                     those tables (which halve each round), O(S + 2^{s'}).
+ * Both give the same transcript bit for bit. */
+enum { GKR_OMEGA_GATES = 0, GKR_OMEGA_TABLES = 1 };
+
 /* Reasons for rejection (gkr_reject_info.check). */
 enum {
     GKR_CHECK_MALFORMED = 1, /* wrong length, or a value not below p          */
@@ -89,6 +98,12 @@ int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_sizes,
 /* Release a circuit and the device memory it holds (NULL is ignored).
  * No proof on the circuit may be running. */
 void gkr_circuit_destroy(gkr_circuit *c);
+
+/* Choose the omega-phase algorithm of a circuit (default GKR_OMEGA_TABLES).
+ * Frees the circuit's proof scratch, which the next proof re-creates.
+ * Must not be called while a proof on the circuit runs.
+ * Errors: GKR_ERR_INVALID. */
+int gkr_circuit_set_algorithm(gkr_circuit *c, int omega_algo);
 
 /* Transcript lengths for the layout above. */
 int gkr_transcript_size(const gkr_circuit *c, uint64_t *n_msgs, uint64_t *n_chals);

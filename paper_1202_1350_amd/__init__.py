@@ -16,6 +16,7 @@ P = (1 << 61) - 1
 
 GKR_OK, GKR_ERR_INVALID, GKR_ERR_RANGE, GKR_ERR_NOMEM, GKR_ERR_DEVICE, GKR_ERR_BUFSIZE = \
     0, -1, -2, -3, -4, -5
+GKR_OMEGA_GATES, GKR_OMEGA_TABLES = 0, 1
 CHECKS = {1: "malformed", 2: "round", 3: "wiring", 4: "line", 5: "input"}
 
 
@@ -36,6 +37,7 @@ _SIGS = [
     ("gkr_circuit_create", C.c_int, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(C.c_void_p)]),
     ("gkr_circuit_destroy", None, [C.c_void_p]),
+    ("gkr_circuit_set_algorithm", C.c_int, [C.c_void_p, C.c_int]),
     ("gkr_transcript_size", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     ("gkr_circuit_info", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                    C.POINTER(C.c_uint32)]),
@@ -138,8 +140,15 @@ class Circuit:
         self.gates, self.rounds = g.value, r.value
 
     @classmethod
-    def from_workload(cls, circ):
-        return cls(circ.sizes, circ.types, circ.in1, circ.in2)
+    def from_workload(cls, circ, omega_algo=None):
+        c = cls(circ.sizes, circ.types, circ.in1, circ.in2)
+        if omega_algo is not None:
+            c.set_algorithm(omega_algo)
+        return c
+
+    def set_algorithm(self, omega_algo: int):
+        """GKR_OMEGA_TABLES (default) or GKR_OMEGA_GATES; same transcript."""
+        _check(lib().gkr_circuit_set_algorithm(self.handle, int(omega_algo)))
 
     def __del__(self):
         h = getattr(self, "handle", None)

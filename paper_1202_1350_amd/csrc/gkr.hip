@@ -216,6 +216,14 @@ struct Workspace {
     u64 *rows[2];
     u64 *msgs, *chals, *rngst, *zbuf, *state;
     u32 *flag;
+    // omega phases over tables
+    u64 *tA0, *tC0, *tA[2], *tC[2], *partA, *partC;
+    struct Group {  // gates of a layer grouped by the wire a phase binds
+        u32 *perm = nullptr, *cstart = nullptr, *xch = nullptr;
+        u32 nch = 0;
+    };
+    std::vector<Group> grp[2];  // [phase - 1][layer]
+    void *gmem = nullptr;       // device memory of the groups
     StepDesc *d_steps;
     JobEntry *d_jobs;
     std::vector<StepDesc> steps;  // host copy of the program
@@ -238,8 +246,11 @@ struct gkr_circuit {
     u32 smax = 0, spmax = 0;
     u64 gmax = 0;
     u64 line_lo = 1, line_hl = 1, line_hh = 1;  // table sizes (entries)
+    u64 nch_max = 1;  // most chunks of a phase grouping
     std::mutex mu;
     Workspace *ws = nullptr;
+    int omega_algo = GKR_OMEGA_TABLES;
+    std::vector<std::vector<u32>> h_in1, h_in2;  // host copies of the wires (grouping)
 };
 
 extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_sizes,
@@ -318,6 +329,8 @@ extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_siz
         p += (n * 4 + 255) & ~size_t(255);
         HIP_TRY(hipMemcpy(c->in1[i], in1[i], n * 4, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(c->in2[i], in2[i], n * 4, hipMemcpyHostToDevice));
+        c->h_in1.emplace_back(in1[i], in1[i] + n);
+        c->h_in2.emplace_back(in2[i], in2[i] + n);
         if (c->kind[i] == KIND_MIXED) {
             c->type[i] = (u8 *)p;
             p += (n + 255) & ~size_t(255);
@@ -331,6 +344,7 @@ extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_siz
 static void free_workspace(Workspace *ws) {
     if (!ws) return;
     if (ws->mem) (void)hipFree(ws->mem);
+    if (ws->gmem) (void)hipFree(ws->gmem);
     if (ws->h_msgs) (void)hipHostFree(ws->h_msgs);
     if (ws->h_chals) (void)hipHostFree(ws->h_chals);
     if (ws->h_seed) (void)hipHostFree(ws->h_seed);
@@ -343,6 +357,19 @@ extern "C" void gkr_circuit_destroy(gkr_circuit *c) {
     free_workspace(c->ws);
     if (c->soa) (void)hipFree(c->soa);
     delete c;
+}
+
+extern "C" int gkr_circuit_set_algorithm(gkr_circuit *c, int omega_algo) {
+    if (!c) return fail(GKR_ERR_INVALID, "circuit is NULL");
+    if (omega_algo != GKR_OMEGA_GATES && omega_algo != GKR_OMEGA_TABLES)
+        return fail(GKR_ERR_INVALID, "unknown omega-phase algorithm");
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->omega_algo != omega_algo) {
+        free_workspace(c->ws);  // the step program is rebuilt on the next proof
+        c->ws = nullptr;
+        c->omega_algo = omega_algo;
+    }
+    return GKR_OK;
 }
 
 extern "C" int gkr_transcript_size(const gkr_circuit *c, uint64_t *n_msgs, uint64_t *n_chals) {
@@ -359,6 +386,32 @@ extern "C" int gkr_circuit_info(const gkr_circuit *c, uint64_t *gates, uint64_t 
     if (rounds) *rounds = c->rounds;
     if (num_layers) *num_layers = c->L;
     return GKR_OK;
+}
+
+// Gates of a layer grouped by the wire x a phase binds: perm lists the
+// gates in order of x (counting sort), cut into chunks of at most
+// GROUP_CHUNK gates of one wire; chunks of wire x are [xch[x], xch[x+1]).
+constexpr u32 GROUP_CHUNK = 32;
+struct HostGroup {
+    std::vector<u32> perm, cstart, xch;
+};
+
+static void build_group(const std::vector<u32> &idx, u64 N, HostGroup &G) {
+    const u64 S = idx.size();
+    std::vector<u32> rowptr(N + 1, 0);
+    for (u64 g = 0; g < S; g++) rowptr[idx[g] + 1]++;
+    for (u64 x = 0; x < N; x++) rowptr[x + 1] += rowptr[x];
+    G.perm.assign(S, 0);
+    std::vector<u32> fill(rowptr.begin(), rowptr.end() - 1);
+    for (u64 g = 0; g < S; g++) G.perm[fill[idx[g]]++] = (u32)g;
+    G.xch.assign(N + 1, 0);
+    G.cstart.clear();
+    for (u64 x = 0; x < N; x++) {
+        G.xch[x] = (u32)G.cstart.size();
+        for (u32 p = rowptr[x]; p < rowptr[x + 1]; p += GROUP_CHUNK) G.cstart.push_back(p);
+    }
+    G.xch[N] = (u32)G.cstart.size();
+    G.cstart.push_back((u32)S);
 }
 
 // Lay out (or size, when a.base is NULL) a proof's scratch.
@@ -393,6 +446,17 @@ static void carve(const gkr_circuit *c, Arena &a, Workspace &w, size_t nsteps) {
     w.flag = a.take<u32>(1);
     w.d_steps = a.take<StepDesc>(nsteps);
     w.d_jobs = a.take<JobEntry>(2 * nsteps);
+    if (c->omega_algo == GKR_OMEGA_TABLES) {
+        const u64 N = 1ull << c->spmax;
+        w.tA0 = a.take<u64>(N);
+        w.tC0 = a.take<u64>(N);
+        w.tA[0] = a.take<u64>(std::max<u64>(N / 2, 2));
+        w.tA[1] = a.take<u64>(std::max<u64>(N / 2, 2));
+        w.tC[0] = a.take<u64>(std::max<u64>(N / 2, 2));
+        w.tC[1] = a.take<u64>(std::max<u64>(N / 2, 2));
+        w.partA = a.take<u64>(c->nch_max);
+        w.partC = a.take<u64>(c->nch_max);
+    }
 }
 
 // Workgroups of the step kernel for n items at `per` items per thread.
@@ -406,6 +470,7 @@ static u32 sblocks(u64 n, u64 per = 1) {
 struct Planner {
     const gkr_circuit *c;
     Workspace *w;
+    const std::vector<HostGroup> *hg;  // [2 * layer + phase - 1], table algorithm
     std::vector<StepDesc> out;
     std::vector<int> cls;
     std::vector<double> bytes;
@@ -479,8 +544,10 @@ struct Planner {
                 e.fin = layer_end;
                 e.u.eq = EqArgs{PT_Z, nz, nz / 2, 1, P_(w ? w->zlo : nullptr), P_(w ? w->zhi : nullptr)};
             }
-            // ---- p-phase (a5)
-            for (u32 j = 0; j < s; j++) {
+            // ---- p-phase (a5): grid rounds while the table is large, then
+            // the remaining rounds in one workgroup
+            const u32 j0 = s ? std::max<u32>(1, s > 10 ? s - 10 : 1) : 0;
+            for (u32 j = 0; j < j0; j++) {
                 const u64 nm = 1ull << (s - j - 1);
                 Fin f = fin_of_prev(FIN_P);
                 const bool first = j == 0;
@@ -508,21 +575,29 @@ struct Planner {
                 st.u.p = pa;
                 reduces(2);
             }
-            // ---- eq tables of a*
+            if (s > 0) {
+                Fin f = fin_of_prev(FIN_P);
+                f.j = j0 - 1;
+                f.draw = (i32)(co + j0 - 1);
+                f.msg = w ? msg + 3ull * (j0 - 1) : nullptr;
+                StepDesc &st = add(ST_PTAIL, 1, PC_PPHASE, 24.0 * (1ull << (s - j0 + 1)));
+                st.fin = f;
+                PtailArgs pt;
+                pt.j0 = j0;
+                pt.s = s;
+                // V^(j0-1) and B_{j0-1}, as the last grid round left them
+                u64 *vbuf[2] = {w ? w->pA : nullptr, w ? w->pB : nullptr};
+                u64 *bbuf[2] = {w ? w->bA : nullptr, w ? w->bB : nullptr};
+                pt.V = j0 == 1 ? V(i) : vbuf[(j0 - 1) & 1];
+                pt.B = bbuf[(j0 - 1) & 1];
+                pt.c0 = co + j0;
+                pt.msg = w ? msg + 3ull * j0 : nullptr;
+                st.u.ptail = pt;
+            }
+            // ---- eq tables of a* (the p-phase tail recorded every challenge)
             {
                 const u32 La = s / 2;
-                Fin f;
-                memset(&f, 0, sizeof f);
-                f.kind = FIN_NONE;
-                f.draw = -1;
-                if (s > 0) {
-                    f = fin_of_prev(FIN_P);
-                    f.j = s - 1;
-                    f.draw = (i32)(co + s - 1);
-                    f.msg = w ? msg + 3ull * (s - 1) : nullptr;
-                }
                 StepDesc &e = add(ST_EQ, sblocks((1ull << La) + (1ull << (s - La))), PC_TABLES, 0);
-                e.fin = f;
                 e.u.eq = EqArgs{PT_CHAL, s, La, co, w ? w->alo : nullptr, w ? w->ahi : nullptr};
             }
             if (sp == 0) {
@@ -537,107 +612,224 @@ struct Planner {
                 layer_end.cstar = chals ? chals + co + s : nullptr;
                 continue;
             }
-            // ---- omega-phases (a6, a7, a8)
-            const u64 *Fend = nullptr;  // table of the phase's last round
-            for (u32 ph = 1; ph <= 2; ph++) {
-                const u32 rbase = s + (ph == 2 ? sp : 0);
-                const u32 Lb = sp / 2;
-                if (ph == 2) {
-                    Fin f = fin_of_prev(FIN_W);
-                    f.draw = (i32)(co + s + sp - 1);
-                    f.msg = w ? msg + 3ull * (s + sp - 1) : nullptr;
-                    f.last = 1;
-                    f.F = Fend;
-                    f.vout = vslot;
-                    StepDesc &e = add(ST_EQ, sblocks((1ull << Lb) + (1ull << (sp - Lb))), PC_TABLES, 0);
-                    e.fin = f;
-                    e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
-                }
-                const u64 *F = V(i + 1);
-                u64 *fbuf[2] = {w ? w->fA : nullptr, w ? w->fB : nullptr};
-                for (u32 k = 0; k < sp; k++) {
-                    WArgs a;
-                    memset(&a, 0, sizeof a);
-                    a.kind = kind;
-                    a.ph = ph;
-                    a.init = k == 0;
-                    a.write_w = k + 1 < sp;
-                    a.inline_fold = k > 0 && S <= INLINE_FOLD_MAX_GATES;
-                    a.S = S;
-                    a.k = k;
-                    a.nfold = 1ull << (sp - k);
-                    a.idx = ph == 1 ? c->in1[i] : c->in2[i];
-                    a.oth = ph == 1 ? c->in2[i] : c->in1[i];
-                    a.type = c->type[i];
-                    a.Vn = V(i + 1);
-                    a.alo = w ? w->alo : nullptr;
-                    a.ahi = w ? w->ahi : nullptr;
-                    a.La = s / 2;
-                    a.blo = w ? w->blo : nullptr;
-                    a.bhi = w ? w->bhi : nullptr;
-                    a.Lb = Lb;
-                    a.rchal = -1;
-                    a.w = w ? w->w : nullptr;
-                    a.off = w ? w->off : nullptr;
-                    Fin f;
-                    memset(&f, 0, sizeof f);
-                    f.kind = FIN_NONE;
-                    f.draw = -1;
-                    if (k > 0) {
-                        f = fin_of_prev(FIN_W);
+            u32 Ll = 0, M = 0, H = 0;  // shape of the line step (a9)
+            if (sp >= 2) line_shape(sp, &Ll, &M, &H);
+            const u64 ntab = sp >= 2 ? (u64)(sp - 1) * ((1ull << Ll) + (1ull << M) + (1ull << H)) : 1;
+            if (c->omega_algo == GKR_OMEGA_TABLES) {
+                // ---- omega-phases over tables (a6, a7, a8)
+                const u64 N = 1ull << sp;
+                const u32 k0 = std::max<u32>(1, sp > 10 ? sp - 10 : 1);
+                for (u32 ph = 1; ph <= 2; ph++) {
+                    const u32 rbase = s + (ph == 2 ? sp : 0);
+                    const u32 Lb = sp / 2;
+                    if (ph == 2) {
+                        StepDesc &e = add(ST_EQ, sblocks((1ull << Lb) + (1ull << (sp - Lb))), PC_TABLES, 0);
+                        e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
+                    }
+                    const HostGroup &G = (*hg)[2 * i + ph - 1];
+                    const u32 nch = (u32)G.cstart.size() - 1;
+                    const Workspace::Group *dg = w ? &w->grp[ph - 1][i] : nullptr;
+                    const u32 hasC = kind != KIND_MUL;
+                    {
+                        WaggArgs a;
+                        memset(&a, 0, sizeof a);
+                        a.kind = kind;
+                        a.ph = ph;
+                        a.nch = nch;
+                        a.perm = dg ? dg->perm : nullptr;
+                        a.cstart = dg ? dg->cstart : nullptr;
+                        a.oth = ph == 1 ? c->in2[i] : c->in1[i];
+                        a.type = c->type[i];
+                        a.Vn = V(i + 1);
+                        a.alo = w ? w->alo : nullptr;
+                        a.ahi = w ? w->ahi : nullptr;
+                        a.La = s / 2;
+                        a.blo = w ? w->blo : nullptr;
+                        a.bhi = w ? w->bhi : nullptr;
+                        a.Lb = Lb;
+                        a.partA = w ? w->partA : nullptr;
+                        a.partC = w ? w->partC : nullptr;
+                        // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1
+                        StepDesc &st = add(ST_WAGG, sblocks(nch), PC_OMEGA,
+                                           S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) + 20.0 * nch);
+                        st.u.wagg = a;
+                    }
+                    {
+                        Wt0Args a;
+                        memset(&a, 0, sizeof a);
+                        a.ph = ph;
+                        a.hasC = hasC;
+                        a.npairs = N / 2;
+                        a.xch = dg ? dg->xch : nullptr;
+                        a.partA = w ? w->partA : nullptr;
+                        a.partC = w ? w->partC : nullptr;
+                        a.F = V(i + 1);
+                        a.A = w ? w->tA0 : nullptr;
+                        a.C = w ? w->tC0 : nullptr;
+                        StepDesc &st = add(ST_WT0, sblocks(N / 2), PC_OMEGA,
+                                           N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 16.0 * nch);
+                        st.u.wt0 = a;
+                        reduces(3);
+                    }
+                    auto level = [&](u32 k, const u64 **A, const u64 **C, const u64 **F) {
+                        if (k == 0) {
+                            *A = w ? w->tA0 : nullptr;
+                            *C = w ? w->tC0 : nullptr;
+                            *F = V(i + 1);
+                        } else {
+                            *A = w ? w->tA[k & 1] : nullptr;
+                            *C = w ? w->tC[k & 1] : nullptr;
+                            *F = w ? (k & 1 ? w->fB : w->fA) : nullptr;
+                        }
+                    };
+                    for (u32 k = 1; k < k0; k++) {
+                        Fin f = fin_of_prev(FIN_T);
                         f.draw = (i32)(co + rbase + k - 1);
                         f.msg = w ? msg + 3ull * (rbase + k - 1) : nullptr;
-                        u64 *dst = fbuf[k & 1];
-                        if (a.inline_fold) {
-                            a.F = F;       // F^(k-1): the kernel folds it into dst
-                            a.Fout = dst;
-                        } else {
-                            StepDesc &fs = add(ST_FOLD, sblocks(a.nfold, 4), PC_FOLD, a.nfold * 24.0);
-                            fs.fin = f;
-                            fs.u.fold = FoldArgs{a.nfold, F, dst};
-                            memset(&f, 0, sizeof f);
-                            f.kind = FIN_NONE;
-                            f.draw = -1;
-                            a.F = dst;
-                            a.rchal = (i32)(co + rbase + k - 1);
-                        }
-                        F = dst;
-                    } else {
+                        WtArgs a;
+                        memset(&a, 0, sizeof a);
+                        a.hasC = hasC;
+                        a.npairs = 1ull << (sp - k - 1);
+                        const u64 *A, *C, *F;
+                        level(k - 1, &A, &C, &F);
+                        a.A = A;
+                        a.C = C;
                         a.F = F;
+                        level(k, &A, &C, &F);
+                        a.An = const_cast<u64 *>(A);
+                        a.Cn = const_cast<u64 *>(C);
+                        a.Fn = const_cast<u64 *>(F);
+                        const double tabs = hasC ? 3.0 : 2.0;
+                        StepDesc &st = add(ST_WT, sblocks(a.npairs), PC_OMEGA, a.npairs * tabs * (32.0 + 16));
+                        st.fin = f;
+                        st.u.wt = a;
+                        reduces(3);
                     }
-                    // algorithmic bytes per gate: index 4, weight read 8 (not at
-                    // init) and write 8 (not in the last round), the additive
-                    // operand 8 (phase 1 with ADD gates), type 1 (mixed), init:
-                    // other index 4 + operand gather 8 (phase 1); plus one pass
-                    // over the fold table (and its folded half when inline).
-                    const double per = 4.0 + (a.init ? 0 : 8) + (a.write_w ? 8 : 0) +
-                                       (ph == 1 && kind != KIND_MUL ? 8 : 0) +
-                                       (kind == KIND_MIXED ? 1 : 0) + (a.init ? 4.0 + (ph == 1 ? 8 : 0) : 0);
-                    const double nb = S * per + (a.inline_fold ? 24.0 : 8.0) * a.nfold;
-                    StepDesc &ws = add(ST_W, sblocks(std::max<u64>(S, a.inline_fold ? a.nfold : 0), 4),
-                                       PC_OMEGA, nb);
-                    ws.fin = f;
-                    ws.u.w = a;
-                    reduces(4);
+                    {
+                        Fin f = fin_of_prev(FIN_T);
+                        f.draw = (i32)(co + rbase + k0 - 1);
+                        f.msg = w ? msg + 3ull * (rbase + k0 - 1) : nullptr;
+                        WtailArgs a;
+                        memset(&a, 0, sizeof a);
+                        a.k0 = k0;
+                        a.sp = sp;
+                        a.hasC = hasC;
+                        a.last = ph;
+                        level(k0 - 1, &a.A, &a.C, &a.F);
+                        a.c0 = co + rbase + k0;
+                        a.msg = w ? msg + 3ull * (rbase + k0) : nullptr;
+                        a.vout = vslot ? vslot + (ph - 1) : nullptr;
+                        StepDesc &st = add(ST_WTAIL, 1, PC_OMEGA, 24.0 * (1ull << (sp - k0 + 1)));
+                        st.fin = f;
+                        st.u.wtail = a;
+                    }
                 }
-                Fend = F;
-            }
-            // ---- line step (a9): finish the last round, then the line tables
-            {
-                Fin f = fin_of_prev(FIN_W);
-                f.draw = (i32)(co + n - 1);
-                f.msg = w ? msg + 3ull * (n - 1) : nullptr;
-                f.last = 2;
-                f.F = Fend;
-                f.vout = vslot ? vslot + 1 : nullptr;
-                u32 Ll = 0, M = 0, H = 0;
-                if (sp >= 2) line_shape(sp, &Ll, &M, &H);
-                const u64 ntab = sp >= 2 ? (u64)(sp - 1) * ((1ull << Ll) + (1ull << M) + (1ull << H)) : 1;
+                // ---- line step (a9): every omega challenge is recorded
                 StepDesc &e = add(ST_LT, sblocks(ntab), PC_TABLES, 0);
-                e.fin = f;
-                e.u.lt = LtArgs{sp >= 2 ? sp : 1, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
+                e.u.lt = LtArgs{sp >= 2 ? sp : 0, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
                                 w ? w->lhl : nullptr, w ? w->lhh : nullptr};
-                if (sp < 2) e.u.lt.sp = 0;  // nothing to tabulate
+            } else {
+                // ---- omega-phases (a6, a7, a8)
+                const u64 *Fend = nullptr;  // table of the phase's last round
+                for (u32 ph = 1; ph <= 2; ph++) {
+                    const u32 rbase = s + (ph == 2 ? sp : 0);
+                    const u32 Lb = sp / 2;
+                    if (ph == 2) {
+                        Fin f = fin_of_prev(FIN_W);
+                        f.draw = (i32)(co + s + sp - 1);
+                        f.msg = w ? msg + 3ull * (s + sp - 1) : nullptr;
+                        f.last = 1;
+                        f.F = Fend;
+                        f.vout = vslot;
+                        StepDesc &e = add(ST_EQ, sblocks((1ull << Lb) + (1ull << (sp - Lb))), PC_TABLES, 0);
+                        e.fin = f;
+                        e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
+                    }
+                    const u64 *F = V(i + 1);
+                    u64 *fbuf[2] = {w ? w->fA : nullptr, w ? w->fB : nullptr};
+                    for (u32 k = 0; k < sp; k++) {
+                        WArgs a;
+                        memset(&a, 0, sizeof a);
+                        a.kind = kind;
+                        a.ph = ph;
+                        a.init = k == 0;
+                        a.write_w = k + 1 < sp;
+                        a.inline_fold = k > 0 && S <= INLINE_FOLD_MAX_GATES;
+                        a.S = S;
+                        a.k = k;
+                        a.nfold = 1ull << (sp - k);
+                        a.idx = ph == 1 ? c->in1[i] : c->in2[i];
+                        a.oth = ph == 1 ? c->in2[i] : c->in1[i];
+                        a.type = c->type[i];
+                        a.Vn = V(i + 1);
+                        a.alo = w ? w->alo : nullptr;
+                        a.ahi = w ? w->ahi : nullptr;
+                        a.La = s / 2;
+                        a.blo = w ? w->blo : nullptr;
+                        a.bhi = w ? w->bhi : nullptr;
+                        a.Lb = Lb;
+                        a.rchal = -1;
+                        a.w = w ? w->w : nullptr;
+                        a.off = w ? w->off : nullptr;
+                        Fin f;
+                        memset(&f, 0, sizeof f);
+                        f.kind = FIN_NONE;
+                        f.draw = -1;
+                        if (k > 0) {
+                            f = fin_of_prev(FIN_W);
+                            f.draw = (i32)(co + rbase + k - 1);
+                            f.msg = w ? msg + 3ull * (rbase + k - 1) : nullptr;
+                            u64 *dst = fbuf[k & 1];
+                            if (a.inline_fold) {
+                                a.F = F;       // F^(k-1): the kernel folds it into dst
+                                a.Fout = dst;
+                            } else {
+                                StepDesc &fs = add(ST_FOLD, sblocks(a.nfold, 4), PC_FOLD, a.nfold * 24.0);
+                                fs.fin = f;
+                                fs.u.fold = FoldArgs{a.nfold, F, dst};
+                                memset(&f, 0, sizeof f);
+                                f.kind = FIN_NONE;
+                                f.draw = -1;
+                                a.F = dst;
+                                a.rchal = (i32)(co + rbase + k - 1);
+                            }
+                            F = dst;
+                        } else {
+                            a.F = F;
+                        }
+                        // algorithmic bytes per gate: index 4, weight read 8 (not at
+                        // init) and write 8 (not in the last round), the additive
+                        // operand 8 (phase 1 with ADD gates), type 1 (mixed), init:
+                        // other index 4 + operand gather 8 (phase 1); plus one pass
+                        // over the fold table (and its folded half when inline).
+                        const double per = 4.0 + (a.init ? 0 : 8) + (a.write_w ? 8 : 0) +
+                                           (ph == 1 && kind != KIND_MUL ? 8 : 0) +
+                                           (kind == KIND_MIXED ? 1 : 0) + (a.init ? 4.0 + (ph == 1 ? 8 : 0) : 0);
+                        const double nb = S * per + (a.inline_fold ? 24.0 : 8.0) * a.nfold;
+                        StepDesc &ws = add(ST_W, sblocks(std::max<u64>(S, a.inline_fold ? a.nfold : 0), 4),
+                                           PC_OMEGA, nb);
+                        ws.fin = f;
+                        ws.u.w = a;
+                        reduces(4);
+                    }
+                    Fend = F;
+                }
+                // ---- line step (a9): finish the last round, then the line tables
+                {
+                    Fin f = fin_of_prev(FIN_W);
+                    f.draw = (i32)(co + n - 1);
+                    f.msg = w ? msg + 3ull * (n - 1) : nullptr;
+                    f.last = 2;
+                    f.F = Fend;
+                    f.vout = vslot ? vslot + 1 : nullptr;
+                    StepDesc &e = add(ST_LT, sblocks(ntab), PC_TABLES, 0);
+                    e.fin = f;
+                    e.u.lt = LtArgs{sp >= 2 ? sp : 1, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
+                                    w ? w->lhl : nullptr, w ? w->lhh : nullptr};
+                    if (sp < 2) e.u.lt.sp = 0;  // nothing to tabulate
+                }
+            }
+            {
                 memset(&layer_end, 0, sizeof layer_end);
                 layer_end.kind = FIN_LINE;
                 layer_end.draw = (i32)(co + n);
@@ -667,7 +859,20 @@ struct Planner {
 
 static int ensure_workspace(gkr_circuit *c) {
     if (c->ws) return GKR_OK;
-    Planner count{c, nullptr};
+    const u32 d = c->L - 1;
+    std::vector<HostGroup> hg;
+    if (c->omega_algo == GKR_OMEGA_TABLES) {
+        hg.resize(2 * d);
+        c->nch_max = 1;
+        for (u32 i = 0; i < d; i++) {
+            const u64 N = 1ull << c->s[i + 1];
+            build_group(c->h_in1[i], N, hg[2 * i]);
+            build_group(c->h_in2[i], N, hg[2 * i + 1]);
+            c->nch_max = std::max<u64>(c->nch_max, hg[2 * i].cstart.size());
+            c->nch_max = std::max<u64>(c->nch_max, hg[2 * i + 1].cstart.size());
+        }
+    }
+    Planner count{c, nullptr, &hg};
     count.build();
     const size_t nsteps = count.out.size();
     Workspace probe;
@@ -679,7 +884,32 @@ static int ensure_workspace(gkr_circuit *c) {
     a.base = (char *)ws->mem;
     a.cap = sz.used;
     carve(c, a, *ws, nsteps);
-    Planner plan{c, ws.get()};
+    if (c->omega_algo == GKR_OMEGA_TABLES) {
+        // upload the groupings: perm, chunk starts and per-wire chunk ranges
+        size_t bytes = 0;
+        for (auto &G : hg)
+            bytes += ((G.perm.size() * 4 + 255) & ~size_t(255)) + ((G.cstart.size() * 4 + 255) & ~size_t(255)) +
+                     ((G.xch.size() * 4 + 255) & ~size_t(255));
+        HIP_TRY(hipMalloc(&ws->gmem, std::max<size_t>(bytes, 256)));
+        char *p = (char *)ws->gmem;
+        auto put = [&](const std::vector<u32> &v, u32 **dst) -> hipError_t {
+            *dst = (u32 *)p;
+            p += (v.size() * 4 + 255) & ~size_t(255);
+            return v.empty() ? hipSuccess : hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice);
+        };
+        ws->grp[0].resize(d);
+        ws->grp[1].resize(d);
+        for (u32 i = 0; i < d; i++)
+            for (int ph = 0; ph < 2; ph++) {
+                const HostGroup &G = hg[2 * i + ph];
+                Workspace::Group &D = ws->grp[ph][i];
+                HIP_TRY(put(G.perm, &D.perm));
+                HIP_TRY(put(G.cstart, &D.cstart));
+                HIP_TRY(put(G.xch, &D.xch));
+                D.nch = (u32)G.cstart.size() - 1;
+            }
+    }
+    Planner plan{c, ws.get(), &hg};
     plan.build();
     if (plan.out.size() != nsteps) return fail(GKR_ERR_INVALID, "step program changed size");
     ws->steps = plan.out;

@@ -121,6 +121,14 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
                 if (f.last == 1) pp.state[1] = v;
             }
         }
+    } else if (f.kind == FIN_T) {
+        u64 t[3];
+        rows_total<3>(f.rows, 0, f.nrows, t);
+        if (threadIdx.x == 0) {
+            f.msg[0] = t[0];
+            f.msg[1] = t[1];
+            f.msg[2] = t[2];
+        }
     } else if (f.kind == FIN_LINE) {
         if (f.T > 0) {
             u64 t[LINE_CHUNK];
@@ -352,6 +360,259 @@ __device__ void step_line(const LineArgs &a, const Ctx &c, u64 *row) {
     block_store<LINE_CHUNK>(acc, row);
 }
 
+// ------------------------------------------- omega phases over tables
+//
+// Grouping the gates of an omega phase by the wire x they bind, the
+// per-gate terms w_g eq(bit_k(x), t) (F(t) + off_g) of round k sum to
+//   G_k(t) = sum_m A_k(t, m) F_k(t, m) + C_k(t, m),
+// with A_0[x] = sum of w_g over the gates on x, C_0[x] = sum of w_g off_g,
+// and A_k, C_k, F_k the folds of A_0, C_0 and V_{i+1} by the phase's first
+// k challenges (all three are multilinear in the bound bits).  The gates are
+// read once per phase instead of once per round.
+
+__device__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp, const Ctx &c) {
+    const u64 beta = pp.state[0];  // beta(z, a*)
+    const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
+    for (u64 ch = c.gtid; ch < a.nch; ch += c.gstride) {
+        const u32 p0 = a.cstart[ch], p1 = a.cstart[ch + 1];
+        u64 sA = 0, sC = 0;
+        for (u32 p = p0; p < p1; p++) {
+            const u32 g = a.perm[p];
+            const bool ismul = a.kind == 1 || (a.kind == 2 && a.type[g]);
+            u64 w = mul(beta, mul(a.alo[g & amask], a.ahi[g >> a.La]));
+            if (a.ph == 1) {
+                // MUL: w V[in2] on the wire's value; ADD: w on it, w V[in2] added
+                const u64 y = a.Vn[a.oth[g]];
+                const u64 wy = mul(w, y);
+                if (ismul) {
+                    sA = add(sA, wy);
+                } else {
+                    sA = add(sA, w);
+                    sC = add(sC, wy);
+                }
+            } else {
+                const u32 i1 = a.oth[g];
+                w = mul(w, mul(a.blo[i1 & bmask], a.bhi[i1 >> a.Lb]));
+                // sums over ADD gates (sA) and MUL gates (sC); v1 enters in WT0
+                if (ismul)
+                    sC = add(sC, w);
+                else
+                    sA = add(sA, w);
+            }
+        }
+        a.partA[ch] = sA;
+        a.partC[ch] = sC;
+    }
+}
+
+// Message sums of one pair of a table round.
+__device__ __forceinline__ void table_terms(u64 A0, u64 A1, u64 C0, u64 C1, u64 F0, u64 F1,
+                                            u64 (&acc)[3]) {
+    const u64 A2 = sub(add(A1, A1), A0), F2 = sub(add(F1, F1), F0), C2 = sub(add(C1, C1), C0);
+    acc[0] = add(acc[0], add(mul(A0, F0), C0));
+    acc[1] = add(acc[1], add(mul(A1, F1), C1));
+    acc[2] = add(acc[2], add(mul(A2, F2), C2));
+}
+
+__device__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
+    const u64 v1 = a.ph == 2 ? pp.state[1] : 0;
+    u64 acc[3] = {0, 0, 0};
+    for (u64 m = c.gtid; m < a.npairs; m += c.gstride) {
+        u64 A[2], C[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const u64 x = 2 * m + h;
+            u64 sA = 0, sC = 0;
+            for (u32 ch = a.xch[x]; ch < a.xch[x + 1]; ch++) {
+                sA = add(sA, a.partA[ch]);
+                sC = add(sC, a.partC[ch]);
+            }
+            if (a.ph == 2) {
+                // ADD gates: w (v1 + G(t)); MUL gates: w v1 G(t)
+                A[h] = add(sA, mul(v1, sC));
+                C[h] = mul(v1, sA);
+            } else {
+                A[h] = sA;
+                C[h] = sC;
+            }
+        }
+        st2(a.A, 2 * m, A[0], A[1]);
+        if (a.hasC) st2(a.C, 2 * m, C[0], C[1]);
+        const u64x2 f = ld2(a.F, 2 * m);
+        table_terms(A[0], A[1], a.hasC ? C[0] : 0, a.hasC ? C[1] : 0, f.x, f.y, acc);
+    }
+    block_store<3>(acc, row);
+}
+
+__device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
+    const u64 r = c.r;
+    u64 acc[3] = {0, 0, 0};
+    for (u64 m = c.gtid; m < a.npairs; m += c.gstride) {
+        const u64x2 a0 = ld2(a.A, 4 * m), a1 = ld2(a.A, 4 * m + 2);
+        const u64x2 f0 = ld2(a.F, 4 * m), f1 = ld2(a.F, 4 * m + 2);
+        const u64 A0 = add(a0.x, mul(r, sub(a0.y, a0.x))), A1 = add(a1.x, mul(r, sub(a1.y, a1.x)));
+        const u64 F0 = add(f0.x, mul(r, sub(f0.y, f0.x))), F1 = add(f1.x, mul(r, sub(f1.y, f1.x)));
+        st2(a.An, 2 * m, A0, A1);
+        st2(a.Fn, 2 * m, F0, F1);
+        u64 C0 = 0, C1 = 0;
+        if (a.hasC) {
+            const u64x2 c0 = ld2(a.C, 4 * m), c1 = ld2(a.C, 4 * m + 2);
+            C0 = add(c0.x, mul(r, sub(c0.y, c0.x)));
+            C1 = add(c1.x, mul(r, sub(c1.y, c1.x)));
+            st2(a.Cn, 2 * m, C0, C1);
+        }
+        table_terms(A0, A1, C0, C1, F0, F1, acc);
+    }
+    block_store<3>(acc, row);
+}
+
+// Sum three values over the workgroup; every thread gets the totals.
+__device__ __forceinline__ void block_total3(u64 (&v)[3]) {
+    __shared__ u64 res[3];
+    block_store<3>(v, res);
+    v[0] = res[0];
+    v[1] = res[1];
+    v[2] = res[2];
+    __syncthreads();
+}
+
+// Remaining omega rounds k0..s'-1 in one workgroup, tables in LDS.  The
+// prologue drew r_{k0-1}; each round's message is written before its
+// challenge is drawn, and after the last fold F holds v1 (or v2).
+__device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx &c) {
+    __shared__ u64 tA[TAIL_LIM], tC[TAIL_LIM], tF[TAIL_LIM];
+    __shared__ u64 s_r2;
+    u32 M = 1u << (a.sp - a.k0);
+    {
+        const u64 r = c.r;
+        for (u32 x = threadIdx.x; x < M; x += SBLOCK) {
+            const u64x2 pa = ld2(a.A, 2 * x), pf = ld2(a.F, 2 * x);
+            tA[x] = add(pa.x, mul(r, sub(pa.y, pa.x)));
+            tF[x] = add(pf.x, mul(r, sub(pf.y, pf.x)));
+            if (a.hasC) {
+                const u64x2 pc = ld2(a.C, 2 * x);
+                tC[x] = add(pc.x, mul(r, sub(pc.y, pc.x)));
+            } else {
+                tC[x] = 0;
+            }
+        }
+    }
+    u64 st = 0;
+    if (threadIdx.x == 0) st = pp.rngst[a.c0];
+    __syncthreads();
+    for (u32 k = a.k0; k < a.sp; k++) {
+        u64 acc[3] = {0, 0, 0};
+        for (u32 m = threadIdx.x; m < M / 2; m += SBLOCK)
+            table_terms(tA[2 * m], tA[2 * m + 1], tC[2 * m], tC[2 * m + 1], tF[2 * m], tF[2 * m + 1], acc);
+        block_total3(acc);
+        if (threadIdx.x == 0) {
+            u64 *msg = a.msg + 3ull * (k - a.k0);
+            msg[0] = acc[0];
+            msg[1] = acc[1];
+            msg[2] = acc[2];
+            const u32 ci = a.c0 + (k - a.k0);
+            const u64 r = fp::sm_field(st);
+            pp.chals[ci] = r;
+            pp.rngst[ci + 1] = st;
+            s_r2 = r;
+        }
+        __syncthreads();
+        const u64 r = s_r2;
+        M /= 2;
+        u64 nA[TAIL_LIM / SBLOCK], nC[TAIL_LIM / SBLOCK], nF[TAIL_LIM / SBLOCK];
+#pragma unroll
+        for (int q = 0; q < TAIL_LIM / SBLOCK; q++) {
+            const u32 x = threadIdx.x + q * SBLOCK;
+            if (x < M) {
+                nA[q] = add(tA[2 * x], mul(r, sub(tA[2 * x + 1], tA[2 * x])));
+                nC[q] = add(tC[2 * x], mul(r, sub(tC[2 * x + 1], tC[2 * x])));
+                nF[q] = add(tF[2 * x], mul(r, sub(tF[2 * x + 1], tF[2 * x])));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TAIL_LIM / SBLOCK; q++) {
+            const u32 x = threadIdx.x + q * SBLOCK;
+            if (x < M) {
+                tA[x] = nA[q];
+                tC[x] = nC[q];
+                tF[x] = nF[q];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const u64 v = tF[0];
+        *a.vout = v;
+        if (a.last == 1) pp.state[1] = v;
+    }
+}
+
+// Remaining p-phase rounds j0..s-1 in one workgroup.  The prologue drew
+// r_{j0-1} and folded its message into the beta prefix C = state[0].
+__device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx &c) {
+    __shared__ u64 tV[TAIL_LIM], tB[TAIL_LIM / 2];
+    __shared__ u64 s_r2;
+    u32 M = 1u << (a.s - a.j0);  // entries of V^(j0)
+    {
+        const u64 r = c.r;
+        for (u32 x = threadIdx.x; x < M; x += SBLOCK) {
+            const u64x2 pv = ld2(a.V, 2 * x);
+            tV[x] = add(pv.x, mul(r, sub(pv.y, pv.x)));
+        }
+        for (u32 x = threadIdx.x; x < M / 2; x += SBLOCK) {
+            const u64x2 pb = ld2(a.B, 2 * x);
+            tB[x] = add(pb.x, pb.y);  // B_{j0}: the coordinate j0 summed out
+        }
+    }
+    u64 st = 0, C = 0;
+    if (threadIdx.x == 0) {
+        st = pp.rngst[a.c0];
+        C = pp.state[0];
+    }
+    __syncthreads();
+    for (u32 j = a.j0; j < a.s; j++) {
+        u64 acc[3] = {0, 0, 0};
+        for (u32 m = threadIdx.x; m < M / 2; m += SBLOCK) {
+            acc[0] = add(acc[0], mul(tB[m], tV[2 * m]));
+            acc[1] = add(acc[1], mul(tB[m], tV[2 * m + 1]));
+        }
+        block_total3(acc);
+        if (threadIdx.x == 0) {
+            const u64 z = pp.zbuf[j], S0 = acc[0], S1 = acc[1];
+            u64 *msg = a.msg + 3ull * (j - a.j0);
+            msg[0] = mul(mul(C, sub(1, z)), S0);
+            msg[1] = mul(mul(C, z), S1);
+            msg[2] = mul(mul(C, sub(add(add(z, z), z), 1)), sub(add(S1, S1), S0));
+            const u32 ci = a.c0 + (j - a.j0);
+            const u64 r = fp::sm_field(st);
+            pp.chals[ci] = r;
+            pp.rngst[ci + 1] = st;
+            C = mul(C, fp::eq(z, r));
+            s_r2 = r;
+        }
+        __syncthreads();
+        const u64 r = s_r2;
+        M /= 2;
+        u64 nV[TAIL_LIM / SBLOCK], nB[TAIL_LIM / SBLOCK];
+#pragma unroll
+        for (int q = 0; q < TAIL_LIM / SBLOCK; q++) {
+            const u32 x = threadIdx.x + q * SBLOCK;
+            if (x < M) nV[q] = add(tV[2 * x], mul(r, sub(tV[2 * x + 1], tV[2 * x])));
+            if (x < M / 2) nB[q] = add(tB[2 * x], tB[2 * x + 1]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TAIL_LIM / SBLOCK; q++) {
+            const u32 x = threadIdx.x + q * SBLOCK;
+            if (x < M) tV[x] = nV[q];
+            if (x < M / 2) tB[x] = nB[q];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) pp.state[0] = C;  // beta(z, a*)
+}
+
 // ---------------------------------------------------------------- kernel
 
 // One step on workgroup lb.  Workgroups [0, nblocks) run the body; a step
@@ -371,9 +632,11 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     c.gstride = (u64)c.nb * SBLOCK;
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
+    const u32 kind = KIND == KALL ? sd.kind : KIND;
+    const bool tail = kind == ST_WTAIL || kind == ST_PTAIL;  // one workgroup does everything
     const bool has_fin = f.kind != FIN_NONE;
-    const bool fin_block = has_fin && lb == sd.nblocks;
-    const bool recorder = has_fin ? fin_block : lb == 0;
+    const bool fin_block = has_fin && !tail && lb == sd.nblocks;
+    const bool recorder = (has_fin && !tail) ? fin_block : lb == 0;
 
     // --- prologue: the challenge (every workgroup draws the same value)
     if (threadIdx.x == 0) {
@@ -396,7 +659,6 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         const u64 bb = f.bstar[threadIdx.x], cc = f.cstar[threadIdx.x];
         s_pt[threadIdx.x] = add(bb, mul(c.r, sub(cc, bb)));  // z_{i+1} = l(tau)
     }
-    const u32 kind = KIND == KALL ? sd.kind : KIND;
     if (kind == ST_EQ && sd.u.eq.point == PT_Z && f.kind != FIN_LINE &&
         threadIdx.x < sd.u.eq.base + sd.u.eq.n)
         s_pt[threadIdx.x] = pp.zbuf[threadIdx.x];  // z of the layer, already recorded
@@ -415,6 +677,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         finalize(sd, c, s_pt);
         return;
     }
+    if (tail && has_fin) finalize(sd, c, s_pt);
 
     // --- body
     u64 *row = sd.rows ? sd.rows + (u64)c.lb * ROW_STRIDE : nullptr;
@@ -443,6 +706,11 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_FOLD: step_fold(sd.u.fold, c); break;
         case ST_LT: step_lt(sd.u.lt, c, s_pt, s_pt + sd.u.lt.sp); break;
         case ST_LINE: step_line(sd.u.line, c, row); break;
+        case ST_WAGG: step_wagg(sd.u.wagg, pp, c); break;
+        case ST_WT0: step_wt0(sd.u.wt0, pp, c, row); break;
+        case ST_WT: step_wt(sd.u.wt, c, row); break;
+        case ST_WTAIL: step_wtail(sd.u.wtail, pp, c); break;
+        case ST_PTAIL: step_ptail(sd.u.ptail, pp, c); break;
         case ST_SGE:
             if (c.lb == 0 && threadIdx.x == 0) {
                 const u64 v = sd.u.sge.Vn[0];
@@ -474,7 +742,10 @@ __global__ void __launch_bounds__(SBLOCK) k_step_jobs(const JobEntry *__restrict
     run_step<KALL, -1, 0>(*jobs[lo].step, b - jobs[lo].block0);
 }
 
-u32 step_grid(const StepDesc &sd) { return sd.nblocks + (sd.fin.kind != FIN_NONE ? 1 : 0); }
+u32 step_grid(const StepDesc &sd) {
+    if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL) return 1;
+    return sd.nblocks + (sd.fin.kind != FIN_NONE ? 1 : 0);
+}
 
 hipError_t launch_step(hipStream_t st, const StepDesc &sd) {
     const dim3 g(step_grid(sd)), b(SBLOCK);
@@ -496,6 +767,11 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd) {
         case ST_LT: L1(ST_LT); break;
         case ST_LINE: L1(ST_LINE); break;
         case ST_SGE: L1(ST_SGE); break;
+        case ST_WAGG: L1(ST_WAGG); break;
+        case ST_WT0: L1(ST_WT0); break;
+        case ST_WT: L1(ST_WT); break;
+        case ST_WTAIL: L1(ST_WTAIL); break;
+        case ST_PTAIL: L1(ST_PTAIL); break;
         default: L1(ST_END); break;
     }
 #undef L1

@@ -43,6 +43,11 @@ enum StepKind : u32 {
     ST_LINE,       // line sums h(t), t = 2..s'
     ST_SGE,        // next layer has one gate: v1 = v2 = V_{i+1}[0]
     ST_END,        // nothing but the prologue
+    ST_WAGG,       // omega phase, tables: per-gate weights summed by bound wire
+    ST_WT0,        // omega phase, tables: level-0 tables and round 0
+    ST_WT,         // omega phase, tables: round k >= 1 (fold, then sum)
+    ST_WTAIL,      // omega phase, tables: remaining rounds in one workgroup
+    ST_PTAIL,      // p-phase: remaining rounds in one workgroup
 };
 
 enum FinKind : u32 {
@@ -50,7 +55,12 @@ enum FinKind : u32 {
     FIN_P,     // p-phase message from rows of (S0, S1)
     FIN_W,     // omega message from rows of (E0, E1, O0, O1)
     FIN_LINE,  // h(t) values from rows of line sums; then tau and z_{i+1}
+    FIN_T,     // message (G(0), G(1), G(2)) from rows of three sums
 };
+
+// Largest table (entries at the level a tail starts from, after its fold)
+// that a one-workgroup tail keeps in LDS.
+constexpr int TAIL_LIM = 1024;
 
 // The point the ST_EQ step expands, assembled in LDS by each workgroup.
 enum PointKind : u32 {
@@ -146,6 +156,49 @@ struct SgeArgs {
     const u64 *Vn;
     u64 *vslot;
 };
+// Tables of an omega phase: A[x] (weights) and C[x] (additive part) over
+// the bound wire x, with F the fold of V_{i+1}:
+//   G_k(t) = sum_m A_k(t, m) F_k(t, m) + C_k(t, m).
+struct WaggArgs {
+    u32 kind, ph;
+    u32 nch;                 // chunks: perm[cstart[ch] .. cstart[ch+1]) share one wire x
+    const u32 *perm, *cstart;
+    const u32 *oth;          // other wire (ph 1: in2; ph 2: in1)
+    const u8 *type;
+    const u64 *Vn;
+    const u64 *alo, *ahi;
+    u32 La;
+    const u64 *blo, *bhi;
+    u32 Lb;
+    u64 *partA, *partC;      // per chunk (ph 2: sums over ADD / MUL gates)
+};
+struct Wt0Args {
+    u32 ph, hasC;
+    u64 npairs;
+    const u32 *xch;          // chunks of wire x: [xch[x], xch[x+1])
+    const u64 *partA, *partC;
+    const u64 *F;            // V_{i+1}
+    u64 *A, *C;              // level-0 tables
+};
+struct WtArgs {
+    u32 hasC;
+    u64 npairs;              // pairs of level k (tables of level k-1 have 4 npairs)
+    const u64 *A, *C, *F;    // level k-1
+    u64 *An, *Cn, *Fn;       // level k
+};
+struct WtailArgs {
+    u32 k0, sp, hasC, last;
+    const u64 *A, *C, *F;    // level k0-1, 2^{sp-k0+1} entries
+    u32 c0;                  // challenge index of round k0
+    u64 *msg;                // message slot of round k0
+    u64 *vout;
+};
+struct PtailArgs {
+    u32 j0, s;
+    const u64 *V, *B;        // V^(j0-1) (2^{s-j0+1}) and B_{j0-1} (2^{s-j0})
+    u32 c0;                  // challenge index of round j0
+    u64 *msg;                // message slot of round j0
+};
 
 struct StepDesc {
     u32 kind;
@@ -165,6 +218,11 @@ struct StepDesc {
         LtArgs lt;
         LineArgs line;
         SgeArgs sge;
+        WaggArgs wagg;
+        Wt0Args wt0;
+        WtArgs wt;
+        WtailArgs wtail;
+        PtailArgs ptail;
     } u;
 };
 

@@ -35,18 +35,25 @@ def random_circuit(rng, sizes, kinds=None):
     return Circuit(list(sizes), types, in1, in2, name=f"rand {sizes}")
 
 
-def check_same(circ, x, seed, name, device_inputs=False):
+def check_same(circ, x, seed, name, device_inputs=False, algos=(1, 0)):
+    """Both omega-phase algorithms (tables, then per-gate rounds) against the
+    oracle; returns the circuit handle (tables) and its transcript."""
     say(name, "gates", circ.gates, "seed", seed)
     O.set_threads(oracle_threads())
     want_m, want_c = O.prove(circ, x, seed)
-    gc = G().Circuit.from_workload(circ)
     inp = device_tensor(x) if device_inputs else x
-    got_m, got_c = G().gkr_prove(gc, inp, seed)
-    assert len(got_m) == len(want_m) and len(got_c) == len(want_c)
-    bad = np.nonzero(got_m != want_m)[0]
-    assert len(bad) == 0, f"{name}: first differing msg {bad[:5]} of {len(want_m)}"
-    assert np.array_equal(got_c, want_c), name
-    return gc, got_m
+    first = None
+    for algo in algos:
+        say(name, "omega algorithm", algo)
+        gc = G().Circuit.from_workload(circ, omega_algo=algo)
+        got_m, got_c = G().gkr_prove(gc, inp, seed)
+        assert len(got_m) == len(want_m) and len(got_c) == len(want_c)
+        bad = np.nonzero(got_m != want_m)[0]
+        assert len(bad) == 0, f"{name} algo {algo}: first differing msg {bad[:5]} of {len(want_m)}"
+        assert np.array_equal(got_c, want_c), name
+        if first is None:
+            first = (gc, got_m)
+    return first
 
 
 TINY = [[1, 1], [1, 2], [2, 1], [3, 5], [1, 2, 3], [3, 4, 4], [2, 3, 5], [1, 2, 2, 4],
