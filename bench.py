@@ -62,6 +62,125 @@ def cpu_baseline(log_n):
                       f"({circ.gates} gates, seed 2) in {dt:.2f} s"}
 
 
+def batch_leg(G, W, np, torch, reps):
+    """64 uneven proofs (F2 n log-uniform in [2^12, 2^20], PM text in
+    [2^14, 2^18], seed 4): the plain path proves them one by one, the
+    batched path in one launch per step (graph replay).  Both must give the
+    same transcripts."""
+    mix = W.batch_mix(4, 64)
+    circs = [G.Circuit.from_workload(c) for _, c, _, _ in mix]
+    xs = [torch.from_numpy(x.view(np.int64)).cuda().view(torch.uint64) for _, _, x, _ in mix]
+    seeds = [sd for _, _, _, sd in mix]
+    gates = sum(c.gates for c in circs)
+    plain = [G.gkr_prove(c, x, sd, want_chals=False)[0] for c, x, sd in zip(circs, xs, seeds)]
+    batched = G.gkr_batch_prove(circs, xs, seeds)
+    same = all(np.array_equal(a, b) for a, b in zip(plain, batched))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        for c, x, sd in zip(circs, xs, seeds):
+            G.gkr_prove(c, x, sd, want_chals=False)
+    t_plain = (time.perf_counter() - t) / reps
+    t = time.perf_counter()
+    for _ in range(reps):
+        G.gkr_batch_prove(circs, xs, seeds)
+    t_batch = (time.perf_counter() - t) / reps
+    return {"workload": "64 uneven proofs: F2 n=2^[12,20], PM text 2^[14,18] (seed 4)",
+            "proofs": len(circs), "gates": gates, "bit_exact_batched_vs_plain": same,
+            "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
+            "plain_gates_per_s": gates / t_plain, "batched_gates_per_s": gates / t_batch,
+            "batched_proofs_per_s": len(circs) / t_batch, "speedup": t_plain / t_batch}
+
+
+def serve_leg(G, W, np, n_req, rates):
+    """Poisson proof requests (seed 5): type uniform over F2 (n = 2^u, u an
+    integer uniform in [14, 22]), MatMult (N in {64, 128, 256}) and PM (text
+    2^16, pattern 8).  Circuits are registered once per shape, as a service
+    would.  First the closed-loop saturation rate, then open-loop arrivals at
+    fractions of it; latency runs from the scheduled arrival to completion."""
+    draws = W.splitmix64(5, 5, 4 * (n_req * (1 + len(rates)) + 8))
+    shapes = {}
+
+    def shape(kind, size):
+        key = (kind, size)
+        if key not in shapes:
+            if kind == "F2":
+                c, x = W.f2_circuit(size), W.f2_inputs(size, 50 + size)
+            elif kind == "MM":
+                c, x = W.matmult_circuit(size), W.matmult_inputs(size, 50 + size)
+            else:
+                c, x = W.pm_circuit(size), W.pm_inputs(size, 50 + size)[0]
+            shapes[key] = (G.Circuit.from_workload(c), x, c.gates)
+        return shapes[key]
+
+    def request(k):
+        u = int(draws[4 * k] % np.uint64(3))
+        if u == 0:
+            kind, size = "F2", 1 << (14 + int(draws[4 * k + 1] % np.uint64(9)))
+        elif u == 1:
+            kind, size = "MM", (64, 128, 256)[int(draws[4 * k + 1] % np.uint64(3))]
+        else:
+            kind, size = "PM", 1 << 16
+        gap = -np.log(1.0 - float(draws[4 * k + 2] >> np.uint64(11)) / float(1 << 53))
+        return kind, size, int(draws[4 * k + 3] >> np.uint64(8)), gap
+
+    reqs = [request(k) for k in range(n_req * (1 + len(rates)))]
+    for kind, size, _, _ in reqs:
+        shape(kind, size)
+    srv = G.Server(32 << 30, 32)
+    try:
+        # warm every shape's scratch pool
+        ids = [srv.submit(shape(k, sz)[0], shape(k, sz)[1], 1) for (k, sz) in list(shapes)]
+        while ids:
+            ids = [r for r in ids if not srv.poll(r)[0]]
+        # closed loop: all requests at once
+        batch = reqs[:n_req]
+        t0 = time.perf_counter()
+        ids = [srv.submit(shape(k, sz)[0], shape(k, sz)[1], sd) for k, sz, sd, _ in batch]
+        pending = set(ids)
+        while pending:
+            pending = {r for r in pending if not srv.poll(r)[0]}
+        sat = n_req / (time.perf_counter() - t0)
+        points = []
+        for pi, frac in enumerate(rates):
+            rate = frac * sat
+            part = reqs[n_req * (pi + 1): n_req * (pi + 2)]
+            arrivals = np.cumsum([gap / rate for _, _, _, gap in part])
+            t0 = time.perf_counter()
+            sched, lats, ids = {}, [], []
+            k = 0
+            pending = set()
+            gates = 0
+            while k < len(part) or pending:
+                now = time.perf_counter() - t0
+                while k < len(part) and arrivals[k] <= now:
+                    kind, sz, sd, _ = part[k]
+                    c, x, g = shape(kind, sz)
+                    rid = srv.submit(c, x, sd)
+                    sched[rid] = arrivals[k]
+                    gates += g
+                    pending.add(rid)
+                    k += 1
+                for rid in list(pending):
+                    done, _, _ = srv.poll(rid)
+                    if done:
+                        lats.append(time.perf_counter() - t0 - sched[rid])
+                        pending.discard(rid)
+                if k < len(part) and not pending:
+                    time.sleep(max(0.0, min(0.001, arrivals[k] - (time.perf_counter() - t0))))
+            span = time.perf_counter() - t0
+            lats.sort()
+            points.append({"rate_frac_of_saturation": frac, "offered_proofs_per_s": rate,
+                           "proofs_per_s": len(part) / span, "gates_per_s": gates / span,
+                           "p50_ms": 1e3 * lats[len(lats) // 2],
+                           "p99_ms": 1e3 * lats[min(len(lats) - 1, int(0.99 * len(lats)))]})
+    finally:
+        srv.close()
+    return {"workload": "Poisson mix of F2 n=2^[14..22], MatMult N in {64,128,256}, "
+                        "PM text 2^16 (seed 5); 32 slots, 32 GiB budget",
+            "requests_per_point": n_req, "closed_loop_proofs_per_s": sat, "points": points}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +190,9 @@ def main():
     ap.add_argument("--f2sc-log-n", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-log-n", type=int, default=22)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=120)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -162,6 +284,10 @@ def main():
                      "avg_launch_us": ms * 1e3 / launches if launches else None,
                      "traffic": traffic},
     }
+    if not args.no_batch:
+        line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2))
+    if not args.no_serve:
+        line["served"] = serve_leg(G, W, np, args.serve_requests, [0.25, 0.5, 0.9, 1.2])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_log_n)
     print(json.dumps(line), flush=True)

@@ -136,6 +136,47 @@ int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inputs_on_devic
                const uint64_t *msgs, uint64_t n_msgs, int *accepted, gkr_reject_info *why,
                void *hip_stream);
 
+/* Batched proving: n proofs advance together, one launch per step running
+ * that step of every proof still going (one workgroup range per proof), so a
+ * batch costs as many launches as its longest proof has steps.  With
+ * GKR_BATCH_GRAPH the launch sequence is captured once as a HIP graph and
+ * replayed by later calls over the same circuits.  Each proof's transcript is
+ * bit for bit the one gkr_prove returns for the same circuit, inputs and seed.
+ *   circuits  n handles (a handle may repeat); inputs: n device pointers of
+ *             S_d values (inputs_on_device must be 1); seeds: n seeds;
+ *   msgs      n host arrays of each circuit's n_msgs values.
+ * The plan (scratch per entry, schedule, graph) of the last few distinct
+ * circuit lists is cached; destroying a circuit drops the plans using it.
+ * Errors: GKR_ERR_INVALID, GKR_ERR_RANGE, GKR_ERR_NOMEM, GKR_ERR_DEVICE. */
+enum { GKR_BATCH_GRAPH = 1 };
+int gkr_batch_prove(uint32_t n, const gkr_circuit *const *circuits, const uint64_t *const *inputs,
+                    int inputs_on_device, const uint64_t *seeds, uint64_t *const *msgs, int flags,
+                    void *hip_stream);
+
+/* Serving: a proof server with continuous batching.  A scheduler thread
+ * keeps up to max_slots proofs in flight; every launch runs the next step of
+ * each of them, so requests that arrive while others run join at the next
+ * launch.  A request is admitted when a slot is free and its device scratch
+ * fits hbm_budget_bytes (idle scratch is pooled per circuit and reused).
+ * Results are bit for bit those of gkr_prove.
+ *   gkr_server_create   max_slots in [1, 127].
+ *   gkr_server_submit   copies the S_d host inputs (each < p); the circuit
+ *                       must outlive the request.  *req_id identifies it.
+ *   gkr_server_poll     *done = 1 once finished; then copies the transcript
+ *                       into msgs (n_msgs values, may be NULL), sets
+ *                       *latency_s (submission to completion) and forgets
+ *                       the request.
+ *   gkr_server_stats    proofs in flight, queued requests, scratch bytes held.
+ *   gkr_server_destroy  waits for the scheduler; pending requests are dropped.
+ * Errors: GKR_ERR_INVALID, GKR_ERR_RANGE, GKR_ERR_NOMEM, GKR_ERR_DEVICE. */
+typedef struct gkr_server gkr_server;
+int gkr_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, gkr_server **out);
+int gkr_server_submit(gkr_server *s, const gkr_circuit *c, const uint64_t *inputs, uint64_t seed,
+                      uint64_t *req_id);
+int gkr_server_poll(gkr_server *s, uint64_t req_id, uint64_t *msgs, int *done, double *latency_s);
+int gkr_server_stats(gkr_server *s, uint32_t *running, uint32_t *queued, uint64_t *hbm_used);
+void gkr_server_destroy(gkr_server *s);
+
 /* Sum-check for F2 = sum_x ~a(x)^2 over {0,1}^l, n = 2^l (the sum-check
  * primitive, Sec. 6, on the second frequency moment of Sec. 2.3).
  *   freq   n uint32 values (device or host); n a power of two, n <= 2^32.

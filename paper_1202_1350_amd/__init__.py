@@ -17,6 +17,7 @@ P = (1 << 61) - 1
 GKR_OK, GKR_ERR_INVALID, GKR_ERR_RANGE, GKR_ERR_NOMEM, GKR_ERR_DEVICE, GKR_ERR_BUFSIZE = \
     0, -1, -2, -3, -4, -5
 GKR_OMEGA_GATES, GKR_OMEGA_TABLES = 0, 1
+GKR_BATCH_GRAPH = 1
 CHECKS = {1: "malformed", 2: "round", 3: "wiring", 4: "line", 5: "input"}
 
 
@@ -50,6 +51,16 @@ _SIGS = [
     ("f2_sumcheck_verify", C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_uint64, C.c_void_p,
                                      C.c_uint64, C.POINTER(C.c_int), C.POINTER(RejectInfo),
                                      C.c_void_p]),
+    ("gkr_batch_prove", C.c_int, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                  C.c_void_p, C.c_int, C.c_void_p]),
+    ("gkr_server_create", C.c_int, [C.c_uint64, C.c_uint32, C.POINTER(C.c_void_p)]),
+    ("gkr_server_submit", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                    C.POINTER(C.c_uint64)]),
+    ("gkr_server_poll", C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_int),
+                                  C.POINTER(C.c_double)]),
+    ("gkr_server_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                   C.POINTER(C.c_uint64)]),
+    ("gkr_server_destroy", None, [C.c_void_p]),
     ("gkr_field_op", C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
                                C.c_void_p]),
     ("gkr_profile_enable", C.c_int, [C.c_int]),
@@ -180,6 +191,74 @@ def gkr_verify(circ: Circuit, inputs, seed: int, msgs, stream=None):
     _check(lib().gkr_verify(circ.handle, p, dev, seed, m.ctypes.data if len(m) else None, len(m),
                             C.byref(acc), C.byref(why), _stream(dev, stream)))
     return bool(acc.value), why.layer, why.round, why.check
+
+
+def gkr_batch_prove(circs, inputs, seeds, graph: bool = True, stream=None):
+    """Prove len(circs) proofs together; inputs are device tensors (uint64).
+    Returns the list of transcripts."""
+    n = len(circs)
+    if n == 0:
+        return []
+    keep = [_ptr(x, np.uint64) for x in inputs]
+    if not all(dev for _, dev, _ in keep):
+        raise TypeError("batched inputs must be device tensors")
+    hs = (C.c_void_p * n)(*[c.handle.value for c in circs])
+    ins = (C.c_void_p * n)(*[p for p, _, _ in keep])
+    sd = np.ascontiguousarray(seeds, np.uint64)
+    outs = [np.zeros(max(c.n_msgs, 1), np.uint64) for c in circs]
+    ms = (C.c_void_p * n)(*[o.ctypes.data for o in outs])
+    _check(lib().gkr_batch_prove(n, C.cast(hs, C.c_void_p), C.cast(ins, C.c_void_p), 1,
+                                 sd.ctypes.data, C.cast(ms, C.c_void_p),
+                                 GKR_BATCH_GRAPH if graph else 0, _stream(1, stream)))
+    return [o[:c.n_msgs] for o, c in zip(outs, circs)]
+
+
+class Server:
+    """Continuous-batching proof server (gkr_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int):
+        h = C.c_void_p()
+        _check(lib().gkr_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        self.handle = h
+        self._circ = {}
+
+    def submit(self, circ: Circuit, inputs, seed: int) -> int:
+        x = np.ascontiguousarray(inputs, np.uint64)
+        rid = C.c_uint64()
+        _check(lib().gkr_server_submit(self.handle, circ.handle, x.ctypes.data, int(seed),
+                                       C.byref(rid)))
+        self._circ[rid.value] = circ
+        return rid.value
+
+    def poll(self, rid: int):
+        """(done, msgs or None, latency_s); raises on a failed request."""
+        circ = self._circ[rid]
+        out = np.zeros(max(circ.n_msgs, 1), np.uint64)
+        done, lat = C.c_int(), C.c_double()
+        try:
+            _check(lib().gkr_server_poll(self.handle, rid, out.ctypes.data, C.byref(done),
+                                         C.byref(lat)))
+        except GkrError:
+            self._circ.pop(rid, None)
+            raise
+        if not done.value:
+            return False, None, None
+        self._circ.pop(rid, None)
+        return True, out[:circ.n_msgs], lat.value
+
+    def stats(self):
+        r, q, u = C.c_uint32(), C.c_uint32(), C.c_uint64()
+        _check(lib().gkr_server_stats(self.handle, C.byref(r), C.byref(q), C.byref(u)))
+        return r.value, q.value, u.value
+
+    def close(self):
+        if self.handle:
+            lib().gkr_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            self.close()
 
 
 def f2_sumcheck_prove(freq, seed: int, stream=None):

@@ -11,6 +11,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -50,10 +55,11 @@ namespace {
 
 enum ProfClass {
     PC_EVAL, PC_PPHASE, PC_OMEGA, PC_FOLD, PC_FINAL, PC_LINE, PC_TABLES, PC_WIRING, PC_MLE,
-    PC_F2SC, PC_MISC, PC_COUNT
+    PC_F2SC, PC_MISC, PC_BATCH, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {"eval", "pphase", "omega", "fold", "final", "line",
-                                    "eq_tables", "wiring", "mle", "f2sc_round", "misc"};
+                                    "eq_tables", "wiring", "mle", "f2sc_round", "misc",
+                                    "batch_step"};
 
 struct ProfRec {
     int cls;
@@ -81,6 +87,19 @@ struct Profiler {
         return e;
     }
 } g_prof;
+
+// Events timing one dispatch when profiling is on (NULL otherwise); the
+// record is kept for gkr_profile_read.
+bool prof_pair(int cls, double bytes, hipEvent_t *a, hipEvent_t *b) {
+    *a = *b = nullptr;
+    if (!g_prof.on) return false;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    *a = g_prof.get();
+    *b = g_prof.get();
+    if (!*a || !*b) return false;
+    g_prof.recs.push_back({cls, *a, *b, bytes});
+    return true;
+}
 
 // Brackets one launch with events when profiling is on.
 struct Scope {
@@ -218,19 +237,14 @@ struct Workspace {
     u32 *flag;
     // omega phases over tables
     u64 *tA0, *tC0, *tA[2], *tC[2], *partA, *partC;
-    struct Group {  // gates of a layer grouped by the wire a phase binds
-        u32 *perm = nullptr, *cstart = nullptr, *xch = nullptr;
-        u32 nch = 0;
-    };
-    std::vector<Group> grp[2];  // [phase - 1][layer]
-    void *gmem = nullptr;       // device memory of the groups
     StepDesc *d_steps;
     JobEntry *d_jobs;
     std::vector<StepDesc> steps;  // host copy of the program
     std::vector<int> pclass;      // profiling class of each step
     std::vector<double> pbytes;   // algorithmic bytes of each step
-    u64 *h_msgs = nullptr, *h_chals = nullptr, *h_seed = nullptr;  // pinned staging
-    u32 *h_flag = nullptr;
+    u64 *instage;  // host inputs land here
+    size_t bytes = 0;  // device memory held
+    u64 *h_msgs = nullptr, *h_chals = nullptr, *h_setup = nullptr;  // pinned staging
 };
 
 struct gkr_circuit {
@@ -247,10 +261,17 @@ struct gkr_circuit {
     u64 gmax = 0;
     u64 line_lo = 1, line_hl = 1, line_hh = 1;  // table sizes (entries)
     u64 nch_max = 1;  // most chunks of a phase grouping
+    size_t ws_bytes = 0;  // device bytes of one workspace (0: not yet sized)
     std::mutex mu;
     Workspace *ws = nullptr;
     int omega_algo = GKR_OMEGA_TABLES;
     std::vector<std::vector<u32>> h_in1, h_in2;  // host copies of the wires (grouping)
+    struct Group {  // gates of a layer grouped by the wire a phase binds
+        u32 *perm = nullptr, *cstart = nullptr, *xch = nullptr;
+        u32 nch = 0;
+    };
+    std::vector<Group> grp[2];  // [phase - 1][layer], built with the first table workspace
+    void *gmem = nullptr;       // device memory of the groups
 };
 
 extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_sizes,
@@ -344,17 +365,19 @@ extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_siz
 static void free_workspace(Workspace *ws) {
     if (!ws) return;
     if (ws->mem) (void)hipFree(ws->mem);
-    if (ws->gmem) (void)hipFree(ws->gmem);
     if (ws->h_msgs) (void)hipHostFree(ws->h_msgs);
     if (ws->h_chals) (void)hipHostFree(ws->h_chals);
-    if (ws->h_seed) (void)hipHostFree(ws->h_seed);
-    if (ws->h_flag) (void)hipHostFree(ws->h_flag);
+    if (ws->h_setup) (void)hipHostFree(ws->h_setup);
     delete ws;
 }
 
+static void drop_batches_of(const gkr_circuit *c);
+
 extern "C" void gkr_circuit_destroy(gkr_circuit *c) {
     if (!c) return;
+    drop_batches_of(c);
     free_workspace(c->ws);
+    if (c->gmem) (void)hipFree(c->gmem);
     if (c->soa) (void)hipFree(c->soa);
     delete c;
 }
@@ -368,6 +391,7 @@ extern "C" int gkr_circuit_set_algorithm(gkr_circuit *c, int omega_algo) {
         free_workspace(c->ws);  // the step program is rebuilt on the next proof
         c->ws = nullptr;
         c->omega_algo = omega_algo;
+        c->ws_bytes = 0;
     }
     return GKR_OK;
 }
@@ -425,8 +449,9 @@ static void carve(const gkr_circuit *c, Arena &a, Workspace &w, size_t nsteps) {
     w.bB = a.take<u64>(half);
     w.fA = a.take<u64>(half);
     w.fB = a.take<u64>(half);
-    w.w = a.take<u64>(c->gmax);
-    w.off = a.take<u64>(c->gmax);
+    const bool gates = c->omega_algo == GKR_OMEGA_GATES;
+    w.w = a.take<u64>(gates ? c->gmax : 1);   // per-gate weights: per-gate rounds only
+    w.off = a.take<u64>(gates ? c->gmax : 1);
     w.zlo = a.take<u64>(HALF_MAX);
     w.zhi = a.take<u64>(HALF_MAX);
     w.alo = a.take<u64>(HALF_MAX);
@@ -442,8 +467,9 @@ static void carve(const gkr_circuit *c, Arena &a, Workspace &w, size_t nsteps) {
     w.chals = a.take<u64>(std::max<u64>(c->n_chals, 1));
     w.rngst = a.take<u64>(c->n_chals + 1);
     w.zbuf = a.take<u64>(64);
-    w.state = a.take<u64>(4);
+    w.state = a.take<u64>(8);
     w.flag = a.take<u32>(1);
+    w.instage = a.take<u64>(c->S[c->L - 1]);
     w.d_steps = a.take<StepDesc>(nsteps);
     w.d_jobs = a.take<JobEntry>(2 * nsteps);
     if (c->omega_algo == GKR_OMEGA_TABLES) {
@@ -470,7 +496,7 @@ static u32 sblocks(u64 n, u64 per = 1) {
 struct Planner {
     const gkr_circuit *c;
     Workspace *w;
-    const std::vector<HostGroup> *hg;  // [2 * layer + phase - 1], table algorithm
+
     std::vector<StepDesc> out;
     std::vector<int> cls;
     std::vector<double> bytes;
@@ -513,6 +539,11 @@ struct Planner {
         if (w) pp = ProofPtrs{w->msgs, w->chals, w->rngst, w->zbuf, w->state};
         auto V = [&](u32 i) -> u64 * { return w ? w->V[i] : nullptr; };
         auto P_ = [&](u64 *p) -> u64 * { return w ? p : nullptr; };
+        {
+            const u64 Sd = c->S[d], npad = 1ull << c->s[d];
+            StepDesc &s = add(ST_LOAD, sblocks(npad, 4), PC_MISC, Sd * 8.0 + npad * 8.0);
+            s.u.load = LoadArgs{c->S[d], npad, V(d)};
+        }
         // circuit evaluation (a3), layer d-1 down to 0
         for (int i = (int)d - 1; i >= 0; i--) {
             const u64 S = c->S[i], npad = 1ull << c->s[i];
@@ -626,9 +657,8 @@ struct Planner {
                         StepDesc &e = add(ST_EQ, sblocks((1ull << Lb) + (1ull << (sp - Lb))), PC_TABLES, 0);
                         e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
                     }
-                    const HostGroup &G = (*hg)[2 * i + ph - 1];
-                    const u32 nch = (u32)G.cstart.size() - 1;
-                    const Workspace::Group *dg = w ? &w->grp[ph - 1][i] : nullptr;
+                    const gkr_circuit::Group *dg = &c->grp[ph - 1][i];
+                    const u32 nch = dg->nch;
                     const u32 hasC = kind != KIND_MUL;
                     {
                         WaggArgs a;
@@ -636,8 +666,8 @@ struct Planner {
                         a.kind = kind;
                         a.ph = ph;
                         a.nch = nch;
-                        a.perm = dg ? dg->perm : nullptr;
-                        a.cstart = dg ? dg->cstart : nullptr;
+                        a.perm = dg->perm;
+                        a.cstart = dg->cstart;
                         a.oth = ph == 1 ? c->in2[i] : c->in1[i];
                         a.type = c->type[i];
                         a.Vn = V(i + 1);
@@ -660,7 +690,7 @@ struct Planner {
                         a.ph = ph;
                         a.hasC = hasC;
                         a.npairs = N / 2;
-                        a.xch = dg ? dg->xch : nullptr;
+                        a.xch = dg->xch;
                         a.partA = w ? w->partA : nullptr;
                         a.partC = w ? w->partC : nullptr;
                         a.F = V(i + 1);
@@ -857,22 +887,56 @@ struct Planner {
     }
 };
 
-static int ensure_workspace(gkr_circuit *c) {
-    if (c->ws) return GKR_OK;
+// A proof's scratch with its step program (for the circuit's own proofs, or
+// one entry of a batch).
+// Group every layer's gates by in1 and by in2 (once per circuit).
+static int ensure_groups(gkr_circuit *c) {
+    if (c->gmem) return GKR_OK;
     const u32 d = c->L - 1;
-    std::vector<HostGroup> hg;
-    if (c->omega_algo == GKR_OMEGA_TABLES) {
-        hg.resize(2 * d);
-        c->nch_max = 1;
-        for (u32 i = 0; i < d; i++) {
-            const u64 N = 1ull << c->s[i + 1];
-            build_group(c->h_in1[i], N, hg[2 * i]);
-            build_group(c->h_in2[i], N, hg[2 * i + 1]);
-            c->nch_max = std::max<u64>(c->nch_max, hg[2 * i].cstart.size());
-            c->nch_max = std::max<u64>(c->nch_max, hg[2 * i + 1].cstart.size());
+    std::vector<HostGroup> hg(2 * d);
+    c->nch_max = 1;
+    size_t bytes = 0;
+    for (u32 i = 0; i < d; i++) {
+        const u64 N = 1ull << c->s[i + 1];
+        build_group(c->h_in1[i], N, hg[2 * i]);
+        build_group(c->h_in2[i], N, hg[2 * i + 1]);
+        for (int ph = 0; ph < 2; ph++) {
+            const HostGroup &G = hg[2 * i + ph];
+            c->nch_max = std::max<u64>(c->nch_max, G.cstart.size());
+            bytes += ((G.perm.size() * 4 + 255) & ~size_t(255)) + ((G.cstart.size() * 4 + 255) & ~size_t(255)) +
+                     ((G.xch.size() * 4 + 255) & ~size_t(255));
         }
     }
-    Planner count{c, nullptr, &hg};
+    HIP_TRY(hipMalloc(&c->gmem, std::max<size_t>(bytes, 256)));
+    char *p = (char *)c->gmem;
+    auto put = [&](const std::vector<u32> &v, u32 **dst) -> hipError_t {
+        *dst = (u32 *)p;
+        p += (v.size() * 4 + 255) & ~size_t(255);
+        return v.empty() ? hipSuccess : hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice);
+    };
+    c->grp[0].resize(d);
+    c->grp[1].resize(d);
+    for (u32 i = 0; i < d; i++)
+        for (int ph = 0; ph < 2; ph++) {
+            const HostGroup &G = hg[2 * i + ph];
+            gkr_circuit::Group &D = c->grp[ph][i];
+            HIP_TRY(put(G.perm, &D.perm));
+            HIP_TRY(put(G.cstart, &D.cstart));
+            HIP_TRY(put(G.xch, &D.xch));
+            D.nch = (u32)G.cstart.size() - 1;
+        }
+    return GKR_OK;
+}
+
+// A proof's scratch with its step program (for the circuit's own proofs, or
+// one entry of a batch).
+static int make_workspace(gkr_circuit *c, Workspace **out) {
+    *out = nullptr;
+    if (c->omega_algo == GKR_OMEGA_TABLES) {
+        int rc = ensure_groups(c);
+        if (rc) return rc;
+    }
+    Planner count{c, nullptr};
     count.build();
     const size_t nsteps = count.out.size();
     Workspace probe;
@@ -880,36 +944,12 @@ static int ensure_workspace(gkr_circuit *c) {
     carve(c, sz, probe, nsteps);
     std::unique_ptr<Workspace> ws(new Workspace());
     HIP_TRY(hipMalloc(&ws->mem, sz.used));
+    ws->bytes = sz.used;
     Arena a;
     a.base = (char *)ws->mem;
     a.cap = sz.used;
     carve(c, a, *ws, nsteps);
-    if (c->omega_algo == GKR_OMEGA_TABLES) {
-        // upload the groupings: perm, chunk starts and per-wire chunk ranges
-        size_t bytes = 0;
-        for (auto &G : hg)
-            bytes += ((G.perm.size() * 4 + 255) & ~size_t(255)) + ((G.cstart.size() * 4 + 255) & ~size_t(255)) +
-                     ((G.xch.size() * 4 + 255) & ~size_t(255));
-        HIP_TRY(hipMalloc(&ws->gmem, std::max<size_t>(bytes, 256)));
-        char *p = (char *)ws->gmem;
-        auto put = [&](const std::vector<u32> &v, u32 **dst) -> hipError_t {
-            *dst = (u32 *)p;
-            p += (v.size() * 4 + 255) & ~size_t(255);
-            return v.empty() ? hipSuccess : hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice);
-        };
-        ws->grp[0].resize(d);
-        ws->grp[1].resize(d);
-        for (u32 i = 0; i < d; i++)
-            for (int ph = 0; ph < 2; ph++) {
-                const HostGroup &G = hg[2 * i + ph];
-                Workspace::Group &D = ws->grp[ph][i];
-                HIP_TRY(put(G.perm, &D.perm));
-                HIP_TRY(put(G.cstart, &D.cstart));
-                HIP_TRY(put(G.xch, &D.xch));
-                D.nch = (u32)G.cstart.size() - 1;
-            }
-    }
-    Planner plan{c, ws.get(), &hg};
+    Planner plan{c, ws.get()};
     plan.build();
     if (plan.out.size() != nsteps) return fail(GKR_ERR_INVALID, "step program changed size");
     ws->steps = plan.out;
@@ -924,10 +964,34 @@ static int ensure_workspace(gkr_circuit *c) {
     HIP_TRY(hipMemcpy(ws->d_jobs, jobs.data(), jobs.size() * sizeof(JobEntry), hipMemcpyHostToDevice));
     HIP_TRY(hipHostMalloc((void **)&ws->h_msgs, c->n_msgs * 8));
     HIP_TRY(hipHostMalloc((void **)&ws->h_chals, std::max<u64>(c->n_chals, 1) * 8));
-    HIP_TRY(hipHostMalloc((void **)&ws->h_seed, 8));
-    HIP_TRY(hipHostMalloc((void **)&ws->h_flag, 4));
-    c->ws = ws.release();
+    HIP_TRY(hipHostMalloc((void **)&ws->h_setup, 3 * 8));
+    *out = ws.release();
     return GKR_OK;
+}
+
+// Device bytes a workspace of c takes (sized without allocating; cached).
+static int workspace_size(gkr_circuit *c, size_t *bytes) {
+    if (c->ws_bytes) {
+        *bytes = c->ws_bytes;
+        return GKR_OK;
+    }
+    if (c->omega_algo == GKR_OMEGA_TABLES) {
+        int rc = ensure_groups(c);
+        if (rc) return rc;
+    }
+    Planner count{c, nullptr};
+    count.build();
+    Workspace probe;
+    Arena sz;
+    carve(c, sz, probe, count.out.size());
+    c->ws_bytes = sz.used;
+    *bytes = sz.used;
+    return GKR_OK;
+}
+
+static int ensure_workspace(gkr_circuit *c) {
+    if (c->ws) return GKR_OK;
+    return make_workspace(c, &c->ws);
 }
 
 // ------------------------------------------------------------------- prover
@@ -942,8 +1006,11 @@ static int ensure_workspace(gkr_circuit *c) {
 // one launch per step.
 static int enqueue_proof(Workspace &w, hipStream_t st) {
     const size_t n = w.steps.size();
-    for (size_t t = 0; t < n; t++)
-        LAUNCH(w.pclass[t], w.pbytes[t], launch_step(st, w.steps[t]));
+    for (size_t t = 0; t < n; t++) {
+        hipEvent_t a, b;
+        prof_pair(w.pclass[t], w.pbytes[t], &a, &b);
+        HIP_TRY(launch_step(st, w.steps[t], a, b));
+    }
     return GKR_OK;
 }
 
@@ -957,29 +1024,237 @@ extern "C" int gkr_prove(const gkr_circuit *cc, const uint64_t *inputs, int inpu
     int rc = ensure_workspace(c);
     if (rc) return rc;
     Workspace &w = *c->ws;
-    const u32 d = c->L - 1;
-    const u64 Sd = c->S[d], npad = 1ull << c->s[d];
-    if (inputs_on_device) {
-        HIP_TRY(hipMemsetAsync(w.flag, 0, 4, st));
-        LAUNCH(PC_MISC, Sd * 8.0 + npad * 8.0, launch_load_inputs(st, inputs, Sd, npad, w.V[d], w.flag));
-    } else {
+    const u64 Sd = c->S[c->L - 1];
+    const u64 *src = inputs;
+    if (!inputs_on_device) {
         for (u64 g = 0; g < Sd; g++)
             if (inputs[g] >= fp::P) return fail(GKR_ERR_RANGE, "input value not below p");
-        HIP_TRY(hipMemcpyAsync(w.V[d], inputs, Sd * 8, hipMemcpyHostToDevice, st));
-        if (npad > Sd) HIP_TRY(hipMemsetAsync(w.V[d] + Sd, 0, (npad - Sd) * 8, st));
+        HIP_TRY(hipMemcpyAsync(w.instage, inputs, Sd * 8, hipMemcpyHostToDevice, st));
+        src = w.instage;
     }
-    *w.h_seed = seed;
-    HIP_TRY(hipMemcpyAsync(w.state + 2, w.h_seed, 8, hipMemcpyHostToDevice, st));
+    // seed, input pointer and a cleared range flag: state[2..4]
+    w.h_setup[0] = seed;
+    w.h_setup[1] = (u64)(uintptr_t)src;
+    w.h_setup[2] = 0;
+    HIP_TRY(hipMemcpyAsync(w.state + 2, w.h_setup, 3 * 8, hipMemcpyHostToDevice, st));
     rc = enqueue_proof(w, st);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(w.h_msgs, w.msgs, c->n_msgs * 8, hipMemcpyDeviceToHost, st));
     if (chals) HIP_TRY(hipMemcpyAsync(w.h_chals, w.chals, c->n_chals * 8, hipMemcpyDeviceToHost, st));
-    if (inputs_on_device) HIP_TRY(hipMemcpyAsync(w.h_flag, w.flag, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(w.h_setup + 2, w.state + 4, 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (inputs_on_device && *w.h_flag) return fail(GKR_ERR_RANGE, "input value not below p");
+    if (w.h_setup[2]) return fail(GKR_ERR_RANGE, "input value not below p");
     memcpy(msgs, w.h_msgs, c->n_msgs * 8);
     if (chals) memcpy(chals, w.h_chals, c->n_chals * 8);
     return GKR_OK;
+}
+
+// ------------------------------------------------------------------ batches
+//
+// A batch plan owns one workspace (scratch + step program) per entry.
+// Launch t runs step t of every proof that has one: a job table maps each
+// workgroup to (proof, step).  The sequence "write seeds and input pointers,
+// all batched steps, gather the transcripts" is captured once as a HIP
+// graph and replayed for later batches over the same circuits.
+
+namespace {
+
+struct BatchPlan {
+    std::vector<gkr_circuit *> key;
+    int flags = 0;
+    std::vector<Workspace *> ws;
+    std::vector<u32> l_off, l_njobs, l_blocks;  // per launch
+    std::vector<u64> out_off;
+    u64 out_words = 0;
+    void *mem = nullptr;  // job tables, slots, gathered transcripts
+    JobEntry *d_jobs = nullptr;
+    BatchSlot *d_slots = nullptr;
+    u64 *d_out = nullptr;
+    BatchSlot *h_slots = nullptr;
+    u64 *h_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    ~BatchPlan() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (Workspace *w : ws) free_workspace(w);
+        if (mem) (void)hipFree(mem);
+        if (h_slots) (void)hipHostFree(h_slots);
+        if (h_out) (void)hipHostFree(h_out);
+    }
+};
+
+std::mutex g_batch_mu;
+std::vector<std::unique_ptr<BatchPlan>> g_batches;  // most recent last
+constexpr size_t BATCH_CACHE = 4;
+
+hipStream_t capture_stream() {
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        return nullptr;
+    return streams[dev];
+}
+
+// Enqueue a batch's launches (setup, steps, gather) on st.
+int enqueue_batch(BatchPlan &B, hipStream_t st, bool profile) {
+    const u32 n = (u32)B.ws.size();
+    HIP_TRY(launch_batch_setup(st, B.d_slots, n));
+    for (size_t t = 0; t < B.l_off.size(); t++) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (profile) prof_pair(PC_BATCH, 0, &a, &b);
+        HIP_TRY(launch_steps(st, B.d_jobs + B.l_off[t], B.l_njobs[t], B.l_blocks[t], a, b));
+    }
+    HIP_TRY(launch_batch_gather(st, B.d_slots, n, B.d_out));
+    return GKR_OK;
+}
+
+int build_batch(const std::vector<gkr_circuit *> &cs, int flags, std::unique_ptr<BatchPlan> &out) {
+    std::unique_ptr<BatchPlan> B(new BatchPlan());
+    B->key = cs;
+    B->flags = flags;
+    const u32 n = (u32)cs.size();
+    for (gkr_circuit *c : cs) {
+        Workspace *w = nullptr;
+        std::lock_guard<std::mutex> lk(c->mu);
+        int rc = make_workspace(c, &w);
+        if (rc) return rc;
+        B->ws.push_back(w);
+    }
+    // schedule: launch t holds step t of every proof with more than t steps
+    size_t T = 0;
+    for (Workspace *w : B->ws) T = std::max(T, w->steps.size());
+    std::vector<JobEntry> jobs;
+    for (size_t t = 0; t < T; t++) {
+        B->l_off.push_back((u32)jobs.size());
+        u32 blocks = 0, nj = 0;
+        for (Workspace *w : B->ws) {
+            if (t >= w->steps.size()) continue;
+            jobs.push_back(JobEntry{w->d_steps + t, blocks, 0});
+            blocks += step_grid(w->steps[t]);
+            nj++;
+        }
+        jobs.push_back(JobEntry{nullptr, blocks, 0});  // sentinel
+        B->l_njobs.push_back(nj);
+        B->l_blocks.push_back(blocks);
+    }
+    B->out_off.resize(n);
+    u64 off = 0;
+    for (u32 q = 0; q < n; q++) {
+        B->out_off[q] = off;
+        off += cs[q]->n_msgs + 1;  // transcript, then the range flag
+    }
+    B->out_words = off;
+    Arena sz, a;
+    auto lay = [&](Arena &ar) {
+        B->d_jobs = ar.take<JobEntry>(jobs.size());
+        B->d_slots = ar.take<BatchSlot>(n);
+        B->d_out = ar.take<u64>(off);
+    };
+    lay(sz);
+    HIP_TRY(hipMalloc(&B->mem, sz.used));
+    a.base = (char *)B->mem;
+    lay(a);
+    HIP_TRY(hipMemcpy(B->d_jobs, jobs.data(), jobs.size() * sizeof(JobEntry), hipMemcpyHostToDevice));
+    HIP_TRY(hipHostMalloc((void **)&B->h_slots, n * sizeof(BatchSlot)));
+    HIP_TRY(hipHostMalloc((void **)&B->h_out, off * 8));
+    for (u32 q = 0; q < n; q++) {
+        BatchSlot &s = B->h_slots[q];
+        s.state = B->ws[q]->state;
+        s.seed = 0;
+        s.input = 0;
+        s.msgs = B->ws[q]->msgs;
+        s.n_msgs = cs[q]->n_msgs;
+        s.out_off = B->out_off[q];
+        s.flag_off = B->out_off[q] + cs[q]->n_msgs;
+    }
+    if (flags & GKR_BATCH_GRAPH) {
+        hipStream_t cst = capture_stream();
+        if (!cst) return fail(GKR_ERR_DEVICE, "no capture stream");
+        HIP_TRY(hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_batch(*B, cst, false);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(cst, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        HIP_TRY(e);
+        B->graph = graph;
+        HIP_TRY(hipGraphInstantiate(&B->gexec, graph, nullptr, nullptr, 0));
+    }
+    out = std::move(B);
+    return GKR_OK;
+}
+
+}  // namespace
+
+// Cached batch plans refer to the circuits' device arrays.
+static void drop_batches_of(const gkr_circuit *c) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (size_t k = 0; k < g_batches.size();) {
+        auto &key = g_batches[k]->key;
+        if (std::find(key.begin(), key.end(), c) != key.end())
+            g_batches.erase(g_batches.begin() + k);
+        else
+            k++;
+    }
+}
+
+extern "C" int gkr_batch_prove(uint32_t n, const gkr_circuit *const *circuits,
+                               const uint64_t *const *inputs, int inputs_on_device,
+                               const uint64_t *seeds, uint64_t *const *msgs, int flags,
+                               void *hip_stream) {
+    if (n == 0) return GKR_OK;
+    if (!circuits || !inputs || !seeds || !msgs) return fail(GKR_ERR_INVALID, "NULL argument");
+    if (!inputs_on_device) return fail(GKR_ERR_INVALID, "batched inputs must be device pointers");
+    for (u32 q = 0; q < n; q++)
+        if (!circuits[q] || !inputs[q] || !msgs[q]) return fail(GKR_ERR_INVALID, "NULL entry");
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    std::vector<gkr_circuit *> key(n);
+    for (u32 q = 0; q < n; q++) key[q] = const_cast<gkr_circuit *>(circuits[q]);
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchPlan *B = nullptr;
+    for (size_t k = 0; k < g_batches.size(); k++)
+        if (g_batches[k]->key == key && g_batches[k]->flags == flags) {
+            std::unique_ptr<BatchPlan> hit = std::move(g_batches[k]);
+            g_batches.erase(g_batches.begin() + k);
+            g_batches.push_back(std::move(hit));
+            B = g_batches.back().get();
+            break;
+        }
+    if (!B) {
+        std::unique_ptr<BatchPlan> fresh;
+        int rc = build_batch(key, flags, fresh);
+        if (rc) return rc;
+        if (g_batches.size() >= BATCH_CACHE) g_batches.erase(g_batches.begin());
+        g_batches.push_back(std::move(fresh));
+        B = g_batches.back().get();
+    }
+    for (u32 q = 0; q < n; q++) {
+        B->h_slots[q].seed = seeds[q];
+        B->h_slots[q].input = (u64)(uintptr_t)inputs[q];
+    }
+    HIP_TRY(hipMemcpyAsync(B->d_slots, B->h_slots, n * sizeof(BatchSlot), hipMemcpyHostToDevice, st));
+    if (B->gexec) {
+        HIP_TRY(hipGraphLaunch(B->gexec, st));
+    } else {
+        int rc = enqueue_batch(*B, st, g_prof.on);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(B->h_out, B->d_out, B->out_words * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int rc = GKR_OK;
+    for (u32 q = 0; q < n; q++) {
+        memcpy(msgs[q], B->h_out + B->out_off[q], circuits[q]->n_msgs * 8);
+        if (B->h_out[B->out_off[q] + circuits[q]->n_msgs]) rc = fail(GKR_ERR_RANGE, "input value not below p");
+    }
+    return rc;
 }
 
 // ----------------------------------------------------------------- verifier
@@ -1413,4 +1688,296 @@ extern "C" int gkr_field_op(int op, const uint64_t *a, const uint64_t *b, uint64
     HIP_TRY(launch_field_op(st, op, a, b, out, n));
     HIP_TRY(hipStreamSynchronize(st));
     return GKR_OK;
+}
+
+// ------------------------------------------------------------------ serving
+//
+// Continuous batching: a scheduler thread keeps up to max_slots proofs in
+// flight.  Every launch runs the next step of each in-flight proof (job
+// table in the kernel arguments), so a request that arrives while others run
+// joins at the next launch.  A request is admitted when a slot is free and
+// its scratch fits the HBM budget; its scratch comes from a per-circuit pool
+// and returns there when the proof completes.
+
+namespace {
+
+struct ServeReq {
+    u64 id = 0;
+    gkr_circuit *c = nullptr;
+    Workspace *ws = nullptr;
+    u64 seed = 0;
+    std::vector<u64> inputs;  // copied at submission
+    size_t next = 0;          // next step of its program
+    hipEvent_t done_ev = nullptr;
+    u64 *h_out = nullptr;     // pinned: transcript, then the range flag
+    std::chrono::steady_clock::time_point t_submit, t_done;
+    int state = 0;            // 0 queued, 1 running, 2 finishing, 3 done
+    int err = GKR_OK;
+};
+
+size_t workspace_bytes(const Workspace *w) { return w ? w->bytes : 0; }
+
+}  // namespace
+
+struct gkr_server {
+    u64 budget = 0, used = 0;
+    u32 max_slots = 1;
+    int device = 0;
+    hipStream_t st = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<ServeReq *> queued;
+    std::vector<ServeReq *> running, finishing;
+    std::unordered_map<u64, ServeReq *> reqs;
+    std::unordered_map<gkr_circuit *, std::vector<Workspace *>> pool;  // idle scratch
+    u64 next_id = 1;
+    bool stop = false;
+    std::thread worker;
+    std::vector<hipEvent_t> ring;  // bounds how far the host runs ahead of the GPU
+    size_t ring_pos = 0;
+    std::string err;
+
+    // Scratch for r: pooled, or new if the budget allows (idle pooled scratch
+    // of other circuits is released first).  1: got it; 0: wait for running
+    // proofs to return scratch; < 0: error (the request fails).
+    int acquire(ServeReq *r) {
+        auto &v = pool[r->c];
+        if (!v.empty()) {
+            r->ws = v.back();
+            v.pop_back();
+            return 1;
+        }
+        size_t need = 0;
+        {
+            std::lock_guard<std::mutex> lk(r->c->mu);
+            const int rc = workspace_size(r->c, &need);
+            if (rc) return rc;
+        }
+        if (need > budget) return fail(GKR_ERR_NOMEM, "a proof's scratch exceeds the server's HBM budget");
+        while (used + need > budget) {
+            bool freed = false;
+            for (auto &kv : pool)
+                if (!kv.second.empty()) {
+                    used -= kv.second.back()->bytes;
+                    free_workspace(kv.second.back());
+                    kv.second.pop_back();
+                    freed = true;
+                    break;
+                }
+            if (!freed) break;
+        }
+        if (used + need > budget) return 0;  // wait for running proofs to return scratch
+        Workspace *w = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(r->c->mu);
+            const int rc = make_workspace(r->c, &w);
+            if (rc) return rc;
+        }
+        used += w->bytes;
+        r->ws = w;
+        return 1;
+    }
+
+    void release(ServeReq *r) {
+        if (r->ws) pool[r->c].push_back(r->ws);
+        r->ws = nullptr;
+    }
+
+    int start(ServeReq *r) {
+        Workspace &w = *r->ws;
+        const u64 Sd = r->inputs.size();
+        HIP_TRY(hipMemcpyAsync(w.instage, r->inputs.data(), Sd * 8, hipMemcpyHostToDevice, st));
+        w.h_setup[0] = r->seed;
+        w.h_setup[1] = (u64)(uintptr_t)w.instage;
+        w.h_setup[2] = 0;
+        HIP_TRY(hipMemcpyAsync(w.state + 2, w.h_setup, 3 * 8, hipMemcpyHostToDevice, st));
+        return GKR_OK;
+    }
+
+    void loop() {
+        if (hipSetDevice(device) != hipSuccess) return;
+        std::unique_lock<std::mutex> lk(mu);
+        while (!stop) {
+            // admission: free slot and scratch within the budget
+            while (!queued.empty() && running.size() + finishing.size() < max_slots) {
+                ServeReq *r = queued.front();
+                const int got = acquire(r);
+                if (got == 0) break;
+                queued.pop_front();
+                r->err = got < 0 ? got : start(r);
+                if (r->err) {
+                    r->state = 3;
+                    release(r);
+                    cv.notify_all();
+                    continue;
+                }
+                r->state = 1;
+                r->next = 0;
+                running.push_back(r);
+            }
+            // completions
+            bool freed = false;
+            for (size_t k = 0; k < finishing.size();) {
+                ServeReq *r = finishing[k];
+                if (hipEventQuery(r->done_ev) == hipSuccess) {
+                    r->t_done = std::chrono::steady_clock::now();
+                    if (r->h_out[r->c->n_msgs]) r->err = GKR_ERR_RANGE;
+                    r->state = 3;
+                    release(r);
+                    finishing.erase(finishing.begin() + k);
+                    freed = true;
+                } else {
+                    k++;
+                }
+            }
+            if (freed) cv.notify_all();
+            if (freed && !queued.empty()) continue;  // returned scratch or slots: admit again
+            if (running.empty()) {
+                // nothing to launch: sleep until a submission (untimed only
+                // when nothing is queued or finishing)
+                if (finishing.empty() && queued.empty())
+                    cv.wait(lk);
+                else
+                    cv.wait_for(lk, std::chrono::microseconds(20));
+                continue;
+            }
+            // one launch: the next step of every running proof
+            JobTable t;
+            t.n = 0;
+            t.total = 0;
+            for (ServeReq *r : running) {
+                const StepDesc &sd = r->ws->steps[r->next];
+                t.e[t.n++] = JobEntry{r->ws->d_steps + r->next, t.total, 0};
+                t.total += step_grid(sd);
+            }
+            t.e[t.n] = JobEntry{nullptr, t.total, 0};
+            lk.unlock();
+            // keep at most ring.size() launches in flight
+            hipEvent_t &slot = ring[ring_pos];
+            (void)hipEventSynchronize(slot);
+            hipError_t e = launch_step_table(st, t);
+            if (e == hipSuccess) e = hipEventRecord(slot, st);
+            ring_pos = (ring_pos + 1) % ring.size();
+            lk.lock();
+            if (e != hipSuccess) {
+                err = hipGetErrorString(e);
+                for (ServeReq *r : running) {
+                    r->err = GKR_ERR_DEVICE;
+                    r->state = 3;
+                }
+                running.clear();
+                cv.notify_all();
+                continue;
+            }
+            for (size_t k = 0; k < running.size();) {
+                ServeReq *r = running[k];
+                r->next++;
+                if (r->next == r->ws->steps.size()) {
+                    // transcript and range flag back to the host
+                    Workspace &w = *r->ws;
+                    (void)hipMemcpyAsync(r->h_out, w.msgs, r->c->n_msgs * 8, hipMemcpyDeviceToHost, st);
+                    (void)hipMemcpyAsync(r->h_out + r->c->n_msgs, w.state + 4, 8, hipMemcpyDeviceToHost, st);
+                    (void)hipEventRecord(r->done_ev, st);
+                    r->state = 2;
+                    finishing.push_back(r);
+                    running.erase(running.begin() + k);
+                } else {
+                    k++;
+                }
+            }
+        }
+    }
+};
+
+extern "C" int gkr_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, gkr_server **out) {
+    if (!out) return fail(GKR_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > (u32)MAX_TABLE_JOBS - 1)
+        return fail(GKR_ERR_INVALID, "max_slots must be in [1, 127]");
+    std::unique_ptr<gkr_server> s(new gkr_server());
+    s->budget = hbm_budget_bytes;
+    s->max_slots = max_slots;
+    HIP_TRY(hipGetDevice(&s->device));
+    HIP_TRY(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+    s->ring.resize(64);
+    for (auto &e : s->ring) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    gkr_server *raw = s.get();
+    s->worker = std::thread([raw] { raw->loop(); });
+    *out = s.release();
+    return GKR_OK;
+}
+
+extern "C" int gkr_server_submit(gkr_server *s, const gkr_circuit *c, const uint64_t *inputs,
+                                 uint64_t seed, uint64_t *req_id) {
+    if (!s || !c || !inputs || !req_id) return fail(GKR_ERR_INVALID, "NULL argument");
+    const u64 Sd = c->S[c->L - 1];
+    for (u64 g = 0; g < Sd; g++)
+        if (inputs[g] >= fp::P) return fail(GKR_ERR_RANGE, "input value not below p");
+    std::unique_ptr<ServeReq> r(new ServeReq());
+    r->c = const_cast<gkr_circuit *>(c);
+    r->seed = seed;
+    r->inputs.assign(inputs, inputs + Sd);
+    HIP_TRY(hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming));
+    HIP_TRY(hipHostMalloc((void **)&r->h_out, (c->n_msgs + 1) * 8));
+    r->t_submit = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->id = s->next_id++;
+    *req_id = r->id;
+    ServeReq *raw = r.release();
+    s->reqs[raw->id] = raw;
+    s->queued.push_back(raw);
+    s->cv.notify_all();
+    return GKR_OK;
+}
+
+extern "C" int gkr_server_poll(gkr_server *s, uint64_t req_id, uint64_t *msgs, int *done,
+                               double *latency_s) {
+    if (!s || !done) return fail(GKR_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(req_id);
+    if (it == s->reqs.end()) return fail(GKR_ERR_INVALID, "unknown request");
+    ServeReq *r = it->second;
+    *done = r->state == 3;
+    if (!*done) return GKR_OK;
+    int err = r->err;
+    if (!err && msgs) memcpy(msgs, r->h_out, r->c->n_msgs * 8);
+    if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    (void)hipEventDestroy(r->done_ev);
+    (void)hipHostFree(r->h_out);
+    s->reqs.erase(it);
+    delete r;
+    if (err) return fail(err, err == GKR_ERR_RANGE ? "input value not below p" : s->err);
+    return GKR_OK;
+}
+
+extern "C" int gkr_server_stats(gkr_server *s, uint32_t *running, uint32_t *queued,
+                                uint64_t *hbm_used) {
+    if (!s) return fail(GKR_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (running) *running = (u32)(s->running.size() + s->finishing.size());
+    if (queued) *queued = (u32)s->queued.size();
+    if (hbm_used) *hbm_used = s->used;
+    return GKR_OK;
+}
+
+extern "C" void gkr_server_destroy(gkr_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipStreamSynchronize(s->st);
+    for (auto &kv : s->reqs) {
+        if (kv.second->ws) free_workspace(kv.second->ws);
+        (void)hipEventDestroy(kv.second->done_ev);
+        (void)hipHostFree(kv.second->h_out);
+        delete kv.second;
+    }
+    for (auto &kv : s->pool)
+        for (Workspace *w : kv.second) free_workspace(w);
+    for (auto &e : s->ring) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(s->st);
+    delete s;
 }

@@ -5,6 +5,8 @@
 // which each workgroup sums its share (wave64 shuffles, then LDS) into one
 // row of partial sums.  All arithmetic is exact in F_p (Sec. 5.1), so the
 // result does not depend on the summation order.
+#include <hip/hip_ext.h>
+
 #include "fp61.hpp"
 #include "steps.hpp"
 
@@ -147,6 +149,20 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
 }
 
 // ------------------------------------------------------------ step bodies
+
+__device__ void step_load(const LoadArgs &a, const ProofPtrs &pp, const Ctx &c) {
+    const u64 *src = reinterpret_cast<const u64 *>(pp.state[3]);
+    u64 bad = 0;
+    for (u64 g = c.gtid; g < a.npad; g += c.gstride) {
+        u64 v = 0;
+        if (g < a.S) {
+            v = src[g];
+            bad |= v >= P;
+        }
+        a.V[g] = v;
+    }
+    if (bad) atomicOr(reinterpret_cast<unsigned long long *>(pp.state + 4), 1ull);
+}
 
 __device__ void step_eval(const EvalArgs &a, const Ctx &c) {
     for (u64 g = c.gtid; g < a.npad; g += c.gstride) {
@@ -682,6 +698,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     // --- body
     u64 *row = sd.rows ? sd.rows + (u64)c.lb * ROW_STRIDE : nullptr;
     switch (kind) {
+        case ST_LOAD: step_load(sd.u.load, pp, c); break;
         case ST_EVAL: step_eval(sd.u.eval, c); break;
         case ST_START: step_start(sd.u.start, pp, c); break;
         case ST_EQ:
@@ -742,16 +759,34 @@ __global__ void __launch_bounds__(SBLOCK) k_step_jobs(const JobEntry *__restrict
     run_step<KALL, -1, 0>(*jobs[lo].step, b - jobs[lo].block0);
 }
 
+// One step of each of several proofs, the job table in the kernel arguments.
+__global__ void __launch_bounds__(SBLOCK) k_step_table(const JobTable t) {
+    u32 lo = 0, hi = t.n;
+    const u32 b = blockIdx.x;
+    while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (t.e[mid].block0 <= b) lo = mid; else hi = mid;
+    }
+    run_step<KALL, -1, 0>(*t.e[lo].step, b - t.e[lo].block0);
+}
+
+hipError_t launch_step_table(hipStream_t st, const JobTable &t) {
+    hipLaunchKernelGGL(k_step_table, dim3(t.total), dim3(SBLOCK), 0, st, t);
+    return hipGetLastError();
+}
+
 u32 step_grid(const StepDesc &sd) {
     if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL) return 1;
     return sd.nblocks + (sd.fin.kind != FIN_NONE ? 1 : 0);
 }
 
-hipError_t launch_step(hipStream_t st, const StepDesc &sd) {
+hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 g(step_grid(sd)), b(SBLOCK);
-#define L1(K) hipLaunchKernelGGL((k_step_one<K, -1, 0>), g, b, 0, st, sd)
-#define LW(G, PH) hipLaunchKernelGGL((k_step_one<ST_W, G, PH>), g, b, 0, st, sd)
+    // with events: the dispatch itself is timed (hipExtLaunchKernelGGL)
+#define L1(K) hipExtLaunchKernelGGL((k_step_one<K, -1, 0>), g, b, 0, st, ev0, ev1, 0, sd)
+#define LW(G, PH) hipExtLaunchKernelGGL((k_step_one<ST_W, G, PH>), g, b, 0, st, ev0, ev1, 0, sd)
     switch (sd.kind) {
+        case ST_LOAD: L1(ST_LOAD); break;
         case ST_EVAL: L1(ST_EVAL); break;
         case ST_START: L1(ST_START); break;
         case ST_EQ: L1(ST_EQ); break;
@@ -779,8 +814,42 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd) {
     return hipGetLastError();
 }
 
-hipError_t launch_steps(hipStream_t st, const JobEntry *jobs, u32 njobs, u32 total_blocks) {
-    hipLaunchKernelGGL(k_step_jobs, dim3(total_blocks), dim3(SBLOCK), 0, st, jobs, njobs);
+hipError_t launch_steps(hipStream_t st, const JobEntry *jobs, u32 njobs, u32 total_blocks,
+                        hipEvent_t ev0, hipEvent_t ev1) {
+    hipExtLaunchKernelGGL(k_step_jobs, dim3(total_blocks), dim3(SBLOCK), 0, st, ev0, ev1, 0, jobs, njobs);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- batches
+
+// Proof q's seed and input pointer into its state; range flag cleared.
+__global__ void k_batch_setup(const BatchSlot *slots, u32 n) {
+    const u32 q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) {
+        u64 *st = slots[q].state;
+        st[2] = slots[q].seed;
+        st[3] = slots[q].input;
+        st[4] = 0;
+    }
+}
+
+// Transcripts (and range flags) of the batch into one contiguous buffer:
+// proof q's msgs at out[slots[q].out_off ...], its flag at out[slots[q].flag_off].
+__global__ void k_batch_gather(const BatchSlot *slots, u32 n, u64 *out) {
+    const u32 q = blockIdx.x;
+    if (q >= n) return;
+    const BatchSlot &s = slots[q];
+    for (u64 k = threadIdx.x; k < s.n_msgs; k += blockDim.x) out[s.out_off + k] = s.msgs[k];
+    if (threadIdx.x == 0) out[s.flag_off] = s.state[4];
+}
+
+hipError_t launch_batch_setup(hipStream_t st, const BatchSlot *slots, u32 n) {
+    hipLaunchKernelGGL(k_batch_setup, dim3((n + 255) / 256), dim3(256), 0, st, slots, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(hipStream_t st, const BatchSlot *slots, u32 n, u64 *out) {
+    hipLaunchKernelGGL(k_batch_gather, dim3(n), dim3(256), 0, st, slots, n, out);
     return hipGetLastError();
 }
 

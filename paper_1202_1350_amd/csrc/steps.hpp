@@ -48,6 +48,7 @@ enum StepKind : u32 {
     ST_WT,         // omega phase, tables: round k >= 1 (fold, then sum)
     ST_WTAIL,      // omega phase, tables: remaining rounds in one workgroup
     ST_PTAIL,      // p-phase: remaining rounds in one workgroup
+    ST_LOAD,       // inputs (pointer in state[3]) into V_d, range check
 };
 
 enum FinKind : u32 {
@@ -74,7 +75,8 @@ struct ProofPtrs {
     u64 *chals;  // challenges
     u64 *rngst;  // rngst[c] = SplitMix64 state before challenge c
     u64 *zbuf;   // z of the current layer
-    u64 *state;  // [0] beta prefix C, [1] v1, [2] the proof's seed
+    u64 *state;  // [0] beta prefix C, [1] v1, [2] seed, [3] input pointer,
+                 // [4] nonzero if an input is not below p
 };
 
 // Prologue: finish the previous round and/or draw challenge `draw`.
@@ -100,6 +102,11 @@ struct EvalArgs {
     const u8 *type;
     const u32 *in1, *in2;
     const u64 *Vn;
+    u64 *V;
+};
+struct LoadArgs {
+    u32 S;
+    u64 npad;
     u64 *V;
 };
 struct StartArgs {
@@ -223,6 +230,7 @@ struct StepDesc {
         WtArgs wt;
         WtailArgs wtail;
         PtailArgs ptail;
+        LoadArgs load;
     } u;
 };
 
@@ -236,11 +244,33 @@ struct JobEntry {
 // Workgroups a step needs: its body's plus one that finishes the previous
 // round when the step has a prologue.
 u32 step_grid(const StepDesc &sd);
-// One step of one proof (descriptor passed by value).
-hipError_t launch_step(hipStream_t st, const StepDesc &sd);
+// One step of one proof (descriptor passed by value); ev0 / ev1 (or NULL)
+// are recorded at the start and end of the dispatch.
+hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 // One step of each of njobs proofs (entries in device memory, sorted by
 // block0, followed by a sentinel whose block0 is the total; each job spans
 // step_grid(*step) workgroups).
-hipError_t launch_steps(hipStream_t st, const JobEntry *jobs, u32 njobs, u32 total_blocks);
+hipError_t launch_steps(hipStream_t st, const JobEntry *jobs, u32 njobs, u32 total_blocks,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// A launch's jobs passed by value (serving: the mix changes every launch).
+constexpr int MAX_TABLE_JOBS = 128;
+struct JobTable {
+    u32 n, total;
+    JobEntry e[MAX_TABLE_JOBS];
+};
+hipError_t launch_step_table(hipStream_t st, const JobTable &t);
+
+// One proof of a batch: where its seed and input pointer go, and where its
+// transcript is gathered.
+struct BatchSlot {
+    u64 *state;
+    u64 seed, input;
+    const u64 *msgs;
+    u64 n_msgs, out_off, flag_off;
+};
+hipError_t launch_batch_setup(hipStream_t st, const BatchSlot *slots, u32 n);
+hipError_t launch_batch_gather(hipStream_t st, const BatchSlot *slots, u32 n, u64 *out);
 
 }  // namespace gkr
