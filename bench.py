@@ -21,16 +21,39 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
+    """Hash of every kernel and launch-planning source: a counter summary
+    taken on other sources no longer describes the kernels."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp", "fp61.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_1202_1350_amd", "csrc", f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_1202_1350_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+# Step kinds in the order of the StepKind enum: the profiling class
+# "step_<kind>" is the kernel k_step_one<kind index, ...>.
+STEP_KINDS = ["eval", "start", "eq", "p", "w", "fold", "lt", "line", "sge", "end", "wagg",
+              "wt0", "wt", "wtail", "ptail", "load"]
+
+
+def rocprof_kernel_name(cls):
+    """How rocprofv3 names the kernel of a profiling class (the
+    single-proof step kernels; other classes are returned unchanged)."""
+    if cls.startswith("step_") and cls[5:] in STEP_KINDS and cls != "step_w":
+        return f"void gkr::k_step_one<{STEP_KINDS.index(cls[5:])}u, -1, 0>(gkr::StepDesc)"
+    return cls
+
+
+def traffic_path(cls):
+    return os.path.join(ROOT, "profiles", f"{cls}_f2_n2p22_traffic.txt")
+
+
+def measured_traffic(cls):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_f2_n2p22_traffic.txt")
+    taken on the current kernel sources (else None)."""
+    path = traffic_path(cls)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -44,6 +67,50 @@ def measured_traffic(kernel):
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def _pmc_rows(d, counter):
+    """(kernel name, value) per dispatch from a rocprofv3 --pmc csv."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    rows = []
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") == counter:
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def traffic_summary(fetch_dir, write_dir, cls, copy_bytes, command):
+    """Text summary of HBM traffic per launch of one kernel from two
+    rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
+    scaled by what the same counter reads for the calibration copy (the
+    largest device-to-device blit, of copy_bytes read and written)."""
+    name = rocprof_kernel_name(cls)
+    out = [f"# HBM traffic of {name} (class {cls}), F2 GKR n=2^22, seed 2",
+           f"# command: {command}"]
+    per = {}
+    for label, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _pmc_rows(d, counter)
+        copies = [v for k, v in rows if "copyBuffer" in k]
+        kern = [v for k, v in rows if k == name]
+        if not copies or not kern:
+            raise SystemExit(f"{counter}: calibration copy or kernel {name} missing")
+        cal = max(copies) * 1024.0
+        factor = copy_bytes / cal
+        per[label] = sum(kern) / len(kern) * 1024.0 * factor
+        out += [f"{label}_counter: {counter}",
+                f"{label}_dispatches: {len(kern)}",
+                f"{label}_calibration_copy_counter_bytes: {cal:.0f}",
+                f"{label}_calibration_factor: {factor:.4f}",
+                f"{label}_bytes_per_launch: {per[label]:.0f}"]
+    out += [f"copy_bytes: {copy_bytes}",
+            f"hbm_bytes_per_launch: {per['fetch'] + per['write']:.0f}",
+            f"kernel_source_hash: {kernel_source_hash()}"]
+    return "\n".join(out) + "\n"
 
 
 def cpu_baseline(log_n):
@@ -193,7 +260,19 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also copy a buffer of this size device to device (the "
+                         "known-size kernel that scales the HBM counters)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the HBM traffic summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--kernel", default="step_wt0", help="profiling class for --traffic-summary")
+    ap.add_argument("--command", default="", help="command line recorded in --traffic-summary")
     args = ap.parse_args()
+    if args.traffic_summary:
+        sys.stdout.write(traffic_summary(args.traffic_summary[0], args.traffic_summary[1],
+                                         args.kernel, args.copy_calibration_mib << 20,
+                                         args.command))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "sharding is a design note, not an implemented path", file=sys.stderr)
@@ -246,11 +325,18 @@ def main():
     G.gkr_profile_enable(False)
     prof = G.gkr_profile_read()
 
+    if args.copy_calibration_mib:
+        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     T = np.array(times)
     prove_s = float(T[:, 0].mean())
     value = circ.gates / prove_s
-    # dominant prover kernel: the class with the most device time
-    prover_classes = [k for k in prof if prof[k][1] > 0]
+    # dominant prover kernel: the step kernel with the most device time
+    prover_classes = [k for k in prof if prof[k][1] > 0 and k.startswith("step_")]
     dom = max(prover_classes, key=lambda k: prof[k][0])
     ms, launches, by = prof[dom]
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -279,9 +365,11 @@ def main():
         "kernels_per_proof": {k: {"ms": v[0] / args.steps, "launches": v[1] / args.steps,
                         "GB_per_s": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None}
                     for k, v in prof.items() if v[1]},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": rocprof_kernel_name(dom), "class": dom, "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "avg_launch_us": ms * 1e3 / launches if launches else None,
+                     "algorithmic_bytes_per_launch": by / launches if launches else None,
                      "traffic": traffic},
     }
     if not args.no_batch:

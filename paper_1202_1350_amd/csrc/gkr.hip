@@ -53,13 +53,18 @@ extern "C" const char *gkr_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
+// Profiling classes: one per step kind (the kernel k_step_one<kind, ...>),
+// then the verifier's and the F2 sum-check's kernels.
 enum ProfClass {
-    PC_EVAL, PC_PPHASE, PC_OMEGA, PC_FOLD, PC_FINAL, PC_LINE, PC_TABLES, PC_WIRING, PC_MLE,
-    PC_F2SC, PC_MISC, PC_BATCH, PC_COUNT
+    PC_STEP = 0,  // + StepKind
+    PC_WIRING = 16, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_COUNT
 };
-const char *kProfNames[PC_COUNT] = {"eval", "pphase", "omega", "fold", "final", "line",
-                                    "eq_tables", "wiring", "mle", "f2sc_round", "misc",
-                                    "batch_step"};
+const char *kProfNames[PC_COUNT] = {
+    "step_eval", "step_start", "step_eq", "step_p", "step_w", "step_fold", "step_lt",
+    "step_line", "step_sge", "step_end", "step_wagg", "step_wt0", "step_wt", "step_wtail",
+    "step_ptail", "step_load", "wiring", "mle", "eq_tables", "f2sc_round", "f2sc_final",
+    "misc", "batch_step"};
+static_assert(ST_LOAD + 1 == PC_WIRING, "one profiling class per step kind");
 
 struct ProfRec {
     int cls;
@@ -502,7 +507,7 @@ struct Planner {
     std::vector<double> bytes;
     ProofPtrs pp{};
 
-    StepDesc &add(u32 kind, u32 nblocks, int pclass, double nbytes) {
+    StepDesc &add(u32 kind, u32 nblocks, double nbytes) {
         StepDesc s;
         memset(&s, 0, sizeof s);
         s.kind = kind;
@@ -511,7 +516,7 @@ struct Planner {
         s.fin.draw = -1;
         s.pp = pp;
         out.push_back(s);
-        cls.push_back(pclass);
+        cls.push_back(PC_STEP + (int)kind);
         bytes.push_back(nbytes);
         return out.back();
     }
@@ -541,19 +546,19 @@ struct Planner {
         auto P_ = [&](u64 *p) -> u64 * { return w ? p : nullptr; };
         {
             const u64 Sd = c->S[d], npad = 1ull << c->s[d];
-            StepDesc &s = add(ST_LOAD, sblocks(npad, 4), PC_MISC, Sd * 8.0 + npad * 8.0);
+            StepDesc &s = add(ST_LOAD, sblocks(npad, 4), Sd * 8.0 + npad * 8.0);
             s.u.load = LoadArgs{c->S[d], npad, V(d)};
         }
         // circuit evaluation (a3), layer d-1 down to 0
         for (int i = (int)d - 1; i >= 0; i--) {
             const u64 S = c->S[i], npad = 1ull << c->s[i];
-            StepDesc &s = add(ST_EVAL, sblocks(npad, 4), PC_EVAL,
+            StepDesc &s = add(ST_EVAL, sblocks(npad, 4),
                               S * (8.0 + 16 + 8 + (c->kind[i] == KIND_MIXED)) + (npad - S) * 8.0);
             s.u.eval = EvalArgs{(u32)c->kind[i], c->S[i], npad, c->type[i], c->in1[i], c->in2[i],
                                 V(i + 1), V(i)};
         }
         {
-            StepDesc &s = add(ST_START, sblocks(c->S[0]), PC_MISC, c->S[0] * 16.0);
+            StepDesc &s = add(ST_START, sblocks(c->S[0]), c->S[0] * 16.0);
             s.u.start = StartArgs{c->s[0], c->S[0], V(0)};
         }
         Fin layer_end;  // how the previous layer is finished (line values, tau)
@@ -571,7 +576,8 @@ struct Planner {
             // ---- eq tables of z_i[1..s) for the p-phase's first round
             {
                 const u32 nz = s ? s - 1 : 0;
-                StepDesc &e = add(ST_EQ, sblocks((1ull << (nz / 2)) + (1ull << (nz - nz / 2))), PC_TABLES, 0);
+                const u64 ne = (1ull << (nz / 2)) + (1ull << (nz - nz / 2));
+                StepDesc &e = add(ST_EQ, sblocks(ne), 8.0 * ne);
                 e.fin = layer_end;
                 e.u.eq = EqArgs{PT_Z, nz, nz / 2, 1, P_(w ? w->zlo : nullptr), P_(w ? w->zhi : nullptr)};
             }
@@ -595,7 +601,7 @@ struct Planner {
                 pa.zhi = w ? w->zhi : nullptr;
                 const u32 nz = s - 1;
                 pa.L = nz / 2;
-                StepDesc &st = add(ST_P, sblocks(nm, 2), PC_PPHASE,
+                StepDesc &st = add(ST_P, sblocks(nm, 2),
                                    first ? nm * (16.0 + 8) : nm * (32.0 + 16 + 16 + 8));
                 if (!first) {
                     f.j = j - 1;
@@ -611,7 +617,7 @@ struct Planner {
                 f.j = j0 - 1;
                 f.draw = (i32)(co + j0 - 1);
                 f.msg = w ? msg + 3ull * (j0 - 1) : nullptr;
-                StepDesc &st = add(ST_PTAIL, 1, PC_PPHASE, 24.0 * (1ull << (s - j0 + 1)));
+                StepDesc &st = add(ST_PTAIL, 1, 24.0 * (1ull << (s - j0 + 1)));
                 st.fin = f;
                 PtailArgs pt;
                 pt.j0 = j0;
@@ -628,11 +634,12 @@ struct Planner {
             // ---- eq tables of a* (the p-phase tail recorded every challenge)
             {
                 const u32 La = s / 2;
-                StepDesc &e = add(ST_EQ, sblocks((1ull << La) + (1ull << (s - La))), PC_TABLES, 0);
+                const u64 ne = (1ull << La) + (1ull << (s - La));
+                StepDesc &e = add(ST_EQ, sblocks(ne), 8.0 * ne);
                 e.u.eq = EqArgs{PT_CHAL, s, La, co, w ? w->alo : nullptr, w ? w->ahi : nullptr};
             }
             if (sp == 0) {
-                StepDesc &e = add(ST_SGE, 1, PC_MISC, 8);
+                StepDesc &e = add(ST_SGE, 1, 8);
                 e.u.sge = SgeArgs{V(i + 1), vslot};
                 memset(&layer_end, 0, sizeof layer_end);
                 layer_end.kind = FIN_LINE;
@@ -654,7 +661,8 @@ struct Planner {
                     const u32 rbase = s + (ph == 2 ? sp : 0);
                     const u32 Lb = sp / 2;
                     if (ph == 2) {
-                        StepDesc &e = add(ST_EQ, sblocks((1ull << Lb) + (1ull << (sp - Lb))), PC_TABLES, 0);
+                        const u64 ne = (1ull << Lb) + (1ull << (sp - Lb));
+                        StepDesc &e = add(ST_EQ, sblocks(ne), 8.0 * ne);
                         e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
                     }
                     const gkr_circuit::Group *dg = &c->grp[ph - 1][i];
@@ -680,7 +688,7 @@ struct Planner {
                         a.partA = w ? w->partA : nullptr;
                         a.partC = w ? w->partC : nullptr;
                         // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1
-                        StepDesc &st = add(ST_WAGG, sblocks(nch), PC_OMEGA,
+                        StepDesc &st = add(ST_WAGG, sblocks(nch),
                                            S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) + 20.0 * nch);
                         st.u.wagg = a;
                     }
@@ -696,7 +704,7 @@ struct Planner {
                         a.F = V(i + 1);
                         a.A = w ? w->tA0 : nullptr;
                         a.C = w ? w->tC0 : nullptr;
-                        StepDesc &st = add(ST_WT0, sblocks(N / 2), PC_OMEGA,
+                        StepDesc &st = add(ST_WT0, sblocks(N / 2),
                                            N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 16.0 * nch);
                         st.u.wt0 = a;
                         reduces(3);
@@ -730,7 +738,7 @@ struct Planner {
                         a.Cn = const_cast<u64 *>(C);
                         a.Fn = const_cast<u64 *>(F);
                         const double tabs = hasC ? 3.0 : 2.0;
-                        StepDesc &st = add(ST_WT, sblocks(a.npairs), PC_OMEGA, a.npairs * tabs * (32.0 + 16));
+                        StepDesc &st = add(ST_WT, sblocks(a.npairs), a.npairs * tabs * (32.0 + 16));
                         st.fin = f;
                         st.u.wt = a;
                         reduces(3);
@@ -749,13 +757,13 @@ struct Planner {
                         a.c0 = co + rbase + k0;
                         a.msg = w ? msg + 3ull * (rbase + k0) : nullptr;
                         a.vout = vslot ? vslot + (ph - 1) : nullptr;
-                        StepDesc &st = add(ST_WTAIL, 1, PC_OMEGA, 24.0 * (1ull << (sp - k0 + 1)));
+                        StepDesc &st = add(ST_WTAIL, 1, 24.0 * (1ull << (sp - k0 + 1)));
                         st.fin = f;
                         st.u.wtail = a;
                     }
                 }
                 // ---- line step (a9): every omega challenge is recorded
-                StepDesc &e = add(ST_LT, sblocks(ntab), PC_TABLES, 0);
+                StepDesc &e = add(ST_LT, sblocks(ntab), 8.0 * ntab);
                 e.u.lt = LtArgs{sp >= 2 ? sp : 0, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
                                 w ? w->lhl : nullptr, w ? w->lhh : nullptr};
             } else {
@@ -771,7 +779,8 @@ struct Planner {
                         f.last = 1;
                         f.F = Fend;
                         f.vout = vslot;
-                        StepDesc &e = add(ST_EQ, sblocks((1ull << Lb) + (1ull << (sp - Lb))), PC_TABLES, 0);
+                        const u64 ne = (1ull << Lb) + (1ull << (sp - Lb));
+                        StepDesc &e = add(ST_EQ, sblocks(ne), 8.0 * ne);
                         e.fin = f;
                         e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
                     }
@@ -814,7 +823,7 @@ struct Planner {
                                 a.F = F;       // F^(k-1): the kernel folds it into dst
                                 a.Fout = dst;
                             } else {
-                                StepDesc &fs = add(ST_FOLD, sblocks(a.nfold, 4), PC_FOLD, a.nfold * 24.0);
+                                StepDesc &fs = add(ST_FOLD, sblocks(a.nfold, 4), a.nfold * 24.0);
                                 fs.fin = f;
                                 fs.u.fold = FoldArgs{a.nfold, F, dst};
                                 memset(&f, 0, sizeof f);
@@ -836,8 +845,7 @@ struct Planner {
                                            (ph == 1 && kind != KIND_MUL ? 8 : 0) +
                                            (kind == KIND_MIXED ? 1 : 0) + (a.init ? 4.0 + (ph == 1 ? 8 : 0) : 0);
                         const double nb = S * per + (a.inline_fold ? 24.0 : 8.0) * a.nfold;
-                        StepDesc &ws = add(ST_W, sblocks(std::max<u64>(S, a.inline_fold ? a.nfold : 0), 4),
-                                           PC_OMEGA, nb);
+                        StepDesc &ws = add(ST_W, sblocks(std::max<u64>(S, a.inline_fold ? a.nfold : 0), 4), nb);
                         ws.fin = f;
                         ws.u.w = a;
                         reduces(4);
@@ -852,7 +860,7 @@ struct Planner {
                     f.last = 2;
                     f.F = Fend;
                     f.vout = vslot ? vslot + 1 : nullptr;
-                    StepDesc &e = add(ST_LT, sblocks(ntab), PC_TABLES, 0);
+                    StepDesc &e = add(ST_LT, sblocks(ntab), 8.0 * ntab);
                     e.fin = f;
                     e.u.lt = LtArgs{sp >= 2 ? sp : 1, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
                                     w ? w->lhl : nullptr, w ? w->lhh : nullptr};
@@ -871,7 +879,7 @@ struct Planner {
                     const u32 T = sp - 1;
                     const u32 chunks = (T + LINE_CHUNK - 1) / LINE_CHUNK;
                     const u32 cb = (u32)(((1ull << M) + (SBLOCK / 64) - 1) / (SBLOCK / 64));
-                    StepDesc &ls = add(ST_LINE, chunks * cb, PC_LINE, 8.0 * (1ull << sp) * chunks);
+                    StepDesc &ls = add(ST_LINE, chunks * cb, 8.0 * (1ull << sp) * chunks);
                     ls.u.line = LineArgs{sp, Ll, M, T, cb, V(i + 1), w ? w->llo : nullptr,
                                          w ? w->lhl : nullptr, w ? w->lhh : nullptr};
                     reduces(LINE_CHUNK);
@@ -882,7 +890,7 @@ struct Planner {
                 }
             }
         }
-        StepDesc &e = add(ST_END, 1, PC_MISC, 0);
+        StepDesc &e = add(ST_END, 1, 0);
         e.fin = layer_end;
     }
 };
