@@ -35,7 +35,7 @@ def kernel_source_hash():
 # Step kinds in the order of the StepKind enum: the profiling class
 # "step_<kind>" is the kernel k_step_one<kind index, ...>.
 STEP_KINDS = ["eval", "start", "eq", "p", "w", "fold", "lt", "line", "sge", "end", "wagg",
-              "wt0", "wt", "wtail", "ptail", "load"]
+              "wt0", "wt", "wtail", "ptail", "load", "wa0"]
 
 
 def rocprof_kernel_name(cls):
@@ -159,13 +159,16 @@ def batch_leg(G, W, np, torch, reps):
             "batched_proofs_per_s": len(circs) / t_batch, "speedup": t_plain / t_batch}
 
 
-def serve_leg(G, W, np, n_req, rates):
+def serve_leg(G, W, np, n_req, n_sat, rates):
     """Poisson proof requests (seed 5): type uniform over F2 (n = 2^u, u an
     integer uniform in [14, 22]), MatMult (N in {64, 128, 256}) and PM (text
     2^16, pattern 8).  Circuits are registered once per shape, as a service
-    would.  First the closed-loop saturation rate, then open-loop arrivals at
-    fractions of it; latency runs from the scheduled arrival to completion."""
-    draws = W.splitmix64(5, 5, 4 * (n_req * (1 + len(rates)) + 8))
+    would.  First the closed-loop saturation rate (n_sat requests submitted
+    at once), then open-loop arrivals at the given fractions of it, n_req
+    requests per point; the first 10% of each point are warm-up.  Latency
+    runs from the scheduled arrival to completion."""
+    total = n_sat + n_req * len(rates)
+    draws = W.splitmix64(5, 5, 4 * total)
     shapes = {}
 
     def shape(kind, size):
@@ -191,7 +194,7 @@ def serve_leg(G, W, np, n_req, rates):
         gap = -np.log(1.0 - float(draws[4 * k + 2] >> np.uint64(11)) / float(1 << 53))
         return kind, size, int(draws[4 * k + 3] >> np.uint64(8)), gap
 
-    reqs = [request(k) for k in range(n_req * (1 + len(rates)))]
+    reqs = [request(k) for k in range(total)]
     for kind, size, _, _ in reqs:
         shape(kind, size)
     srv = G.Server(32 << 30, 32)
@@ -201,51 +204,58 @@ def serve_leg(G, W, np, n_req, rates):
         while ids:
             ids = [r for r in ids if not srv.poll(r)[0]]
         # closed loop: all requests at once
-        batch = reqs[:n_req]
         t0 = time.perf_counter()
-        ids = [srv.submit(shape(k, sz)[0], shape(k, sz)[1], sd) for k, sz, sd, _ in batch]
+        ids = [srv.submit(shape(k, sz)[0], shape(k, sz)[1], sd) for k, sz, sd, _ in reqs[:n_sat]]
         pending = set(ids)
         while pending:
             pending = {r for r in pending if not srv.poll(r)[0]}
-        sat = n_req / (time.perf_counter() - t0)
+        sat = n_sat / (time.perf_counter() - t0)
         points = []
         for pi, frac in enumerate(rates):
             rate = frac * sat
-            part = reqs[n_req * (pi + 1): n_req * (pi + 2)]
+            part = reqs[n_sat + n_req * pi: n_sat + n_req * (pi + 1)]
             arrivals = np.cumsum([gap / rate for _, _, _, gap in part])
+            warm = len(part) // 10
             t0 = time.perf_counter()
-            sched, lats, ids = {}, [], []
+            sched, done_at, gates_of = {}, {}, {}
             k = 0
             pending = set()
-            gates = 0
             while k < len(part) or pending:
                 now = time.perf_counter() - t0
                 while k < len(part) and arrivals[k] <= now:
                     kind, sz, sd, _ = part[k]
                     c, x, g = shape(kind, sz)
                     rid = srv.submit(c, x, sd)
-                    sched[rid] = arrivals[k]
-                    gates += g
+                    sched[rid] = (k, arrivals[k])
+                    gates_of[rid] = g
                     pending.add(rid)
                     k += 1
                 for rid in list(pending):
-                    done, _, _ = srv.poll(rid)
-                    if done:
-                        lats.append(time.perf_counter() - t0 - sched[rid])
+                    if srv.poll(rid)[0]:
+                        done_at[rid] = time.perf_counter() - t0
                         pending.discard(rid)
                 if k < len(part) and not pending:
                     time.sleep(max(0.0, min(0.001, arrivals[k] - (time.perf_counter() - t0))))
-            span = time.perf_counter() - t0
-            lats.sort()
+            # measurement window: after the warm-up requests have arrived
+            w0 = arrivals[warm] if warm < len(arrivals) else 0.0
+            in_win = [r for r in done_at if sched[r][0] >= warm]
+            span = max(done_at[r] for r in in_win) - w0
+            lats = sorted(done_at[r] - sched[r][1] for r in in_win)
             points.append({"rate_frac_of_saturation": frac, "offered_proofs_per_s": rate,
-                           "proofs_per_s": len(part) / span, "gates_per_s": gates / span,
+                           "requests_measured": len(in_win),
+                           "proofs_per_s": len(in_win) / span,
+                           "gates_per_s": sum(gates_of[r] for r in in_win) / span,
                            "p50_ms": 1e3 * lats[len(lats) // 2],
                            "p99_ms": 1e3 * lats[min(len(lats) - 1, int(0.99 * len(lats)))]})
+            print(f"serve point {frac:.2f}x: {points[-1]['proofs_per_s']:.1f} proofs/s, "
+                  f"p50 {points[-1]['p50_ms']:.1f} ms, p99 {points[-1]['p99_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
     finally:
         srv.close()
     return {"workload": "Poisson mix of F2 n=2^[14..22], MatMult N in {64,128,256}, "
                         "PM text 2^16 (seed 5); 32 slots, 32 GiB budget",
-            "requests_per_point": n_req, "closed_loop_proofs_per_s": sat, "points": points}
+            "requests_per_point": n_req, "warmup_fraction": 0.1,
+            "closed_loop_requests": n_sat, "closed_loop_proofs_per_s": sat, "points": points}
 
 
 def main():
@@ -259,7 +269,9 @@ def main():
     ap.add_argument("--cpu-log-n", type=int, default=22)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate point")
+    ap.add_argument("--serve-points", type=int, default=8,
+                    help="rate points, geometric from 0.1x to 1.5x saturation")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also copy a buffer of this size device to device (the "
                          "known-size kernel that scales the HBM counters)")
@@ -375,7 +387,9 @@ def main():
     if not args.no_batch:
         line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2))
     if not args.no_serve:
-        line["served"] = serve_leg(G, W, np, args.serve_requests, [0.25, 0.5, 0.9, 1.2])
+        k = max(1, args.serve_points)
+        rates = [0.1 * 15.0 ** (j / (k - 1)) for j in range(k)] if k > 1 else [1.0]
+        line["served"] = serve_leg(G, W, np, args.serve_requests, 200, rates)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_log_n)
     print(json.dumps(line), flush=True)

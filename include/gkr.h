@@ -195,9 +195,11 @@ int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_device, uint64_t
                        const uint64_t *msgs, uint64_t n_msgs, int *accepted,
                        gkr_reject_info *why, void *hip_stream);
 
-/* Elementwise F_p arithmetic on the device field module (Sec. 5.1), for
- * checking it: out[k] = a[k] op b[k], op 0 = add, 1 = sub, 2 = mul;
- * a, b, out are device arrays of n canonical values.  Errors:
+/* F_p arithmetic on the device field module (Sec. 5.1), for checking it:
+ * out[k] = a[k] op b[k], op 0 = add, 1 = sub, 2 = mul; op 3 = the sum of
+ * the 64 products a[j] b[j], j = k, k+1, ..., k+63 (indices mod n),
+ * accumulated in 128 bits and reduced once (the lazy reduction the prover's
+ * sums use).  a, b, out are device arrays of n canonical values.  Errors:
  * GKR_ERR_INVALID, GKR_ERR_DEVICE. */
 int gkr_field_op(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
                  void *hip_stream);

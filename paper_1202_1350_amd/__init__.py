@@ -284,7 +284,7 @@ def f2_sumcheck_verify(freq, seed: int, msgs, stream=None):
 
 
 def gkr_field_op(op: int, a, b, out, stream=None):
-    """Elementwise field op on device tensors (0 add, 1 sub, 2 mul)."""
+    """Field op on device tensors (0 add, 1 sub, 2 mul, 3 lazy sum of 64 products)."""
     pa, _, _ = _ptr(a, np.uint64)
     pb, _, _ = _ptr(b, np.uint64)
     po, dev, _ = _ptr(out, np.uint64)

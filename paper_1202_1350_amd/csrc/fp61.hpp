@@ -39,6 +39,20 @@ __host__ __device__ __forceinline__ u64 mul(u64 a, u64 b) {
     return canon(s);
 }
 
+// Lazy reduction: a sum of up to 64 products of canonical values (each
+// below 2^122) is accumulated exactly in 128 bits and reduced once.
+typedef unsigned __int128 u128;
+
+__host__ __device__ __forceinline__ u128 wide(u64 a, u64 b) { return (u128)a * b; }
+
+__host__ __device__ __forceinline__ u64 red128(u128 x) {
+    const u64 lo = (u64)x, hi = (u64)(x >> 64);
+    // x = hi 2^64 + lo and 2^64 = 8 (mod p); hi 8 = (hi >> 58) 2^61 + ((hi << 3) & p)
+    u64 s = (lo & P) + (lo >> 61) + ((hi << 3) & P) + (hi >> 58);  // < 2^63
+    s = (s & P) + (s >> 61);                                          // <= p + 3
+    return canon(s);
+}
+
 // eq(bit, r) = r if bit else 1 - r
 __host__ __device__ __forceinline__ u64 eqbit(u32 bit, u64 r) { return bit ? r : sub(1, r); }
 

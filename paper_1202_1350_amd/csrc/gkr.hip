@@ -57,14 +57,14 @@ namespace {
 // then the verifier's and the F2 sum-check's kernels.
 enum ProfClass {
     PC_STEP = 0,  // + StepKind
-    PC_WIRING = 16, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_COUNT
+    PC_WIRING = 17, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {
     "step_eval", "step_start", "step_eq", "step_p", "step_w", "step_fold", "step_lt",
     "step_line", "step_sge", "step_end", "step_wagg", "step_wt0", "step_wt", "step_wtail",
-    "step_ptail", "step_load", "wiring", "mle", "eq_tables", "f2sc_round", "f2sc_final",
-    "misc", "batch_step"};
-static_assert(ST_LOAD + 1 == PC_WIRING, "one profiling class per step kind");
+    "step_ptail", "step_load", "step_wa0", "wiring", "mle", "eq_tables", "f2sc_round",
+    "f2sc_final", "misc", "batch_step"};
+static_assert(ST_WA0 + 1 == PC_WIRING, "one profiling class per step kind");
 
 struct ProfRec {
     int cls;
@@ -274,6 +274,7 @@ struct gkr_circuit {
     struct Group {  // gates of a layer grouped by the wire a phase binds
         u32 *perm = nullptr, *cstart = nullptr, *xch = nullptr;
         u32 nch = 0;
+        bool single = false;  // every wire carries at most one chunk
     };
     std::vector<Group> grp[2];  // [phase - 1][layer], built with the first table workspace
     void *gmem = nullptr;       // device memory of the groups
@@ -668,14 +669,17 @@ struct Planner {
                     const gkr_circuit::Group *dg = &c->grp[ph - 1][i];
                     const u32 nch = dg->nch;
                     const u32 hasC = kind != KIND_MUL;
-                    {
-                        WaggArgs a;
+                    if (dg->single) {
+                        // gates summed per wire and round 0 in one pass
+                        Wa0Args a;
                         memset(&a, 0, sizeof a);
                         a.kind = kind;
                         a.ph = ph;
-                        a.nch = nch;
+                        a.hasC = hasC;
+                        a.npairs = N / 2;
                         a.perm = dg->perm;
                         a.cstart = dg->cstart;
+                        a.xch = dg->xch;
                         a.oth = ph == 1 ? c->in2[i] : c->in1[i];
                         a.type = c->type[i];
                         a.Vn = V(i + 1);
@@ -685,29 +689,58 @@ struct Planner {
                         a.blo = w ? w->blo : nullptr;
                         a.bhi = w ? w->bhi : nullptr;
                         a.Lb = Lb;
-                        a.partA = w ? w->partA : nullptr;
-                        a.partC = w ? w->partC : nullptr;
-                        // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1
-                        StepDesc &st = add(ST_WAGG, sblocks(nch),
-                                           S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) + 20.0 * nch);
-                        st.u.wagg = a;
-                    }
-                    {
-                        Wt0Args a;
-                        memset(&a, 0, sizeof a);
-                        a.ph = ph;
-                        a.hasC = hasC;
-                        a.npairs = N / 2;
-                        a.xch = dg->xch;
-                        a.partA = w ? w->partA : nullptr;
-                        a.partC = w ? w->partC : nullptr;
-                        a.F = V(i + 1);
                         a.A = w ? w->tA0 : nullptr;
                         a.C = w ? w->tC0 : nullptr;
-                        StepDesc &st = add(ST_WT0, sblocks(N / 2),
-                                           N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 16.0 * nch);
-                        st.u.wt0 = a;
+                        // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1;
+                        // per table entry: chunk index 4, F 8, A 8 (+ C 8)
+                        StepDesc &st = add(ST_WA0, sblocks(N / 2),
+                                           S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) +
+                                               N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 8.0 * nch);
+                        st.u.wa0 = a;
                         reduces(3);
+                    } else {
+                        // gate sums per chunk, then level-0 tables and round 0
+                        {
+                            WaggArgs a;
+                            memset(&a, 0, sizeof a);
+                            a.kind = kind;
+                            a.ph = ph;
+                            a.nch = nch;
+                            a.perm = dg->perm;
+                            a.cstart = dg->cstart;
+                            a.oth = ph == 1 ? c->in2[i] : c->in1[i];
+                            a.type = c->type[i];
+                            a.Vn = V(i + 1);
+                            a.alo = w ? w->alo : nullptr;
+                            a.ahi = w ? w->ahi : nullptr;
+                            a.La = s / 2;
+                            a.blo = w ? w->blo : nullptr;
+                            a.bhi = w ? w->bhi : nullptr;
+                            a.Lb = Lb;
+                            a.partA = w ? w->partA : nullptr;
+                            a.partC = w ? w->partC : nullptr;
+                            // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1
+                            StepDesc &st = add(ST_WAGG, sblocks(nch),
+                                               S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) + 20.0 * nch);
+                            st.u.wagg = a;
+                        }
+                        {
+                            Wt0Args a;
+                            memset(&a, 0, sizeof a);
+                            a.ph = ph;
+                            a.hasC = hasC;
+                            a.npairs = N / 2;
+                            a.xch = dg->xch;
+                            a.partA = w ? w->partA : nullptr;
+                            a.partC = w ? w->partC : nullptr;
+                            a.F = V(i + 1);
+                            a.A = w ? w->tA0 : nullptr;
+                            a.C = w ? w->tC0 : nullptr;
+                            StepDesc &st = add(ST_WT0, sblocks(N / 2),
+                                               N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 16.0 * nch);
+                            st.u.wt0 = a;
+                            reduces(3);
+                        }
                     }
                     auto level = [&](u32 k, const u64 **A, const u64 **C, const u64 **F) {
                         if (k == 0) {
@@ -932,6 +965,9 @@ static int ensure_groups(gkr_circuit *c) {
             HIP_TRY(put(G.cstart, &D.cstart));
             HIP_TRY(put(G.xch, &D.xch));
             D.nch = (u32)G.cstart.size() - 1;
+            D.single = true;
+            for (size_t x = 0; x + 1 < G.xch.size() && D.single; x++)
+                D.single = G.xch[x + 1] - G.xch[x] <= 1;
         }
     return GKR_OK;
 }
@@ -960,6 +996,9 @@ static int make_workspace(gkr_circuit *c, Workspace **out) {
     Planner plan{c, ws.get()};
     plan.build();
     if (plan.out.size() != nsteps) return fail(GKR_ERR_INVALID, "step program changed size");
+    for (const StepDesc &sd : plan.out)
+        if (sd.fin.kind != FIN_NONE && !((fin_mask(sd.kind) >> sd.fin.kind) & 1))
+            return fail(GKR_ERR_INVALID, "step program: a step carries a finish its kernel lacks");
     ws->steps = plan.out;
     ws->pclass = plan.cls;
     ws->pbytes = plan.bytes;
@@ -1689,7 +1728,7 @@ extern "C" int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_devic
 
 extern "C" int gkr_field_op(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
                             void *hip_stream) {
-    if (op < 0 || op > 2 || (n && (!a || !b || !out))) return fail(GKR_ERR_INVALID, "bad argument");
+    if (op < 0 || op > 3 || (n && (!a || !b || !out))) return fail(GKR_ERR_INVALID, "bad argument");
     hipStream_t st = pick_stream(hip_stream);
     if (!st) return fail(GKR_ERR_DEVICE, "no stream");
     if (n == 0) return GKR_OK;

@@ -310,6 +310,15 @@ hipError_t launch_f2sc_single(hipStream_t st, const u32 *a32, u64 *msg) {
 __global__ void __launch_bounds__(BLOCK) k_field_op(int op, const u64 *a, const u64 *b, u64 *out,
                                                     u64 n) {
     for (u64 i = GTID; i < n; i += GSTRIDE) {
+        if (op == 3) {
+            fp::u128 s = 0;
+            for (u64 j = 0; j < 64; j++) {
+                const u64 k = (i + j) % n;
+                s += fp::wide(a[k], b[k]);
+            }
+            out[i] = fp::red128(s);
+            continue;
+        }
         const u64 x = a[i], y = b[i];
         out[i] = op == 0 ? add(x, y) : (op == 1 ? sub(x, y) : mul(x, y));
     }

@@ -16,6 +16,7 @@ using fp::add;
 using fp::mul;
 using fp::P;
 using fp::sub;
+using fp::u128;
 
 struct alignas(16) u64x2 {
     u64 x, y;
@@ -30,22 +31,45 @@ __device__ __forceinline__ void st2(u64 *p, u64 i, u64 a, u64 b) {
 
 constexpr int NWAVES = SBLOCK / 64;
 
-template <int K>
-__device__ __forceinline__ void wave_reduce(u64 (&v)[K]) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-        for (int k = 0; k < K; k++) v[k] = add(v[k], __shfl_xor(v[k], o));
-    }
+// Data-parallel primitives moving one u64 as two 32-bit halves.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ u64 dpp64(u64 v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u32)v, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u32)(v >> 32), CTRL, ROWS, 0xf, true);
+    return ((u64)(u32)hi << 32) | (u64)(u32)lo;
+}
+__device__ __forceinline__ u64 down64(u64 v, u32 d) {
+    const int lo = __shfl_down((int)(u32)v, d), hi = __shfl_down((int)(u32)(v >> 32), d);
+    return ((u64)(u32)hi << 32) | (u64)(u32)lo;
+}
+__device__ __forceinline__ u64 lane63(u64 v) {
+    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, 63);
+    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(v >> 32), 63);
+    return ((u64)hi << 32) | lo;
+}
+
+// Sum over the wave, left in lane 63: prefix sums within each row of 16
+// lanes (shifts 1, 2, 4, 8), then row 0's total into row 1 and row 2's into
+// row 3, then lane 31's into rows 2 and 3.  Lanes a shift leaves without a
+// source read 0.
+__device__ __forceinline__ u64 wave_sum63(u64 v) {
+    v = add(v, dpp64<0x111, 0xf>(v));  // row_shr:1
+    v = add(v, dpp64<0x112, 0xf>(v));  // row_shr:2
+    v = add(v, dpp64<0x114, 0xf>(v));  // row_shr:4
+    v = add(v, dpp64<0x118, 0xf>(v));  // row_shr:8
+    v = add(v, dpp64<0x142, 0xa>(v));  // row_bcast:15 into rows 1, 3
+    v = add(v, dpp64<0x143, 0xc>(v));  // row_bcast:31 into rows 2, 3
+    return v;
 }
 
 // Workgroup sum of v; thread k < K writes total k to out[k].
 template <int K>
 __device__ __forceinline__ void block_store(u64 (&v)[K], u64 *out) {
     __shared__ u64 sm[K][NWAVES];
-    wave_reduce<K>(v);
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = wave_sum63(v[k]);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < K; k++) sm[k][wid] = v[k];
     }
@@ -64,15 +88,33 @@ __device__ __forceinline__ void block_store(u64 (&v)[K], u64 *out) {
 template <int K>
 __device__ __forceinline__ void rows_total(const u64 *rows, u32 first, u32 n, u64 (&tot)[K]) {
     __shared__ u64 res[K];
-    u64 v[K];
+    if constexpr (K >= 8) {
+        // thread t adds column t % K of rows t / K, t / K + G, ...; then the
+        // G partial columns are added in LDS
+        constexpr u32 G = SBLOCK / K;
+        __shared__ u64 part[G][K];
+        const u32 k = threadIdx.x % K, g = threadIdx.x / K;
+        u64 v = 0;
+        for (u32 r = g; r < n; r += G) v = add(v, rows[(u64)(first + r) * ROW_STRIDE + k]);
+        part[g][k] = v;
+        __syncthreads();
+        if (threadIdx.x < K) {
+            u64 a = 0;
+            for (u32 q = 0; q < G; q++) a = add(a, part[q][threadIdx.x]);
+            res[threadIdx.x] = a;
+        }
+        __syncthreads();
+    } else {
+        u64 v[K];
 #pragma unroll
-    for (int k = 0; k < K; k++) v[k] = 0;
-    for (u32 r = threadIdx.x; r < n; r += SBLOCK) {
-        const u64 *row = rows + (u64)(first + r) * ROW_STRIDE;
+        for (int k = 0; k < K; k++) v[k] = 0;
+        for (u32 r = threadIdx.x; r < n; r += SBLOCK) {
+            const u64 *row = rows + (u64)(first + r) * ROW_STRIDE;
 #pragma unroll
-        for (int k = 0; k < K; k++) v[k] = add(v[k], row[k]);
+            for (int k = 0; k < K; k++) v[k] = add(v[k], row[k]);
+        }
+        block_store<K>(v, res);
     }
-    block_store<K>(v, res);
 #pragma unroll
     for (int k = 0; k < K; k++) tot[k] = res[k];
 }
@@ -92,10 +134,12 @@ struct Ctx {
 
 // ------------------------------------------------------------- prologue
 
+template <u32 KIND>
 __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
-    if (f.kind == FIN_P) {
+    constexpr u32 FM = fin_mask(KIND);
+    if ((FM & (1u << FIN_P)) && f.kind == FIN_P) {
         u64 t[2];
         rows_total<2>(f.rows, 0, f.nrows, t);
         if (threadIdx.x == 0) {
@@ -106,7 +150,7 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
             f.msg[2] = mul(mul(C, c3), sub(add(S1, S1), S0));
             pp.state[0] = mul(C, fp::eq(z, c.r));     // beta prefix over r_0..r_j
         }
-    } else if (f.kind == FIN_W) {
+    } else if ((FM & (1u << FIN_W)) && f.kind == FIN_W) {
         u64 t[4];
         rows_total<4>(f.rows, 0, f.nrows, t);
         if (threadIdx.x == 0) {
@@ -123,7 +167,7 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
                 if (f.last == 1) pp.state[1] = v;
             }
         }
-    } else if (f.kind == FIN_T) {
+    } else if ((FM & (1u << FIN_T)) && f.kind == FIN_T) {
         u64 t[3];
         rows_total<3>(f.rows, 0, f.nrows, t);
         if (threadIdx.x == 0) {
@@ -131,7 +175,7 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
             f.msg[1] = t[1];
             f.msg[2] = t[2];
         }
-    } else if (f.kind == FIN_LINE) {
+    } else if ((FM & (1u << FIN_LINE)) && f.kind == FIN_LINE) {
         if (f.T > 0) {
             u64 t[LINE_CHUNK];
             rows_total<LINE_CHUNK>(f.rows, 0, f.chunk_blocks, t);
@@ -361,17 +405,26 @@ __device__ void step_line(const LineArgs &a, const Ctx &c, u64 *row) {
 #pragma unroll
     for (int t = 0; t < LINE_CHUNK; t++) acc[t] = 0;
     if (lane < nlo && mid < nhl) {
+        // products summed exactly in 128 bits, reduced every 64 terms
+        u128 w128[LINE_CHUNK];
+#pragma unroll
+        for (int t = 0; t < LINE_CHUNK; t++) w128[t] = 0;
         for (u64 h = 0; h < nhh; h++) {
             const u64 v = a.V[(((h << a.M) + mid) << a.L) + lane];
             const u64 *w = a.hh + h * T + t0;
 #pragma unroll
             for (int t = 0; t < LINE_CHUNK; t++)
-                if (t0 + t < T) acc[t] = add(acc[t], mul(w[t], v));
+                if (t0 + t < T) w128[t] += fp::wide(w[t], v);
+            if ((h & 63) == 63) {
+#pragma unroll
+                for (int t = 0; t < LINE_CHUNK; t++) w128[t] = fp::red128(w128[t]);
+            }
         }
 #pragma unroll
         for (int t = 0; t < LINE_CHUNK; t++)
             if (t0 + t < T)
-                acc[t] = mul(acc[t], mul(a.hl[(u64)(t0 + t) * nhl + mid], a.lo[(u64)(t0 + t) * nlo + lane]));
+                acc[t] = mul(fp::red128(w128[t]),
+                             mul(a.hl[(u64)(t0 + t) * nhl + mid], a.lo[(u64)(t0 + t) * nlo + lane]));
     }
     block_store<LINE_CHUNK>(acc, row);
 }
@@ -386,36 +439,44 @@ __device__ void step_line(const LineArgs &a, const Ctx &c, u64 *row) {
 // k challenges (all three are multilinear in the bound bits).  The gates are
 // read once per phase instead of once per round.
 
+// Sums over the gates perm[p0 .. p1) of one wire x.  Phase 1: MUL gates
+// put w V[in2] on x's value (sA), ADD gates put w on it (sA) and add
+// w V[in2] (sC).  Phase 2: sums of the weights over ADD gates (sA) and MUL
+// gates (sC); v1 enters when the level-0 tables are formed.
+template <typename Args>
+__device__ __forceinline__ void wire_sums(const Args &a, u64 beta, u32 p0, u32 p1, u64 &sA, u64 &sC) {
+    const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
+    sA = 0;
+    sC = 0;
+    for (u32 p = p0; p < p1; p++) {
+        const u32 g = a.perm[p];
+        const bool ismul = a.kind == 1 || (a.kind == 2 && a.type[g]);
+        u64 w = mul(beta, mul(a.alo[g & amask], a.ahi[g >> a.La]));
+        if (a.ph == 1) {
+            const u64 y = a.Vn[a.oth[g]];
+            const u64 wy = mul(w, y);
+            if (ismul) {
+                sA = add(sA, wy);
+            } else {
+                sA = add(sA, w);
+                sC = add(sC, wy);
+            }
+        } else {
+            const u32 i1 = a.oth[g];
+            w = mul(w, mul(a.blo[i1 & bmask], a.bhi[i1 >> a.Lb]));
+            if (ismul)
+                sC = add(sC, w);
+            else
+                sA = add(sA, w);
+        }
+    }
+}
+
 __device__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp, const Ctx &c) {
     const u64 beta = pp.state[0];  // beta(z, a*)
-    const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
     for (u64 ch = c.gtid; ch < a.nch; ch += c.gstride) {
-        const u32 p0 = a.cstart[ch], p1 = a.cstart[ch + 1];
-        u64 sA = 0, sC = 0;
-        for (u32 p = p0; p < p1; p++) {
-            const u32 g = a.perm[p];
-            const bool ismul = a.kind == 1 || (a.kind == 2 && a.type[g]);
-            u64 w = mul(beta, mul(a.alo[g & amask], a.ahi[g >> a.La]));
-            if (a.ph == 1) {
-                // MUL: w V[in2] on the wire's value; ADD: w on it, w V[in2] added
-                const u64 y = a.Vn[a.oth[g]];
-                const u64 wy = mul(w, y);
-                if (ismul) {
-                    sA = add(sA, wy);
-                } else {
-                    sA = add(sA, w);
-                    sC = add(sC, wy);
-                }
-            } else {
-                const u32 i1 = a.oth[g];
-                w = mul(w, mul(a.blo[i1 & bmask], a.bhi[i1 >> a.Lb]));
-                // sums over ADD gates (sA) and MUL gates (sC); v1 enters in WT0
-                if (ismul)
-                    sC = add(sC, w);
-                else
-                    sA = add(sA, w);
-            }
-        }
+        u64 sA, sC;
+        wire_sums(a, beta, a.cstart[ch], a.cstart[ch + 1], sA, sC);
         a.partA[ch] = sA;
         a.partC[ch] = sC;
     }
@@ -428,6 +489,18 @@ __device__ __forceinline__ void table_terms(u64 A0, u64 A1, u64 C0, u64 C1, u64 
     acc[0] = add(acc[0], add(mul(A0, F0), C0));
     acc[1] = add(acc[1], add(mul(A1, F1), C1));
     acc[2] = add(acc[2], add(mul(A2, F2), C2));
+}
+
+// Level-0 entries from a wire's sums (phase 2: ADD gates w (v1 + G(t)),
+// MUL gates w v1 G(t)).
+__device__ __forceinline__ void level0(u32 ph, u64 v1, u64 sA, u64 sC, u64 &A, u64 &C) {
+    if (ph == 2) {
+        A = add(sA, mul(v1, sC));
+        C = mul(v1, sA);
+    } else {
+        A = sA;
+        C = sC;
+    }
 }
 
 __device__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
@@ -443,18 +516,33 @@ __device__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, const Ctx &c, u6
                 sA = add(sA, a.partA[ch]);
                 sC = add(sC, a.partC[ch]);
             }
-            if (a.ph == 2) {
-                // ADD gates: w (v1 + G(t)); MUL gates: w v1 G(t)
-                A[h] = add(sA, mul(v1, sC));
-                C[h] = mul(v1, sA);
-            } else {
-                A[h] = sA;
-                C[h] = sC;
-            }
+            level0(a.ph, v1, sA, sC, A[h], C[h]);
         }
         st2(a.A, 2 * m, A[0], A[1]);
         if (a.hasC) st2(a.C, 2 * m, C[0], C[1]);
         const u64x2 f = ld2(a.F, 2 * m);
+        table_terms(A[0], A[1], a.hasC ? C[0] : 0, a.hasC ? C[1] : 0, f.x, f.y, acc);
+    }
+    block_store<3>(acc, row);
+}
+
+__device__ void step_wa0(const Wa0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
+    const u64 beta = pp.state[0];
+    const u64 v1 = a.ph == 2 ? pp.state[1] : 0;
+    u64 acc[3] = {0, 0, 0};
+    for (u64 m = c.gtid; m < a.npairs; m += c.gstride) {
+        u64 A[2], C[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const u64 x = 2 * m + h;
+            const u32 ch = a.xch[x];
+            u64 sA = 0, sC = 0;
+            if (ch < a.xch[x + 1]) wire_sums(a, beta, a.cstart[ch], a.cstart[ch + 1], sA, sC);
+            level0(a.ph, v1, sA, sC, A[h], C[h]);
+        }
+        st2(a.A, 2 * m, A[0], A[1]);
+        if (a.hasC) st2(a.C, 2 * m, C[0], C[1]);
+        const u64x2 f = ld2(a.Vn, 2 * m);
         table_terms(A[0], A[1], a.hasC ? C[0] : 0, a.hasC ? C[1] : 0, f.x, f.y, acc);
     }
     block_store<3>(acc, row);
@@ -482,151 +570,302 @@ __device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
     block_store<3>(acc, row);
 }
 
-// Sum three values over the workgroup; every thread gets the totals.
-__device__ __forceinline__ void block_total3(u64 (&v)[3]) {
-    __shared__ u64 res[3];
-    block_store<3>(v, res);
-    v[0] = res[0];
-    v[1] = res[1];
-    v[2] = res[2];
+// ------------------------------------------------------------------ tails
+//
+// A tail runs the last rounds of a phase in one workgroup.  Level-l tables
+// live in registers: while a table has at least 2 * SBLOCK entries, thread t
+// holds entries [t E, (t + 1) E) and pairs are thread-local; below that,
+// entry e sits in thread e * sg (stride sg doubles each round) and a pair's
+// second entry comes from sg lanes up; once 64 entries remain they are
+// gathered into wave 0, which finishes the phase without barriers.  A round
+// costs one barrier while several waves hold entries, none afterwards.
+
+// Workgroup totals of K values, received by every thread; one barrier.
+// Consecutive calls must alternate between two slot areas.
+template <int K>
+__device__ __forceinline__ void group_total(u64 (&v)[K], u64 (*slot)[NWAVES]) {
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = wave_sum63(v[k]);
+    if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+        for (int k = 0; k < K; k++) slot[k][threadIdx.x >> 6] = v[k];
+    }
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        u64 t = slot[k][0];
+#pragma unroll
+        for (int w = 1; w < NWAVES; w++) t = add(t, slot[k][w]);
+        v[k] = t;
+    }
 }
 
-// Remaining omega rounds k0..s'-1 in one workgroup, tables in LDS.  The
-// prologue drew r_{k0-1}; each round's message is written before its
-// challenge is drawn, and after the last fold F holds v1 (or v2).
+// Wave totals of K values, received by every lane (no barrier).
+template <int K>
+__device__ __forceinline__ void wave_total(u64 (&v)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = lane63(wave_sum63(v[k]));
+}
+
+__device__ __forceinline__ u64 fold1(u64 x0, u64 x1, u64 r) { return add(x0, mul(r, sub(x1, x0))); }
+
+constexpr int TAIL_E = TAIL_LIM / SBLOCK;  // entries per thread at most
+
+// Remaining omega rounds k0..s'-1.  The prologue drew r_{k0-1}; each round
+// writes its message, then draws its challenge; after the last fold F holds
+// v1 (or v2).
 __device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx &c) {
-    __shared__ u64 tA[TAIL_LIM], tC[TAIL_LIM], tF[TAIL_LIM];
-    __shared__ u64 s_r2;
-    u32 M = 1u << (a.sp - a.k0);
+    __shared__ u64 s_sum[2][3][NWAVES];
+    __shared__ u64 s_g[3][64];
+    const u32 tid = threadIdx.x, lane = tid & 63;
+    const bool hc = a.hasC != 0;
+    u32 n = 1u << (a.sp - a.k0);  // entries of level k0
+    u32 E = n >= 2 * SBLOCK ? n / SBLOCK : 1;
+    u64 A[TAIL_E], C[TAIL_E], F[TAIL_E];
     {
+        // level k0 = fold of level k0-1 (2n entries in memory) by r_{k0-1}
         const u64 r = c.r;
-        for (u32 x = threadIdx.x; x < M; x += SBLOCK) {
-            const u64x2 pa = ld2(a.A, 2 * x), pf = ld2(a.F, 2 * x);
-            tA[x] = add(pa.x, mul(r, sub(pa.y, pa.x)));
-            tF[x] = add(pf.x, mul(r, sub(pf.y, pf.x)));
-            if (a.hasC) {
-                const u64x2 pc = ld2(a.C, 2 * x);
-                tC[x] = add(pc.x, mul(r, sub(pc.y, pc.x)));
-            } else {
-                tC[x] = 0;
+        const u32 e0 = tid * E;
+#pragma unroll
+        for (int q = 0; q < TAIL_E; q++) {
+            A[q] = C[q] = F[q] = 0;
+            if (q < (int)E && e0 + q < n) {
+                const u64x2 pa = ld2(a.A, 2 * (e0 + q)), pf = ld2(a.F, 2 * (e0 + q));
+                A[q] = fold1(pa.x, pa.y, r);
+                F[q] = fold1(pf.x, pf.y, r);
+                if (hc) {
+                    const u64x2 pc = ld2(a.C, 2 * (e0 + q));
+                    C[q] = fold1(pc.x, pc.y, r);
+                }
             }
         }
     }
-    u64 st = 0;
-    if (threadIdx.x == 0) st = pp.rngst[a.c0];
-    __syncthreads();
-    for (u32 k = a.k0; k < a.sp; k++) {
-        u64 acc[3] = {0, 0, 0};
-        for (u32 m = threadIdx.x; m < M / 2; m += SBLOCK)
-            table_terms(tA[2 * m], tA[2 * m + 1], tC[2 * m], tC[2 * m + 1], tF[2 * m], tF[2 * m + 1], acc);
-        block_total3(acc);
-        if (threadIdx.x == 0) {
-            u64 *msg = a.msg + 3ull * (k - a.k0);
-            msg[0] = acc[0];
-            msg[1] = acc[1];
-            msg[2] = acc[2];
-            const u32 ci = a.c0 + (k - a.k0);
-            const u64 r = fp::sm_field(st);
-            pp.chals[ci] = r;
-            pp.rngst[ci + 1] = st;
-            s_r2 = r;
+    u64 st = pp.rngst[a.c0];
+    u32 k = 0;  // rounds done
+    auto emit = [&](const u64 (&t)[3]) -> u64 {
+        if (tid == 0) {
+            u64 *m = a.msg + 3ull * k;
+            m[0] = t[0];
+            m[1] = t[1];
+            m[2] = t[2];
         }
-        __syncthreads();
-        const u64 r = s_r2;
-        M /= 2;
-        u64 nA[TAIL_LIM / SBLOCK], nC[TAIL_LIM / SBLOCK], nF[TAIL_LIM / SBLOCK];
+        const u64 r = fp::sm_field(st);
+        if (tid == 0) {
+            pp.chals[a.c0 + k] = r;
+            pp.rngst[a.c0 + k + 1] = st;
+        }
+        k++;
+        return r;
+    };
+    // rounds with thread-local pairs
+    while (E >= 2) {
+        u64 t[3] = {0, 0, 0};
 #pragma unroll
-        for (int q = 0; q < TAIL_LIM / SBLOCK; q++) {
-            const u32 x = threadIdx.x + q * SBLOCK;
-            if (x < M) {
-                nA[q] = add(tA[2 * x], mul(r, sub(tA[2 * x + 1], tA[2 * x])));
-                nC[q] = add(tC[2 * x], mul(r, sub(tC[2 * x + 1], tC[2 * x])));
-                nF[q] = add(tF[2 * x], mul(r, sub(tF[2 * x + 1], tF[2 * x])));
+        for (int q = 0; q < TAIL_E / 2; q++)
+            if (q < (int)E / 2)
+                table_terms(A[2 * q], A[2 * q + 1], C[2 * q], C[2 * q + 1], F[2 * q], F[2 * q + 1], t);
+        group_total<3>(t, s_sum[k & 1]);
+        const u64 r = emit(t);
+#pragma unroll
+        for (int q = 0; q < TAIL_E / 2; q++) {
+            if (q < (int)E / 2) {
+                A[q] = fold1(A[2 * q], A[2 * q + 1], r);
+                if (hc) C[q] = fold1(C[2 * q], C[2 * q + 1], r);
+                F[q] = fold1(F[2 * q], F[2 * q + 1], r);
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < TAIL_LIM / SBLOCK; q++) {
-            const u32 x = threadIdx.x + q * SBLOCK;
-            if (x < M) {
-                tA[x] = nA[q];
-                tC[x] = nC[q];
-                tF[x] = nF[q];
-            }
-        }
-        __syncthreads();
+        E /= 2;
+        n /= 2;
     }
-    if (threadIdx.x == 0) {
-        const u64 v = tF[0];
-        *a.vout = v;
-        if (a.last == 1) pp.state[1] = v;
+    // one entry per thread: entry e in thread e * sg
+    u32 sg = 1;
+    u64 a0 = A[0], c0 = C[0], f0 = F[0];
+    while (n > 64) {
+        const u64 a1 = down64(a0, sg), c1 = hc ? down64(c0, sg) : 0, f1 = down64(f0, sg);
+        const bool act = (tid & (2 * sg - 1)) == 0 && tid < n * sg;
+        u64 t[3] = {0, 0, 0};
+        if (act) table_terms(a0, a1, c0, c1, f0, f1, t);
+        group_total<3>(t, s_sum[k & 1]);
+        const u64 r = emit(t);
+        if (act) {
+            a0 = fold1(a0, a1, r);
+            if (hc) c0 = fold1(c0, c1, r);
+            f0 = fold1(f0, f1, r);
+        }
+        sg *= 2;
+        n /= 2;
+    }
+    if (n * sg > 64) {  // entries still spread over several waves
+        if ((tid & (sg - 1)) == 0 && tid < n * sg) {
+            s_g[0][tid / sg] = a0;
+            s_g[1][tid / sg] = c0;
+            s_g[2][tid / sg] = f0;
+        }
+        __syncthreads();
+        if (tid >= 64) return;
+        a0 = lane < n ? s_g[0][lane] : 0;
+        c0 = lane < n ? s_g[1][lane] : 0;
+        f0 = lane < n ? s_g[2][lane] : 0;
+        sg = 1;
+    } else if (tid >= 64) {
+        return;
+    }
+    // wave 0 alone
+    while (n > 1) {
+        const u64 a1 = down64(a0, sg), c1 = hc ? down64(c0, sg) : 0, f1 = down64(f0, sg);
+        const bool act = (lane & (2 * sg - 1)) == 0 && lane < n * sg;
+        u64 t[3] = {0, 0, 0};
+        if (act) table_terms(a0, a1, c0, c1, f0, f1, t);
+        wave_total<3>(t);
+        const u64 r = emit(t);
+        if (act) {
+            a0 = fold1(a0, a1, r);
+            if (hc) c0 = fold1(c0, c1, r);
+            f0 = fold1(f0, f1, r);
+        }
+        sg *= 2;
+        n /= 2;
+    }
+    if (tid == 0) {
+        *a.vout = f0;
+        if (a.last == 1) pp.state[1] = f0;
     }
 }
 
-// Remaining p-phase rounds j0..s-1 in one workgroup.  The prologue drew
-// r_{j0-1} and folded its message into the beta prefix C = state[0].
+// Remaining p-phase rounds j0..s-1.  The prologue drew r_{j0-1} and folded
+// its message into the beta prefix C = state[0].  B is the table of sums of
+// the eq weights of the a-coordinates not yet reached (beta over z's
+// suffix); pair m of V goes with B[m], which sits in the pair's first
+// thread (stride 2 sg, or entries [t E / 2, (t + 1) E / 2) while pairs are
+// thread-local).
 __device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx &c) {
-    __shared__ u64 tV[TAIL_LIM], tB[TAIL_LIM / 2];
-    __shared__ u64 s_r2;
-    u32 M = 1u << (a.s - a.j0);  // entries of V^(j0)
+    __shared__ u64 s_sum[2][2][NWAVES];
+    __shared__ u64 s_g[2][64];
+    const u32 tid = threadIdx.x, lane = tid & 63;
+    u32 n = 1u << (a.s - a.j0);  // entries of V^(j0)
+    u32 E = n >= 2 * SBLOCK ? n / SBLOCK : 1;
+    u64 V[TAIL_E], B[TAIL_E / 2 > 0 ? TAIL_E / 2 : 1];
     {
         const u64 r = c.r;
-        for (u32 x = threadIdx.x; x < M; x += SBLOCK) {
-            const u64x2 pv = ld2(a.V, 2 * x);
-            tV[x] = add(pv.x, mul(r, sub(pv.y, pv.x)));
-        }
-        for (u32 x = threadIdx.x; x < M / 2; x += SBLOCK) {
-            const u64x2 pb = ld2(a.B, 2 * x);
-            tB[x] = add(pb.x, pb.y);  // B_{j0}: the coordinate j0 summed out
-        }
-    }
-    u64 st = 0, C = 0;
-    if (threadIdx.x == 0) {
-        st = pp.rngst[a.c0];
-        C = pp.state[0];
-    }
-    __syncthreads();
-    for (u32 j = a.j0; j < a.s; j++) {
-        u64 acc[3] = {0, 0, 0};
-        for (u32 m = threadIdx.x; m < M / 2; m += SBLOCK) {
-            acc[0] = add(acc[0], mul(tB[m], tV[2 * m]));
-            acc[1] = add(acc[1], mul(tB[m], tV[2 * m + 1]));
-        }
-        block_total3(acc);
-        if (threadIdx.x == 0) {
-            const u64 z = pp.zbuf[j], S0 = acc[0], S1 = acc[1];
-            u64 *msg = a.msg + 3ull * (j - a.j0);
-            msg[0] = mul(mul(C, sub(1, z)), S0);
-            msg[1] = mul(mul(C, z), S1);
-            msg[2] = mul(mul(C, sub(add(add(z, z), z), 1)), sub(add(S1, S1), S0));
-            const u32 ci = a.c0 + (j - a.j0);
-            const u64 r = fp::sm_field(st);
-            pp.chals[ci] = r;
-            pp.rngst[ci + 1] = st;
-            C = mul(C, fp::eq(z, r));
-            s_r2 = r;
-        }
-        __syncthreads();
-        const u64 r = s_r2;
-        M /= 2;
-        u64 nV[TAIL_LIM / SBLOCK], nB[TAIL_LIM / SBLOCK];
+        const u32 e0 = tid * E;
 #pragma unroll
-        for (int q = 0; q < TAIL_LIM / SBLOCK; q++) {
-            const u32 x = threadIdx.x + q * SBLOCK;
-            if (x < M) nV[q] = add(tV[2 * x], mul(r, sub(tV[2 * x + 1], tV[2 * x])));
-            if (x < M / 2) nB[q] = add(tB[2 * x], tB[2 * x + 1]);
+        for (int q = 0; q < TAIL_E; q++) {
+            V[q] = 0;
+            if (q < (int)E && e0 + q < n) {
+                const u64x2 pv = ld2(a.V, 2 * (e0 + q));
+                V[q] = fold1(pv.x, pv.y, r);
+            }
         }
-        __syncthreads();
+        // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1], m < n/2
+        if (E >= 2) {
 #pragma unroll
-        for (int q = 0; q < TAIL_LIM / SBLOCK; q++) {
-            const u32 x = threadIdx.x + q * SBLOCK;
-            if (x < M) tV[x] = nV[q];
-            if (x < M / 2) tB[x] = nB[q];
+            for (int q = 0; q < TAIL_E / 2; q++) {
+                B[q] = 0;
+                if (q < (int)E / 2) {
+                    const u64x2 pb = ld2(a.B, 2 * (e0 / 2 + q));
+                    B[q] = add(pb.x, pb.y);
+                }
+            }
+        } else {
+            B[0] = 0;
+            if ((tid & 1) == 0 && (tid >> 1) < (n >> 1)) {
+                const u64x2 pb = ld2(a.B, tid);  // entries 2 (tid/2), 2 (tid/2) + 1
+                B[0] = add(pb.x, pb.y);
+            }
         }
-        __syncthreads();
     }
-    if (threadIdx.x == 0) pp.state[0] = C;  // beta(z, a*)
+    u64 st = pp.rngst[a.c0];
+    // The prologue's finish of round j0-1 left C in state[0], written by
+    // thread 0; only thread 0's copy of C is used.
+    u64 Cp = pp.state[0];
+    u32 k = 0;
+    auto emit = [&](const u64 (&t)[2]) -> u64 {
+        const u64 z = pp.zbuf[a.j0 + k], S0 = t[0], S1 = t[1];
+        if (tid == 0) {
+            u64 *m = a.msg + 3ull * k;
+            m[0] = mul(mul(Cp, sub(1, z)), S0);
+            m[1] = mul(mul(Cp, z), S1);
+            m[2] = mul(mul(Cp, sub(add(add(z, z), z), 1)), sub(add(S1, S1), S0));
+        }
+        const u64 r = fp::sm_field(st);
+        if (tid == 0) {
+            pp.chals[a.c0 + k] = r;
+            pp.rngst[a.c0 + k + 1] = st;
+        }
+        Cp = mul(Cp, fp::eq(z, r));
+        k++;
+        return r;
+    };
+    while (E >= 2) {
+        u64 t[2] = {0, 0};
+#pragma unroll
+        for (int q = 0; q < TAIL_E / 2; q++) {
+            if (q < (int)E / 2) {
+                t[0] = add(t[0], mul(B[q], V[2 * q]));
+                t[1] = add(t[1], mul(B[q], V[2 * q + 1]));
+            }
+        }
+        group_total<2>(t, s_sum[k & 1]);
+        const u64 r = emit(t);
+#pragma unroll
+        for (int q = 0; q < TAIL_E / 2; q++)
+            if (q < (int)E / 2) V[q] = fold1(V[2 * q], V[2 * q + 1], r);
+        if (E >= 4) {
+#pragma unroll
+            for (int q = 0; q < TAIL_E / 4; q++)
+                if (q < (int)E / 4) B[q] = add(B[2 * q], B[2 * q + 1]);
+        } else {
+            // one V entry per thread from here: B[m] moves to thread 2m
+            const u64 b1 = down64(B[0], 1);
+            B[0] = (tid & 1) == 0 ? add(B[0], b1) : 0;
+        }
+        E /= 2;
+        n /= 2;
+    }
+    u32 sg = 1;
+    u64 v0 = V[0], b0 = B[0];
+    while (n > 64) {
+        const u64 v1 = down64(v0, sg), b1 = down64(b0, 2 * sg);
+        const bool act = (tid & (2 * sg - 1)) == 0 && tid < n * sg;
+        u64 t[2] = {0, 0};
+        if (act) {
+            t[0] = mul(b0, v0);
+            t[1] = mul(b0, v1);
+        }
+        group_total<2>(t, s_sum[k & 1]);
+        const u64 r = emit(t);
+        if (act) v0 = fold1(v0, v1, r);
+        if ((tid & (4 * sg - 1)) == 0 && tid < n * sg) b0 = add(b0, b1);
+        sg *= 2;
+        n /= 2;
+    }
+    if (n * sg > 64) {
+        if ((tid & (sg - 1)) == 0 && tid < n * sg) s_g[0][tid / sg] = v0;
+        if ((tid & (2 * sg - 1)) == 0 && tid < n * sg) s_g[1][tid / (2 * sg)] = b0;
+        __syncthreads();
+        if (tid >= 64) return;
+        v0 = lane < n ? s_g[0][lane] : 0;
+        b0 = (lane & 1) == 0 && lane < n ? s_g[1][lane / 2] : 0;
+        sg = 1;
+    } else if (tid >= 64) {
+        return;
+    }
+    while (n > 1) {
+        const u64 v1 = down64(v0, sg), b1 = down64(b0, 2 * sg);
+        const bool act = (lane & (2 * sg - 1)) == 0 && lane < n * sg;
+        u64 t[2] = {0, 0};
+        if (act) {
+            t[0] = mul(b0, v0);
+            t[1] = mul(b0, v1);
+        }
+        wave_total<2>(t);
+        const u64 r = emit(t);
+        if (act) v0 = fold1(v0, v1, r);
+        if ((lane & (4 * sg - 1)) == 0 && lane < n * sg) b0 = add(b0, b1);
+        sg *= 2;
+        n /= 2;
+    }
+    if (tid == 0) pp.state[0] = Cp;  // beta(z, a*)
 }
 
 // ---------------------------------------------------------------- kernel
@@ -635,8 +874,6 @@ __device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx &c
 // that finishes the previous round has one more workgroup, lb == nblocks,
 // which only folds the previous rows into the message (so that work runs
 // beside the body instead of ahead of it) and records the drawn challenge.
-constexpr u32 KALL = 0xFFFF;  // kind resolved at run time (mixed batches)
-
 template <u32 KIND, int GK, int PH>
 __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     __shared__ u64 s_r;
@@ -671,7 +908,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     c.r = s_r;
     // points assembled in LDS (challenges drawn by earlier launches are in
     // chals; the one drawn just now is c.r)
-    if (f.kind == FIN_LINE && threadIdx.x < f.sp) {
+    if ((fin_mask(KIND) & (1u << FIN_LINE)) && f.kind == FIN_LINE && threadIdx.x < f.sp) {
         const u64 bb = f.bstar[threadIdx.x], cc = f.cstar[threadIdx.x];
         s_pt[threadIdx.x] = add(bb, mul(c.r, sub(cc, bb)));  // z_{i+1} = l(tau)
     }
@@ -690,10 +927,10 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     }
     __syncthreads();
     if (fin_block) {
-        finalize(sd, c, s_pt);
+        finalize<KIND>(sd, c, s_pt);
         return;
     }
-    if (tail && has_fin) finalize(sd, c, s_pt);
+    if (tail && has_fin) finalize<KIND>(sd, c, s_pt);
 
     // --- body
     u64 *row = sd.rows ? sd.rows + (u64)c.lb * ROW_STRIDE : nullptr;
@@ -725,6 +962,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_LINE: step_line(sd.u.line, c, row); break;
         case ST_WAGG: step_wagg(sd.u.wagg, pp, c); break;
         case ST_WT0: step_wt0(sd.u.wt0, pp, c, row); break;
+        case ST_WA0: step_wa0(sd.u.wa0, pp, c, row); break;
         case ST_WT: step_wt(sd.u.wt, c, row); break;
         case ST_WTAIL: step_wtail(sd.u.wtail, pp, c); break;
         case ST_PTAIL: step_ptail(sd.u.ptail, pp, c); break;
@@ -804,6 +1042,7 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_SGE: L1(ST_SGE); break;
         case ST_WAGG: L1(ST_WAGG); break;
         case ST_WT0: L1(ST_WT0); break;
+        case ST_WA0: L1(ST_WA0); break;
         case ST_WT: L1(ST_WT); break;
         case ST_WTAIL: L1(ST_WTAIL); break;
         case ST_PTAIL: L1(ST_PTAIL); break;

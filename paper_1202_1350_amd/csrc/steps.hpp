@@ -49,6 +49,8 @@ enum StepKind : u32 {
     ST_WTAIL,      // omega phase, tables: remaining rounds in one workgroup
     ST_PTAIL,      // p-phase: remaining rounds in one workgroup
     ST_LOAD,       // inputs (pointer in state[3]) into V_d, range check
+    ST_WA0,        // omega phase, tables: ST_WAGG and ST_WT0 in one pass, for
+                   // layers whose wires each carry at most one chunk of gates
 };
 
 enum FinKind : u32 {
@@ -58,6 +60,20 @@ enum FinKind : u32 {
     FIN_LINE,  // h(t) values from rows of line sums; then tau and z_{i+1}
     FIN_T,     // message (G(0), G(1), G(2)) from rows of three sums
 };
+
+constexpr u32 KALL = 0xFFFF;  // kind resolved at run time (mixed batches)
+
+// The finishes (bit f for FinKind f) a step of the given kind can carry;
+// each kernel instantiation compiles only these.
+__host__ __device__ constexpr u32 fin_mask(u32 kind) {
+    return kind == KALL                              ? 0xFFu
+           : (kind == ST_P || kind == ST_PTAIL)      ? 1u << FIN_P
+           : (kind == ST_WT || kind == ST_WTAIL)     ? 1u << FIN_T
+           : kind == ST_EQ                           ? (1u << FIN_LINE) | (1u << FIN_W)
+           : kind == ST_END                          ? 1u << FIN_LINE
+           : (kind == ST_W || kind == ST_FOLD || kind == ST_LT) ? 1u << FIN_W
+                                                     : 0u;
+}
 
 // Largest table (entries at the level a tail starts from, after its fold)
 // that a one-workgroup tail keeps in LDS.
@@ -187,6 +203,21 @@ struct Wt0Args {
     const u64 *F;            // V_{i+1}
     u64 *A, *C;              // level-0 tables
 };
+// ST_WA0: wire x's gates are perm[cstart[xch[x]] .. cstart[xch[x] + 1])
+// when xch[x] < xch[x + 1] (at most one chunk per wire).
+struct Wa0Args {
+    u32 kind, ph, hasC;
+    u64 npairs;
+    const u32 *perm, *cstart, *xch;
+    const u32 *oth;
+    const u8 *type;
+    const u64 *Vn;           // V_{i+1}: gathered operands and the table F
+    const u64 *alo, *ahi;
+    u32 La;
+    const u64 *blo, *bhi;
+    u32 Lb;
+    u64 *A, *C;              // level-0 tables
+};
 struct WtArgs {
     u32 hasC;
     u64 npairs;              // pairs of level k (tables of level k-1 have 4 npairs)
@@ -231,6 +262,7 @@ struct StepDesc {
         WtailArgs wtail;
         PtailArgs ptail;
         LoadArgs load;
+        Wa0Args wa0;
     } u;
 };
 

@@ -27,3 +27,24 @@ def test_field_ops_match_integers():
         got = out.cpu().view(torch.int64).numpy().view(np.uint64)
         want = np.array([f(x, y) for x, y in zip(a, b)], np.uint64)
         assert np.array_equal(got, want), op
+
+
+def test_lazy_sums_match_integers():
+    """64 products summed in 128 bits and reduced once, including the
+    largest sums (every factor p - 1)."""
+    import torch
+    import paper_1202_1350_amd as G
+    rng = random.Random(4)
+    n = 4096
+    a = [P - 1] * 200 + [rng.randrange(P) for _ in range(n - 200)]
+    b = [P - 1] * 200 + [rng.randrange(P) for _ in range(n - 200)]
+    a[300:310] = [0, 1, 2, 1 << 60, P - 2, 0, 0, 1, P - 1, 3]
+    ta = device_tensor(np.array(a, np.uint64))
+    tb = device_tensor(np.array(b, np.uint64))
+    out = torch.zeros_like(ta)
+    say("lazy sums", n)
+    G.gkr_field_op(3, ta, tb, out)
+    got = out.cpu().view(torch.int64).numpy().view(np.uint64)
+    want = np.array([sum(a[(k + j) % n] * b[(k + j) % n] for j in range(64)) % P
+                     for k in range(n)], np.uint64)
+    assert np.array_equal(got, want)

@@ -90,6 +90,30 @@ def test_many_blocks_and_ragged_tail():
         check_same(circ, x, 11, f"ragged {sizes}")
 
 
+def test_wire_fanout_around_chunk_size():
+    """Wires read by 0, 1, 31, 32, 33, 64 and 100 gates: layers whose wires
+    all fit one chunk of gates take the fused pass, the others the per-chunk
+    pass; both phases and both gate kinds."""
+    rng = random.Random(21)
+    fan = [0, 1, 31, 32, 33, 64, 100, 2, 0, 5, 17, 40, 0, 3, 1, 9]
+    for kinds in (None, [0, 1], [1, 0]):
+        reads = [x for x, f in enumerate(fan) for _ in range(f)]
+        rng.shuffle(reads)
+        S0 = len(reads)
+        other = [rng.randrange(16) for _ in range(S0)]
+        small = [rng.randrange(16) for _ in range(16)]
+        t0 = [rng.randrange(2) if kinds is None else kinds[0] for _ in range(S0)]
+        t1 = [rng.randrange(2) if kinds is None else kinds[1] for _ in range(16)]
+        for swap in (False, True):
+            a, b = (other, reads) if swap else (reads, other)
+            circ = Circuit([S0, 16, 16], [np.array(t0, np.uint8), np.array(t1, np.uint8)],
+                           [np.array(a, np.uint32), np.array(small, np.uint32)],
+                           [np.array(b, np.uint32), np.array(small[::-1], np.uint32)],
+                           name="fan-out")
+            x = np.array([rng.randrange(P) for _ in range(16)], np.uint64)
+            check_same(circ, x, 31, f"fan-out kinds {kinds} swap {swap}")
+
+
 def test_c1_f2_1024():
     circ, x, seed = W.c1_f2()
     gc, m = check_same(circ, x, seed, "C1 F2 n=2^10")
