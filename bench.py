@@ -129,16 +129,21 @@ def cpu_baseline(log_n):
                       f"({circ.gates} gates, seed 2) in {dt:.2f} s"}
 
 
-def batch_leg(G, W, np, torch, reps):
+def batch_leg(G, W, np, torch, reps, tune):
     """64 uneven proofs (F2 n log-uniform in [2^12, 2^20], PM text in
     [2^14, 2^18], seed 4): the plain path proves them one by one, the
     batched path in one launch per step (graph replay).  Both must give the
-    same transcripts."""
+    same transcripts.  Launch shapes are first tuned on these circuits."""
     mix = W.batch_mix(4, 64)
     circs = [G.Circuit.from_workload(c) for _, c, _, _ in mix]
     xs = [torch.from_numpy(x.view(np.int64)).cuda().view(torch.uint64) for _, _, x, _ in mix]
     seeds = [sd for _, _, _, sd in mix]
     gates = sum(c.gates for c in circs)
+    tune_s = None
+    if tune:
+        t = time.perf_counter()
+        G.gkr_autotune(circs, xs, reps=1)
+        tune_s = time.perf_counter() - t
     plain = [G.gkr_prove(c, x, sd, want_chals=False)[0] for c, x, sd in zip(circs, xs, seeds)]
     batched = G.gkr_batch_prove(circs, xs, seeds)
     same = all(np.array_equal(a, b) for a, b in zip(plain, batched))
@@ -156,7 +161,8 @@ def batch_leg(G, W, np, torch, reps):
             "proofs": len(circs), "gates": gates, "bit_exact_batched_vs_plain": same,
             "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
             "plain_gates_per_s": gates / t_plain, "batched_gates_per_s": gates / t_batch,
-            "batched_proofs_per_s": len(circs) / t_batch, "speedup": t_plain / t_batch}
+            "batched_proofs_per_s": len(circs) / t_batch, "speedup": t_plain / t_batch,
+            "autotune_seconds": tune_s}
 
 
 def serve_leg(G, W, np, n_req, n_sat, rates):
@@ -258,6 +264,35 @@ def serve_leg(G, W, np, n_req, n_sat, rates):
             "closed_loop_requests": n_sat, "closed_loop_proofs_per_s": sat, "points": points}
 
 
+def mulmod_rate(G, torch, dev):
+    """Products per second of the device field module: 2^24 independent
+    chains of 256 dependent products each (best of three)."""
+    n = 1 << 24
+    g = torch.Generator().manual_seed(7)
+    a = torch.randint(0, (1 << 61) - 1, (n,), generator=g, dtype=torch.int64).to(dev).view(torch.uint64)
+    b = torch.randint(0, (1 << 61) - 1, (n,), generator=g, dtype=torch.int64).to(dev).view(torch.uint64)
+    out = torch.empty_like(a)
+    G.gkr_field_op(4, a, b, out)
+    best = None
+    for _ in range(3):
+        t = time.perf_counter()
+        G.gkr_field_op(4, a, b, out)  # synchronises
+        dt = time.perf_counter() - t
+        best = dt if best is None else min(best, dt)
+    return n * 256 / best
+
+
+def line_mulmods(circ):
+    """Products of the line sums of one proof: (s'-1) per entry of V_{i+1}
+    for every layer with s' >= 2."""
+    tot = 0
+    for i in range(len(circ.sizes) - 1):
+        sp = (circ.sizes[i + 1] - 1).bit_length() if circ.sizes[i + 1] > 1 else 0
+        if sp >= 2:
+            tot += (sp - 1) << sp
+    return tot
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +304,7 @@ def main():
     ap.add_argument("--cpu-log-n", type=int, default=22)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate point")
     ap.add_argument("--serve-points", type=int, default=8,
                     help="rate points, geometric from 0.1x to 1.5x saturation")
@@ -303,6 +339,13 @@ def main():
     xt = torch.from_numpy(x.view(np.int64)).to(dev).view(torch.uint64)
     at = torch.from_numpy(a.view(np.int32)).to(dev).view(torch.uint32)
     torch.cuda.synchronize()
+    tune = {}
+    if not args.no_autotune:
+        t = time.perf_counter()
+        G.gkr_autotune([gc], [xt], reps=2)
+        table = G.gkr_tune_get()
+        tune = {"circuits": "the benchmark circuit", "seconds": time.perf_counter() - t,
+                "tuned_entries": sum(1 for v in table[4:] if v != 0xFF)}
 
     def step(times):
         t0 = time.perf_counter()
@@ -377,6 +420,7 @@ def main():
         "kernels_per_proof": {k: {"ms": v[0] / args.steps, "launches": v[1] / args.steps,
                         "GB_per_s": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None}
                     for k, v in prof.items() if v[1]},
+        "autotune": tune or None,
         "roofline": {"kernel": rocprof_kernel_name(dom), "class": dom, "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -384,8 +428,17 @@ def main():
                      "algorithmic_bytes_per_launch": by / launches if launches else None,
                      "traffic": traffic},
     }
+    peak_mm = mulmod_rate(G, torch, dev)
+    lm = line_mulmods(circ)
+    if "step_line" in prof and prof["step_line"][0] > 0:
+        line_rate = lm * args.steps / (prof["step_line"][0] * 1e-3)
+        line["alu"] = {"mulmod_peak_per_s": peak_mm,
+                       "peak_probe": "2^24 independent chains of 256 dependent products",
+                       "line_kernel_mulmods_per_proof": lm,
+                       "line_kernel_mulmods_per_s": line_rate,
+                       "line_kernel_frac_of_peak": line_rate / peak_mm}
     if not args.no_batch:
-        line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2))
+        line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2), not args.no_autotune)
     if not args.no_serve:
         k = max(1, args.serve_points)
         rates = [0.1 * 15.0 ** (j / (k - 1)) for j in range(k)] if k > 1 else [1.0]

@@ -136,6 +136,28 @@ int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inputs_on_devic
                const uint64_t *msgs, uint64_t n_msgs, int *accepted, gkr_reject_info *why,
                void *hip_stream);
 
+/* Launch shapes.  A grid step over U work items (gates, wires, table
+ * entries or quads of them) launches ceil(U / (512 q)) workgroups of 512
+ * threads, at most `cap`, where q (items per thread: 1, 2, 4, 8) and cap
+ * (256, 512, 1024, 2048) are chosen per step kind and size class (ceil
+ * log2 U).  gkr_autotune proves each of the n circuits (inputs as in
+ * gkr_prove, seeds 1..reps) under each of the 16 shapes, timing every grid
+ * launch with events (one warm-up proof per shape), and keeps for each
+ * (kind, class) met the fastest shape; plans made afterwards, including
+ * cached batch plans and a server's idle scratch, use it.  Transcripts do
+ * not depend on the shapes (the sums are exact).  Not safe to call while
+ * other threads prove on the same circuits.  Errors: GKR_ERR_INVALID,
+ * GKR_ERR_RANGE, GKR_ERR_NOMEM, GKR_ERR_DEVICE. */
+int gkr_autotune(uint32_t n, const gkr_circuit *const *circuits, const uint64_t *const *inputs,
+                 int inputs_on_device, uint32_t reps, void *hip_stream);
+/* The shape table as bytes, to keep a tuning across processes: with buf
+ * NULL, *len receives the size; otherwise *len is the buffer size (at
+ * least that) and receives it.  Errors: GKR_ERR_INVALID, GKR_ERR_BUFSIZE. */
+int gkr_tune_get(uint8_t *buf, uint32_t *len);
+/* Restore a table from gkr_tune_get (buf NULL: back to the defaults).
+ * Errors: GKR_ERR_INVALID (not a table of this library). */
+int gkr_tune_set(const uint8_t *buf, uint32_t len);
+
 /* Batched proving: n proofs advance together, one launch per step running
  * that step of every proof still going (one workgroup range per proof), so a
  * batch costs as many launches as its longest proof has steps.  With
@@ -199,8 +221,9 @@ int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_device, uint64_t
  * out[k] = a[k] op b[k], op 0 = add, 1 = sub, 2 = mul; op 3 = the sum of
  * the 64 products a[j] b[j], j = k, k+1, ..., k+63 (indices mod n),
  * accumulated in 128 bits and reduced once (the lazy reduction the prover's
- * sums use).  a, b, out are device arrays of n canonical values.  Errors:
- * GKR_ERR_INVALID, GKR_ERR_DEVICE. */
+ * sums use); op 4 = a[k] b[k]^256 by 256 successive products (independent
+ * chains over k: a probe of the product rate).  a, b, out are device arrays
+ * of n canonical values.  Errors: GKR_ERR_INVALID, GKR_ERR_DEVICE. */
 int gkr_field_op(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
                  void *hip_stream);
 

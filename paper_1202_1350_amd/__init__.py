@@ -61,6 +61,9 @@ _SIGS = [
     ("gkr_server_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                    C.POINTER(C.c_uint64)]),
     ("gkr_server_destroy", None, [C.c_void_p]),
+    ("gkr_autotune", C.c_int, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_int, C.c_uint32, C.c_void_p]),
+    ("gkr_tune_get", C.c_int, [C.c_void_p, C.POINTER(C.c_uint32)]),
+    ("gkr_tune_set", C.c_int, [C.c_void_p, C.c_uint32]),
     ("gkr_field_op", C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
                                C.c_void_p]),
     ("gkr_profile_enable", C.c_int, [C.c_int]),
@@ -213,6 +216,39 @@ def gkr_batch_prove(circs, inputs, seeds, graph: bool = True, stream=None):
     return [o[:c.n_msgs] for o, c in zip(outs, circs)]
 
 
+def gkr_autotune(circs, inputs, reps: int = 2, stream=None):
+    """Pick launch shapes by timing proofs of circs (inputs: all host arrays
+    or all device tensors)."""
+    n = len(circs)
+    keep = [_ptr(x, np.uint64) for x in inputs]
+    ondev = {bool(dev) for _, dev, _ in keep}
+    if len(ondev) != 1:
+        raise TypeError("inputs must be all host arrays or all device tensors")
+    hs = (C.c_void_p * n)(*[c.handle.value for c in circs])
+    ins = (C.c_void_p * n)(*[p for p, _, _ in keep])
+    dev = ondev.pop()
+    _check(lib().gkr_autotune(n, C.cast(hs, C.c_void_p), C.cast(ins, C.c_void_p), int(dev),
+                              int(reps), _stream(1 if dev else 0, stream)))
+
+
+def gkr_tune_get() -> bytes:
+    """The launch-shape table (to restore with gkr_tune_set)."""
+    n = C.c_uint32(0)
+    _check(lib().gkr_tune_get(None, C.byref(n)))
+    buf = (C.c_uint8 * n.value)()
+    _check(lib().gkr_tune_get(buf, C.byref(n)))
+    return bytes(buf)
+
+
+def gkr_tune_set(table):
+    """Restore a table from gkr_tune_get; None restores the defaults."""
+    if table is None:
+        _check(lib().gkr_tune_set(None, 0))
+    else:
+        b = (C.c_uint8 * len(table)).from_buffer_copy(table)
+        _check(lib().gkr_tune_set(b, len(table)))
+
+
 class Server:
     """Continuous-batching proof server (gkr_server_*)."""
 
@@ -284,7 +320,8 @@ def f2_sumcheck_verify(freq, seed: int, msgs, stream=None):
 
 
 def gkr_field_op(op: int, a, b, out, stream=None):
-    """Field op on device tensors (0 add, 1 sub, 2 mul, 3 lazy sum of 64 products)."""
+    """Field op on device tensors (0 add, 1 sub, 2 mul, 3 lazy sum of 64
+    products, 4 a * b^256 by successive products)."""
     pa, _, _ = _ptr(a, np.uint64)
     pb, _, _ = _ptr(b, np.uint64)
     po, dev, _ = _ptr(out, np.uint64)

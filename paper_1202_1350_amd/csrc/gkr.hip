@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -230,6 +231,58 @@ void line_shape(u32 sp, u32 *L, u32 *M, u32 *H) {
 // Scratch of one proof on a circuit: the layer tables, the per-round tables
 // of the sum-checks, the transcript, and the step program (descriptors and
 // one-job launch entries) with every pointer bound to this scratch.
+// ------------------------------------------------------------ launch shapes
+//
+// A grid step over `units` work items launches ceil(units / (SBLOCK q))
+// workgroups, at most `cap`, with q (items per thread) and cap chosen per
+// step kind and size class (ceil log2 of the units) by gkr_autotune; kinds
+// and classes it has not measured keep their defaults.  A shape code packs
+// log2 q (bits 0-1) and log2 cap - 8 (bits 2-3): 16 candidates.
+constexpr u32 CAP_MAX = 2048;
+constexpr int NKIND = ST_WA0 + 1;
+constexpr int NCLASS = 48;
+constexpr u8 SHAPE_DEFAULT = 0xFF;
+constexpr int NSHAPE = 16;
+std::mutex g_tune_mu;
+u8 g_tune[NKIND][NCLASS];
+std::atomic<u32> g_tune_epoch{1};  // bumped when shapes change: plans are rebuilt
+int g_force = -1;                  // while tuning: the shape of every tunable step
+
+struct TuneInit {
+    TuneInit() { memset(g_tune, SHAPE_DEFAULT, sizeof g_tune); }
+} g_tune_init;
+
+bool tunable(u32 kind) {
+    switch (kind) {
+        case ST_LOAD: case ST_EVAL: case ST_EQ: case ST_P: case ST_W: case ST_FOLD:
+        case ST_LT: case ST_WAGG: case ST_WT0: case ST_WT: case ST_WA0:
+            return true;
+        default:
+            return false;
+    }
+}
+
+u32 size_class(u64 units) {
+    u32 b = 0;
+    while (b + 1 < NCLASS && (1ull << b) < units) b++;
+    return b;
+}
+
+u32 grid_for(u32 kind, u64 units, u32 qdef) {
+    u32 qlog = 0;
+    while ((1u << qlog) < qdef) qlog++;
+    u32 caplog = 9;  // 512 workgroups: two per CU
+    int code = SHAPE_DEFAULT;
+    if (tunable(kind)) code = g_force >= 0 ? g_force : g_tune[kind][size_class(units)];
+    if (code != SHAPE_DEFAULT) {
+        qlog = code & 3;
+        caplog = 8 + ((code >> 2) & 3);
+    }
+    const u64 t = (units + (1ull << qlog) - 1) >> qlog;
+    const u64 b = (t + SBLOCK - 1) / SBLOCK;
+    return (u32)std::max<u64>(1, std::min<u64>(b, 1ull << caplog));
+}
+
 struct Workspace {
     void *mem = nullptr;
     std::vector<u64 *> V;  // per layer, 2^{s_i} values
@@ -247,6 +300,8 @@ struct Workspace {
     std::vector<StepDesc> steps;  // host copy of the program
     std::vector<int> pclass;      // profiling class of each step
     std::vector<double> pbytes;   // algorithmic bytes of each step
+    std::vector<u64> punits;      // work items of each tunable step (0: not tunable)
+    u32 epoch = 0;                // launch shapes the program was planned with
     u64 *instage;  // host inputs land here
     size_t bytes = 0;  // device memory held
     u64 *h_msgs = nullptr, *h_chals = nullptr, *h_setup = nullptr;  // pinned staging
@@ -271,10 +326,14 @@ struct gkr_circuit {
     Workspace *ws = nullptr;
     int omega_algo = GKR_OMEGA_TABLES;
     std::vector<std::vector<u32>> h_in1, h_in2;  // host copies of the wires (grouping)
+    std::vector<std::vector<u8>> h_type;         // host gate types of mixed layers (else empty)
     struct Group {  // gates of a layer grouped by the wire a phase binds
         u32 *perm = nullptr, *cstart = nullptr, *xch = nullptr;
+        u32 *rowptr = nullptr;  // wire x's gates: sorted positions [rowptr[x], rowptr[x+1])
+        u32 *oths = nullptr;    // other wire of each gate, in sorted order
+        u8 *types = nullptr;    // gate types in sorted order (mixed layers)
         u32 nch = 0;
-        bool single = false;  // every wire carries at most one chunk
+        bool single = false;    // every wire carries at most one chunk
     };
     std::vector<Group> grp[2];  // [phase - 1][layer], built with the first table workspace
     void *gmem = nullptr;       // device memory of the groups
@@ -358,7 +417,9 @@ extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_siz
         HIP_TRY(hipMemcpy(c->in2[i], in2[i], n * 4, hipMemcpyHostToDevice));
         c->h_in1.emplace_back(in1[i], in1[i] + n);
         c->h_in2.emplace_back(in2[i], in2[i] + n);
+        c->h_type.emplace_back();
         if (c->kind[i] == KIND_MIXED) {
+            c->h_type.back().assign(gate_type[i], gate_type[i] + n);
             c->type[i] = (u8 *)p;
             p += (n + 255) & ~size_t(255);
             HIP_TRY(hipMemcpy(c->type[i], gate_type[i], n, hipMemcpyHostToDevice));
@@ -423,17 +484,30 @@ extern "C" int gkr_circuit_info(const gkr_circuit *c, uint64_t *gates, uint64_t 
 // GROUP_CHUNK gates of one wire; chunks of wire x are [xch[x], xch[x+1]).
 constexpr u32 GROUP_CHUNK = 32;
 struct HostGroup {
-    std::vector<u32> perm, cstart, xch;
+    std::vector<u32> perm, cstart, xch, rowptr, oths;
+    std::vector<u8> types;
 };
 
-static void build_group(const std::vector<u32> &idx, u64 N, HostGroup &G) {
+// Counting sort of the gates by their wire idx (stable): positions, the
+// other wire and the type in that order, chunks of <= GROUP_CHUNK gates of
+// one wire.
+static void build_group(const std::vector<u32> &idx, const std::vector<u32> &other,
+                        const std::vector<u8> &type, u64 N, HostGroup &G) {
     const u64 S = idx.size();
-    std::vector<u32> rowptr(N + 1, 0);
+    std::vector<u32> &rowptr = G.rowptr;
+    rowptr.assign(N + 1, 0);
     for (u64 g = 0; g < S; g++) rowptr[idx[g] + 1]++;
     for (u64 x = 0; x < N; x++) rowptr[x + 1] += rowptr[x];
     G.perm.assign(S, 0);
     std::vector<u32> fill(rowptr.begin(), rowptr.end() - 1);
     for (u64 g = 0; g < S; g++) G.perm[fill[idx[g]]++] = (u32)g;
+    G.oths.resize(S);
+    for (u64 p = 0; p < S; p++) G.oths[p] = other[G.perm[p]];
+    G.types.clear();
+    if (!type.empty()) {
+        G.types.resize(S);
+        for (u64 p = 0; p < S; p++) G.types[p] = type[G.perm[p]];
+    }
     G.xch.assign(N + 1, 0);
     G.cstart.clear();
     for (u64 x = 0; x < N; x++) {
@@ -467,8 +541,8 @@ static void carve(const gkr_circuit *c, Arena &a, Workspace &w, size_t nsteps) {
     w.llo = a.take<u64>(c->line_lo);
     w.lhl = a.take<u64>(c->line_hl);
     w.lhh = a.take<u64>(c->line_hh);
-    w.rows[0] = a.take<u64>((u64)SMAX_BLOCKS * ROW_STRIDE);
-    w.rows[1] = a.take<u64>((u64)SMAX_BLOCKS * ROW_STRIDE);
+    w.rows[0] = a.take<u64>((u64)std::max<u32>(CAP_MAX, SMAX_BLOCKS) * ROW_STRIDE);
+    w.rows[1] = a.take<u64>((u64)std::max<u32>(CAP_MAX, SMAX_BLOCKS) * ROW_STRIDE);
     w.msgs = a.take<u64>(c->n_msgs);
     w.chals = a.take<u64>(std::max<u64>(c->n_chals, 1));
     w.rngst = a.take<u64>(c->n_chals + 1);
@@ -491,12 +565,6 @@ static void carve(const gkr_circuit *c, Arena &a, Workspace &w, size_t nsteps) {
     }
 }
 
-// Workgroups of the step kernel for n items at `per` items per thread.
-static u32 sblocks(u64 n, u64 per = 1) {
-    u64 t = (n + per - 1) / per;
-    u64 b = (t + SBLOCK - 1) / SBLOCK;
-    return (u32)std::max<u64>(1, std::min<u64>(b, SMAX_BLOCKS));
-}
 
 // Builds a proof's step program.  With `ws` NULL it only counts the steps.
 struct Planner {
@@ -506,6 +574,7 @@ struct Planner {
     std::vector<StepDesc> out;
     std::vector<int> cls;
     std::vector<double> bytes;
+    std::vector<u64> units;
     ProofPtrs pp{};
 
     StepDesc &add(u32 kind, u32 nblocks, double nbytes) {
@@ -519,7 +588,14 @@ struct Planner {
         out.push_back(s);
         cls.push_back(PC_STEP + (int)kind);
         bytes.push_back(nbytes);
+        units.push_back(0);
         return out.back();
+    }
+    // A grid step over n work items, qdef items per thread by default.
+    StepDesc &addg(u32 kind, u64 n, u32 qdef, double nbytes) {
+        StepDesc &s = add(kind, grid_for(kind, n, qdef), nbytes);
+        if (tunable(kind)) units.back() = std::max<u64>(n, 1);
+        return s;
     }
     // The step just added writes K-value rows into the buffer of its parity.
     void reduces(u32 K) {
@@ -547,19 +623,19 @@ struct Planner {
         auto P_ = [&](u64 *p) -> u64 * { return w ? p : nullptr; };
         {
             const u64 Sd = c->S[d], npad = 1ull << c->s[d];
-            StepDesc &s = add(ST_LOAD, sblocks(npad, 4), Sd * 8.0 + npad * 8.0);
+            StepDesc &s = addg(ST_LOAD, npad, 4, Sd * 8.0 + npad * 8.0);
             s.u.load = LoadArgs{c->S[d], npad, V(d)};
         }
         // circuit evaluation (a3), layer d-1 down to 0
         for (int i = (int)d - 1; i >= 0; i--) {
             const u64 S = c->S[i], npad = 1ull << c->s[i];
-            StepDesc &s = add(ST_EVAL, sblocks(npad, 4),
+            StepDesc &s = addg(ST_EVAL, npad, 4,
                               S * (8.0 + 16 + 8 + (c->kind[i] == KIND_MIXED)) + (npad - S) * 8.0);
             s.u.eval = EvalArgs{(u32)c->kind[i], c->S[i], npad, c->type[i], c->in1[i], c->in2[i],
                                 V(i + 1), V(i)};
         }
         {
-            StepDesc &s = add(ST_START, sblocks(c->S[0]), c->S[0] * 16.0);
+            StepDesc &s = addg(ST_START, c->S[0], 1, c->S[0] * 16.0);
             s.u.start = StartArgs{c->s[0], c->S[0], V(0)};
         }
         Fin layer_end;  // how the previous layer is finished (line values, tau)
@@ -578,56 +654,73 @@ struct Planner {
             {
                 const u32 nz = s ? s - 1 : 0;
                 const u64 ne = (1ull << (nz / 2)) + (1ull << (nz - nz / 2));
-                StepDesc &e = add(ST_EQ, sblocks(ne), 8.0 * ne);
+                StepDesc &e = addg(ST_EQ, ne, 1, 8.0 * ne);
                 e.fin = layer_end;
                 e.u.eq = EqArgs{PT_Z, nz, nz / 2, 1, P_(w ? w->zlo : nullptr), P_(w ? w->zhi : nullptr)};
             }
-            // ---- p-phase (a5): grid rounds while the table is large, then
-            // the remaining rounds in one workgroup
-            const u32 j0 = s ? std::max<u32>(1, s > 10 ? s - 10 : 1) : 0;
-            for (u32 j = 0; j < j0; j++) {
-                const u64 nm = 1ull << (s - j - 1);
-                Fin f = fin_of_prev(FIN_P);
-                const bool first = j == 0;
+            // ---- p-phase (a5): grid steps of two rounds while the table is
+            // large, then the remaining rounds in one workgroup.  The first
+            // step does round 0 (and round 1's coefficients); a step reading
+            // V^(j) does rounds j+2, j+3; the tail starts at round j0.
+            if (s > 0) {
+                const bool look = s >= 2;
+                u32 j0 = 1;
+                if (look) j0 = s > 12 ? ((s - 10 + 1) & ~1u) : 2;  // even, 2^(s - j0) <= TAIL_LIM
                 u64 *vbuf[2] = {w ? w->pA : nullptr, w ? w->pB : nullptr};
                 u64 *bbuf[2] = {w ? w->bA : nullptr, w ? w->bB : nullptr};
-                PArgs pa;
-                pa.first = first;
-                pa.nm = nm;
-                pa.Vsrc = j <= 1 ? V(i) : vbuf[(j - 1) & 1];
-                pa.Vout = first ? nullptr : vbuf[j & 1];
-                pa.Bprev = first ? nullptr : bbuf[(j - 1) & 1];
-                pa.Bout = j + 1 < s ? bbuf[j & 1] : nullptr;
-                pa.zlo = w ? w->zlo : nullptr;
-                pa.zhi = w ? w->zhi : nullptr;
                 const u32 nz = s - 1;
-                pa.L = nz / 2;
-                StepDesc &st = add(ST_P, sblocks(nm, 2),
-                                   first ? nm * (16.0 + 8) : nm * (32.0 + 16 + 16 + 8));
-                if (!first) {
-                    f.j = j - 1;
-                    f.draw = (i32)(co + j - 1);
-                    f.msg = w ? msg + 3ull * (j - 1) : nullptr;
-                    st.fin = f;
+                int bw = 0;           // B buffer the last step wrote
+                const u64 *vlast = V(i);
+                {
+                    PArgs pa;
+                    memset(&pa, 0, sizeof pa);
+                    pa.first = 1;
+                    pa.look = look;
+                    pa.nu = look ? 1ull << (s - 2) : 1;
+                    pa.Vsrc = V(i);
+                    pa.Bout = look ? bbuf[0] : nullptr;  // B_1
+                    pa.zlo = w ? w->zlo : nullptr;
+                    pa.zhi = w ? w->zhi : nullptr;
+                    pa.L = nz / 2;
+                    // V 8 per entry, eq halves 16 per pair, B_1 8 per quad
+                    StepDesc &st = addg(ST_P, look ? 4 * pa.nu : pa.nu, 1, look ? pa.nu * (32.0 + 32 + 8) : 32.0);
+                    st.u.p = pa;
+                    reduces(look ? 6 : 2);
                 }
-                st.u.p = pa;
-                reduces(2);
-            }
-            if (s > 0) {
-                Fin f = fin_of_prev(FIN_P);
-                f.j = j0 - 1;
-                f.draw = (i32)(co + j0 - 1);
-                f.msg = w ? msg + 3ull * (j0 - 1) : nullptr;
-                StepDesc &st = add(ST_PTAIL, 1, 24.0 * (1ull << (s - j0 + 1)));
+                for (u32 j = 0; j + 2 < j0; j += 2) {
+                    Fin f = fin_of_prev(FIN_P2);
+                    f.j = j;
+                    f.draw = (i32)(co + j);
+                    f.msg = w ? msg + 3ull * j : nullptr;
+                    PArgs pa;
+                    memset(&pa, 0, sizeof pa);
+                    pa.nu = 1ull << (s - j - 4);
+                    pa.Vsrc = vlast;
+                    pa.Vout = vbuf[(j / 2) & 1];
+                    pa.Bprev = bbuf[bw];
+                    pa.Bout = bbuf[bw ^ 1];
+                    // per unit: V^(j) 16 read, V^(j+2) 4 written, B 4 read and 1 written
+                    StepDesc &st = addg(ST_P, 4 * pa.nu, 1, pa.nu * 8.0 * (16 + 4 + 4 + 1));
+                    st.fin = f;
+                    st.u.p = pa;
+                    reduces(6);
+                    vlast = pa.Vout;
+                    bw ^= 1;
+                }
+                const u32 pend = look ? 2 : 1;
+                Fin f = fin_of_prev(look ? FIN_P2 : FIN_P);
+                f.j = j0 - pend;
+                f.draw = (i32)(co + j0 - pend);
+                f.msg = w ? msg + 3ull * (j0 - pend) : nullptr;
+                StepDesc &st = add(ST_PTAIL, 1, 8.0 * (1ull << (s - j0 + pend)));
                 st.fin = f;
                 PtailArgs pt;
+                memset(&pt, 0, sizeof pt);
                 pt.j0 = j0;
                 pt.s = s;
-                // V^(j0-1) and B_{j0-1}, as the last grid round left them
-                u64 *vbuf[2] = {w ? w->pA : nullptr, w ? w->pB : nullptr};
-                u64 *bbuf[2] = {w ? w->bA : nullptr, w ? w->bB : nullptr};
-                pt.V = j0 == 1 ? V(i) : vbuf[(j0 - 1) & 1];
-                pt.B = bbuf[(j0 - 1) & 1];
+                pt.pend = pend;
+                pt.V = vlast;       // V^(j0 - pend)
+                pt.B = bbuf[bw];    // B_{j0-1}
                 pt.c0 = co + j0;
                 pt.msg = w ? msg + 3ull * j0 : nullptr;
                 st.u.ptail = pt;
@@ -636,7 +729,7 @@ struct Planner {
             {
                 const u32 La = s / 2;
                 const u64 ne = (1ull << La) + (1ull << (s - La));
-                StepDesc &e = add(ST_EQ, sblocks(ne), 8.0 * ne);
+                StepDesc &e = addg(ST_EQ, ne, 1, 8.0 * ne);
                 e.u.eq = EqArgs{PT_CHAL, s, La, co, w ? w->alo : nullptr, w ? w->ahi : nullptr};
             }
             if (sp == 0) {
@@ -655,15 +748,23 @@ struct Planner {
             if (sp >= 2) line_shape(sp, &Ll, &M, &H);
             const u64 ntab = sp >= 2 ? (u64)(sp - 1) * ((1ull << Ll) + (1ull << M) + (1ull << H)) : 1;
             if (c->omega_algo == GKR_OMEGA_TABLES) {
-                // ---- omega-phases over tables (a6, a7, a8)
+                // ---- omega-phases over tables (a6, a7, a8): round 0 (and
+                // round 1's coefficients) with the level-0 tables, then grid
+                // steps of two rounds while the tables are large, then the
+                // remaining rounds in one workgroup from round k0
+                // Round 0 with the level-0 tables.  If level 1 fits a tail it
+                // starts at round 1; otherwise a step folding once gives round 1
+                // and round 2's coefficients, steps folding twice follow, and
+                // the tail starts at an odd round k0 >= 3 (2^(s' - k0) <= TAIL_LIM).
                 const u64 N = 1ull << sp;
-                const u32 k0 = std::max<u32>(1, sp > 10 ? sp - 10 : 1);
+                u32 k0 = 1;
+                if (sp > 11) k0 = std::max<u32>(3, (sp - 10) | 1u);
                 for (u32 ph = 1; ph <= 2; ph++) {
                     const u32 rbase = s + (ph == 2 ? sp : 0);
                     const u32 Lb = sp / 2;
                     if (ph == 2) {
                         const u64 ne = (1ull << Lb) + (1ull << (sp - Lb));
-                        StepDesc &e = add(ST_EQ, sblocks(ne), 8.0 * ne);
+                        StepDesc &e = addg(ST_EQ, ne, 1, 8.0 * ne);
                         e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
                     }
                     const gkr_circuit::Group *dg = &c->grp[ph - 1][i];
@@ -678,10 +779,9 @@ struct Planner {
                         a.hasC = hasC;
                         a.npairs = N / 2;
                         a.perm = dg->perm;
-                        a.cstart = dg->cstart;
-                        a.xch = dg->xch;
-                        a.oth = ph == 1 ? c->in2[i] : c->in1[i];
-                        a.type = c->type[i];
+                        a.rowptr = dg->rowptr;
+                        a.oths = dg->oths;
+                        a.types = dg->types;
                         a.Vn = V(i + 1);
                         a.alo = w ? w->alo : nullptr;
                         a.ahi = w ? w->ahi : nullptr;
@@ -693,7 +793,7 @@ struct Planner {
                         a.C = w ? w->tC0 : nullptr;
                         // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1;
                         // per table entry: chunk index 4, F 8, A 8 (+ C 8)
-                        StepDesc &st = add(ST_WA0, sblocks(N / 2),
+                        StepDesc &st = addg(ST_WA0, N / 2, 1,
                                            S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) +
                                                N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 8.0 * nch);
                         st.u.wa0 = a;
@@ -708,8 +808,8 @@ struct Planner {
                             a.nch = nch;
                             a.perm = dg->perm;
                             a.cstart = dg->cstart;
-                            a.oth = ph == 1 ? c->in2[i] : c->in1[i];
-                            a.type = c->type[i];
+                            a.oths = dg->oths;
+                            a.types = dg->types;
                             a.Vn = V(i + 1);
                             a.alo = w ? w->alo : nullptr;
                             a.ahi = w ? w->ahi : nullptr;
@@ -720,7 +820,7 @@ struct Planner {
                             a.partA = w ? w->partA : nullptr;
                             a.partC = w ? w->partC : nullptr;
                             // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1
-                            StepDesc &st = add(ST_WAGG, sblocks(nch),
+                            StepDesc &st = addg(ST_WAGG, nch, 1,
                                                S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) + 20.0 * nch);
                             st.u.wagg = a;
                         }
@@ -736,67 +836,76 @@ struct Planner {
                             a.F = V(i + 1);
                             a.A = w ? w->tA0 : nullptr;
                             a.C = w ? w->tC0 : nullptr;
-                            StepDesc &st = add(ST_WT0, sblocks(N / 2),
+                            StepDesc &st = addg(ST_WT0, N / 2, 1,
                                                N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 16.0 * nch);
                             st.u.wt0 = a;
                             reduces(3);
                         }
                     }
+                    // tables of level k (0, or odd k: two buffers alternate)
                     auto level = [&](u32 k, const u64 **A, const u64 **C, const u64 **F) {
                         if (k == 0) {
                             *A = w ? w->tA0 : nullptr;
                             *C = w ? w->tC0 : nullptr;
                             *F = V(i + 1);
                         } else {
-                            *A = w ? w->tA[k & 1] : nullptr;
-                            *C = w ? w->tC[k & 1] : nullptr;
-                            *F = w ? (k & 1 ? w->fB : w->fA) : nullptr;
+                            const u32 b = ((k - 1) / 2) & 1;
+                            *A = w ? w->tA[b] : nullptr;
+                            *C = w ? w->tC[b] : nullptr;
+                            *F = w ? (b ? w->fB : w->fA) : nullptr;
                         }
                     };
-                    for (u32 k = 1; k < k0; k++) {
-                        Fin f = fin_of_prev(FIN_T);
-                        f.draw = (i32)(co + rbase + k - 1);
-                        f.msg = w ? msg + 3ull * (rbase + k - 1) : nullptr;
+                    // a table step reading level k with pend pending challenges
+                    auto table_step = [&](u32 k, u32 pend) {
+                        Fin f = fin_of_prev(pend == 1 ? FIN_T : FIN_T2);
+                        f.draw = (i32)(co + rbase + k);
+                        f.msg = w ? msg + 3ull * (rbase + k) : nullptr;
                         WtArgs a;
                         memset(&a, 0, sizeof a);
                         a.hasC = hasC;
-                        a.npairs = 1ull << (sp - k - 1);
+                        a.pend = pend;
+                        a.nu = 1ull << (sp - k - pend - 2);  // quads of level k + pend
                         const u64 *A, *C, *F;
-                        level(k - 1, &A, &C, &F);
+                        level(k, &A, &C, &F);
                         a.A = A;
                         a.C = C;
                         a.F = F;
-                        level(k, &A, &C, &F);
+                        level(k + pend, &A, &C, &F);
                         a.An = const_cast<u64 *>(A);
                         a.Cn = const_cast<u64 *>(C);
                         a.Fn = const_cast<u64 *>(F);
+                        // per unit and table: 4 << pend entries read, 4 written
                         const double tabs = hasC ? 3.0 : 2.0;
-                        StepDesc &st = add(ST_WT, sblocks(a.npairs), a.npairs * tabs * (32.0 + 16));
+                        StepDesc &st = addg(ST_WT, 4 * a.nu, 1, a.nu * tabs * 8.0 * ((4u << pend) + 4));
                         st.fin = f;
                         st.u.wt = a;
-                        reduces(3);
-                    }
+                        reduces(12);
+                    };
+                    if (k0 > 1) table_step(0, 1);
+                    for (u32 k = 1; k + 4 <= k0; k += 2) table_step(k, 2);
                     {
-                        Fin f = fin_of_prev(FIN_T);
-                        f.draw = (i32)(co + rbase + k0 - 1);
-                        f.msg = w ? msg + 3ull * (rbase + k0 - 1) : nullptr;
+                        const u32 pend = k0 == 1 ? 1 : 2;
+                        Fin f = fin_of_prev(pend == 1 ? FIN_T : FIN_T2);
+                        f.draw = (i32)(co + rbase + k0 - pend);
+                        f.msg = w ? msg + 3ull * (rbase + k0 - pend) : nullptr;
                         WtailArgs a;
                         memset(&a, 0, sizeof a);
                         a.k0 = k0;
                         a.sp = sp;
                         a.hasC = hasC;
                         a.last = ph;
-                        level(k0 - 1, &a.A, &a.C, &a.F);
+                        a.pend = pend;
+                        level(k0 - pend, &a.A, &a.C, &a.F);
                         a.c0 = co + rbase + k0;
                         a.msg = w ? msg + 3ull * (rbase + k0) : nullptr;
                         a.vout = vslot ? vslot + (ph - 1) : nullptr;
-                        StepDesc &st = add(ST_WTAIL, 1, 24.0 * (1ull << (sp - k0 + 1)));
+                        StepDesc &st = add(ST_WTAIL, 1, 24.0 * (1ull << (sp - k0 + pend)));
                         st.fin = f;
                         st.u.wtail = a;
                     }
                 }
                 // ---- line step (a9): every omega challenge is recorded
-                StepDesc &e = add(ST_LT, sblocks(ntab), 8.0 * ntab);
+                StepDesc &e = addg(ST_LT, ntab, 1, 8.0 * ntab);
                 e.u.lt = LtArgs{sp >= 2 ? sp : 0, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
                                 w ? w->lhl : nullptr, w ? w->lhh : nullptr};
             } else {
@@ -813,7 +922,7 @@ struct Planner {
                         f.F = Fend;
                         f.vout = vslot;
                         const u64 ne = (1ull << Lb) + (1ull << (sp - Lb));
-                        StepDesc &e = add(ST_EQ, sblocks(ne), 8.0 * ne);
+                        StepDesc &e = addg(ST_EQ, ne, 1, 8.0 * ne);
                         e.fin = f;
                         e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
                     }
@@ -856,7 +965,7 @@ struct Planner {
                                 a.F = F;       // F^(k-1): the kernel folds it into dst
                                 a.Fout = dst;
                             } else {
-                                StepDesc &fs = add(ST_FOLD, sblocks(a.nfold, 4), a.nfold * 24.0);
+                                StepDesc &fs = addg(ST_FOLD, a.nfold, 4, a.nfold * 24.0);
                                 fs.fin = f;
                                 fs.u.fold = FoldArgs{a.nfold, F, dst};
                                 memset(&f, 0, sizeof f);
@@ -878,7 +987,7 @@ struct Planner {
                                            (ph == 1 && kind != KIND_MUL ? 8 : 0) +
                                            (kind == KIND_MIXED ? 1 : 0) + (a.init ? 4.0 + (ph == 1 ? 8 : 0) : 0);
                         const double nb = S * per + (a.inline_fold ? 24.0 : 8.0) * a.nfold;
-                        StepDesc &ws = add(ST_W, sblocks(std::max<u64>(S, a.inline_fold ? a.nfold : 0), 4), nb);
+                        StepDesc &ws = addg(ST_W, std::max<u64>(S, a.inline_fold ? a.nfold : 0), 4, nb);
                         ws.fin = f;
                         ws.u.w = a;
                         reduces(4);
@@ -893,7 +1002,7 @@ struct Planner {
                     f.last = 2;
                     f.F = Fend;
                     f.vout = vslot ? vslot + 1 : nullptr;
-                    StepDesc &e = add(ST_LT, sblocks(ntab), 8.0 * ntab);
+                    StepDesc &e = addg(ST_LT, ntab, 1, 8.0 * ntab);
                     e.fin = f;
                     e.u.lt = LtArgs{sp >= 2 ? sp : 1, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
                                     w ? w->lhl : nullptr, w ? w->lhh : nullptr};
@@ -928,8 +1037,6 @@ struct Planner {
     }
 };
 
-// A proof's scratch with its step program (for the circuit's own proofs, or
-// one entry of a batch).
 // Group every layer's gates by in1 and by in2 (once per circuit).
 static int ensure_groups(gkr_circuit *c) {
     if (c->gmem) return GKR_OK;
@@ -939,13 +1046,14 @@ static int ensure_groups(gkr_circuit *c) {
     size_t bytes = 0;
     for (u32 i = 0; i < d; i++) {
         const u64 N = 1ull << c->s[i + 1];
-        build_group(c->h_in1[i], N, hg[2 * i]);
-        build_group(c->h_in2[i], N, hg[2 * i + 1]);
+        build_group(c->h_in1[i], c->h_in2[i], c->h_type[i], N, hg[2 * i]);
+        build_group(c->h_in2[i], c->h_in1[i], c->h_type[i], N, hg[2 * i + 1]);
         for (int ph = 0; ph < 2; ph++) {
             const HostGroup &G = hg[2 * i + ph];
             c->nch_max = std::max<u64>(c->nch_max, G.cstart.size());
-            bytes += ((G.perm.size() * 4 + 255) & ~size_t(255)) + ((G.cstart.size() * 4 + 255) & ~size_t(255)) +
-                     ((G.xch.size() * 4 + 255) & ~size_t(255));
+            for (size_t n : {G.perm.size() * 4, G.cstart.size() * 4, G.xch.size() * 4, G.rowptr.size() * 4,
+                             G.oths.size() * 4, G.types.size()})
+                bytes += (n + 255) & ~size_t(255);
         }
     }
     HIP_TRY(hipMalloc(&c->gmem, std::max<size_t>(bytes, 256)));
@@ -964,12 +1072,50 @@ static int ensure_groups(gkr_circuit *c) {
             HIP_TRY(put(G.perm, &D.perm));
             HIP_TRY(put(G.cstart, &D.cstart));
             HIP_TRY(put(G.xch, &D.xch));
+            HIP_TRY(put(G.rowptr, &D.rowptr));
+            HIP_TRY(put(G.oths, &D.oths));
+            if (!G.types.empty()) {
+                D.types = (u8 *)p;
+                p += (G.types.size() + 255) & ~size_t(255);
+                HIP_TRY(hipMemcpy(D.types, G.types.data(), G.types.size(), hipMemcpyHostToDevice));
+            }
             D.nch = (u32)G.cstart.size() - 1;
             D.single = true;
             for (size_t x = 0; x + 1 < G.xch.size() && D.single; x++)
                 D.single = G.xch[x + 1] - G.xch[x] <= 1;
         }
     return GKR_OK;
+}
+
+// (Re)build a workspace's step program with the current launch shapes and
+// upload it; the workspace must be idle.
+static int plan_into(gkr_circuit *c, Workspace &ws) {
+    const u32 epoch = g_tune_epoch.load();
+    Planner plan{c, &ws};
+    plan.build();
+    const size_t nsteps = plan.out.size();
+    if (nsteps != ws.steps.size()) return fail(GKR_ERR_INVALID, "step program changed size");
+    for (const StepDesc &sd : plan.out)
+        if (sd.fin.kind != FIN_NONE && !((fin_mask(sd.kind) >> sd.fin.kind) & 1))
+            return fail(GKR_ERR_INVALID, "step program: a step carries a finish its kernel lacks");
+    ws.steps = plan.out;
+    ws.pclass = plan.cls;
+    ws.pbytes = plan.bytes;
+    ws.punits = plan.units;
+    std::vector<JobEntry> jobs(2 * nsteps);
+    for (size_t t = 0; t < nsteps; t++) {
+        jobs[2 * t] = JobEntry{ws.d_steps + t, 0, 0};
+        jobs[2 * t + 1] = JobEntry{nullptr, step_grid(plan.out[t]), 0};
+    }
+    HIP_TRY(hipMemcpy(ws.d_steps, plan.out.data(), nsteps * sizeof(StepDesc), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ws.d_jobs, jobs.data(), jobs.size() * sizeof(JobEntry), hipMemcpyHostToDevice));
+    ws.epoch = epoch;
+    return GKR_OK;
+}
+
+// Re-plan an idle workspace planned before the launch shapes last changed.
+static int refresh_plan(gkr_circuit *c, Workspace &ws) {
+    return ws.epoch == g_tune_epoch.load() ? GKR_OK : plan_into(c, ws);
 }
 
 // A proof's scratch with its step program (for the circuit's own proofs, or
@@ -986,29 +1132,16 @@ static int make_workspace(gkr_circuit *c, Workspace **out) {
     Workspace probe;
     Arena sz;
     carve(c, sz, probe, nsteps);
-    std::unique_ptr<Workspace> ws(new Workspace());
+    std::unique_ptr<Workspace, void (*)(Workspace *)> ws(new Workspace(), free_workspace);
     HIP_TRY(hipMalloc(&ws->mem, sz.used));
     ws->bytes = sz.used;
     Arena a;
     a.base = (char *)ws->mem;
     a.cap = sz.used;
     carve(c, a, *ws, nsteps);
-    Planner plan{c, ws.get()};
-    plan.build();
-    if (plan.out.size() != nsteps) return fail(GKR_ERR_INVALID, "step program changed size");
-    for (const StepDesc &sd : plan.out)
-        if (sd.fin.kind != FIN_NONE && !((fin_mask(sd.kind) >> sd.fin.kind) & 1))
-            return fail(GKR_ERR_INVALID, "step program: a step carries a finish its kernel lacks");
-    ws->steps = plan.out;
-    ws->pclass = plan.cls;
-    ws->pbytes = plan.bytes;
-    std::vector<JobEntry> jobs(2 * nsteps);
-    for (size_t t = 0; t < nsteps; t++) {
-        jobs[2 * t] = JobEntry{ws->d_steps + t, 0, 0};
-        jobs[2 * t + 1] = JobEntry{nullptr, step_grid(plan.out[t]), 0};
-    }
-    HIP_TRY(hipMemcpy(ws->d_steps, plan.out.data(), nsteps * sizeof(StepDesc), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(ws->d_jobs, jobs.data(), jobs.size() * sizeof(JobEntry), hipMemcpyHostToDevice));
+    ws->steps.resize(nsteps);
+    int rc = plan_into(c, *ws);
+    if (rc) return rc;
     HIP_TRY(hipHostMalloc((void **)&ws->h_msgs, c->n_msgs * 8));
     HIP_TRY(hipHostMalloc((void **)&ws->h_chals, std::max<u64>(c->n_chals, 1) * 8));
     HIP_TRY(hipHostMalloc((void **)&ws->h_setup, 3 * 8));
@@ -1037,7 +1170,7 @@ static int workspace_size(gkr_circuit *c, size_t *bytes) {
 }
 
 static int ensure_workspace(gkr_circuit *c) {
-    if (c->ws) return GKR_OK;
+    if (c->ws) return refresh_plan(c, *c->ws);
     return make_workspace(c, &c->ws);
 }
 
@@ -1061,6 +1194,26 @@ static int enqueue_proof(Workspace &w, hipStream_t st) {
     return GKR_OK;
 }
 
+// Host inputs checked and copied in (device inputs are read in place), then
+// seed, input pointer and a cleared range flag into state[2..4]
+// (asynchronous on st; h_setup must not be reused before st has passed).
+static int stage_proof(gkr_circuit *c, Workspace &w, const uint64_t *inputs, int inputs_on_device,
+                       uint64_t seed, hipStream_t st) {
+    const u64 Sd = c->S[c->L - 1];
+    const u64 *src = inputs;
+    if (!inputs_on_device) {
+        for (u64 g = 0; g < Sd; g++)
+            if (inputs[g] >= fp::P) return fail(GKR_ERR_RANGE, "input value not below p");
+        HIP_TRY(hipMemcpyAsync(w.instage, inputs, Sd * 8, hipMemcpyHostToDevice, st));
+        src = w.instage;
+    }
+    w.h_setup[0] = seed;
+    w.h_setup[1] = (u64)(uintptr_t)src;
+    w.h_setup[2] = 0;
+    HIP_TRY(hipMemcpyAsync(w.state + 2, w.h_setup, 3 * 8, hipMemcpyHostToDevice, st));
+    return GKR_OK;
+}
+
 extern "C" int gkr_prove(const gkr_circuit *cc, const uint64_t *inputs, int inputs_on_device,
                          uint64_t seed, uint64_t *msgs, uint64_t *chals, void *hip_stream) {
     if (!cc || !inputs || !msgs) return fail(GKR_ERR_INVALID, "NULL argument");
@@ -1071,19 +1224,8 @@ extern "C" int gkr_prove(const gkr_circuit *cc, const uint64_t *inputs, int inpu
     int rc = ensure_workspace(c);
     if (rc) return rc;
     Workspace &w = *c->ws;
-    const u64 Sd = c->S[c->L - 1];
-    const u64 *src = inputs;
-    if (!inputs_on_device) {
-        for (u64 g = 0; g < Sd; g++)
-            if (inputs[g] >= fp::P) return fail(GKR_ERR_RANGE, "input value not below p");
-        HIP_TRY(hipMemcpyAsync(w.instage, inputs, Sd * 8, hipMemcpyHostToDevice, st));
-        src = w.instage;
-    }
-    // seed, input pointer and a cleared range flag: state[2..4]
-    w.h_setup[0] = seed;
-    w.h_setup[1] = (u64)(uintptr_t)src;
-    w.h_setup[2] = 0;
-    HIP_TRY(hipMemcpyAsync(w.state + 2, w.h_setup, 3 * 8, hipMemcpyHostToDevice, st));
+    rc = stage_proof(c, w, inputs, inputs_on_device, seed, st);
+    if (rc) return rc;
     rc = enqueue_proof(w, st);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(w.h_msgs, w.msgs, c->n_msgs * 8, hipMemcpyDeviceToHost, st));
@@ -1093,6 +1235,117 @@ extern "C" int gkr_prove(const gkr_circuit *cc, const uint64_t *inputs, int inpu
     if (w.h_setup[2]) return fail(GKR_ERR_RANGE, "input value not below p");
     memcpy(msgs, w.h_msgs, c->n_msgs * 8);
     if (chals) memcpy(chals, w.h_chals, c->n_chals * 8);
+    return GKR_OK;
+}
+
+// ----------------------------------------------------------------- autotune
+
+extern "C" int gkr_autotune(uint32_t n, const gkr_circuit *const *circuits, const uint64_t *const *inputs,
+                            int inputs_on_device, uint32_t reps, void *hip_stream) {
+    if (n == 0 || !circuits || !inputs) return fail(GKR_ERR_INVALID, "no circuits to tune on");
+    for (u32 q = 0; q < n; q++)
+        if (!circuits[q] || !inputs[q]) return fail(GKR_ERR_INVALID, "NULL circuit or inputs");
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    reps = std::max<u32>(reps, 1);
+    std::lock_guard<std::mutex> tl(g_tune_mu);
+    const size_t nkey = (size_t)NKIND * NCLASS * NSHAPE;
+    std::vector<double> tot(nkey, 0.0);
+    std::vector<u32> cnt(nkey, 0);
+    std::vector<hipEvent_t> ev;
+    int rc = GKR_OK;
+    for (int shape = 0; shape < NSHAPE && !rc; shape++) {
+        g_force = shape;  // every tunable step of every plan made now
+        g_tune_epoch++;
+        for (u32 q = 0; q < n && !rc; q++) {
+            gkr_circuit *c = const_cast<gkr_circuit *>(circuits[q]);
+            std::lock_guard<std::mutex> lk(c->mu);
+            rc = ensure_workspace(c);
+            if (rc) break;
+            Workspace &w = *c->ws;
+            const size_t T = w.steps.size();
+            while (ev.size() < 2 * T) {
+                hipEvent_t e = nullptr;
+                if (hipEventCreate(&e) != hipSuccess) {
+                    rc = fail(GKR_ERR_DEVICE, "hipEventCreate failed");
+                    break;
+                }
+                ev.push_back(e);
+            }
+            for (u32 rep = 0; rep <= reps && !rc; rep++) {  // run 0 warms up
+                rc = stage_proof(c, w, inputs[q], inputs_on_device, 1 + rep, st);
+                for (size_t t = 0; t < T && !rc; t++) {
+                    const bool timed = rep > 0 && w.punits[t] != 0;
+                    if (launch_step(st, w.steps[t], timed ? ev[2 * t] : nullptr,
+                                    timed ? ev[2 * t + 1] : nullptr) != hipSuccess)
+                        rc = fail(GKR_ERR_DEVICE, "step launch failed");
+                }
+                if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(GKR_ERR_DEVICE, "stream failed");
+                if (rc || rep == 0) continue;
+                for (size_t t = 0; t < T; t++) {
+                    if (!w.punits[t]) continue;
+                    float ms = 0;
+                    if (hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]) != hipSuccess) continue;
+                    const size_t key = ((size_t)w.steps[t].kind * NCLASS + size_class(w.punits[t])) * NSHAPE + shape;
+                    tot[key] += ms;
+                    cnt[key]++;
+                }
+            }
+        }
+    }
+    g_force = -1;
+    if (!rc) {
+        for (int k = 0; k < NKIND; k++)
+            for (int b = 0; b < NCLASS; b++) {
+                int best = -1;
+                double bm = 0;
+                for (int shape = 0; shape < NSHAPE; shape++) {
+                    const size_t key = ((size_t)k * NCLASS + b) * NSHAPE + shape;
+                    if (!cnt[key]) continue;
+                    const double m = tot[key] / cnt[key];
+                    if (best < 0 || m < bm) {
+                        best = shape;
+                        bm = m;
+                    }
+                }
+                if (best >= 0) g_tune[k][b] = (u8)best;
+            }
+    }
+    g_tune_epoch++;  // plans made during tuning are rebuilt with the choice
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
+extern "C" int gkr_tune_get(uint8_t *buf, uint32_t *len) {
+    if (!len) return fail(GKR_ERR_INVALID, "len is NULL");
+    const uint32_t need = 4 + NKIND * NCLASS;
+    if (!buf) {
+        *len = need;
+        return GKR_OK;
+    }
+    if (*len < need) return fail(GKR_ERR_BUFSIZE, "tuning buffer too small");
+    std::lock_guard<std::mutex> tl(g_tune_mu);
+    buf[0] = 1;
+    buf[1] = (uint8_t)NKIND;
+    buf[2] = (uint8_t)NCLASS;
+    buf[3] = 0;
+    memcpy(buf + 4, g_tune, NKIND * NCLASS);
+    *len = need;
+    return GKR_OK;
+}
+
+extern "C" int gkr_tune_set(const uint8_t *buf, uint32_t len) {
+    std::lock_guard<std::mutex> tl(g_tune_mu);
+    if (!buf) {
+        memset(g_tune, SHAPE_DEFAULT, sizeof g_tune);
+    } else {
+        if (len != 4 + (uint32_t)NKIND * NCLASS || buf[0] != 1 || buf[1] != NKIND || buf[2] != NCLASS)
+            return fail(GKR_ERR_INVALID, "not a tuning table of this library");
+        for (uint32_t q = 4; q < len; q++)
+            if (buf[q] != SHAPE_DEFAULT && buf[q] >= NSHAPE) return fail(GKR_ERR_INVALID, "bad shape code");
+        memcpy(g_tune, buf + 4, NKIND * NCLASS);
+    }
+    g_tune_epoch++;
     return GKR_OK;
 }
 
@@ -1109,6 +1362,7 @@ namespace {
 struct BatchPlan {
     std::vector<gkr_circuit *> key;
     int flags = 0;
+    u32 epoch = 0;  // launch shapes its programs were planned with
     std::vector<Workspace *> ws;
     std::vector<u32> l_off, l_njobs, l_blocks;  // per launch
     std::vector<u64> out_off;
@@ -1164,6 +1418,7 @@ int build_batch(const std::vector<gkr_circuit *> &cs, int flags, std::unique_ptr
     std::unique_ptr<BatchPlan> B(new BatchPlan());
     B->key = cs;
     B->flags = flags;
+    B->epoch = g_tune_epoch.load();
     const u32 n = (u32)cs.size();
     for (gkr_circuit *c : cs) {
         Workspace *w = nullptr;
@@ -1269,6 +1524,10 @@ extern "C" int gkr_batch_prove(uint32_t n, const gkr_circuit *const *circuits,
     BatchPlan *B = nullptr;
     for (size_t k = 0; k < g_batches.size(); k++)
         if (g_batches[k]->key == key && g_batches[k]->flags == flags) {
+            if (g_batches[k]->epoch != g_tune_epoch.load()) {  // planned with older shapes
+                g_batches.erase(g_batches.begin() + k);
+                break;
+            }
             std::unique_ptr<BatchPlan> hit = std::move(g_batches[k]);
             g_batches.erase(g_batches.begin() + k);
             g_batches.push_back(std::move(hit));
@@ -1728,7 +1987,7 @@ extern "C" int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_devic
 
 extern "C" int gkr_field_op(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
                             void *hip_stream) {
-    if (op < 0 || op > 3 || (n && (!a || !b || !out))) return fail(GKR_ERR_INVALID, "bad argument");
+    if (op < 0 || op > 4 || (n && (!a || !b || !out))) return fail(GKR_ERR_INVALID, "bad argument");
     hipStream_t st = pick_stream(hip_stream);
     if (!st) return fail(GKR_ERR_DEVICE, "no stream");
     if (n == 0) return GKR_OK;
@@ -1792,6 +2051,13 @@ struct gkr_server {
         if (!v.empty()) {
             r->ws = v.back();
             v.pop_back();
+            std::lock_guard<std::mutex> lk(r->c->mu);
+            const int rc = refresh_plan(r->c, *r->ws);
+            if (rc) {
+                pool[r->c].push_back(r->ws);
+                r->ws = nullptr;
+                return rc;
+            }
             return 1;
         }
         size_t need = 0;

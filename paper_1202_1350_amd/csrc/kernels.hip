@@ -310,6 +310,16 @@ hipError_t launch_f2sc_single(hipStream_t st, const u32 *a32, u64 *msg) {
 __global__ void __launch_bounds__(BLOCK) k_field_op(int op, const u64 *a, const u64 *b, u64 *out,
                                                     u64 n) {
     for (u64 i = GTID; i < n; i += GSTRIDE) {
+        if (op == 4) {
+            // 256 dependent products per element: independent chains across
+            // elements, for measuring the product rate
+            u64 x = a[i];
+            const u64 y = b[i];
+#pragma unroll 16
+            for (int k = 0; k < 256; k++) x = mul(x, y);
+            out[i] = x;
+            continue;
+        }
         if (op == 3) {
             fp::u128 s = 0;
             for (u64 j = 0; j < 64; j++) {

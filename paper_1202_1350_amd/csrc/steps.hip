@@ -48,6 +48,12 @@ __device__ __forceinline__ u64 lane63(u64 v) {
     return ((u64)hi << 32) | lo;
 }
 
+// Value of lane Q of this lane's quad (lanes 4m..4m+3).
+template <int Q>
+__device__ __forceinline__ u64 quad_get(u64 v) {
+    return dpp64<Q | (Q << 2) | (Q << 4) | (Q << 6), 0xf>(v);
+}
+
 // Sum over the wave, left in lane 63: prefix sums within each row of 16
 // lanes (shifts 1, 2, 4, 8), then row 0's total into row 1 and row 2's into
 // row 3, then lane 31's into rows 2 and 3.  Lanes a shift leaves without a
@@ -94,9 +100,11 @@ __device__ __forceinline__ void rows_total(const u64 *rows, u32 first, u32 n, u6
         constexpr u32 G = SBLOCK / K;
         __shared__ u64 part[G][K];
         const u32 k = threadIdx.x % K, g = threadIdx.x / K;
-        u64 v = 0;
-        for (u32 r = g; r < n; r += G) v = add(v, rows[(u64)(first + r) * ROW_STRIDE + k]);
-        part[g][k] = v;
+        if (g < G) {
+            u64 v = 0;
+            for (u32 r = g; r < n; r += G) v = add(v, rows[(u64)(first + r) * ROW_STRIDE + k]);
+            part[g][k] = v;
+        }
         __syncthreads();
         if (threadIdx.x < K) {
             u64 a = 0;
@@ -130,7 +138,18 @@ struct Ctx {
     u32 lb, nb;      // this workgroup within the step, workgroups of the step
     u64 gtid, gstride;
     u64 r;           // challenge drawn in the prologue
+    u64 r2;          // the second one, after a two-round step
 };
+
+__device__ __forceinline__ u64 fold1(u64 x0, u64 x1, u64 r) { return add(x0, mul(r, sub(x1, x0))); }
+
+// p-phase message from the two sums: G(0) = C (1-z) S0, G(1) = C z S1,
+// G(2) = C (3z - 1)(2 S1 - S0).
+__device__ __forceinline__ void p_message(u64 *msg, u64 C, u64 z, u64 S0, u64 S1) {
+    msg[0] = mul(mul(C, sub(1, z)), S0);
+    msg[1] = mul(mul(C, z), S1);
+    msg[2] = mul(mul(C, sub(add(add(z, z), z), 1)), sub(add(S1, S1), S0));
+}
 
 // ------------------------------------------------------------- prologue
 
@@ -143,12 +162,20 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
         u64 t[2];
         rows_total<2>(f.rows, 0, f.nrows, t);
         if (threadIdx.x == 0) {
-            const u64 z = pp.zbuf[f.j], C = pp.state[0], S0 = t[0], S1 = t[1];
-            f.msg[0] = mul(mul(C, sub(1, z)), S0);
-            f.msg[1] = mul(mul(C, z), S1);
-            const u64 c3 = sub(add(add(z, z), z), 1);  // eq(z, 2) = 3z - 1
-            f.msg[2] = mul(mul(C, c3), sub(add(S1, S1), S0));
+            const u64 z = pp.zbuf[f.j], C = pp.state[0];
+            p_message(f.msg, C, z, t[0], t[1]);
             pp.state[0] = mul(C, fp::eq(z, c.r));     // beta prefix over r_0..r_j
+        }
+    } else if ((FM & (1u << FIN_P2)) && f.kind == FIN_P2) {
+        u64 t[6];
+        rows_total<6>(f.rows, 0, f.nrows, t);
+        if (threadIdx.x == 0) {
+            const u64 z0 = pp.zbuf[f.j], z1 = pp.zbuf[f.j + 1];
+            u64 C = pp.state[0];
+            p_message(f.msg, C, z0, t[0], t[1]);
+            C = mul(C, fp::eq(z0, c.r));
+            p_message(f.msg + 3, C, z1, add(t[2], mul(c.r, t[3])), add(t[4], mul(c.r, t[5])));
+            pp.state[0] = mul(C, fp::eq(z1, c.r2));
         }
     } else if ((FM & (1u << FIN_W)) && f.kind == FIN_W) {
         u64 t[4];
@@ -174,6 +201,16 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
             f.msg[0] = t[0];
             f.msg[1] = t[1];
             f.msg[2] = t[2];
+        }
+    } else if ((FM & (1u << FIN_T2)) && f.kind == FIN_T2) {
+        u64 t[12];
+        rows_total<12>(f.rows, 0, f.nrows, t);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                f.msg[q] = t[q];
+                f.msg[3 + q] = add(t[3 + q], mul(c.r, add(t[6 + q], mul(c.r, t[9 + q]))));
+            }
         }
     } else if ((FM & (1u << FIN_LINE)) && f.kind == FIN_LINE) {
         if (f.T > 0) {
@@ -246,30 +283,73 @@ __device__ void step_eq(const EqArgs &a, const Ctx &c, const u64 *pt) {
     }
 }
 
-__device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
-    const u64 r = c.r;
-    const u64 mask = (1ull << a.L) - 1;
-    u64 acc[2] = {0, 0};
-    for (u64 m = c.gtid; m < a.nm; m += c.gstride) {
-        u64 v0, v1, b;
-        if (a.first) {
-            const u64x2 p = ld2(a.Vsrc, 2 * m);
-            v0 = p.x;
-            v1 = p.y;
-            b = mul(a.zlo[m & mask], a.zhi[m >> a.L]);
-        } else {
-            const u64x2 p = ld2(a.Vsrc, 4 * m), q = ld2(a.Vsrc, 4 * m + 2);
-            v0 = add(p.x, mul(r, sub(p.y, p.x)));
-            v1 = add(q.x, mul(r, sub(q.y, q.x)));
-            if (a.Vout) st2(a.Vout, 2 * m, v0, v1);
-            const u64x2 bb = ld2(a.Bprev, 2 * m);
-            b = add(bb.x, bb.y);
-        }
-        if (a.Bout) a.Bout[m] = b;
-        acc[0] = add(acc[0], mul(b, v0));
-        acc[1] = add(acc[1], mul(b, v1));
+// Two-round steps give each quad (four consecutive entries of the level
+// they sum over) to four adjacent lanes: lane j of the quad holds entry j,
+// loads and stores stay coalesced, the quad's values are exchanged with DPP
+// quad permutes and the quad's products are split over its lanes.
+
+// p-phase quad v0..v3 of V^(j) with b0 = B_j[2u], b1 = B_j[2u+1]: round j's
+// sums S0, S1 and the coefficients of round j+1's sums in r_j (U0 + r U1,
+// W0 + r W1); lane j of the quad adds its share.  B_{j+1}[u] = b0 + b1.
+__device__ __forceinline__ void p_quad(u32 j, u64 v0, u64 v1, u64 v2, u64 v3, u64 b0, u64 b1,
+                                       u64 (&acc)[6]) {
+    const u64 bb = add(b0, b1);
+    if (j == 0) acc[0] = add(acc[0], add(mul(b0, v0), mul(b1, v2)));
+    else if (j == 1) acc[1] = add(acc[1], add(mul(b0, v1), mul(b1, v3)));
+    else if (j == 2) {
+        acc[2] = add(acc[2], mul(bb, v0));
+        acc[3] = add(acc[3], mul(bb, sub(v1, v0)));
+    } else {
+        acc[4] = add(acc[4], mul(bb, v2));
+        acc[5] = add(acc[5], mul(bb, sub(v3, v2)));
     }
-    block_store<2>(acc, row);
+}
+
+__device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
+    const u64 mask = (1ull << a.L) - 1;
+    auto beta0 = [&](u64 m) { return mul(a.zlo[m & mask], a.zhi[m >> a.L]); };  // B_0[m]
+    if (a.first && !a.look) {
+        // one round (s = 1)
+        u64 acc[2] = {0, 0};
+        for (u64 m = c.gtid; m < a.nu; m += c.gstride) {
+            const u64x2 p = ld2(a.Vsrc, 2 * m);
+            const u64 b = beta0(m);
+            acc[0] = add(acc[0], mul(b, p.x));
+            acc[1] = add(acc[1], mul(b, p.y));
+        }
+        block_store<2>(acc, row);
+        return;
+    }
+    u64 acc[6] = {0, 0, 0, 0, 0, 0};
+    const u64 r0 = c.r, r1 = c.r2;
+    // lanes g = 4u + j; the stride is a multiple of 4, so a quad's lanes
+    // leave the loop together
+    for (u64 g = c.gtid; (g >> 2) < a.nu; g += c.gstride) {
+        const u64 u = g >> 2;
+        const u32 j = (u32)(g & 3);
+        u64 v, bq;  // entry 4u + j of this step's level; B of that level at pair 2u + j/2
+        if (a.first) {
+            v = a.Vsrc[g];
+            bq = beta0(2 * u + (j >> 1));  // lanes 0, 1: B_0[2u]; lanes 2, 3: B_0[2u+1]
+        } else {
+            const u64x2 p = ld2(a.Vsrc, 4 * g), q = ld2(a.Vsrc, 4 * g + 2);
+            v = fold1(fold1(p.x, p.y, r0), fold1(q.x, q.y, r0), r1);
+            if (a.Vout) a.Vout[g] = v;
+            bq = a.Bprev[g];  // B_{j+1}[4u + j]
+        }
+        const u64 v0 = quad_get<0>(v), v1 = quad_get<1>(v), v2 = quad_get<2>(v), v3 = quad_get<3>(v);
+        u64 b0, b1;
+        if (a.first) {
+            b0 = quad_get<0>(bq);
+            b1 = quad_get<2>(bq);
+        } else {
+            b0 = add(quad_get<0>(bq), quad_get<1>(bq));  // B_{j+2}[2u]
+            b1 = add(quad_get<2>(bq), quad_get<3>(bq));  // B_{j+2}[2u+1]
+        }
+        if (j == 0 && a.Bout) a.Bout[u] = add(b0, b1);
+        p_quad(j, v0, v1, v2, v3, b0, b1, acc);
+    }
+    block_store<6>(acc, row);
 }
 
 // Gate g with bound-wire index idx, at round k of its phase:
@@ -444,32 +524,28 @@ __device__ void step_line(const LineArgs &a, const Ctx &c, u64 *row) {
 // w V[in2] (sC).  Phase 2: sums of the weights over ADD gates (sA) and MUL
 // gates (sC); v1 enters when the level-0 tables are formed.
 template <typename Args>
-__device__ __forceinline__ void wire_sums(const Args &a, u64 beta, u32 p0, u32 p1, u64 &sA, u64 &sC) {
+__device__ __forceinline__ void wire_sums(const Args &a, u64 beta, u32 p0, u32 p1, u64 &sA_out,
+                                          u64 &sC_out) {
     const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
-    sA = 0;
-    sC = 0;
+    // branch-free updates keep both sums in registers
+    u64 sA = 0, sC = 0;
     for (u32 p = p0; p < p1; p++) {
-        const u32 g = a.perm[p];
-        const bool ismul = a.kind == 1 || (a.kind == 2 && a.type[g]);
+        const u32 g = a.perm[p], o = a.oths[p];
+        const bool ismul = a.kind == 1 || (a.kind == 2 && a.types[p]);
         u64 w = mul(beta, mul(a.alo[g & amask], a.ahi[g >> a.La]));
         if (a.ph == 1) {
-            const u64 y = a.Vn[a.oth[g]];
-            const u64 wy = mul(w, y);
-            if (ismul) {
-                sA = add(sA, wy);
-            } else {
-                sA = add(sA, w);
-                sC = add(sC, wy);
-            }
+            const u64 wy = mul(w, a.Vn[o]);
+            sA = add(sA, ismul ? wy : w);
+            sC = add(sC, ismul ? 0 : wy);
         } else {
-            const u32 i1 = a.oth[g];
+            const u32 i1 = o;
             w = mul(w, mul(a.blo[i1 & bmask], a.bhi[i1 >> a.Lb]));
-            if (ismul)
-                sC = add(sC, w);
-            else
-                sA = add(sA, w);
+            sA = add(sA, ismul ? 0 : w);
+            sC = add(sC, ismul ? w : 0);
         }
     }
+    sA_out = sA;
+    sC_out = sC;
 }
 
 __device__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp, const Ctx &c) {
@@ -491,6 +567,60 @@ __device__ __forceinline__ void table_terms(u64 A0, u64 A1, u64 C0, u64 C1, u64 
     acc[2] = add(acc[2], add(mul(A2, F2), C2));
 }
 
+// One quad of level-k tables, held one entry per lane by four adjacent
+// lanes (this lane is j): round k's sums over its two pairs (acc[0..2],
+// lane 3) and the coefficients of round k+1's sums in r_k (lane t < 3 takes
+// t).  The quad folds to the pair (X0 + r dX0, X2 + r dX2), dX0 = X1 - X0,
+// dX2 = X3 - X2, whose value at t is a_t + r b_t with a = (X0, X2, 2 X2 - X0),
+// b = (dX0, dX2, 2 dX2 - dX0):
+//   Q0(t) += aA aF + aC, Q1(t) += aA bF + bA aF + bC, Q2(t) += bA bF.
+__device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC, u64 (&acc)[12]) {
+    const u64 A0 = quad_get<0>(A), A1 = quad_get<1>(A), A2 = quad_get<2>(A), A3 = quad_get<3>(A);
+    const u64 F0 = quad_get<0>(F), F1 = quad_get<1>(F), F2 = quad_get<2>(F), F3 = quad_get<3>(F);
+    u64 C0 = 0, C1 = 0, C2 = 0, C3 = 0;
+    if (hasC) {
+        C0 = quad_get<0>(C);
+        C1 = quad_get<1>(C);
+        C2 = quad_get<2>(C);
+        C3 = quad_get<3>(C);
+    }
+    if (j == 3) {
+        u64 m[3] = {acc[0], acc[1], acc[2]};
+        table_terms(A0, A1, C0, C1, F0, F1, m);
+        table_terms(A2, A3, C2, C3, F2, F3, m);
+        acc[0] = m[0];
+        acc[1] = m[1];
+        acc[2] = m[2];
+        return;
+    }
+    // a_t, b_t of this lane's t = j
+    auto ab = [&](u64 X0, u64 X1, u64 X2, u64 X3, u64 &at, u64 &bt) {
+        const u64 d0 = sub(X1, X0), d2 = sub(X3, X2);
+        if (j == 0) {
+            at = X0;
+            bt = d0;
+        } else if (j == 1) {
+            at = X2;
+            bt = d2;
+        } else {
+            at = sub(add(X2, X2), X0);
+            bt = sub(add(d2, d2), d0);
+        }
+    };
+    u64 aA, bA, aF, bF, aC = 0, bC = 0;
+    ab(A0, A1, A2, A3, aA, bA);
+    ab(F0, F1, F2, F3, aF, bF);
+    if (hasC) ab(C0, C1, C2, C3, aC, bC);
+    // slot t = j of each coefficient (a dynamic index would spill acc)
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+        if ((u32)t != j) continue;
+        acc[3 + t] = add(acc[3 + t], add(mul(aA, aF), aC));
+        acc[6 + t] = add(acc[6 + t], add(add(mul(aA, bF), mul(bA, aF)), bC));
+        acc[9 + t] = add(acc[9 + t], mul(bA, bF));
+    }
+}
+
 // Level-0 entries from a wire's sums (phase 2: ADD gates w (v1 + G(t)),
 // MUL gates w v1 G(t)).
 __device__ __forceinline__ void level0(u32 ph, u64 v1, u64 sA, u64 sC, u64 &A, u64 &C) {
@@ -503,71 +633,73 @@ __device__ __forceinline__ void level0(u32 ph, u64 v1, u64 sA, u64 sC, u64 &A, u
     }
 }
 
-__device__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
-    const u64 v1 = a.ph == 2 ? pp.state[1] : 0;
+// Level-0 tables of an omega phase and round 0; a thread takes a pair of
+// wires.  wire(x, sA, sC) gives the sums of wire x's gates.
+template <typename Wire>
+__device__ __forceinline__ void level0_round(u32 ph, u32 hasC, u64 npairs, const u64 *F, u64 *At, u64 *Ct,
+                                             const ProofPtrs &pp, const Ctx &c, u64 *row, Wire wire) {
+    const u64 v1 = ph == 2 ? pp.state[1] : 0;
     u64 acc[3] = {0, 0, 0};
-    for (u64 m = c.gtid; m < a.npairs; m += c.gstride) {
+    for (u64 m = c.gtid; m < npairs; m += c.gstride) {
         u64 A[2], C[2];
 #pragma unroll
         for (int h = 0; h < 2; h++) {
-            const u64 x = 2 * m + h;
-            u64 sA = 0, sC = 0;
-            for (u32 ch = a.xch[x]; ch < a.xch[x + 1]; ch++) {
-                sA = add(sA, a.partA[ch]);
-                sC = add(sC, a.partC[ch]);
-            }
-            level0(a.ph, v1, sA, sC, A[h], C[h]);
+            u64 sA, sC;
+            wire(2 * m + h, sA, sC);
+            level0(ph, v1, sA, sC, A[h], C[h]);
+            if (!hasC) C[h] = 0;
         }
-        st2(a.A, 2 * m, A[0], A[1]);
-        if (a.hasC) st2(a.C, 2 * m, C[0], C[1]);
-        const u64x2 f = ld2(a.F, 2 * m);
-        table_terms(A[0], A[1], a.hasC ? C[0] : 0, a.hasC ? C[1] : 0, f.x, f.y, acc);
+        st2(At, 2 * m, A[0], A[1]);
+        if (hasC) st2(Ct, 2 * m, C[0], C[1]);
+        const u64x2 f = ld2(F, 2 * m);
+        table_terms(A[0], A[1], C[0], C[1], f.x, f.y, acc);
     }
     block_store<3>(acc, row);
+}
+
+__device__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
+    level0_round(a.ph, a.hasC, a.npairs, a.F, a.A, a.C, pp, c, row, [&](u64 x, u64 &sA, u64 &sC) {
+        sA = 0;
+        sC = 0;
+        for (u32 ch = a.xch[x]; ch < a.xch[x + 1]; ch++) {
+            sA = add(sA, a.partA[ch]);
+            sC = add(sC, a.partC[ch]);
+        }
+    });
 }
 
 __device__ void step_wa0(const Wa0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
     const u64 beta = pp.state[0];
-    const u64 v1 = a.ph == 2 ? pp.state[1] : 0;
-    u64 acc[3] = {0, 0, 0};
-    for (u64 m = c.gtid; m < a.npairs; m += c.gstride) {
-        u64 A[2], C[2];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const u64 x = 2 * m + h;
-            const u32 ch = a.xch[x];
-            u64 sA = 0, sC = 0;
-            if (ch < a.xch[x + 1]) wire_sums(a, beta, a.cstart[ch], a.cstart[ch + 1], sA, sC);
-            level0(a.ph, v1, sA, sC, A[h], C[h]);
-        }
-        st2(a.A, 2 * m, A[0], A[1]);
-        if (a.hasC) st2(a.C, 2 * m, C[0], C[1]);
-        const u64x2 f = ld2(a.Vn, 2 * m);
-        table_terms(A[0], A[1], a.hasC ? C[0] : 0, a.hasC ? C[1] : 0, f.x, f.y, acc);
-    }
-    block_store<3>(acc, row);
+    level0_round(a.ph, a.hasC, a.npairs, a.Vn, a.A, a.C, pp, c, row, [&](u64 x, u64 &sA, u64 &sC) {
+        wire_sums(a, beta, a.rowptr[x], a.rowptr[x + 1], sA, sC);
+    });
 }
 
 __device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
-    const u64 r = c.r;
-    u64 acc[3] = {0, 0, 0};
-    for (u64 m = c.gtid; m < a.npairs; m += c.gstride) {
-        const u64x2 a0 = ld2(a.A, 4 * m), a1 = ld2(a.A, 4 * m + 2);
-        const u64x2 f0 = ld2(a.F, 4 * m), f1 = ld2(a.F, 4 * m + 2);
-        const u64 A0 = add(a0.x, mul(r, sub(a0.y, a0.x))), A1 = add(a1.x, mul(r, sub(a1.y, a1.x)));
-        const u64 F0 = add(f0.x, mul(r, sub(f0.y, f0.x))), F1 = add(f1.x, mul(r, sub(f1.y, f1.x)));
-        st2(a.An, 2 * m, A0, A1);
-        st2(a.Fn, 2 * m, F0, F1);
-        u64 C0 = 0, C1 = 0;
-        if (a.hasC) {
-            const u64x2 c0 = ld2(a.C, 4 * m), c1 = ld2(a.C, 4 * m + 2);
-            C0 = add(c0.x, mul(r, sub(c0.y, c0.x)));
-            C1 = add(c1.x, mul(r, sub(c1.y, c1.x)));
-            st2(a.Cn, 2 * m, C0, C1);
+    const u64 r0 = c.r, r1 = c.r2;
+    u64 acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; q++) acc[q] = 0;
+    const u32 pend = a.pend;
+    auto foldp = [&](const u64 *X, u64 g) {  // level-(k+pend) entry g from level k
+        if (pend == 1) {
+            const u64x2 p = ld2(X, 2 * g);
+            return fold1(p.x, p.y, r0);
         }
-        table_terms(A0, A1, C0, C1, F0, F1, acc);
+        const u64x2 p = ld2(X, 4 * g), q = ld2(X, 4 * g + 2);
+        return fold1(fold1(p.x, p.y, r0), fold1(q.x, q.y, r0), r1);
+    };
+    // lane g = entry 4u + j of level k+pend (the stride is a multiple of 4)
+    for (u64 g = c.gtid; (g >> 2) < a.nu; g += c.gstride) {
+        const u32 j = (u32)(g & 3);
+        const u64 A = foldp(a.A, g), F = foldp(a.F, g);
+        const u64 C = a.hasC ? foldp(a.C, g) : 0;
+        a.An[g] = A;
+        a.Fn[g] = F;
+        if (a.hasC) a.Cn[g] = C;
+        table_quad(j, A, C, F, a.hasC != 0, acc);
     }
-    block_store<3>(acc, row);
+    block_store<12>(acc, row);
 }
 
 // ------------------------------------------------------------------ tails
@@ -607,13 +739,22 @@ __device__ __forceinline__ void wave_total(u64 (&v)[K]) {
     for (int k = 0; k < K; k++) v[k] = lane63(wave_sum63(v[k]));
 }
 
-__device__ __forceinline__ u64 fold1(u64 x0, u64 x1, u64 r) { return add(x0, mul(r, sub(x1, x0))); }
-
 constexpr int TAIL_E = TAIL_LIM / SBLOCK;  // entries per thread at most
 
-// Remaining omega rounds k0..s'-1.  The prologue drew r_{k0-1}; each round
-// writes its message, then draws its challenge; after the last fold F holds
-// v1 (or v2).
+// Entry e of the level a tail starts from, folded from memory by the
+// pending challenge(s) of the prologue.
+__device__ __forceinline__ u64 tail_entry(const u64 *X, u32 e, u32 pend, const Ctx &c) {
+    if (pend == 1) {
+        const u64x2 p = ld2(X, 2 * e);
+        return fold1(p.x, p.y, c.r);
+    }
+    const u64x2 p = ld2(X, 4 * e), q = ld2(X, 4 * e + 2);
+    return fold1(fold1(p.x, p.y, c.r), fold1(q.x, q.y, c.r), c.r2);
+}
+
+// Remaining omega rounds k0..s'-1.  The prologue drew the pending
+// challenge(s) up to r_{k0-1}; each round writes its message, then draws its
+// challenge; after the last fold F holds v1 (or v2).
 __device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx &c) {
     __shared__ u64 s_sum[2][3][NWAVES];
     __shared__ u64 s_g[3][64];
@@ -623,20 +764,16 @@ __device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx &c
     u32 E = n >= 2 * SBLOCK ? n / SBLOCK : 1;
     u64 A[TAIL_E], C[TAIL_E], F[TAIL_E];
     {
-        // level k0 = fold of level k0-1 (2n entries in memory) by r_{k0-1}
-        const u64 r = c.r;
+        // level k0 from level k0 - pend in memory, folded by the pending
+        // challenges (r_{k0-1}; or r_{k0-2}, r_{k0-1})
         const u32 e0 = tid * E;
 #pragma unroll
         for (int q = 0; q < TAIL_E; q++) {
             A[q] = C[q] = F[q] = 0;
             if (q < (int)E && e0 + q < n) {
-                const u64x2 pa = ld2(a.A, 2 * (e0 + q)), pf = ld2(a.F, 2 * (e0 + q));
-                A[q] = fold1(pa.x, pa.y, r);
-                F[q] = fold1(pf.x, pf.y, r);
-                if (hc) {
-                    const u64x2 pc = ld2(a.C, 2 * (e0 + q));
-                    C[q] = fold1(pc.x, pc.y, r);
-                }
+                A[q] = tail_entry(a.A, e0 + q, a.pend, c);
+                F[q] = tail_entry(a.F, e0 + q, a.pend, c);
+                if (hc) C[q] = tail_entry(a.C, e0 + q, a.pend, c);
             }
         }
     }
@@ -732,8 +869,9 @@ __device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx &c
     }
 }
 
-// Remaining p-phase rounds j0..s-1.  The prologue drew r_{j0-1} and folded
-// its message into the beta prefix C = state[0].  B is the table of sums of
+// Remaining p-phase rounds j0..s-1.  The prologue drew the pending
+// challenge(s) up to r_{j0-1} and folded them into the beta prefix
+// C = state[0].  B is the table of sums of
 // the eq weights of the a-coordinates not yet reached (beta over z's
 // suffix); pair m of V goes with B[m], which sits in the pair's first
 // thread (stride 2 sg, or entries [t E / 2, (t + 1) E / 2) while pairs are
@@ -746,15 +884,11 @@ __device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx &c
     u32 E = n >= 2 * SBLOCK ? n / SBLOCK : 1;
     u64 V[TAIL_E], B[TAIL_E / 2 > 0 ? TAIL_E / 2 : 1];
     {
-        const u64 r = c.r;
         const u32 e0 = tid * E;
 #pragma unroll
         for (int q = 0; q < TAIL_E; q++) {
             V[q] = 0;
-            if (q < (int)E && e0 + q < n) {
-                const u64x2 pv = ld2(a.V, 2 * (e0 + q));
-                V[q] = fold1(pv.x, pv.y, r);
-            }
+            if (q < (int)E && e0 + q < n) V[q] = tail_entry(a.V, e0 + q, a.pend, c);
         }
         // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1], m < n/2
         if (E >= 2) {
@@ -876,7 +1010,7 @@ __device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx &c
 // beside the body instead of ahead of it) and records the drawn challenge.
 template <u32 KIND, int GK, int PH>
 __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
-    __shared__ u64 s_r;
+    __shared__ u64 s_r, s_r2;
     __shared__ u64 s_pt[64];  // a point (EQ), or b* and c* (LT), or z_{i+1} (FIN_LINE)
     Ctx c;
     c.lb = lb;
@@ -893,7 +1027,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
 
     // --- prologue: the challenge (every workgroup draws the same value)
     if (threadIdx.x == 0) {
-        u64 r = 0;
+        u64 r = 0, r2 = 0;
         if (f.draw >= 0) {
             u64 st = pp.rngst[f.draw];
             r = fp::sm_field(st);
@@ -901,11 +1035,20 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
                 pp.chals[f.draw] = r;
                 pp.rngst[f.draw + 1] = st;
             }
+            if (f.kind == FIN_P2 || f.kind == FIN_T2) {  // two rounds finish here
+                r2 = fp::sm_field(st);
+                if (recorder) {
+                    pp.chals[f.draw + 1] = r2;
+                    pp.rngst[f.draw + 2] = st;
+                }
+            }
         }
         s_r = r;
+        s_r2 = r2;
     }
     __syncthreads();
     c.r = s_r;
+    c.r2 = s_r2;
     // points assembled in LDS (challenges drawn by earlier launches are in
     // chals; the one drawn just now is c.r)
     if ((fin_mask(KIND) & (1u << FIN_LINE)) && f.kind == FIN_LINE && threadIdx.x < f.sp) {

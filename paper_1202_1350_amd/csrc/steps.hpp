@@ -59,7 +59,17 @@ enum FinKind : u32 {
     FIN_W,     // omega message from rows of (E0, E1, O0, O1)
     FIN_LINE,  // h(t) values from rows of line sums; then tau and z_{i+1}
     FIN_T,     // message (G(0), G(1), G(2)) from rows of three sums
+    FIN_P2,    // two p-phase messages from rows of (S0, S1, U0, U1, W0, W1)
+    FIN_T2,    // two table-round messages from rows of (G(0..2), Q0(0..2), Q1(0..2), Q2(0..2))
 };
+
+// Two rounds per launch.  The sums of round k+1 are, before r_k is known,
+// polynomials in r_k with coefficients that are sums over the level-k
+// tables: a step that reaches round k also sums those coefficients, and the
+// finish of its rows writes message k, draws r_k, evaluates message k+1 at
+// r_k, writes it and draws r_{k+1}.
+//   p-phase: S0' = U0 + r_k U1, S1' = W0 + r_k W1.
+//   table rounds: G'(t) = Q0(t) + r_k Q1(t) + r_k^2 Q2(t).
 
 constexpr u32 KALL = 0xFFFF;  // kind resolved at run time (mixed batches)
 
@@ -67,8 +77,10 @@ constexpr u32 KALL = 0xFFFF;  // kind resolved at run time (mixed batches)
 // each kernel instantiation compiles only these.
 __host__ __device__ constexpr u32 fin_mask(u32 kind) {
     return kind == KALL                              ? 0xFFu
-           : (kind == ST_P || kind == ST_PTAIL)      ? 1u << FIN_P
-           : (kind == ST_WT || kind == ST_WTAIL)     ? 1u << FIN_T
+           : kind == ST_P                            ? 1u << FIN_P2
+           : kind == ST_PTAIL                        ? (1u << FIN_P) | (1u << FIN_P2)
+           : kind == ST_WT                           ? (1u << FIN_T) | (1u << FIN_T2)
+           : kind == ST_WTAIL                        ? (1u << FIN_T) | (1u << FIN_T2)
            : kind == ST_EQ                           ? (1u << FIN_LINE) | (1u << FIN_W)
            : kind == ST_END                          ? 1u << FIN_LINE
            : (kind == ST_W || kind == ST_FOLD || kind == ST_LT) ? 1u << FIN_W
@@ -136,9 +148,14 @@ struct EqArgs {
     u32 base;   // PT_CHAL: first challenge index; PT_Z: first coordinate of z
     u64 *lo, *hi;
 };
+// p-phase grid step.  first: round 0 (and 1) on V_i and the eq tables of
+// z_i[1..s); a unit is a quad of V_i (look) or a pair (s = 1); writes
+// B_1 (look).  Otherwise: rounds j+2, j+3 from V^(j) and B_{j+1} folded by
+// r_j, r_{j+1}; a unit is a quad of V^(j+2) (16 entries of V^(j), 4 of
+// B_{j+1}); writes V^(j+2) and B_{j+3}.
 struct PArgs {
-    u32 first;
-    u64 nm;
+    u32 first, look;
+    u64 nu;        // units
     const u64 *Vsrc;
     u64 *Vout;
     const u64 *Bprev;
@@ -184,10 +201,10 @@ struct SgeArgs {
 //   G_k(t) = sum_m A_k(t, m) F_k(t, m) + C_k(t, m).
 struct WaggArgs {
     u32 kind, ph;
-    u32 nch;                 // chunks: perm[cstart[ch] .. cstart[ch+1]) share one wire x
-    const u32 *perm, *cstart;
-    const u32 *oth;          // other wire (ph 1: in2; ph 2: in1)
-    const u8 *type;
+    u32 nch;                 // chunks: sorted positions [cstart[ch], cstart[ch+1]) share one wire x
+    const u32 *perm, *cstart;  // perm[p]: the gate at sorted position p
+    const u32 *oths;         // other wire (ph 1: in2; ph 2: in1) by sorted position
+    const u8 *types;         // gate type by sorted position (mixed layers)
     const u64 *Vn;
     const u64 *alo, *ahi;
     u32 La;
@@ -203,14 +220,14 @@ struct Wt0Args {
     const u64 *F;            // V_{i+1}
     u64 *A, *C;              // level-0 tables
 };
-// ST_WA0: wire x's gates are perm[cstart[xch[x]] .. cstart[xch[x] + 1])
-// when xch[x] < xch[x + 1] (at most one chunk per wire).
+// ST_WA0: wire x's gates sit at sorted positions [rowptr[x], rowptr[x+1])
+// (at most one chunk of gates per wire).
 struct Wa0Args {
     u32 kind, ph, hasC;
     u64 npairs;
-    const u32 *perm, *cstart, *xch;
-    const u32 *oth;
-    const u8 *type;
+    const u32 *perm, *rowptr;
+    const u32 *oths;
+    const u8 *types;
     const u64 *Vn;           // V_{i+1}: gathered operands and the table F
     const u64 *alo, *ahi;
     u32 La;
@@ -218,22 +235,28 @@ struct Wa0Args {
     u32 Lb;
     u64 *A, *C;              // level-0 tables
 };
+// Table step reading level k with pend (1 or 2) pending challenges: the
+// tables folded to level k+pend, that round's sums and the next round's
+// coefficients; a unit is a quad of level k+pend (4 << pend entries of
+// level k).
 struct WtArgs {
-    u32 hasC;
-    u64 npairs;              // pairs of level k (tables of level k-1 have 4 npairs)
-    const u64 *A, *C, *F;    // level k-1
-    u64 *An, *Cn, *Fn;       // level k
+    u32 hasC, pend;
+    u64 nu;
+    const u64 *A, *C, *F;    // level k
+    u64 *An, *Cn, *Fn;       // level k+pend
 };
 struct WtailArgs {
     u32 k0, sp, hasC, last;
-    const u64 *A, *C, *F;    // level k0-1, 2^{sp-k0+1} entries
+    u32 pend;                // challenges the prologue drew (1 or 2): level k0 - pend is in memory
+    const u64 *A, *C, *F;    // level k0-pend, 2^{sp-k0+pend} entries
     u32 c0;                  // challenge index of round k0
     u64 *msg;                // message slot of round k0
     u64 *vout;
 };
 struct PtailArgs {
     u32 j0, s;
-    const u64 *V, *B;        // V^(j0-1) (2^{s-j0+1}) and B_{j0-1} (2^{s-j0})
+    u32 pend;                // challenges the prologue drew (1 or 2)
+    const u64 *V, *B;        // V^(j0-pend) (2^{s-j0+pend}) and B_{j0-1} (2^{s-j0})
     u32 c0;                  // challenge index of round j0
     u64 *msg;                // message slot of round j0
 };

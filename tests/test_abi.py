@@ -3,6 +3,8 @@
 import os
 import re
 
+import pytest
+
 import paper_1202_1350_amd as G
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -42,3 +44,23 @@ def test_no_oracle_in_product_path():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), os.path.join(dirpath, f)
+
+
+def test_tune_table_round_trip_and_rejects():
+    """The shape table is host state: get/set round-trip, reset, and
+    malformed tables rejected, without touching a GPU."""
+    import paper_1202_1350_amd as G
+    G.gkr_tune_set(None)
+    t0 = G.gkr_tune_get()
+    assert t0[0] == 1 and len(t0) == 4 + t0[1] * t0[2]
+    assert set(t0[4:]) == {0xFF}
+    t1 = bytearray(t0)
+    t1[4] = 5
+    G.gkr_tune_set(bytes(t1))
+    assert G.gkr_tune_get() == bytes(t1)
+    for bad in (bytes(t1[:-1]), bytes([2]) + bytes(t1[1:]), bytes(t1[:4]) + bytes([16]) + bytes(t1[5:])):
+        with pytest.raises(G.GkrError):
+            G.gkr_tune_set(bad)
+    assert G.gkr_tune_get() == bytes(t1)
+    G.gkr_tune_set(None)
+    assert G.gkr_tune_get() == t0

@@ -48,3 +48,19 @@ def test_lazy_sums_match_integers():
     want = np.array([sum(a[(k + j) % n] * b[(k + j) % n] for j in range(64)) % P
                      for k in range(n)], np.uint64)
     assert np.array_equal(got, want)
+
+
+def test_product_chains_match_integers():
+    import torch
+    import paper_1202_1350_amd as G
+    rng = random.Random(5)
+    a = [0, 1, P - 1, 2] + [rng.randrange(P) for _ in range(2000)]
+    b = [P - 1, P - 1, P - 1, 2] + [rng.randrange(P) for _ in range(2000)]
+    ta = device_tensor(np.array(a, np.uint64))
+    tb = device_tensor(np.array(b, np.uint64))
+    out = torch.zeros_like(ta)
+    say("product chains", len(a))
+    G.gkr_field_op(4, ta, tb, out)
+    got = out.cpu().view(torch.int64).numpy().view(np.uint64)
+    want = np.array([x * pow(y, 256, P) % P for x, y in zip(a, b)], np.uint64)
+    assert np.array_equal(got, want)
