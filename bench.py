@@ -113,6 +113,28 @@ def traffic_summary(fetch_dir, write_dir, cls, copy_bytes, command):
     return "\n".join(out) + "\n"
 
 
+TUNE_FILE = os.path.join(ROOT, "paper_1202_1350_amd", "tune_table.txt")
+
+
+def load_tune_table(G, path):
+    """Install a saved launch-shape table if it was tuned on the current
+    kernel sources; returns True if installed."""
+    if not os.path.exists(path):
+        return False
+    vals = dict(l.split(":", 1) for l in open(path) if ":" in l and not l.startswith("#"))
+    if vals.get("kernel_source_hash", "").strip() != kernel_source_hash():
+        return False
+    G.gkr_tune_set(bytes.fromhex(vals["table"].strip()))
+    return True
+
+
+def save_tune_table(G, path, note):
+    with open(path, "w") as f:
+        f.write("# launch shapes chosen by gkr_autotune (" + note + ")\n")
+        f.write(f"kernel_source_hash: {kernel_source_hash()}\n")
+        f.write(f"table: {G.gkr_tune_get().hex()}\n")
+
+
 def cpu_baseline(log_n):
     """The oracle (plain C, the tests' reference) on the host cores."""
     from oracle import oracle as O
@@ -304,7 +326,11 @@ def main():
     ap.add_argument("--cpu-log-n", type=int, default=22)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--autotune", choices=["auto", "off", "force"], default="auto",
+                    help="auto: load the saved launch-shape table if it matches the kernel "
+                         "sources, else tune on the benchmark circuit; off: default shapes; "
+                         "force: tune")
+    ap.add_argument("--write-tune", metavar="PATH", help="save the launch-shape table used")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate point")
     ap.add_argument("--serve-points", type=int, default=8,
                     help="rate points, geometric from 0.1x to 1.5x saturation")
@@ -339,13 +365,17 @@ def main():
     xt = torch.from_numpy(x.view(np.int64)).to(dev).view(torch.uint64)
     at = torch.from_numpy(a.view(np.int32)).to(dev).view(torch.uint32)
     torch.cuda.synchronize()
-    tune = {}
-    if not args.no_autotune:
+    tune = {"mode": args.autotune}
+    G.gkr_tune_set(None)
+    if args.autotune == "auto" and load_tune_table(G, TUNE_FILE):
+        tune["source"] = os.path.relpath(TUNE_FILE, ROOT)
+    elif args.autotune != "off":
         t = time.perf_counter()
         G.gkr_autotune([gc], [xt], reps=2)
-        table = G.gkr_tune_get()
-        tune = {"circuits": "the benchmark circuit", "seconds": time.perf_counter() - t,
-                "tuned_entries": sum(1 for v in table[4:] if v != 0xFF)}
+        tune.update(source="tuned now on the benchmark circuit", seconds=time.perf_counter() - t)
+    tune["tuned_entries"] = sum(1 for v in G.gkr_tune_get()[4:] if v != 0xFF)
+    if args.write_tune:
+        save_tune_table(G, args.write_tune, f"F2 n=2^{args.log_n}, seed {seed}")
 
     def step(times):
         t0 = time.perf_counter()
@@ -391,7 +421,7 @@ def main():
     prove_s = float(T[:, 0].mean())
     value = circ.gates / prove_s
     # dominant prover kernel: the step kernel with the most device time
-    prover_classes = [k for k in prof if prof[k][1] > 0 and k.startswith("step_")]
+    prover_classes = [k for k in prof if prof[k][1] > 0 and k.startswith("step_") and k[5:] in STEP_KINDS]
     dom = max(prover_classes, key=lambda k: prof[k][0])
     ms, launches, by = prof[dom]
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -420,7 +450,7 @@ def main():
         "kernels_per_proof": {k: {"ms": v[0] / args.steps, "launches": v[1] / args.steps,
                         "GB_per_s": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None}
                     for k, v in prof.items() if v[1]},
-        "autotune": tune or None,
+        "autotune": tune,
         "roofline": {"kernel": rocprof_kernel_name(dom), "class": dom, "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -438,7 +468,7 @@ def main():
                        "line_kernel_mulmods_per_s": line_rate,
                        "line_kernel_frac_of_peak": line_rate / peak_mm}
     if not args.no_batch:
-        line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2), not args.no_autotune)
+        line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2), args.autotune != "off")
     if not args.no_serve:
         k = max(1, args.serve_points)
         rates = [0.1 * 15.0 ** (j / (k - 1)) for j in range(k)] if k > 1 else [1.0]
