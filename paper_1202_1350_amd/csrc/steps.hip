@@ -289,20 +289,22 @@ __device__ void step_eq(const EqArgs &a, const Ctx &c, const u64 *pt) {
 // quad permutes and the quad's products are split over its lanes.
 
 // p-phase quad v0..v3 of V^(j) with b0 = B_j[2u], b1 = B_j[2u+1]: round j's
-// sums S0, S1 and the coefficients of round j+1's sums in r_j (U0 + r U1,
-// W0 + r W1); lane j of the quad adds its share.  B_{j+1}[u] = b0 + b1.
+// sums S0 = b0 v0 + b1 v2, S1 = b0 v1 + b1 v3 and the coefficients of round
+// j+1's sums in r_j: U0 = bb v0, U1 = bb (v1 - v0), W0 = bb v2,
+// W1 = bb (v3 - v2), bb = b0 + b1.  Lane j of the quad takes S0 (j = 0), S1
+// (1), U0 and U1 (2), W0 and W1 (3): two products each, operands chosen by
+// j so that all lanes run the same instructions.  x: its first (or only)
+// sum, y: its second.
 __device__ __forceinline__ void p_quad(u32 j, u64 v0, u64 v1, u64 v2, u64 v3, u64 b0, u64 b1,
-                                       u64 (&acc)[6]) {
+                                       u64 &x, u64 &y) {
     const u64 bb = add(b0, b1);
-    if (j == 0) acc[0] = add(acc[0], add(mul(b0, v0), mul(b1, v2)));
-    else if (j == 1) acc[1] = add(acc[1], add(mul(b0, v1), mul(b1, v3)));
-    else if (j == 2) {
-        acc[2] = add(acc[2], mul(bb, v0));
-        acc[3] = add(acc[3], mul(bb, sub(v1, v0)));
-    } else {
-        acc[4] = add(acc[4], mul(bb, v2));
-        acc[5] = add(acc[5], mul(bb, sub(v3, v2)));
-    }
+    const bool s = j < 2;
+    const u64 m1 = s ? b0 : bb, m2 = s ? b1 : bb;
+    const u64 o1 = j == 0 ? v0 : (j == 1 ? v1 : (j == 2 ? v0 : v2));
+    const u64 o2 = j == 0 ? v2 : (j == 1 ? v3 : (j == 2 ? sub(v1, v0) : sub(v3, v2)));
+    const u64 p1 = mul(m1, o1), p2 = mul(m2, o2);
+    x = add(x, s ? add(p1, p2) : p1);
+    y = add(y, s ? 0 : p2);
 }
 
 __device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
@@ -320,7 +322,7 @@ __device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
         block_store<2>(acc, row);
         return;
     }
-    u64 acc[6] = {0, 0, 0, 0, 0, 0};
+    u64 x = 0, y = 0;  // this lane's sums (see p_quad)
     const u64 r0 = c.r, r1 = c.r2;
     // lanes g = 4u + j; the stride is a multiple of 4, so a quad's lanes
     // leave the loop together
@@ -347,8 +349,12 @@ __device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
             b1 = add(quad_get<2>(bq), quad_get<3>(bq));  // B_{j+2}[2u+1]
         }
         if (j == 0 && a.Bout) a.Bout[u] = add(b0, b1);
-        p_quad(j, v0, v1, v2, v3, b0, b1, acc);
+        p_quad(j, v0, v1, v2, v3, b0, b1, x, y);
     }
+    // rows: S0, S1, U0, U1, W0, W1
+    const u32 j = (u32)(c.gtid & 3);
+    u64 acc[6] = {j == 0 ? x : 0, j == 1 ? x : 0, j == 2 ? x : 0, j == 2 ? y : 0, j == 3 ? x : 0,
+                  j == 3 ? y : 0};
     block_store<6>(acc, row);
 }
 
@@ -568,13 +574,25 @@ __device__ __forceinline__ void table_terms(u64 A0, u64 A1, u64 C0, u64 C1, u64 
 }
 
 // One quad of level-k tables, held one entry per lane by four adjacent
-// lanes (this lane is j): round k's sums over its two pairs (acc[0..2],
-// lane 3) and the coefficients of round k+1's sums in r_k (lane t < 3 takes
-// t).  The quad folds to the pair (X0 + r dX0, X2 + r dX2), dX0 = X1 - X0,
-// dX2 = X3 - X2, whose value at t is a_t + r b_t with a = (X0, X2, 2 X2 - X0),
+// lanes.  Lane t < 3 adds, for its t, round k's value over the quad's two
+// pairs and round k+1's three coefficients (lane 3 adds nothing): the quad
+// folds to the pair (X0 + r dX0, X2 + r dX2), dX0 = X1 - X0, dX2 = X3 - X2,
+// whose value at t is a_t + r b_t with a = (X0, X2, 2 X2 - X0),
 // b = (dX0, dX2, 2 dX2 - dX0):
 //   Q0(t) += aA aF + aC, Q1(t) += aA bF + bA aF + bC, Q2(t) += bA bF.
-__device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC, u64 (&acc)[12]) {
+// Every lane runs the same instructions (operands chosen by t), so a wave
+// does six products per quad.  acc: G(t), Q0(t), Q1(t), Q2(t) of this lane.
+struct QuadAcc {
+    u64 g = 0, q0 = 0, q1 = 0, q2 = 0;
+};
+
+// x at t in {0, 1, 2} on the line through (0, x0), (1, x1)
+__device__ __forceinline__ u64 at_t(u64 x0, u64 x1, u32 t) {
+    const u64 x2 = sub(add(x1, x1), x0);
+    return t == 0 ? x0 : (t == 1 ? x1 : x2);
+}
+
+__device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC, QuadAcc &acc) {
     const u64 A0 = quad_get<0>(A), A1 = quad_get<1>(A), A2 = quad_get<2>(A), A3 = quad_get<3>(A);
     const u64 F0 = quad_get<0>(F), F1 = quad_get<1>(F), F2 = quad_get<2>(F), F3 = quad_get<3>(F);
     u64 C0 = 0, C1 = 0, C2 = 0, C3 = 0;
@@ -584,41 +602,37 @@ __device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC
         C2 = quad_get<2>(C);
         C3 = quad_get<3>(C);
     }
-    if (j == 3) {
-        u64 m[3] = {acc[0], acc[1], acc[2]};
-        table_terms(A0, A1, C0, C1, F0, F1, m);
-        table_terms(A2, A3, C2, C3, F2, F3, m);
-        acc[0] = m[0];
-        acc[1] = m[1];
-        acc[2] = m[2];
-        return;
-    }
-    // a_t, b_t of this lane's t = j
-    auto ab = [&](u64 X0, u64 X1, u64 X2, u64 X3, u64 &at, u64 &bt) {
-        const u64 d0 = sub(X1, X0), d2 = sub(X3, X2);
-        if (j == 0) {
-            at = X0;
-            bt = d0;
-        } else if (j == 1) {
-            at = X2;
-            bt = d2;
-        } else {
-            at = sub(add(X2, X2), X0);
-            bt = sub(add(d2, d2), d0);
-        }
-    };
-    u64 aA, bA, aF, bF, aC = 0, bC = 0;
-    ab(A0, A1, A2, A3, aA, bA);
-    ab(F0, F1, F2, F3, aF, bF);
-    if (hasC) ab(C0, C1, C2, C3, aC, bC);
-    // slot t = j of each coefficient (a dynamic index would spill acc)
+    const u32 t = j < 3 ? j : 2;
+    // round k at t: pairs (X0, X1) and (X2, X3)
+    const u64 g = add(add(mul(at_t(A0, A1, t), at_t(F0, F1, t)), at_t(C0, C1, t)),
+                      add(mul(at_t(A2, A3, t), at_t(F2, F3, t)), at_t(C2, C3, t)));
+    // round k+1's coefficients at t
+    const u64 aA = at_t(A0, A2, t), bA = at_t(sub(A1, A0), sub(A3, A2), t);
+    const u64 aF = at_t(F0, F2, t), bF = at_t(sub(F1, F0), sub(F3, F2), t);
+    const u64 aC = at_t(C0, C2, t), bC = at_t(sub(C1, C0), sub(C3, C2), t);
+    const u64 q0 = add(mul(aA, aF), aC);
+    const u64 q1 = add(add(mul(aA, bF), mul(bA, aF)), bC);
+    const u64 q2 = mul(bA, bF);
+    const bool on = j < 3;
+    acc.g = add(acc.g, on ? g : 0);
+    acc.q0 = add(acc.q0, on ? q0 : 0);
+    acc.q1 = add(acc.q1, on ? q1 : 0);
+    acc.q2 = add(acc.q2, on ? q2 : 0);
+}
+
+// Rows of a two-round table step: G(0..2), Q0(0..2), Q1(0..2), Q2(0..2);
+// lane t contributes slot t of each.
+__device__ __forceinline__ void table_quad_store(u32 j, const QuadAcc &q, u64 *row) {
+    u64 v[12];
 #pragma unroll
     for (int t = 0; t < 3; t++) {
-        if ((u32)t != j) continue;
-        acc[3 + t] = add(acc[3 + t], add(mul(aA, aF), aC));
-        acc[6 + t] = add(acc[6 + t], add(add(mul(aA, bF), mul(bA, aF)), bC));
-        acc[9 + t] = add(acc[9 + t], mul(bA, bF));
+        const bool me = j == (u32)t;
+        v[t] = me ? q.g : 0;
+        v[3 + t] = me ? q.q0 : 0;
+        v[6 + t] = me ? q.q1 : 0;
+        v[9 + t] = me ? q.q2 : 0;
     }
+    block_store<12>(v, row);
 }
 
 // Level-0 entries from a wire's sums (phase 2: ADD gates w (v1 + G(t)),
@@ -677,9 +691,7 @@ __device__ void step_wa0(const Wa0Args &a, const ProofPtrs &pp, const Ctx &c, u6
 
 __device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
     const u64 r0 = c.r, r1 = c.r2;
-    u64 acc[12];
-#pragma unroll
-    for (int q = 0; q < 12; q++) acc[q] = 0;
+    QuadAcc acc;
     const u32 pend = a.pend;
     auto foldp = [&](const u64 *X, u64 g) {  // level-(k+pend) entry g from level k
         if (pend == 1) {
@@ -699,7 +711,7 @@ __device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
         if (a.hasC) a.Cn[g] = C;
         table_quad(j, A, C, F, a.hasC != 0, acc);
     }
-    block_store<12>(acc, row);
+    table_quad_store((u32)(c.gtid & 3), acc, row);
 }
 
 // ------------------------------------------------------------------ tails
