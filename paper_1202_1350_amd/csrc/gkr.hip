@@ -1020,15 +1020,17 @@ struct Planner {
                 if (sp >= 2) {
                     const u32 T = sp - 1;
                     const u32 chunks = (T + LINE_CHUNK - 1) / LINE_CHUNK;
+                    const u32 ch = ((T + chunks - 1) / chunks + 3) / 4 * 4;  // equal chunks, 4 | ch
                     const u32 cb = (u32)(((1ull << M) + (SBLOCK / 64) - 1) / (SBLOCK / 64));
                     StepDesc &ls = add(ST_LINE, chunks * cb, 8.0 * (1ull << sp) * chunks);
-                    ls.u.line = LineArgs{sp, Ll, M, T, cb, V(i + 1), w ? w->llo : nullptr,
+                    ls.u.line = LineArgs{sp, Ll, M, T, cb, ch, V(i + 1), w ? w->llo : nullptr,
                                          w ? w->lhl : nullptr, w ? w->lhh : nullptr};
                     reduces(LINE_CHUNK);
                     layer_end.T = T;
                     layer_end.rows = ls.rows;
                     layer_end.nrows = ls.nblocks;
                     layer_end.chunk_blocks = cb;
+                    layer_end.ch = ch;
                 }
             }
         }

@@ -213,16 +213,11 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
             }
         }
     } else if ((FM & (1u << FIN_LINE)) && f.kind == FIN_LINE) {
-        if (f.T > 0) {
+        for (u32 q = 0; q * f.ch < f.T; q++) {  // chunk q: points q ch .. q ch + ch - 1
             u64 t[LINE_CHUNK];
-            rows_total<LINE_CHUNK>(f.rows, 0, f.chunk_blocks, t);
+            rows_total<LINE_CHUNK>(f.rows, q * f.chunk_blocks, f.chunk_blocks, t);
             if (threadIdx.x == 0)
-                for (u32 q = 0; q < LINE_CHUNK && q < f.T; q++) f.msg[q] = t[q];
-            if (f.T > LINE_CHUNK) {
-                rows_total<LINE_CHUNK>(f.rows, f.chunk_blocks, f.chunk_blocks, t);
-                if (threadIdx.x == 0)
-                    for (u32 q = 0; q + LINE_CHUNK < f.T; q++) f.msg[LINE_CHUNK + q] = t[q];
-            }
+                for (u32 e = 0; e < f.ch && q * f.ch + e < f.T; e++) f.msg[q * f.ch + e] = t[e];
         }
         if (threadIdx.x < f.sp) pp.zbuf[threadIdx.x] = s_pt[threadIdx.x];
         if (threadIdx.x == 0) pp.state[0] = 1;  // the next layer's a-variables start unbound
@@ -480,39 +475,60 @@ __device__ void step_lt(const LtArgs &a, const Ctx &c, const u64 *bstar, const u
 
 // Workgroups [q * chunk_blocks, (q+1) * chunk_blocks) sum line points
 // t' = 16 q .. 16 q + 15; within a chunk, wave `mid` walks hh.
-__device__ void step_line(const LineArgs &a, const Ctx &c, u64 *row) {
+// The weights hh[h][t] of 64 consecutive h pass through LDS (one read per
+// tile, broadcast reads in the loop); every lane runs the loop, lanes past
+// the table adding zeros.  Products are summed exactly in 128 bits and
+// reduced once per tile (<= 64 terms).
+template <int CH>
+__device__ void line_sums(const LineArgs &a, const Ctx &c, u64 *row) {
+    __shared__ u64 s_w[64][CH];
     const u32 T = a.T, H = a.sp - a.L - a.M;
     const u64 nlo = 1ull << a.L, nhl = 1ull << a.M, nhh = 1ull << H;
     const u32 chunk = c.lb / a.chunk_blocks;
-    const u32 t0 = chunk * LINE_CHUNK;
+    const u32 t0 = chunk * CH;
     const u32 lane = threadIdx.x & 63;
     const u64 mid = (u64)(c.lb - chunk * a.chunk_blocks) * NWAVES + (threadIdx.x >> 6);
-    u64 acc[LINE_CHUNK];
+    const bool ok = lane < nlo && mid < nhl;
+    const u64 x0 = ok ? (mid << a.L) + lane : 0;
+    u64 s[CH];
 #pragma unroll
-    for (int t = 0; t < LINE_CHUNK; t++) acc[t] = 0;
-    if (lane < nlo && mid < nhl) {
-        // products summed exactly in 128 bits, reduced every 64 terms
-        u128 w128[LINE_CHUNK];
+    for (int t = 0; t < CH; t++) s[t] = 0;
+    for (u64 h0 = 0; h0 < nhh; h0 += 64) {
+        const u32 nh = nhh - h0 < 64 ? (u32)(nhh - h0) : 64u;
+        __syncthreads();  // the previous tile's weights are read
+        for (u32 i = threadIdx.x; i < 64u * CH; i += SBLOCK) {
+            const u32 hl = i / CH, t = i % CH;
+            s_w[hl][t] = hl < nh && t0 + t < T ? a.hh[(h0 + hl) * T + t0 + t] : 0;
+        }
+        __syncthreads();
+        u128 w128[CH];
 #pragma unroll
-        for (int t = 0; t < LINE_CHUNK; t++) w128[t] = 0;
-        for (u64 h = 0; h < nhh; h++) {
-            const u64 v = a.V[(((h << a.M) + mid) << a.L) + lane];
-            const u64 *w = a.hh + h * T + t0;
+        for (int t = 0; t < CH; t++) w128[t] = s[t];
+        for (u32 hl = 0; hl < nh; hl++) {
+            const u64 v = ok ? a.V[((h0 + hl) << (a.M + a.L)) + x0] : 0;
 #pragma unroll
-            for (int t = 0; t < LINE_CHUNK; t++)
-                if (t0 + t < T) w128[t] += fp::wide(w[t], v);
-            if ((h & 63) == 63) {
-#pragma unroll
-                for (int t = 0; t < LINE_CHUNK; t++) w128[t] = fp::red128(w128[t]);
-            }
+            for (int t = 0; t < CH; t++) w128[t] += fp::wide(s_w[hl][t], v);
         }
 #pragma unroll
-        for (int t = 0; t < LINE_CHUNK; t++)
-            if (t0 + t < T)
-                acc[t] = mul(fp::red128(w128[t]),
-                             mul(a.hl[(u64)(t0 + t) * nhl + mid], a.lo[(u64)(t0 + t) * nlo + lane]));
+        for (int t = 0; t < CH; t++) s[t] = fp::red128(w128[t]);
+    }
+    u64 acc[LINE_CHUNK];
+#pragma unroll
+    for (int t = 0; t < LINE_CHUNK; t++) {
+        acc[t] = 0;
+        if (t < CH && t0 + t < T && ok)
+            acc[t] = mul(s[t < CH ? t : 0], mul(a.hl[(u64)(t0 + t) * nhl + mid], a.lo[(u64)(t0 + t) * nlo + lane]));
     }
     block_store<LINE_CHUNK>(acc, row);
+}
+
+__device__ void step_line(const LineArgs &a, const Ctx &c, u64 *row) {
+    switch (a.ch) {
+        case 4: line_sums<4>(a, c, row); break;
+        case 8: line_sums<8>(a, c, row); break;
+        case 12: line_sums<12>(a, c, row); break;
+        default: line_sums<16>(a, c, row); break;
+    }
 }
 
 // ------------------------------------------- omega phases over tables

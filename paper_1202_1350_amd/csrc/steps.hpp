@@ -118,6 +118,7 @@ struct Fin {
     u32 T;             // FIN_LINE: number of line values
     u32 sp;            // FIN_LINE: coordinates of z_{i+1}
     u32 chunk_blocks;  // FIN_LINE: workgroups per chunk of line points
+    u32 ch;            // FIN_LINE: line points per chunk
     const u64 *F;      // FIN_W last: the 2-entry table
     u64 *msg;          // where the message goes
     u64 *vout;         // FIN_W last: transcript slot of v1 / v2
@@ -188,8 +189,11 @@ struct LtArgs {
     u32 bbase, cbase;  // challenge indices of b* and c*
     u64 *lo, *hl, *hh;
 };
+// Line sums: chunk q of the workgroups takes points t' = q ch .. q ch + ch - 1
+// (ch in {4, 8, 12, 16}, chunks of equal size); workgroups [q chunk_blocks,
+// (q+1) chunk_blocks) make up a chunk.
 struct LineArgs {
-    u32 sp, L, M, T, chunk_blocks;
+    u32 sp, L, M, T, chunk_blocks, ch;
     const u64 *V, *lo, *hl, *hh;
 };
 struct SgeArgs {
