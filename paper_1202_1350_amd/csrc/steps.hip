@@ -95,21 +95,20 @@ template <int K>
 __device__ __forceinline__ void rows_total(const u64 *rows, u32 first, u32 n, u64 (&tot)[K]) {
     __shared__ u64 res[K];
     if constexpr (K >= 8) {
-        // thread t adds column t % K of rows t / K, t / K + G, ...; then the
-        // G partial columns are added in LDS
-        constexpr u32 G = SBLOCK / K;
-        __shared__ u64 part[G][K];
-        const u32 k = threadIdx.x % K, g = threadIdx.x / K;
-        if (g < G) {
+        // half-wave h (32 lanes) adds column h of rows lane, lane + 32, ...;
+        // DPP row shifts then row 0's total into row 1 (and 2 into 3) leave
+        // the half's total in its lane 31
+        constexpr u32 HALVES = SBLOCK / 32;
+        const u32 hl = threadIdx.x & 31;
+        for (u32 k = threadIdx.x >> 5; k < (u32)K; k += HALVES) {
             u64 v = 0;
-            for (u32 r = g; r < n; r += G) v = add(v, rows[(u64)(first + r) * ROW_STRIDE + k]);
-            part[g][k] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < K) {
-            u64 a = 0;
-            for (u32 q = 0; q < G; q++) a = add(a, part[q][threadIdx.x]);
-            res[threadIdx.x] = a;
+            for (u32 r = hl; r < n; r += 32) v = add(v, rows[(u64)(first + r) * ROW_STRIDE + k]);
+            v = add(v, dpp64<0x111, 0xf>(v));  // row_shr:1
+            v = add(v, dpp64<0x112, 0xf>(v));  // row_shr:2
+            v = add(v, dpp64<0x114, 0xf>(v));  // row_shr:4
+            v = add(v, dpp64<0x118, 0xf>(v));  // row_shr:8
+            v = add(v, dpp64<0x142, 0xa>(v));  // row_bcast:15 into rows 1, 3
+            if (hl == 31) res[k] = v;
         }
         __syncthreads();
     } else {
