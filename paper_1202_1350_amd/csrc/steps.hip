@@ -89,39 +89,53 @@ __device__ __forceinline__ void block_store(u64 (&v)[K], u64 *out) {
     __syncthreads();
 }
 
-// Sum rows [first, first + n) of K values (row stride ROW_STRIDE); every
-// thread of the workgroup receives the totals.
+__device__ __forceinline__ u64 xor64(u64 v, int m) {
+    const int lo = __shfl_xor((int)(u32)v, m), hi = __shfl_xor((int)(u32)(v >> 32), m);
+    return ((u64)(u32)hi << 32) | (u64)(u32)lo;
+}
+
+// Sum rows [first, first + n) of K <= ROW_STRIDE values; every thread of the
+// workgroup receives the totals.  Lane l of a wave reads column l % 16 of
+// row l / 16, so one load brings four whole rows and the rows stream in as
+// coalesced, independent loads (eight in flight per lane); the four lanes
+// of a column are then summed across the wave and the waves in LDS.
 template <int K>
 __device__ __forceinline__ void rows_total(const u64 *rows, u32 first, u32 n, u64 (&tot)[K]) {
+    static_assert(K <= ROW_STRIDE, "a row holds at most ROW_STRIDE values");
+    constexpr u32 STEP = NWAVES * 4;  // rows per pass of the workgroup
+    constexpr u32 U = 8;              // passes per batch of loads
+    __shared__ u64 part[NWAVES][ROW_STRIDE];
     __shared__ u64 res[K];
-    if constexpr (K >= 8) {
-        // half-wave h (32 lanes) adds column h of rows lane, lane + 32, ...;
-        // DPP row shifts then row 0's total into row 1 (and 2 into 3) leave
-        // the half's total in its lane 31
-        constexpr u32 HALVES = SBLOCK / 32;
-        const u32 hl = threadIdx.x & 31;
-        for (u32 k = threadIdx.x >> 5; k < (u32)K; k += HALVES) {
-            u64 v = 0;
-            for (u32 r = hl; r < n; r += 32) v = add(v, rows[(u64)(first + r) * ROW_STRIDE + k]);
-            v = add(v, dpp64<0x111, 0xf>(v));  // row_shr:1
-            v = add(v, dpp64<0x112, 0xf>(v));  // row_shr:2
-            v = add(v, dpp64<0x114, 0xf>(v));  // row_shr:4
-            v = add(v, dpp64<0x118, 0xf>(v));  // row_shr:8
-            v = add(v, dpp64<0x142, 0xa>(v));  // row_bcast:15 into rows 1, 3
-            if (hl == 31) res[k] = v;
-        }
-        __syncthreads();
-    } else {
-        u64 v[K];
+    const u32 lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const u32 r0 = wid * 4 + (lane >> 4);
+    const u64 *p = rows + ((u64)first + wid * 4) * ROW_STRIDE + lane;  // row first + r0, column lane % 16
+    const u32 passes = r0 < n ? (n - r0 + STEP - 1) / STEP : 0;
+    u64 acc[U];
 #pragma unroll
-        for (int k = 0; k < K; k++) v[k] = 0;
-        for (u32 r = threadIdx.x; r < n; r += SBLOCK) {
-            const u64 *row = rows + (u64)(first + r) * ROW_STRIDE;
+    for (int q = 0; q < (int)U; q++) acc[q] = 0;
+    u32 j = 0;
+    for (; j + U <= passes; j += U) {
+        u64 x[U];
 #pragma unroll
-            for (int k = 0; k < K; k++) v[k] = add(v[k], row[k]);
-        }
-        block_store<K>(v, res);
+        for (int q = 0; q < (int)U; q++) x[q] = p[(u64)(j + q) * STEP * ROW_STRIDE];
+#pragma unroll
+        for (int q = 0; q < (int)U; q++) acc[q] = add(acc[q], x[q]);
     }
+    for (; j < passes; j++) acc[0] = add(acc[0], p[(u64)j * STEP * ROW_STRIDE]);
+#pragma unroll
+    for (int q = 1; q < (int)U; q++) acc[0] = add(acc[0], acc[q]);
+    u64 v = acc[0];
+    v = add(v, xor64(v, 16));
+    v = add(v, xor64(v, 32));
+    if (lane < (u32)K) part[wid][lane] = v;
+    __syncthreads();
+    if (threadIdx.x < (u32)K) {
+        u64 t = part[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < NWAVES; w++) t = add(t, part[w][threadIdx.x]);
+        res[threadIdx.x] = t;
+    }
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; k++) tot[k] = res[k];
 }
@@ -637,17 +651,33 @@ __device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC
 
 // Rows of a two-round table step: G(0..2), Q0(0..2), Q1(0..2), Q2(0..2);
 // lane t contributes slot t of each.
+// The workgroup's row: G(t), Q0(t), Q1(t), Q2(t) at t, 3 + t, 6 + t, 9 + t.
+// Lane j of every quad holds t = j, so lanes of equal j are summed: row
+// shifts by 4 and 8 leave a row's sums in its lanes 12 + j, shuffles add the
+// four rows of the wave, LDS the waves.
 __device__ __forceinline__ void table_quad_store(u32 j, const QuadAcc &q, u64 *row) {
-    u64 v[12];
+    __shared__ u64 sm[NWAVES][12];
+    u64 v[4] = {q.g, q.q0, q.q1, q.q2};
 #pragma unroll
-    for (int t = 0; t < 3; t++) {
-        const bool me = j == (u32)t;
-        v[t] = me ? q.g : 0;
-        v[3 + t] = me ? q.q0 : 0;
-        v[6 + t] = me ? q.q1 : 0;
-        v[9 + t] = me ? q.q2 : 0;
+    for (int k = 0; k < 4; k++) {
+        v[k] = add(v[k], dpp64<0x114, 0xf>(v[k]));  // row_shr:4
+        v[k] = add(v[k], dpp64<0x118, 0xf>(v[k]));  // row_shr:8
+        v[k] = add(v[k], xor64(v[k], 16));
+        v[k] = add(v[k], xor64(v[k], 32));
     }
-    block_store<12>(v, row);
+    const u32 lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane >= 12 && lane < 15) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) sm[wid][3 * k + (lane - 12)] = v[k];
+    }
+    (void)j;
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        u64 t = sm[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < NWAVES; w++) t = add(t, sm[w][threadIdx.x]);
+        row[threadIdx.x] = t;
+    }
 }
 
 // Level-0 entries from a wire's sums (phase 2: ADD gates w (v1 + G(t)),
@@ -731,42 +761,35 @@ __device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
 
 // ------------------------------------------------------------------ tails
 //
-// A tail runs the last rounds of a phase in one workgroup.  Level-l tables
-// live in registers: while a table has at least 2 * SBLOCK entries, thread t
-// holds entries [t E, (t + 1) E) and pairs are thread-local; below that,
-// entry e sits in thread e * sg (stride sg doubles each round) and a pair's
-// second entry comes from sg lanes up; once 64 entries remain they are
-// gathered into wave 0, which finishes the phase without barriers.  A round
-// costs one barrier while several waves hold entries, none afterwards.
+// A tail runs the last rounds of a phase in one workgroup.  The level the
+// tail starts from is folded from memory into LDS; each round reads level
+// l from one of two LDS areas and writes level l + 1 to the other (the
+// second area half as large), so a round costs one barrier.  Value t of a
+// round's message is a sum over pairs of a term taken at t, and wave t
+// computes it alone: three waves produce the three values side by side,
+// each with its own wave reduction, then each folds one table.  No value
+// crosses waves inside a round.  The challenge stream is uniform, so it
+// runs on the scalar unit of every wave.  The other waves load and join
+// the barriers.
 
-// Workgroup totals of K values, received by every thread; one barrier.
-// Consecutive calls must alternate between two slot areas.
-template <int K>
-__device__ __forceinline__ void group_total(u64 (&v)[K], u64 (*slot)[NWAVES]) {
-#pragma unroll
-    for (int k = 0; k < K; k++) v[k] = wave_sum63(v[k]);
-    if ((threadIdx.x & 63) == 63) {
-#pragma unroll
-        for (int k = 0; k < K; k++) slot[k][threadIdx.x >> 6] = v[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        u64 t = slot[k][0];
-#pragma unroll
-        for (int w = 1; w < NWAVES; w++) t = add(t, slot[k][w]);
-        v[k] = t;
-    }
+constexpr int TAIL_TAB = TAIL_LIM + TAIL_LIM / 2;  // LDS entries per table
+
+__device__ __forceinline__ u64 *tail_lds() {
+    __shared__ __align__(16) u64 t[3 * TAIL_TAB];
+    return t;
 }
 
-// Wave totals of K values, received by every lane (no barrier).
-template <int K>
-__device__ __forceinline__ void wave_total(u64 (&v)[K]) {
-#pragma unroll
-    for (int k = 0; k < K; k++) v[k] = lane63(wave_sum63(v[k]));
+// A value every lane holds the same copy of, moved to scalar registers.
+__device__ __forceinline__ u64 uniform(u64 v) {
+    const u32 lo = (u32)__builtin_amdgcn_readfirstlane((int)(u32)v);
+    const u32 hi = (u32)__builtin_amdgcn_readfirstlane((int)(u32)(v >> 32));
+    return ((u64)hi << 32) | lo;
 }
-
-constexpr int TAIL_E = TAIL_LIM / SBLOCK;  // entries per thread at most
+__device__ __forceinline__ u64 lane_value(u64 v, u32 l) {  // l uniform
+    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, l);
+    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(v >> 32), l);
+    return ((u64)hi << 32) | lo;
+}
 
 // Entry e of the level a tail starts from, folded from memory by the
 // pending challenge(s) of the prologue.
@@ -779,254 +802,150 @@ __device__ __forceinline__ u64 tail_entry(const u64 *X, u32 e, u32 pend, const C
     return fold1(fold1(p.x, p.y, c.r), fold1(q.x, q.y, c.r), c.r2);
 }
 
-// Remaining omega rounds k0..s'-1.  The prologue drew the pending
-// challenge(s) up to r_{k0-1}; each round writes its message, then draws its
-// challenge; after the last fold F holds v1 (or v2).
+// This lane's share of G(T) = sum over pairs m of A_T F_T + C_T, where
+// X_T is X at t = T on the line through X[2m], X[2m+1].
+template <int T>
+__device__ __forceinline__ u64 wtail_term(const u64 *X, u32 half, u32 lane, bool hc) {
+    u64 s = 0;
+    for (u32 m = lane; m < half; m += 64) {
+        const u64x2 pa = ld2(X, 2 * m), pf = ld2(X + 2 * TAIL_TAB, 2 * m);
+        u64 ct = 0;
+        if (hc) {
+            const u64x2 pc = ld2(X + TAIL_TAB, 2 * m);
+            ct = T == 0 ? pc.x : (T == 1 ? pc.y : sub(add(pc.y, pc.y), pc.x));
+        }
+        const u64 at = T == 0 ? pa.x : (T == 1 ? pa.y : sub(add(pa.y, pa.y), pa.x));
+        const u64 ft = T == 0 ? pf.x : (T == 1 ? pf.y : sub(add(pf.y, pf.y), pf.x));
+        s = add(s, add(mul(at, ft), ct));
+    }
+    return s;
+}
+
+// Remaining omega rounds k0..s'-1 over A, C, F.  The prologue drew the
+// pending challenge(s) up to r_{k0-1}; each round writes its message, then
+// draws its challenge; after the last fold F holds v1 (or v2).
 __device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx &c) {
-    __shared__ u64 s_sum[2][3][NWAVES];
-    __shared__ u64 s_g[3][64];
+    __shared__ u64 s_st;
+    u64 *tab = tail_lds();
     const u32 tid = threadIdx.x, lane = tid & 63;
+    const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
     const bool hc = a.hasC != 0;
-    u32 n = 1u << (a.sp - a.k0);  // entries of level k0
-    u32 E = n >= 2 * SBLOCK ? n / SBLOCK : 1;
-    u64 A[TAIL_E], C[TAIL_E], F[TAIL_E];
-    {
-        // level k0 from level k0 - pend in memory, folded by the pending
-        // challenges (r_{k0-1}; or r_{k0-2}, r_{k0-1})
-        const u32 e0 = tid * E;
-#pragma unroll
-        for (int q = 0; q < TAIL_E; q++) {
-            A[q] = C[q] = F[q] = 0;
-            if (q < (int)E && e0 + q < n) {
-                A[q] = tail_entry(a.A, e0 + q, a.pend, c);
-                F[q] = tail_entry(a.F, e0 + q, a.pend, c);
-                if (hc) C[q] = tail_entry(a.C, e0 + q, a.pend, c);
+    u32 n = 1u << (a.sp - a.k0);  // entries of level k0, at most TAIL_LIM
+    for (u32 e = tid; e < n; e += SBLOCK) {
+        tab[e] = tail_entry(a.A, e, a.pend, c);
+        if (hc) tab[TAIL_TAB + e] = tail_entry(a.C, e, a.pend, c);
+        tab[2 * TAIL_TAB + e] = tail_entry(a.F, e, a.pend, c);
+    }
+    if (tid == 0) s_st = pp.rngst[a.c0];
+    __syncthreads();
+    u64 st = uniform(s_st);
+    u32 k = 0;  // rounds done; level k0 + k sits in area k & 1
+    for (; n > 1; n >>= 1, k++) {
+        const u64 *X = tab + ((k & 1) ? TAIL_LIM : 0);
+        u64 *Y = tab + ((k & 1) ? 0 : TAIL_LIM);
+        const u32 half = n >> 1;
+        if (w < 3) {
+            u64 s = w == 0 ? wtail_term<0>(X, half, lane, hc)
+                           : (w == 1 ? wtail_term<1>(X, half, lane, hc) : wtail_term<2>(X, half, lane, hc));
+            s = wave_sum63(s);
+            if (lane == 63) a.msg[3 * k + w] = s;
+            const u64 r = fp::sm_field(st);
+            if (w == 0 && lane == 63) {
+                pp.chals[a.c0 + k] = r;
+                pp.rngst[a.c0 + k + 1] = st;
             }
-        }
-    }
-    u64 st = pp.rngst[a.c0];
-    u32 k = 0;  // rounds done
-    auto emit = [&](const u64 (&t)[3]) -> u64 {
-        if (tid == 0) {
-            u64 *m = a.msg + 3ull * k;
-            m[0] = t[0];
-            m[1] = t[1];
-            m[2] = t[2];
-        }
-        const u64 r = fp::sm_field(st);
-        if (tid == 0) {
-            pp.chals[a.c0 + k] = r;
-            pp.rngst[a.c0 + k + 1] = st;
-        }
-        k++;
-        return r;
-    };
-    // rounds with thread-local pairs
-    while (E >= 2) {
-        u64 t[3] = {0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < TAIL_E / 2; q++)
-            if (q < (int)E / 2)
-                table_terms(A[2 * q], A[2 * q + 1], C[2 * q], C[2 * q + 1], F[2 * q], F[2 * q + 1], t);
-        group_total<3>(t, s_sum[k & 1]);
-        const u64 r = emit(t);
-#pragma unroll
-        for (int q = 0; q < TAIL_E / 2; q++) {
-            if (q < (int)E / 2) {
-                A[q] = fold1(A[2 * q], A[2 * q + 1], r);
-                if (hc) C[q] = fold1(C[2 * q], C[2 * q + 1], r);
-                F[q] = fold1(F[2 * q], F[2 * q + 1], r);
+            if (w != 1 || hc) {  // wave w folds table w (A, C, F)
+                const u64 *Xw = X + w * TAIL_TAB;
+                u64 *Yw = Y + w * TAIL_TAB;
+                for (u32 m = lane; m < half; m += 64) {
+                    const u64x2 p = ld2(Xw, 2 * m);
+                    Yw[m] = fold1(p.x, p.y, r);
+                }
             }
-        }
-        E /= 2;
-        n /= 2;
-    }
-    // one entry per thread: entry e in thread e * sg
-    u32 sg = 1;
-    u64 a0 = A[0], c0 = C[0], f0 = F[0];
-    while (n > 64) {
-        const u64 a1 = down64(a0, sg), c1 = hc ? down64(c0, sg) : 0, f1 = down64(f0, sg);
-        const bool act = (tid & (2 * sg - 1)) == 0 && tid < n * sg;
-        u64 t[3] = {0, 0, 0};
-        if (act) table_terms(a0, a1, c0, c1, f0, f1, t);
-        group_total<3>(t, s_sum[k & 1]);
-        const u64 r = emit(t);
-        if (act) {
-            a0 = fold1(a0, a1, r);
-            if (hc) c0 = fold1(c0, c1, r);
-            f0 = fold1(f0, f1, r);
-        }
-        sg *= 2;
-        n /= 2;
-    }
-    if (n * sg > 64) {  // entries still spread over several waves
-        if ((tid & (sg - 1)) == 0 && tid < n * sg) {
-            s_g[0][tid / sg] = a0;
-            s_g[1][tid / sg] = c0;
-            s_g[2][tid / sg] = f0;
         }
         __syncthreads();
-        if (tid >= 64) return;
-        a0 = lane < n ? s_g[0][lane] : 0;
-        c0 = lane < n ? s_g[1][lane] : 0;
-        f0 = lane < n ? s_g[2][lane] : 0;
-        sg = 1;
-    } else if (tid >= 64) {
-        return;
-    }
-    // wave 0 alone
-    while (n > 1) {
-        const u64 a1 = down64(a0, sg), c1 = hc ? down64(c0, sg) : 0, f1 = down64(f0, sg);
-        const bool act = (lane & (2 * sg - 1)) == 0 && lane < n * sg;
-        u64 t[3] = {0, 0, 0};
-        if (act) table_terms(a0, a1, c0, c1, f0, f1, t);
-        wave_total<3>(t);
-        const u64 r = emit(t);
-        if (act) {
-            a0 = fold1(a0, a1, r);
-            if (hc) c0 = fold1(c0, c1, r);
-            f0 = fold1(f0, f1, r);
-        }
-        sg *= 2;
-        n /= 2;
     }
     if (tid == 0) {
-        *a.vout = f0;
-        if (a.last == 1) pp.state[1] = f0;
+        const u64 v = tab[2 * TAIL_TAB + ((k & 1) ? TAIL_LIM : 0)];
+        *a.vout = v;
+        if (a.last == 1) pp.state[1] = v;
     }
 }
 
+// This lane's share of S_T = sum over pairs m of B[m] V_T, V_T on the line
+// through V[2m], V[2m+1].
+template <int T>
+__device__ __forceinline__ u64 ptail_term(const u64 *V, const u64 *B, u32 half, u32 lane) {
+    u64 s = 0;
+    for (u32 m = lane; m < half; m += 64) {
+        const u64x2 p = ld2(V, 2 * m);
+        const u64 vt = T == 0 ? p.x : (T == 1 ? p.y : sub(add(p.y, p.y), p.x));
+        s = add(s, mul(B[m], vt));
+    }
+    return s;
+}
+
 // Remaining p-phase rounds j0..s-1.  The prologue drew the pending
-// challenge(s) up to r_{j0-1} and folded them into the beta prefix
-// C = state[0].  B is the table of sums of
+// challenge(s) up to r_{j0-1} and its finish of round j0-1 left the beta
+// prefix C in state[0] (written by thread 0).  B is the table of sums of
 // the eq weights of the a-coordinates not yet reached (beta over z's
-// suffix); pair m of V goes with B[m], which sits in the pair's first
-// thread (stride 2 sg, or entries [t E / 2, (t + 1) E / 2) while pairs are
-// thread-local).
+// suffix); pair m of V goes with B[m].  Round j's message is
+// G(t) = C eq_t(z_j) S_t with eq_t(z) the line through (0, 1 - z), (1, z):
+// 1 - z, z, 3z - 1 at t = 0, 1, 2.
 __device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx &c) {
-    __shared__ u64 s_sum[2][2][NWAVES];
-    __shared__ u64 s_g[2][64];
+    __shared__ u64 s_st, s_c;
+    u64 *tab = tail_lds();
+    u64 *tv = tab, *tb = tab + TAIL_TAB;  // V areas: TAIL_LIM, TAIL_LIM / 2; B: half of each
     const u32 tid = threadIdx.x, lane = tid & 63;
-    u32 n = 1u << (a.s - a.j0);  // entries of V^(j0)
-    u32 E = n >= 2 * SBLOCK ? n / SBLOCK : 1;
-    u64 V[TAIL_E], B[TAIL_E / 2 > 0 ? TAIL_E / 2 : 1];
-    {
-        const u32 e0 = tid * E;
-#pragma unroll
-        for (int q = 0; q < TAIL_E; q++) {
-            V[q] = 0;
-            if (q < (int)E && e0 + q < n) V[q] = tail_entry(a.V, e0 + q, a.pend, c);
-        }
-        // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1], m < n/2
-        if (E >= 2) {
-#pragma unroll
-            for (int q = 0; q < TAIL_E / 2; q++) {
-                B[q] = 0;
-                if (q < (int)E / 2) {
-                    const u64x2 pb = ld2(a.B, 2 * (e0 / 2 + q));
-                    B[q] = add(pb.x, pb.y);
+    const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
+    u32 n = 1u << (a.s - a.j0);  // entries of V^(j0), at most TAIL_LIM
+    for (u32 e = tid; e < n; e += SBLOCK) tv[e] = tail_entry(a.V, e, a.pend, c);
+    for (u32 m = tid; m < n / 2; m += SBLOCK) {  // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1]
+        const u64x2 pb = ld2(a.B, 2 * m);
+        tb[m] = add(pb.x, pb.y);
+    }
+    const u32 rounds = a.s - a.j0;
+    const u64 zr = lane < rounds ? pp.zbuf[a.j0 + lane] : 0;  // z_{j0 + l} in lane l
+    if (tid == 0) {
+        s_st = pp.rngst[a.c0];
+        s_c = pp.state[0];
+    }
+    __syncthreads();
+    u64 st = uniform(s_st), C = uniform(s_c);
+    u32 k = 0;  // rounds done; V^(j0 + k) and B_{j0 + k} sit in area k & 1
+    for (; n > 1; n >>= 1, k++) {
+        const u32 off = (k & 1) ? TAIL_LIM : 0, noff = (k & 1) ? 0 : TAIL_LIM;
+        const u64 *V = tv + off, *B = tb + off;
+        u64 *Vn = tv + noff, *Bn = tb + noff;
+        const u32 half = n >> 1;
+        if (w < 3) {
+            u64 s = w == 0 ? ptail_term<0>(V, B, half, lane)
+                           : (w == 1 ? ptail_term<1>(V, B, half, lane) : ptail_term<2>(V, B, half, lane));
+            s = wave_sum63(s);
+            const u64 z = lane_value(zr, k);
+            const u64 e = w == 0 ? sub(1, z) : (w == 1 ? z : sub(add(add(z, z), z), 1));
+            if (lane == 63) a.msg[3 * k + w] = mul(mul(C, e), s);
+            const u64 r = fp::sm_field(st);
+            if (w == 0 && lane == 63) {
+                pp.chals[a.c0 + k] = r;
+                pp.rngst[a.c0 + k + 1] = st;
+            }
+            C = mul(C, fp::eq(z, r));
+            if (w == 1) {  // B_{j+1}[m] = B_j[2m] + B_j[2m+1]
+                for (u32 m = lane; m < half / 2; m += 64) {
+                    const u64x2 p = ld2(B, 2 * m);
+                    Bn[m] = add(p.x, p.y);
+                }
+            } else {  // waves 0 and 2 fold V, alternating runs of 64 pairs
+                for (u32 m = lane + (w == 2 ? 64 : 0); m < half; m += 128) {
+                    const u64x2 p = ld2(V, 2 * m);
+                    Vn[m] = fold1(p.x, p.y, r);
                 }
             }
-        } else {
-            B[0] = 0;
-            if ((tid & 1) == 0 && (tid >> 1) < (n >> 1)) {
-                const u64x2 pb = ld2(a.B, tid);  // entries 2 (tid/2), 2 (tid/2) + 1
-                B[0] = add(pb.x, pb.y);
-            }
         }
-    }
-    u64 st = pp.rngst[a.c0];
-    // The prologue's finish of round j0-1 left C in state[0], written by
-    // thread 0; only thread 0's copy of C is used.
-    u64 Cp = pp.state[0];
-    u32 k = 0;
-    auto emit = [&](const u64 (&t)[2]) -> u64 {
-        const u64 z = pp.zbuf[a.j0 + k], S0 = t[0], S1 = t[1];
-        if (tid == 0) {
-            u64 *m = a.msg + 3ull * k;
-            m[0] = mul(mul(Cp, sub(1, z)), S0);
-            m[1] = mul(mul(Cp, z), S1);
-            m[2] = mul(mul(Cp, sub(add(add(z, z), z), 1)), sub(add(S1, S1), S0));
-        }
-        const u64 r = fp::sm_field(st);
-        if (tid == 0) {
-            pp.chals[a.c0 + k] = r;
-            pp.rngst[a.c0 + k + 1] = st;
-        }
-        Cp = mul(Cp, fp::eq(z, r));
-        k++;
-        return r;
-    };
-    while (E >= 2) {
-        u64 t[2] = {0, 0};
-#pragma unroll
-        for (int q = 0; q < TAIL_E / 2; q++) {
-            if (q < (int)E / 2) {
-                t[0] = add(t[0], mul(B[q], V[2 * q]));
-                t[1] = add(t[1], mul(B[q], V[2 * q + 1]));
-            }
-        }
-        group_total<2>(t, s_sum[k & 1]);
-        const u64 r = emit(t);
-#pragma unroll
-        for (int q = 0; q < TAIL_E / 2; q++)
-            if (q < (int)E / 2) V[q] = fold1(V[2 * q], V[2 * q + 1], r);
-        if (E >= 4) {
-#pragma unroll
-            for (int q = 0; q < TAIL_E / 4; q++)
-                if (q < (int)E / 4) B[q] = add(B[2 * q], B[2 * q + 1]);
-        } else {
-            // one V entry per thread from here: B[m] moves to thread 2m
-            const u64 b1 = down64(B[0], 1);
-            B[0] = (tid & 1) == 0 ? add(B[0], b1) : 0;
-        }
-        E /= 2;
-        n /= 2;
-    }
-    u32 sg = 1;
-    u64 v0 = V[0], b0 = B[0];
-    while (n > 64) {
-        const u64 v1 = down64(v0, sg), b1 = down64(b0, 2 * sg);
-        const bool act = (tid & (2 * sg - 1)) == 0 && tid < n * sg;
-        u64 t[2] = {0, 0};
-        if (act) {
-            t[0] = mul(b0, v0);
-            t[1] = mul(b0, v1);
-        }
-        group_total<2>(t, s_sum[k & 1]);
-        const u64 r = emit(t);
-        if (act) v0 = fold1(v0, v1, r);
-        if ((tid & (4 * sg - 1)) == 0 && tid < n * sg) b0 = add(b0, b1);
-        sg *= 2;
-        n /= 2;
-    }
-    if (n * sg > 64) {
-        if ((tid & (sg - 1)) == 0 && tid < n * sg) s_g[0][tid / sg] = v0;
-        if ((tid & (2 * sg - 1)) == 0 && tid < n * sg) s_g[1][tid / (2 * sg)] = b0;
         __syncthreads();
-        if (tid >= 64) return;
-        v0 = lane < n ? s_g[0][lane] : 0;
-        b0 = (lane & 1) == 0 && lane < n ? s_g[1][lane / 2] : 0;
-        sg = 1;
-    } else if (tid >= 64) {
-        return;
     }
-    while (n > 1) {
-        const u64 v1 = down64(v0, sg), b1 = down64(b0, 2 * sg);
-        const bool act = (lane & (2 * sg - 1)) == 0 && lane < n * sg;
-        u64 t[2] = {0, 0};
-        if (act) {
-            t[0] = mul(b0, v0);
-            t[1] = mul(b0, v1);
-        }
-        wave_total<2>(t);
-        const u64 r = emit(t);
-        if (act) v0 = fold1(v0, v1, r);
-        if ((lane & (4 * sg - 1)) == 0 && lane < n * sg) b0 = add(b0, b1);
-        sg *= 2;
-        n /= 2;
-    }
-    if (tid == 0) pp.state[0] = Cp;  // beta(z, a*)
+    if (tid == 0) pp.state[0] = C;  // beta(z, a*)
 }
 
 // ---------------------------------------------------------------- kernel
