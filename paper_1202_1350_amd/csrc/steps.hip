@@ -97,34 +97,28 @@ __device__ __forceinline__ u64 xor64(u64 v, int m) {
 // Sum rows [first, first + n) of K <= ROW_STRIDE values; every thread of the
 // workgroup receives the totals.  Lane l of a wave reads column l % 16 of
 // row l / 16, so one load brings four whole rows and the rows stream in as
-// coalesced, independent loads (eight in flight per lane); the four lanes
-// of a column are then summed across the wave and the waves in LDS.
+// coalesced, independent loads (sixteen in flight per lane); the four
+// lanes of a column are then summed across the wave and the waves in LDS.
 template <int K>
 __device__ __forceinline__ void rows_total(const u64 *rows, u32 first, u32 n, u64 (&tot)[K]) {
     static_assert(K <= ROW_STRIDE, "a row holds at most ROW_STRIDE values");
     constexpr u32 STEP = NWAVES * 4;  // rows per pass of the workgroup
-    constexpr u32 U = 8;              // passes per batch of loads
+    constexpr u32 U = 16;             // passes per batch of loads
     __shared__ u64 part[NWAVES][ROW_STRIDE];
     __shared__ u64 res[K];
     const u32 lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const u32 r0 = wid * 4 + (lane >> 4);
     const u64 *p = rows + ((u64)first + wid * 4) * ROW_STRIDE + lane;  // row first + r0, column lane % 16
     const u32 passes = r0 < n ? (n - r0 + STEP - 1) / STEP : 0;
-    u64 acc[U];
-#pragma unroll
-    for (int q = 0; q < (int)U; q++) acc[q] = 0;
-    u32 j = 0;
-    for (; j + U <= passes; j += U) {
+    u64 acc[4] = {0, 0, 0, 0};
+    for (u32 j = 0; j < passes; j += U) {  // a batch's loads are all issued before any add
         u64 x[U];
 #pragma unroll
-        for (int q = 0; q < (int)U; q++) x[q] = p[(u64)(j + q) * STEP * ROW_STRIDE];
+        for (int q = 0; q < (int)U; q++) x[q] = j + q < passes ? p[(u64)(j + q) * STEP * ROW_STRIDE] : 0;
 #pragma unroll
-        for (int q = 0; q < (int)U; q++) acc[q] = add(acc[q], x[q]);
+        for (int q = 0; q < (int)U; q++) acc[q & 3] = add(acc[q & 3], x[q]);
     }
-    for (; j < passes; j++) acc[0] = add(acc[0], p[(u64)j * STEP * ROW_STRIDE]);
-#pragma unroll
-    for (int q = 1; q < (int)U; q++) acc[0] = add(acc[0], acc[q]);
-    u64 v = acc[0];
+    u64 v = add(add(acc[0], acc[1]), add(acc[2], acc[3]));
     v = add(v, xor64(v, 16));
     v = add(v, xor64(v, 32));
     if (lane < (u32)K) part[wid][lane] = v;
@@ -154,46 +148,75 @@ struct Ctx {
     u64 r2;          // the second one, after a two-round step
 };
 
+// What a tail takes over from its launch's prologue and finish: the RNG
+// state after the drawn challenges (if the prologue drew any) and the beta
+// prefix C (if the finish computed it, p-phase rounds).
+struct TailIn {
+    u64 st, C;
+    u32 drew, have_c;
+};
+
 __device__ __forceinline__ u64 fold1(u64 x0, u64 x1, u64 r) { return add(x0, mul(r, sub(x1, x0))); }
 
-// p-phase message from the two sums: G(0) = C (1-z) S0, G(1) = C z S1,
-// G(2) = C (3z - 1)(2 S1 - S0).
-__device__ __forceinline__ void p_message(u64 *msg, u64 C, u64 z, u64 S0, u64 S1) {
-    msg[0] = mul(mul(C, sub(1, z)), S0);
-    msg[1] = mul(mul(C, z), S1);
-    msg[2] = mul(mul(C, sub(add(add(z, z), z), 1)), sub(add(S1, S1), S0));
+// Value t of a p-phase message from the two sums: G(0) = C (1-z) S0,
+// G(1) = C z S1, G(2) = C (3z - 1)(2 S1 - S0); t is chosen per lane.
+__device__ __forceinline__ u64 p_value(u32 t, u64 C, u64 z, u64 S0, u64 S1) {
+    const u64 e = t == 0 ? sub(1, z) : (t == 1 ? z : sub(add(add(z, z), z), 1));
+    const u64 S = t == 0 ? S0 : (t == 1 ? S1 : sub(add(S1, S1), S0));
+    return mul(mul(C, e), S);
 }
 
-// ------------------------------------------------------------- prologue
+// Value k of tot, k chosen per lane.
+template <int K>
+__device__ __forceinline__ u64 pick(const u64 (&tot)[K], u32 k) {
+    u64 v = 0;
+#pragma unroll
+    for (int q = 0; q < K; q++) v = k == (u32)q ? tot[q] : v;
+    return v;
+}
+
+// The finish of the previous round(s): rows into the message, lanes
+// t < 3 (and 3..5 for a second message) writing one value each.  Operands
+// that do not depend on the rows are loaded before the row sums.
+// A p-phase finish returns the beta prefix it leaves in state[0].
+struct FinOut {
+    bool have_c;
+    u64 cfin;
+};
 
 template <u32 KIND>
-__device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
+__device__ FinOut finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
     constexpr u32 FM = fin_mask(KIND);
+    const u32 tid = threadIdx.x;
+    FinOut out = {false, 0};
     if ((FM & (1u << FIN_P)) && f.kind == FIN_P) {
+        const u64 z = pp.zbuf[f.j], C = pp.state[0];
         u64 t[2];
         rows_total<2>(f.rows, 0, f.nrows, t);
-        if (threadIdx.x == 0) {
-            const u64 z = pp.zbuf[f.j], C = pp.state[0];
-            p_message(f.msg, C, z, t[0], t[1]);
-            pp.state[0] = mul(C, fp::eq(z, c.r));     // beta prefix over r_0..r_j
-        }
+        if (tid < 3) f.msg[tid] = p_value(tid, C, z, t[0], t[1]);
+        out = {true, mul(C, fp::eq(z, c.r))};  // beta prefix over r_0..r_j
+        if (tid == 0) pp.state[0] = out.cfin;
     } else if ((FM & (1u << FIN_P2)) && f.kind == FIN_P2) {
+        const u64 z0 = pp.zbuf[f.j], z1 = pp.zbuf[f.j + 1], C = pp.state[0];
         u64 t[6];
         rows_total<6>(f.rows, 0, f.nrows, t);
-        if (threadIdx.x == 0) {
-            const u64 z0 = pp.zbuf[f.j], z1 = pp.zbuf[f.j + 1];
-            u64 C = pp.state[0];
-            p_message(f.msg, C, z0, t[0], t[1]);
-            C = mul(C, fp::eq(z0, c.r));
-            p_message(f.msg + 3, C, z1, add(t[2], mul(c.r, t[3])), add(t[4], mul(c.r, t[5])));
-            pp.state[0] = mul(C, fp::eq(z1, c.r2));
-        }
+        const u64 C1 = mul(C, fp::eq(z0, c.r));
+        if (tid < 3) f.msg[tid] = p_value(tid, C, z0, t[0], t[1]);
+        else if (tid < 6)
+            f.msg[tid] = p_value(tid - 3, C1, z1, add(t[2], mul(c.r, t[3])), add(t[4], mul(c.r, t[5])));
+        out = {true, mul(C1, fp::eq(z1, c.r2))};
+        if (tid == 0) pp.state[0] = out.cfin;
     } else if ((FM & (1u << FIN_W)) && f.kind == FIN_W) {
+        u64 f0 = 0, f1 = 0;
+        if (f.last && tid == 0) {
+            f0 = f.F[0];
+            f1 = f.F[1];
+        }
         u64 t[4];
         rows_total<4>(f.rows, 0, f.nrows, t);
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             const u64 E0 = t[0], E1 = t[1], O0 = t[2], O1 = t[3];
             f.msg[0] = E0;
             f.msg[1] = O1;
@@ -201,7 +224,6 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
             o4 = add(o4, o4);
             f.msg[2] = sub(add(sub(E0, add(E1, E1)), o4), add(O0, O0));
             if (f.last) {
-                const u64 f0 = f.F[0], f1 = f.F[1];
                 const u64 v = add(f0, mul(c.r, sub(f1, f0)));
                 *f.vout = v;
                 if (f.last == 1) pp.state[1] = v;
@@ -210,31 +232,26 @@ __device__ void finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
     } else if ((FM & (1u << FIN_T)) && f.kind == FIN_T) {
         u64 t[3];
         rows_total<3>(f.rows, 0, f.nrows, t);
-        if (threadIdx.x == 0) {
-            f.msg[0] = t[0];
-            f.msg[1] = t[1];
-            f.msg[2] = t[2];
-        }
+        if (tid < 3) f.msg[tid] = pick(t, tid);
     } else if ((FM & (1u << FIN_T2)) && f.kind == FIN_T2) {
         u64 t[12];
         rows_total<12>(f.rows, 0, f.nrows, t);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int q = 0; q < 3; q++) {
-                f.msg[q] = t[q];
-                f.msg[3 + q] = add(t[3 + q], mul(c.r, add(t[6 + q], mul(c.r, t[9 + q]))));
-            }
+        if (tid < 3) {
+            f.msg[tid] = pick(t, tid);
+        } else if (tid < 6) {  // round k+1 at t = tid - 3: Q0 + r (Q1 + r Q2)
+            const u32 q = tid - 3;
+            f.msg[tid] = add(pick(t, 3 + q), mul(c.r, add(pick(t, 6 + q), mul(c.r, pick(t, 9 + q)))));
         }
     } else if ((FM & (1u << FIN_LINE)) && f.kind == FIN_LINE) {
         for (u32 q = 0; q * f.ch < f.T; q++) {  // chunk q: points q ch .. q ch + ch - 1
             u64 t[LINE_CHUNK];
             rows_total<LINE_CHUNK>(f.rows, q * f.chunk_blocks, f.chunk_blocks, t);
-            if (threadIdx.x == 0)
-                for (u32 e = 0; e < f.ch && q * f.ch + e < f.T; e++) f.msg[q * f.ch + e] = t[e];
+            if (tid < f.ch && q * f.ch + tid < f.T) f.msg[q * f.ch + tid] = pick(t, tid);
         }
-        if (threadIdx.x < f.sp) pp.zbuf[threadIdx.x] = s_pt[threadIdx.x];
-        if (threadIdx.x == 0) pp.state[0] = 1;  // the next layer's a-variables start unbound
+        if (tid < f.sp) pp.zbuf[tid] = s_pt[tid];
+        if (tid == 0) pp.state[0] = 1;  // the next layer's a-variables start unbound
     }
+    return out;
 }
 
 // ------------------------------------------------------------ step bodies
@@ -769,10 +786,16 @@ __device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
 // computes it alone: three waves produce the three values side by side,
 // each with its own wave reduction, then each folds one table.  No value
 // crosses waves inside a round.  The challenge stream is uniform, so it
-// runs on the scalar unit of every wave.  The other waves load and join
-// the barriers.
+// runs on the scalar unit of every wave; the message never depends on the
+// challenge, so the fold is computed alongside the message's reduction.
+// The other waves load and join the barriers.
 
 constexpr int TAIL_TAB = TAIL_LIM + TAIL_LIM / 2;  // LDS entries per table
+// Rounds with at least this many pairs run wide: thread m takes pair m of
+// every table and all three values, the waves' sums meet in LDS (a second
+// barrier), and the folds are spread the same way.
+constexpr u32 WIDE_HALF = 256;
+static_assert(TAIL_LIM / 2 <= SBLOCK, "a wide round gives every pair a thread");
 
 __device__ __forceinline__ u64 *tail_lds() {
     __shared__ __align__(16) u64 t[3 * TAIL_TAB];
@@ -791,6 +814,35 @@ __device__ __forceinline__ u64 lane_value(u64 v, u32 l) {  // l uniform
     return ((u64)hi << 32) | lo;
 }
 
+// Sum over the wave of field elements, left in lane 63: as wave_sum63, but
+// the first three and the last three steps add without reducing (eight
+// values below p stay below 2^64), with one reduction after each three.
+__device__ __forceinline__ u64 wave_sum63_lazy(u64 v) {
+    v += dpp64<0x111, 0xf>(v);  // row_shr:1
+    v += dpp64<0x112, 0xf>(v);  // row_shr:2
+    v += dpp64<0x114, 0xf>(v);  // row_shr:4
+    v = fp::canon(fp::fold64(v));
+    v += dpp64<0x118, 0xf>(v);  // row_shr:8
+    v += dpp64<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+    v += dpp64<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+    return fp::canon(fp::fold64(v));
+}
+
+// Total of the k-th value over the workgroup's waves, from the partial sums
+// lane 63 of each wave left in part[k].
+__device__ __forceinline__ u64 waves_total(const u64 (*part)[NWAVES], int k) {
+    u64 t = part[k][0];
+#pragma unroll
+    for (int w = 1; w < NWAVES; w++) t = add(t, part[k][w]);
+    return t;
+}
+
+// X at t = T on the line through (0, x0), (1, x1).
+template <int T>
+__device__ __forceinline__ u64 line_at(u64 x0, u64 x1) {
+    return T == 0 ? x0 : (T == 1 ? x1 : sub(add(x1, x1), x0));
+}
+
 // Entry e of the level a tail starts from, folded from memory by the
 // pending challenge(s) of the prologue.
 __device__ __forceinline__ u64 tail_entry(const u64 *X, u32 e, u32 pend, const Ctx &c) {
@@ -802,30 +854,76 @@ __device__ __forceinline__ u64 tail_entry(const u64 *X, u32 e, u32 pend, const C
     return fold1(fold1(p.x, p.y, c.r), fold1(q.x, q.y, c.r), c.r2);
 }
 
-// This lane's share of G(T) = sum over pairs m of A_T F_T + C_T, where
-// X_T is X at t = T on the line through X[2m], X[2m+1].
+// RNG state of the tail's first round: the prologue drew the pending
+// challenges and left the state after them; a tail without them reads it.
+__device__ __forceinline__ u64 tail_state(const ProofPtrs &pp, u32 c0, u32 drew, u64 st) {
+    __shared__ u64 s_st;
+    if (drew) return uniform(st);
+    if (threadIdx.x == 0) s_st = pp.rngst[c0];
+    __syncthreads();
+    return uniform(s_st);
+}
+
+// Narrow round of an omega tail, wave T: message value T and table T's
+// fold.  With at most 64 pairs a lane keeps its pair in registers.
 template <int T>
-__device__ __forceinline__ u64 wtail_term(const u64 *X, u32 half, u32 lane, bool hc) {
+__device__ __forceinline__ void wtail_narrow(const u64 *X, u64 *Y, u32 half, u32 lane, bool hc, u64 &st,
+                                             u64 *msg, u64 *chal, u64 *stn) {
+    if (half <= 64) {
+        const bool on = lane < half;
+        u64x2 pa = {0, 0}, pc = {0, 0}, pf = {0, 0};
+        if (on) {
+            pa = ld2(X, 2 * lane);
+            pf = ld2(X + 2 * TAIL_TAB, 2 * lane);
+            if (hc) pc = ld2(X + TAIL_TAB, 2 * lane);
+        }
+        const u64 term = add(mul(line_at<T>(pa.x, pa.y), line_at<T>(pf.x, pf.y)), line_at<T>(pc.x, pc.y));
+        const u64 r = fp::sm_field(st);
+        const u64x2 own = T == 0 ? pa : (T == 1 ? pc : pf);
+        const u64 fv = fold1(own.x, own.y, r);
+        const u64 s = wave_sum63_lazy(term);
+        if (lane == 63) {
+            *msg = s;
+            if (T == 0) {
+                *chal = r;
+                *stn = st;
+            }
+        }
+        if (on && (T != 1 || hc)) Y[T * TAIL_TAB + lane] = fv;
+        return;
+    }
     u64 s = 0;
     for (u32 m = lane; m < half; m += 64) {
         const u64x2 pa = ld2(X, 2 * m), pf = ld2(X + 2 * TAIL_TAB, 2 * m);
         u64 ct = 0;
         if (hc) {
             const u64x2 pc = ld2(X + TAIL_TAB, 2 * m);
-            ct = T == 0 ? pc.x : (T == 1 ? pc.y : sub(add(pc.y, pc.y), pc.x));
+            ct = line_at<T>(pc.x, pc.y);
         }
-        const u64 at = T == 0 ? pa.x : (T == 1 ? pa.y : sub(add(pa.y, pa.y), pa.x));
-        const u64 ft = T == 0 ? pf.x : (T == 1 ? pf.y : sub(add(pf.y, pf.y), pf.x));
-        s = add(s, add(mul(at, ft), ct));
+        s = add(s, add(mul(line_at<T>(pa.x, pa.y), line_at<T>(pf.x, pf.y)), ct));
     }
-    return s;
+    s = wave_sum63_lazy(s);
+    const u64 r = fp::sm_field(st);
+    if (lane == 63) {
+        *msg = s;
+        if (T == 0) {
+            *chal = r;
+            *stn = st;
+        }
+    }
+    if (T != 1 || hc) {
+        for (u32 m = lane; m < half; m += 64) {
+            const u64x2 p = ld2(X + T * TAIL_TAB, 2 * m);
+            Y[T * TAIL_TAB + m] = fold1(p.x, p.y, r);
+        }
+    }
 }
 
 // Remaining omega rounds k0..s'-1 over A, C, F.  The prologue drew the
 // pending challenge(s) up to r_{k0-1}; each round writes its message, then
-// draws its challenge; after the last fold F holds v1 (or v2).
-__device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx &c) {
-    __shared__ u64 s_st;
+// records its challenge; after the last fold F holds v1 (or v2).
+__device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0) {
+    __shared__ u64 s_part[3][NWAVES];
     u64 *tab = tail_lds();
     const u32 tid = threadIdx.x, lane = tid & 63;
     const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
@@ -836,32 +934,45 @@ __device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx &c
         if (hc) tab[TAIL_TAB + e] = tail_entry(a.C, e, a.pend, c);
         tab[2 * TAIL_TAB + e] = tail_entry(a.F, e, a.pend, c);
     }
-    if (tid == 0) s_st = pp.rngst[a.c0];
+    u64 st = tail_state(pp, a.c0, drew, st0);
     __syncthreads();
-    u64 st = uniform(s_st);
     u32 k = 0;  // rounds done; level k0 + k sits in area k & 1
     for (; n > 1; n >>= 1, k++) {
         const u64 *X = tab + ((k & 1) ? TAIL_LIM : 0);
         u64 *Y = tab + ((k & 1) ? 0 : TAIL_LIM);
         const u32 half = n >> 1;
-        if (w < 3) {
-            u64 s = w == 0 ? wtail_term<0>(X, half, lane, hc)
-                           : (w == 1 ? wtail_term<1>(X, half, lane, hc) : wtail_term<2>(X, half, lane, hc));
-            s = wave_sum63(s);
-            if (lane == 63) a.msg[3 * k + w] = s;
+        if (half >= WIDE_HALF) {
+            u64x2 pa = {0, 0}, pc = {0, 0}, pf = {0, 0};
+            u64 t[3] = {0, 0, 0};
+            if (tid < half) {
+                pa = ld2(X, 2 * tid);
+                pf = ld2(X + 2 * TAIL_TAB, 2 * tid);
+                if (hc) pc = ld2(X + TAIL_TAB, 2 * tid);
+                table_terms(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
+            }
+#pragma unroll
+            for (int q = 0; q < 3; q++) t[q] = wave_sum63_lazy(t[q]);
+            if (lane == 63) {
+#pragma unroll
+                for (int q = 0; q < 3; q++) s_part[q][w] = t[q];
+            }
+            __syncthreads();
+            if (w < 3 && lane == 0) a.msg[3 * k + w] = waves_total(s_part, (int)w);
             const u64 r = fp::sm_field(st);
-            if (w == 0 && lane == 63) {
+            if (tid == 0) {
                 pp.chals[a.c0 + k] = r;
                 pp.rngst[a.c0 + k + 1] = st;
             }
-            if (w != 1 || hc) {  // wave w folds table w (A, C, F)
-                const u64 *Xw = X + w * TAIL_TAB;
-                u64 *Yw = Y + w * TAIL_TAB;
-                for (u32 m = lane; m < half; m += 64) {
-                    const u64x2 p = ld2(Xw, 2 * m);
-                    Yw[m] = fold1(p.x, p.y, r);
-                }
+            if (tid < half) {
+                Y[tid] = fold1(pa.x, pa.y, r);
+                Y[2 * TAIL_TAB + tid] = fold1(pf.x, pf.y, r);
+                if (hc) Y[TAIL_TAB + tid] = fold1(pc.x, pc.y, r);
             }
+        } else if (w < 3) {
+            u64 *msg = a.msg + 3 * k + w, *chal = pp.chals + a.c0 + k, *stn = pp.rngst + a.c0 + k + 1;
+            if (w == 0) wtail_narrow<0>(X, Y, half, lane, hc, st, msg, chal, stn);
+            else if (w == 1) wtail_narrow<1>(X, Y, half, lane, hc, st, msg, chal, stn);
+            else wtail_narrow<2>(X, Y, half, lane, hc, st, msg, chal, stn);
         }
         __syncthreads();
     }
@@ -872,28 +983,85 @@ __device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx &c
     }
 }
 
-// This lane's share of S_T = sum over pairs m of B[m] V_T, V_T on the line
-// through V[2m], V[2m+1].
+// eq_T(z): the line through (0, 1 - z), (1, z) at t = T.
 template <int T>
-__device__ __forceinline__ u64 ptail_term(const u64 *V, const u64 *B, u32 half, u32 lane) {
+__device__ __forceinline__ u64 eq_at(u64 z) {
+    return T == 0 ? sub(1, z) : (T == 1 ? z : sub(add(add(z, z), z), 1));
+}
+
+// Narrow round of the p-phase tail, wave T: message value T; wave 0 folds
+// V (waves 0 and 2 share it beyond 64 pairs), wave 1 sums B.
+template <int T>
+__device__ __forceinline__ void ptail_narrow(const u64 *V, const u64 *B, u64 *Vn, u64 *Bn, u32 half, u32 lane,
+                                             u64 &st, u64 &C, u64 z, u64 *msg, u64 *chal, u64 *stn) {
+    const u64 Ce = mul(C, eq_at<T>(z));
+    if (half <= 64) {
+        const bool on = lane < half;
+        u64x2 pv = {0, 0};
+        u64 b = 0;
+        if (on) {
+            pv = ld2(V, 2 * lane);
+            b = B[lane];
+        }
+        const u64 term = mul(b, line_at<T>(pv.x, pv.y));
+        const u64 r = fp::sm_field(st);
+        u64 nv = 0;
+        if (T == 0) nv = fold1(pv.x, pv.y, r);
+        if (T == 1 && lane < half / 2) {
+            const u64x2 pb = ld2(B, 2 * lane);
+            nv = add(pb.x, pb.y);
+        }
+        const u64 s = wave_sum63_lazy(term);
+        if (lane == 63) {
+            *msg = mul(Ce, s);
+            if (T == 0) {
+                *chal = r;
+                *stn = st;
+            }
+        }
+        if (T == 0 && on) Vn[lane] = nv;
+        if (T == 1 && lane < half / 2) Bn[lane] = nv;
+        C = mul(C, fp::eq(z, r));
+        return;
+    }
     u64 s = 0;
     for (u32 m = lane; m < half; m += 64) {
         const u64x2 p = ld2(V, 2 * m);
-        const u64 vt = T == 0 ? p.x : (T == 1 ? p.y : sub(add(p.y, p.y), p.x));
-        s = add(s, mul(B[m], vt));
+        s = add(s, mul(B[m], line_at<T>(p.x, p.y)));
     }
-    return s;
+    s = wave_sum63_lazy(s);
+    const u64 r = fp::sm_field(st);
+    if (lane == 63) {
+        *msg = mul(Ce, s);
+        if (T == 0) {
+            *chal = r;
+            *stn = st;
+        }
+    }
+    C = mul(C, fp::eq(z, r));
+    if (T == 1) {  // B_{j+1}[m] = B_j[2m] + B_j[2m+1]
+        for (u32 m = lane; m < half / 2; m += 64) {
+            const u64x2 p = ld2(B, 2 * m);
+            Bn[m] = add(p.x, p.y);
+        }
+    } else {  // waves 0 and 2 fold V, alternating runs of 64 pairs
+        for (u32 m = lane + (T == 2 ? 64 : 0); m < half; m += 128) {
+            const u64x2 p = ld2(V, 2 * m);
+            Vn[m] = fold1(p.x, p.y, r);
+        }
+    }
 }
 
 // Remaining p-phase rounds j0..s-1.  The prologue drew the pending
-// challenge(s) up to r_{j0-1} and its finish of round j0-1 left the beta
-// prefix C in state[0] (written by thread 0).  B is the table of sums of
-// the eq weights of the a-coordinates not yet reached (beta over z's
-// suffix); pair m of V goes with B[m].  Round j's message is
-// G(t) = C eq_t(z_j) S_t with eq_t(z) the line through (0, 1 - z), (1, z):
-// 1 - z, z, 3z - 1 at t = 0, 1, 2.
-__device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx &c) {
-    __shared__ u64 s_st, s_c;
+// challenge(s) up to r_{j0-1} and its finish of round j0-1 computed the
+// beta prefix C.  B is the table of sums of the eq weights of the
+// a-coordinates not yet reached (beta over z's suffix); pair m of V goes
+// with B[m].  Round j's message is G(t) = C eq_t(z_j) S_t with eq_t(z) the
+// line through (0, 1 - z), (1, z): 1 - z, z, 3z - 1 at t = 0, 1, 2.
+__device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0, u32 have_c,
+                           u64 C0) {
+    __shared__ u64 s_c;
+    __shared__ u64 s_part[3][NWAVES];
     u64 *tab = tail_lds();
     u64 *tv = tab, *tb = tab + TAIL_TAB;  // V areas: TAIL_LIM, TAIL_LIM / 2; B: half of each
     const u32 tid = threadIdx.x, lane = tid & 63;
@@ -906,42 +1074,54 @@ __device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx &c
     }
     const u32 rounds = a.s - a.j0;
     const u64 zr = lane < rounds ? pp.zbuf[a.j0 + lane] : 0;  // z_{j0 + l} in lane l
-    if (tid == 0) {
-        s_st = pp.rngst[a.c0];
-        s_c = pp.state[0];
-    }
+    if (!have_c && tid == 0) s_c = pp.state[0];
+    u64 st = tail_state(pp, a.c0, drew, st0);
     __syncthreads();
-    u64 st = uniform(s_st), C = uniform(s_c);
+    u64 C = uniform(have_c ? C0 : s_c);
     u32 k = 0;  // rounds done; V^(j0 + k) and B_{j0 + k} sit in area k & 1
     for (; n > 1; n >>= 1, k++) {
         const u32 off = (k & 1) ? TAIL_LIM : 0, noff = (k & 1) ? 0 : TAIL_LIM;
         const u64 *V = tv + off, *B = tb + off;
         u64 *Vn = tv + noff, *Bn = tb + noff;
         const u32 half = n >> 1;
-        if (w < 3) {
-            u64 s = w == 0 ? ptail_term<0>(V, B, half, lane)
-                           : (w == 1 ? ptail_term<1>(V, B, half, lane) : ptail_term<2>(V, B, half, lane));
-            s = wave_sum63(s);
-            const u64 z = lane_value(zr, k);
-            const u64 e = w == 0 ? sub(1, z) : (w == 1 ? z : sub(add(add(z, z), z), 1));
-            if (lane == 63) a.msg[3 * k + w] = mul(mul(C, e), s);
+        const u64 z = lane_value(zr, k);
+        if (half >= WIDE_HALF) {
+            u64x2 pv = {0, 0};
+            u64 t[3] = {0, 0, 0};
+            if (tid < half) {
+                pv = ld2(V, 2 * tid);
+                const u64 b = B[tid];
+                t[0] = mul(b, pv.x);
+                t[1] = mul(b, pv.y);
+                t[2] = mul(b, sub(add(pv.y, pv.y), pv.x));
+            }
+#pragma unroll
+            for (int q = 0; q < 3; q++) t[q] = wave_sum63_lazy(t[q]);
+            if (lane == 63) {
+#pragma unroll
+                for (int q = 0; q < 3; q++) s_part[q][w] = t[q];
+            }
+            __syncthreads();
+            if (w < 3 && lane == 0) {
+                const u64 e = w == 0 ? eq_at<0>(z) : (w == 1 ? eq_at<1>(z) : eq_at<2>(z));
+                a.msg[3 * k + w] = mul(mul(C, e), waves_total(s_part, (int)w));
+            }
             const u64 r = fp::sm_field(st);
-            if (w == 0 && lane == 63) {
+            if (tid == 0) {
                 pp.chals[a.c0 + k] = r;
                 pp.rngst[a.c0 + k + 1] = st;
             }
             C = mul(C, fp::eq(z, r));
-            if (w == 1) {  // B_{j+1}[m] = B_j[2m] + B_j[2m+1]
-                for (u32 m = lane; m < half / 2; m += 64) {
-                    const u64x2 p = ld2(B, 2 * m);
-                    Bn[m] = add(p.x, p.y);
-                }
-            } else {  // waves 0 and 2 fold V, alternating runs of 64 pairs
-                for (u32 m = lane + (w == 2 ? 64 : 0); m < half; m += 128) {
-                    const u64x2 p = ld2(V, 2 * m);
-                    Vn[m] = fold1(p.x, p.y, r);
-                }
+            if (tid < half) Vn[tid] = fold1(pv.x, pv.y, r);
+            if (tid < half / 2) {
+                const u64x2 pb = ld2(B, 2 * tid);
+                Bn[tid] = add(pb.x, pb.y);
             }
+        } else if (w < 3) {
+            u64 *msg = a.msg + 3 * k + w, *chal = pp.chals + a.c0 + k, *stn = pp.rngst + a.c0 + k + 1;
+            if (w == 0) ptail_narrow<0>(V, B, Vn, Bn, half, lane, st, C, z, msg, chal, stn);
+            else if (w == 1) ptail_narrow<1>(V, B, Vn, Bn, half, lane, st, C, z, msg, chal, stn);
+            else ptail_narrow<2>(V, B, Vn, Bn, half, lane, st, C, z, msg, chal, stn);
         }
         __syncthreads();
     }
@@ -956,20 +1136,21 @@ __device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx &c
 // beside the body instead of ahead of it) and records the drawn challenge.
 template <u32 KIND, int GK, int PH>
 __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
-    __shared__ u64 s_r, s_r2;
+    __shared__ u64 s_r, s_r2, s_st;
     __shared__ u64 s_pt[64];  // a point (EQ), or b* and c* (LT), or z_{i+1} (FIN_LINE)
-    Ctx c;
-    c.lb = lb;
-    c.nb = sd.nblocks;
-    c.gtid = (u64)c.lb * SBLOCK + threadIdx.x;
-    c.gstride = (u64)c.nb * SBLOCK;
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
     const u32 kind = KIND == KALL ? sd.kind : KIND;
     const bool tail = kind == ST_WTAIL || kind == ST_PTAIL;  // one workgroup does everything
     const bool has_fin = f.kind != FIN_NONE;
-    const bool fin_block = has_fin && !tail && lb == sd.nblocks;
-    const bool recorder = (has_fin && !tail) ? fin_block : lb == 0;
+    const bool split = has_fin && !tail;  // workgroup nblocks finishes, the others run the body
+    const bool fin_block = split && lb == sd.nblocks;
+    const bool recorder = split ? fin_block : lb == 0;
+    Ctx c;
+    c.lb = lb;
+    c.nb = sd.nblocks;
+    c.gtid = (u64)c.lb * SBLOCK + threadIdx.x;
+    c.gstride = (u64)c.nb * SBLOCK;
 
     // --- prologue: the challenge (every workgroup draws the same value)
     if (threadIdx.x == 0) {
@@ -988,6 +1169,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
                     pp.rngst[f.draw + 2] = st;
                 }
             }
+            s_st = st;  // the state after the drawn challenge(s)
         }
         s_r = r;
         s_r2 = r2;
@@ -995,6 +1177,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     __syncthreads();
     c.r = s_r;
     c.r2 = s_r2;
+    TailIn ti = {f.draw >= 0 ? s_st : 0, 0, f.draw >= 0 ? 1u : 0u, 0u};
     // points assembled in LDS (challenges drawn by earlier launches are in
     // chals; the one drawn just now is c.r)
     if ((fin_mask(KIND) & (1u << FIN_LINE)) && f.kind == FIN_LINE && threadIdx.x < f.sp) {
@@ -1019,7 +1202,11 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         finalize<KIND>(sd, c, s_pt);
         return;
     }
-    if (tail && has_fin) finalize<KIND>(sd, c, s_pt);
+    if (tail && has_fin) {
+        const FinOut o = finalize<KIND>(sd, c, s_pt);
+        ti.have_c = o.have_c ? 1u : 0u;
+        ti.C = o.cfin;
+    }
 
     // --- body
     u64 *row = sd.rows ? sd.rows + (u64)c.lb * ROW_STRIDE : nullptr;
@@ -1053,8 +1240,8 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_WT0: step_wt0(sd.u.wt0, pp, c, row); break;
         case ST_WA0: step_wa0(sd.u.wa0, pp, c, row); break;
         case ST_WT: step_wt(sd.u.wt, c, row); break;
-        case ST_WTAIL: step_wtail(sd.u.wtail, pp, c); break;
-        case ST_PTAIL: step_ptail(sd.u.ptail, pp, c); break;
+        case ST_WTAIL: step_wtail(sd.u.wtail, pp, c, ti.drew, ti.st); break;
+        case ST_PTAIL: step_ptail(sd.u.ptail, pp, c, ti.drew, ti.st, ti.have_c, ti.C); break;
         case ST_SGE:
             if (c.lb == 0 && threadIdx.x == 0) {
                 const u64 v = sd.u.sge.Vn[0];
