@@ -58,14 +58,14 @@ namespace {
 // then the verifier's and the F2 sum-check's kernels.
 enum ProfClass {
     PC_STEP = 0,  // + StepKind
-    PC_WIRING = 17, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_COUNT
+    PC_WIRING = 18, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {
     "step_eval", "step_start", "step_eq", "step_p", "step_w", "step_fold", "step_lt",
     "step_line", "step_sge", "step_end", "step_wagg", "step_wt0", "step_wt", "step_wtail",
-    "step_ptail", "step_load", "step_wa0", "wiring", "mle", "eq_tables", "f2sc_round",
+    "step_ptail", "step_load", "step_wa0", "step_finish", "wiring", "mle", "eq_tables", "f2sc_round",
     "f2sc_final", "misc", "batch_step"};
-static_assert(ST_WA0 + 1 == PC_WIRING, "one profiling class per step kind");
+static_assert(ST_FINISH + 1 == PC_WIRING, "one profiling class per step kind");
 
 struct ProfRec {
     int cls;
@@ -290,7 +290,9 @@ struct Workspace {
     u64 *w, *off;
     u64 *zlo, *zhi, *alo, *ahi, *blo, *bhi;
     u64 *llo, *lhl, *lhh;
-    u64 *rows[2];
+    u64 *rowpool;        // every reducing step's rows, each at its own offset
+    u64 *frec;           // records of p-phase finishes (C, z_j, z_{j+1})
+    FinItem *d_items;    // the finish step's items
     u64 *msgs, *chals, *rngst, *zbuf, *state;
     u32 *flag;
     // omega phases over tables
@@ -302,6 +304,7 @@ struct Workspace {
     std::vector<double> pbytes;   // algorithmic bytes of each step
     std::vector<u64> punits;      // work items of each tunable step (0: not tunable)
     u32 epoch = 0;                // launch shapes the program was planned with
+    u64 cap_rows = 0, cap_recs = 0, cap_items = 0;  // room carved for them
     u64 *instage;  // host inputs land here
     size_t bytes = 0;  // device memory held
     u64 *h_msgs = nullptr, *h_chals = nullptr, *h_setup = nullptr;  // pinned staging
@@ -519,7 +522,15 @@ static void build_group(const std::vector<u32> &idx, const std::vector<u32> &oth
 }
 
 // Lay out (or size, when a.base is NULL) a proof's scratch.
-static void carve(const gkr_circuit *c, Arena &a, Workspace &w, size_t nsteps) {
+// What a step program needs besides its steps: row storage, p-phase
+// records and finish items (the same for every launch shape).
+struct PlanSizes {
+    size_t nsteps;
+    u64 rows, recs, items;
+};
+
+static void carve(const gkr_circuit *c, Arena &a, Workspace &w, const PlanSizes &ps) {
+    const size_t nsteps = ps.nsteps;
     w.V.assign(c->L, nullptr);
     for (u32 i = 0; i < c->L; i++) w.V[i] = a.take<u64>(1ull << c->s[i]);
     const u64 half = std::max<u64>(1ull << (c->smax ? c->smax - 1 : 0), 2);
@@ -541,8 +552,9 @@ static void carve(const gkr_circuit *c, Arena &a, Workspace &w, size_t nsteps) {
     w.llo = a.take<u64>(c->line_lo);
     w.lhl = a.take<u64>(c->line_hl);
     w.lhh = a.take<u64>(c->line_hh);
-    w.rows[0] = a.take<u64>((u64)std::max<u32>(CAP_MAX, SMAX_BLOCKS) * ROW_STRIDE);
-    w.rows[1] = a.take<u64>((u64)std::max<u32>(CAP_MAX, SMAX_BLOCKS) * ROW_STRIDE);
+    w.rowpool = a.take<u64>(std::max<u64>(ps.rows, 1));
+    w.frec = a.take<u64>(std::max<u64>(ps.recs, 1));
+    w.d_items = a.take<FinItem>(std::max<u64>(ps.items, 1));
     w.msgs = a.take<u64>(c->n_msgs);
     w.chals = a.take<u64>(std::max<u64>(c->n_chals, 1));
     w.rngst = a.take<u64>(c->n_chals + 1);
@@ -575,7 +587,11 @@ struct Planner {
     std::vector<int> cls;
     std::vector<double> bytes;
     std::vector<u64> units;
+    std::vector<FinItem> items;
+    u64 rows_used = 0, recs_used = 0;
     ProofPtrs pp{};
+
+    PlanSizes sizes() const { return PlanSizes{out.size(), rows_used, recs_used, items.size()}; }
 
     StepDesc &add(u32 kind, u32 nblocks, double nbytes) {
         StepDesc s;
@@ -597,15 +613,21 @@ struct Planner {
         if (tunable(kind)) units.back() = std::max<u64>(n, 1);
         return s;
     }
-    // The step just added writes K-value rows into the buffer of its parity.
+    // The step just added writes K-value rows: room for as many workgroups
+    // as any launch shape gives it (q = 1, the largest cap), so a re-plan
+    // with other shapes keeps every offset.
     void reduces(u32 K) {
         StepDesc &s = out.back();
         s.reduces = 1;
         s.K = K;
-        s.rows = w ? w->rows[(out.size() - 1) & 1] : nullptr;
+        const u64 n = units.back();
+        const u64 most = n ? std::min<u64>(CAP_MAX, std::max<u64>(1, (n + SBLOCK - 1) / SBLOCK)) : s.nblocks;
+        s.rows = w ? w->rowpool + rows_used : nullptr;
+        rows_used += std::max<u64>(most, s.nblocks) * ROW_STRIDE;
     }
-    // Finalize info for a step that follows a reducing step.
-    Fin fin_of_prev(u32 kind) const {
+    // Finish info for a step that follows a reducing step (p-phase finishes
+    // get a record slot).
+    Fin fin_of_prev(u32 kind) {
         Fin f;
         memset(&f, 0, sizeof f);
         f.kind = kind;
@@ -613,7 +635,33 @@ struct Planner {
         const StepDesc &p = out.back();
         f.rows = p.rows;
         f.nrows = p.nblocks;
+        if (kind == FIN_P || kind == FIN_P2) {
+            f.rec = w ? w->frec + recs_used : nullptr;
+            recs_used += 3;
+        }
         return f;
+    }
+    // The finish step: one item per message (per chunk of line values).
+    void add_finish() {
+        for (const StepDesc &sd : out) {
+            const Fin &f = sd.fin;
+            if (f.kind == FIN_NONE) continue;
+            if (f.kind == FIN_LINE) {
+                for (u32 q = 0; q * f.ch < f.T; q++)
+                    items.push_back(FinItem{FIN_LINE, f.chunk_blocks, f.rows ? f.rows + (u64)q * f.chunk_blocks * ROW_STRIDE : nullptr,
+                                            f.msg ? f.msg + q * f.ch : nullptr, nullptr, -1,
+                                            std::min<u32>(f.ch, f.T - q * f.ch)});
+                continue;
+            }
+            items.push_back(FinItem{f.kind, f.nrows, f.rows, f.msg, f.rec, f.draw + 0, 0});
+        }
+        if (items.empty()) return;
+        double nbytes = 0;
+        for (const FinItem &it : items)
+            nbytes += it.nrows * 8.0 * (it.kind == FIN_P ? 2 : it.kind == FIN_P2 ? 6 : it.kind == FIN_W ? 4
+                                        : it.kind == FIN_T ? 3 : it.kind == FIN_T2 ? 12 : LINE_CHUNK);
+        StepDesc &s = add(ST_FINISH, (u32)items.size(), nbytes);
+        s.u.finish = FinishArgs{w ? w->d_items : nullptr, w ? w->chals : nullptr};
     }
 
     void build() {
@@ -1036,6 +1084,7 @@ struct Planner {
         }
         StepDesc &e = add(ST_END, 1, 0);
         e.fin = layer_end;
+        add_finish();
     }
 };
 
@@ -1097,6 +1146,8 @@ static int plan_into(gkr_circuit *c, Workspace &ws) {
     plan.build();
     const size_t nsteps = plan.out.size();
     if (nsteps != ws.steps.size()) return fail(GKR_ERR_INVALID, "step program changed size");
+    if (plan.rows_used > ws.cap_rows || plan.recs_used > ws.cap_recs || plan.items.size() > ws.cap_items)
+        return fail(GKR_ERR_INVALID, "step program outgrew its workspace");
     for (const StepDesc &sd : plan.out)
         if (sd.fin.kind != FIN_NONE && !((fin_mask(sd.kind) >> sd.fin.kind) & 1))
             return fail(GKR_ERR_INVALID, "step program: a step carries a finish its kernel lacks");
@@ -1111,6 +1162,8 @@ static int plan_into(gkr_circuit *c, Workspace &ws) {
     }
     HIP_TRY(hipMemcpy(ws.d_steps, plan.out.data(), nsteps * sizeof(StepDesc), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ws.d_jobs, jobs.data(), jobs.size() * sizeof(JobEntry), hipMemcpyHostToDevice));
+    if (!plan.items.empty())
+        HIP_TRY(hipMemcpy(ws.d_items, plan.items.data(), plan.items.size() * sizeof(FinItem), hipMemcpyHostToDevice));
     ws.epoch = epoch;
     return GKR_OK;
 }
@@ -1130,17 +1183,21 @@ static int make_workspace(gkr_circuit *c, Workspace **out) {
     }
     Planner count{c, nullptr};
     count.build();
-    const size_t nsteps = count.out.size();
+    const PlanSizes ps = count.sizes();
+    const size_t nsteps = ps.nsteps;
     Workspace probe;
     Arena sz;
-    carve(c, sz, probe, nsteps);
+    carve(c, sz, probe, ps);
     std::unique_ptr<Workspace, void (*)(Workspace *)> ws(new Workspace(), free_workspace);
     HIP_TRY(hipMalloc(&ws->mem, sz.used));
     ws->bytes = sz.used;
     Arena a;
     a.base = (char *)ws->mem;
     a.cap = sz.used;
-    carve(c, a, *ws, nsteps);
+    carve(c, a, *ws, ps);
+    ws->cap_rows = ps.rows;
+    ws->cap_recs = ps.recs;
+    ws->cap_items = ps.items;
     ws->steps.resize(nsteps);
     int rc = plan_into(c, *ws);
     if (rc) return rc;
@@ -1165,7 +1222,7 @@ static int workspace_size(gkr_circuit *c, size_t *bytes) {
     count.build();
     Workspace probe;
     Arena sz;
-    carve(c, sz, probe, count.out.size());
+    carve(c, sz, probe, count.sizes());
     c->ws_bytes = sz.used;
     *bytes = sz.used;
     return GKR_OK;

@@ -175,83 +175,112 @@ __device__ __forceinline__ u64 pick(const u64 (&tot)[K], u32 k) {
     return v;
 }
 
-// The finish of the previous round(s): rows into the message, lanes
-// t < 3 (and 3..5 for a second message) writing one value each.  Operands
-// that do not depend on the rows are loaded before the row sums.
-// A p-phase finish returns the beta prefix it leaves in state[0].
-struct FinOut {
-    bool have_c;
-    u64 cfin;
-};
-
+// The part of a round's finish that later rounds need; it reads no rows.
+// Thread 0 records the beta prefix C and z of a p-phase round for its
+// message, advances C by the drawn challenge(s) (left in *s_c as well), and
+// at the end of an omega phase folds the last pair into v1 / v2; the line
+// finish stores z_{i+1}.
 template <u32 KIND>
-__device__ FinOut finalize(const StepDesc &sd, const Ctx &c, u64 *s_pt) {
+__device__ void fin_inline(const StepDesc &sd, const Ctx &c, const u64 *s_pt, u64 *s_c) {
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
     constexpr u32 FM = fin_mask(KIND);
     const u32 tid = threadIdx.x;
-    FinOut out = {false, 0};
     if ((FM & (1u << FIN_P)) && f.kind == FIN_P) {
-        const u64 z = pp.zbuf[f.j], C = pp.state[0];
-        u64 t[2];
-        rows_total<2>(f.rows, 0, f.nrows, t);
-        if (tid < 3) f.msg[tid] = p_value(tid, C, z, t[0], t[1]);
-        out = {true, mul(C, fp::eq(z, c.r))};  // beta prefix over r_0..r_j
-        if (tid == 0) pp.state[0] = out.cfin;
-    } else if ((FM & (1u << FIN_P2)) && f.kind == FIN_P2) {
-        const u64 z0 = pp.zbuf[f.j], z1 = pp.zbuf[f.j + 1], C = pp.state[0];
-        u64 t[6];
-        rows_total<6>(f.rows, 0, f.nrows, t);
-        const u64 C1 = mul(C, fp::eq(z0, c.r));
-        if (tid < 3) f.msg[tid] = p_value(tid, C, z0, t[0], t[1]);
-        else if (tid < 6)
-            f.msg[tid] = p_value(tid - 3, C1, z1, add(t[2], mul(c.r, t[3])), add(t[4], mul(c.r, t[5])));
-        out = {true, mul(C1, fp::eq(z1, c.r2))};
-        if (tid == 0) pp.state[0] = out.cfin;
-    } else if ((FM & (1u << FIN_W)) && f.kind == FIN_W) {
-        u64 f0 = 0, f1 = 0;
-        if (f.last && tid == 0) {
-            f0 = f.F[0];
-            f1 = f.F[1];
-        }
-        u64 t[4];
-        rows_total<4>(f.rows, 0, f.nrows, t);
         if (tid == 0) {
-            const u64 E0 = t[0], E1 = t[1], O0 = t[2], O1 = t[3];
-            f.msg[0] = E0;
-            f.msg[1] = O1;
-            u64 o4 = add(O1, O1);
-            o4 = add(o4, o4);
-            f.msg[2] = sub(add(sub(E0, add(E1, E1)), o4), add(O0, O0));
-            if (f.last) {
-                const u64 v = add(f0, mul(c.r, sub(f1, f0)));
-                *f.vout = v;
-                if (f.last == 1) pp.state[1] = v;
-            }
+            const u64 z = pp.zbuf[f.j], C = pp.state[0];
+            f.rec[0] = C;
+            f.rec[1] = z;
+            const u64 Cn = mul(C, fp::eq(z, c.r));  // beta prefix over r_0..r_j
+            pp.state[0] = Cn;
+            *s_c = Cn;
         }
-    } else if ((FM & (1u << FIN_T)) && f.kind == FIN_T) {
-        u64 t[3];
-        rows_total<3>(f.rows, 0, f.nrows, t);
-        if (tid < 3) f.msg[tid] = pick(t, tid);
-    } else if ((FM & (1u << FIN_T2)) && f.kind == FIN_T2) {
-        u64 t[12];
-        rows_total<12>(f.rows, 0, f.nrows, t);
-        if (tid < 3) {
-            f.msg[tid] = pick(t, tid);
-        } else if (tid < 6) {  // round k+1 at t = tid - 3: Q0 + r (Q1 + r Q2)
-            const u32 q = tid - 3;
-            f.msg[tid] = add(pick(t, 3 + q), mul(c.r, add(pick(t, 6 + q), mul(c.r, pick(t, 9 + q)))));
+    } else if ((FM & (1u << FIN_P2)) && f.kind == FIN_P2) {
+        if (tid == 0) {
+            const u64 z0 = pp.zbuf[f.j], z1 = pp.zbuf[f.j + 1], C = pp.state[0];
+            f.rec[0] = C;
+            f.rec[1] = z0;
+            f.rec[2] = z1;
+            const u64 Cn = mul(mul(C, fp::eq(z0, c.r)), fp::eq(z1, c.r2));
+            pp.state[0] = Cn;
+            *s_c = Cn;
+        }
+    } else if ((FM & (1u << FIN_W)) && f.kind == FIN_W) {
+        if (f.last && tid == 0) {
+            const u64 f0 = f.F[0], f1 = f.F[1];
+            const u64 v = add(f0, mul(c.r, sub(f1, f0)));
+            *f.vout = v;
+            if (f.last == 1) pp.state[1] = v;
         }
     } else if ((FM & (1u << FIN_LINE)) && f.kind == FIN_LINE) {
-        for (u32 q = 0; q * f.ch < f.T; q++) {  // chunk q: points q ch .. q ch + ch - 1
-            u64 t[LINE_CHUNK];
-            rows_total<LINE_CHUNK>(f.rows, q * f.chunk_blocks, f.chunk_blocks, t);
-            if (tid < f.ch && q * f.ch + tid < f.T) f.msg[q * f.ch + tid] = pick(t, tid);
-        }
         if (tid < f.sp) pp.zbuf[tid] = s_pt[tid];
         if (tid == 0) pp.state[0] = 1;  // the next layer's a-variables start unbound
     }
-    return out;
+}
+
+// One item of ST_FINISH: a round's rows into its message, lanes t < 3 (and
+// 3..5 for a second message) writing one value each; operands that do not
+// depend on the rows are loaded before the row sums.
+__device__ void step_finish(const FinishArgs &a, const Ctx &c) {
+    const FinItem &it = a.items[c.lb];
+    const u32 tid = threadIdx.x;
+    switch (it.kind) {
+        case FIN_P: {
+            const u64 C = it.rec[0], z = it.rec[1];
+            u64 t[2];
+            rows_total<2>(it.rows, 0, it.nrows, t);
+            if (tid < 3) it.msg[tid] = p_value(tid, C, z, t[0], t[1]);
+            break;
+        }
+        case FIN_P2: {
+            const u64 C = it.rec[0], z0 = it.rec[1], z1 = it.rec[2], r = a.chals[it.draw];
+            u64 t[6];
+            rows_total<6>(it.rows, 0, it.nrows, t);
+            const u64 C1 = mul(C, fp::eq(z0, r));
+            if (tid < 3) it.msg[tid] = p_value(tid, C, z0, t[0], t[1]);
+            else if (tid < 6)
+                it.msg[tid] = p_value(tid - 3, C1, z1, add(t[2], mul(r, t[3])), add(t[4], mul(r, t[5])));
+            break;
+        }
+        case FIN_W: {
+            u64 t[4];
+            rows_total<4>(it.rows, 0, it.nrows, t);
+            if (tid == 0) {
+                const u64 E0 = t[0], E1 = t[1], O0 = t[2], O1 = t[3];
+                it.msg[0] = E0;
+                it.msg[1] = O1;
+                u64 o4 = add(O1, O1);
+                o4 = add(o4, o4);
+                it.msg[2] = sub(add(sub(E0, add(E1, E1)), o4), add(O0, O0));
+            }
+            break;
+        }
+        case FIN_T: {
+            u64 t[3];
+            rows_total<3>(it.rows, 0, it.nrows, t);
+            if (tid < 3) it.msg[tid] = pick(t, tid);
+            break;
+        }
+        case FIN_T2: {
+            const u64 r = a.chals[it.draw];
+            u64 t[12];
+            rows_total<12>(it.rows, 0, it.nrows, t);
+            if (tid < 3) {
+                it.msg[tid] = pick(t, tid);
+            } else if (tid < 6) {  // round k+1 at t = tid - 3: Q0 + r (Q1 + r Q2)
+                const u32 q = tid - 3;
+                it.msg[tid] = add(pick(t, 3 + q), mul(r, add(pick(t, 6 + q), mul(r, pick(t, 9 + q)))));
+            }
+            break;
+        }
+        case FIN_LINE: {
+            u64 t[LINE_CHUNK];
+            rows_total<LINE_CHUNK>(it.rows, 0, it.nrows, t);
+            if (tid < it.nvals) it.msg[tid] = pick(t, tid);
+            break;
+        }
+        default: break;
+    }
 }
 
 // ------------------------------------------------------------ step bodies
@@ -1136,7 +1165,7 @@ __device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx c,
 // beside the body instead of ahead of it) and records the drawn challenge.
 template <u32 KIND, int GK, int PH>
 __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
-    __shared__ u64 s_r, s_r2, s_st;
+    __shared__ u64 s_r, s_r2, s_st, s_c;
     __shared__ u64 s_pt[64];  // a point (EQ), or b* and c* (LT), or z_{i+1} (FIN_LINE)
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
@@ -1199,13 +1228,16 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     }
     __syncthreads();
     if (fin_block) {
-        finalize<KIND>(sd, c, s_pt);
+        fin_inline<KIND>(sd, c, s_pt, &s_c);
         return;
     }
     if (tail && has_fin) {
-        const FinOut o = finalize<KIND>(sd, c, s_pt);
-        ti.have_c = o.have_c ? 1u : 0u;
-        ti.C = o.cfin;
+        fin_inline<KIND>(sd, c, s_pt, &s_c);
+        if (kind == ST_PTAIL && (f.kind == FIN_P || f.kind == FIN_P2)) {
+            __syncthreads();
+            ti.have_c = 1;
+            ti.C = s_c;
+        }
     }
 
     // --- body
@@ -1242,6 +1274,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_WT: step_wt(sd.u.wt, c, row); break;
         case ST_WTAIL: step_wtail(sd.u.wtail, pp, c, ti.drew, ti.st); break;
         case ST_PTAIL: step_ptail(sd.u.ptail, pp, c, ti.drew, ti.st, ti.have_c, ti.C); break;
+        case ST_FINISH: step_finish(sd.u.finish, c); break;
         case ST_SGE:
             if (c.lb == 0 && threadIdx.x == 0) {
                 const u64 v = sd.u.sge.Vn[0];
@@ -1322,6 +1355,7 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_WT: L1(ST_WT); break;
         case ST_WTAIL: L1(ST_WTAIL); break;
         case ST_PTAIL: L1(ST_PTAIL); break;
+        case ST_FINISH: L1(ST_FINISH); break;
         default: L1(ST_END); break;
     }
 #undef L1

@@ -6,13 +6,16 @@
 // Every step is one grid pass; a step that ends a sum-check round leaves one
 // row of partial sums per workgroup.
 //
-// The next step finishes that round in its prologue: workgroup 0 of the
-// step folds the rows into the round's message and writes it, and every
-// workgroup draws the round's challenge from the same SplitMix64 state
-// (the verifier's coins do not depend on the messages), so no step ever
-// synchronises workgroups inside a kernel.  The challenge of round j is
-// drawn only in a launch that starts after the launch computing message j
-// has completed.
+// Every workgroup of the next step draws the round's challenge from the
+// same SplitMix64 state (the verifier's coins do not depend on the
+// messages), so no step ever synchronises workgroups inside a kernel; its
+// workgroup 0 records the challenge and does the part of the round's finish
+// that later rounds need (the beta prefix, v1 / v2, the next layer's z).
+// Folding the rows into the message values is needed by nothing but the
+// transcript, so every reducing step keeps rows of its own and one last
+// step, ST_FINISH, folds all of them at once, one workgroup per message.
+// The challenge of round j is drawn only in a launch that starts after the
+// launch computing message j's sums has completed.
 //
 // One launch runs one step of each of several proofs (a job table maps
 // workgroups to (proof, step)); a single proof is the one-job case.
@@ -51,6 +54,7 @@ enum StepKind : u32 {
     ST_LOAD,       // inputs (pointer in state[3]) into V_d, range check
     ST_WA0,        // omega phase, tables: ST_WAGG and ST_WT0 in one pass, for
                    // layers whose wires each carry at most one chunk of gates
+    ST_FINISH,     // every round's rows into its message values
 };
 
 enum FinKind : u32 {
@@ -107,12 +111,15 @@ struct ProofPtrs {
                  // [4] nonzero if an input is not below p
 };
 
-// Prologue: finish the previous round and/or draw challenge `draw`.
+// Prologue: finish the previous round and/or draw challenge `draw`.  The
+// message values themselves are written by ST_FINISH from `rows` (and, for
+// p-phase rounds, the beta prefix and z values recorded in `rec`).
 struct Fin {
     u32 kind;          // FinKind
     i32 draw;          // challenge index drawn here (-1: none)
     const u64 *rows;   // partial rows of the previous step
     u32 nrows;
+    u64 *rec;          // FIN_P / FIN_P2: C, z_j (, z_{j+1}) at the time of the round
     u32 j;             // FIN_P: round index (z_j)
     u32 last;          // FIN_W: 1 / 2 = end of phase 1 / 2 (v1 / v2)
     u32 T;             // FIN_LINE: number of line values
@@ -123,6 +130,21 @@ struct Fin {
     u64 *msg;          // where the message goes
     u64 *vout;         // FIN_W last: transcript slot of v1 / v2
     const u64 *bstar, *cstar;  // FIN_LINE: line endpoints (chals)
+};
+
+// One message (or one chunk of line values) of ST_FINISH.
+struct FinItem {
+    u32 kind;          // FinKind
+    u32 nrows;
+    const u64 *rows;
+    u64 *msg;
+    const u64 *rec;    // FIN_P / FIN_P2
+    i32 draw;          // FIN_P2 / FIN_T2: the challenge drawn after the first message
+    u32 nvals;         // FIN_LINE: values of this chunk
+};
+struct FinishArgs {
+    const FinItem *items;  // one per workgroup
+    const u64 *chals;
 };
 
 struct EvalArgs {
@@ -290,6 +312,7 @@ struct StepDesc {
         PtailArgs ptail;
         LoadArgs load;
         Wa0Args wa0;
+        FinishArgs finish;
     } u;
 };
 
@@ -300,8 +323,7 @@ struct JobEntry {
     u32 pad;
 };
 
-// Workgroups a step needs: its body's plus one that finishes the previous
-// round when the step has a prologue.
+// Workgroups a step needs.
 u32 step_grid(const StepDesc &sd);
 // One step of one proof (descriptor passed by value); ev0 / ev1 (or NULL)
 // are recorded at the start and end of the dispatch.
