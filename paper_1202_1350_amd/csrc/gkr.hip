@@ -305,6 +305,9 @@ struct Workspace {
     std::vector<u64> punits;      // work items of each tunable step (0: not tunable)
     u32 epoch = 0;                // launch shapes the program was planned with
     u64 cap_rows = 0, cap_recs = 0, cap_items = 0;  // room carved for them
+    hipGraph_t graph = nullptr;   // the proof's launches, captured once per plan
+    hipGraphExec_t gexec = nullptr;
+    u32 gepoch = 0;
     u64 *instage;  // host inputs land here
     size_t bytes = 0;  // device memory held
     u64 *h_msgs = nullptr, *h_chals = nullptr, *h_setup = nullptr;  // pinned staging
@@ -434,6 +437,8 @@ extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_siz
 
 static void free_workspace(Workspace *ws) {
     if (!ws) return;
+    if (ws->gexec) (void)hipGraphExecDestroy(ws->gexec);
+    if (ws->graph) (void)hipGraphDestroy(ws->graph);
     if (ws->mem) (void)hipFree(ws->mem);
     if (ws->h_msgs) (void)hipHostFree(ws->h_msgs);
     if (ws->h_chals) (void)hipHostFree(ws->h_chals);
@@ -1253,6 +1258,45 @@ static int enqueue_proof(Workspace &w, hipStream_t st) {
     return GKR_OK;
 }
 
+namespace {
+hipStream_t capture_stream();
+}
+
+// A proof's launches as a graph, captured on first use and again after a
+// re-plan; a replay costs one enqueue instead of one per step.
+static int proof_graph(Workspace &w) {
+    if (w.gexec && w.gepoch == w.epoch) return GKR_OK;
+    if (w.gexec) (void)hipGraphExecDestroy(w.gexec);
+    if (w.graph) (void)hipGraphDestroy(w.graph);
+    w.gexec = nullptr;
+    w.graph = nullptr;
+    hipStream_t cst = capture_stream();
+    if (!cst) return fail(GKR_ERR_DEVICE, "no capture stream");
+    HIP_TRY(hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_proof(w, cst);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cst, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    HIP_TRY(e);
+    w.graph = graph;
+    HIP_TRY(hipGraphInstantiate(&w.gexec, graph, nullptr, nullptr, 0));
+    w.gepoch = w.epoch;
+    return GKR_OK;
+}
+
+// One proof's launches on st: replayed from its graph, or launched one by
+// one while per-launch profiling is on.
+static int run_proof(Workspace &w, hipStream_t st) {
+    if (g_prof.on) return enqueue_proof(w, st);
+    const int rc = proof_graph(w);
+    if (rc) return rc;
+    HIP_TRY(hipGraphLaunch(w.gexec, st));
+    return GKR_OK;
+}
+
 // Host inputs checked and copied in (device inputs are read in place), then
 // seed, input pointer and a cleared range flag into state[2..4]
 // (asynchronous on st; h_setup must not be reused before st has passed).
@@ -1285,7 +1329,7 @@ extern "C" int gkr_prove(const gkr_circuit *cc, const uint64_t *inputs, int inpu
     Workspace &w = *c->ws;
     rc = stage_proof(c, w, inputs, inputs_on_device, seed, st);
     if (rc) return rc;
-    rc = enqueue_proof(w, st);
+    rc = run_proof(w, st);
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(w.h_msgs, w.msgs, c->n_msgs * 8, hipMemcpyDeviceToHost, st));
     if (chals) HIP_TRY(hipMemcpyAsync(w.h_chals, w.chals, c->n_chals * 8, hipMemcpyDeviceToHost, st));
