@@ -151,6 +151,54 @@ def cpu_baseline(log_n):
                       f"({circ.gates} gates, seed 2) in {dt:.2f} s"}
 
 
+# Table 2's GPU prover times in seconds (the paper's GPU; context only).
+TABLE2_GPU_PROVE_S = {"F0": 128.5, "PM": 38.9, "MatMult": 39.6}
+
+
+def table2_leg(G, W, np, torch, reps, with_oracle):
+    """Table 2's other three rows at its sizes, on circuits built on the F0
+    (Fermat) stage: F0 of 2^21 values, pattern matching with the F0 count on
+    a 2^19 text (q = 8), MatMult with the C = AB check (N = 256).  Prove and
+    verify times with inputs resident; the oracle on a bounded sample of
+    each circuit family."""
+    from oracle import oracle as O
+    fams = (("F0", W.f1_f0, lambda: (W.f0_circuit(1 << 12), W.f0_inputs(1 << 12, 6), 6), "F0 n=2^12"),
+            ("PM", W.f1_pm_f0, lambda: (W.pm_f0_circuit(1 << 12, 8), W.pm_inputs(1 << 12, 7, 8)[0], 7),
+             "PM-F0 text 2^12, q=8"),
+            ("MatMult", W.f1_matmult_check,
+             lambda: (W.matmult_check_circuit(16), W.matmult_check_inputs(16, 8)[0], 8), "MatMult-check N=16"))
+    out = {}
+    for name, make, small, small_name in fams:
+        circ, x, seed = make()
+        gc = G.Circuit.from_workload(circ)
+        xt = torch.from_numpy(x.view(np.int64)).cuda().view(torch.uint64)
+        m, _ = G.gkr_prove(gc, xt, seed, want_chals=False)  # scratch and graph set up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            G.gkr_prove(gc, xt, seed, want_chals=False)
+        dt = (time.perf_counter() - t) / reps
+        t = time.perf_counter()
+        ok = G.gkr_verify(gc, xt, seed, m)[0]
+        tv = time.perf_counter() - t
+        rec = {"circuit": circ.name, "gates": circ.gates, "depth": circ.depth, "output": int(m[0]),
+               "accepted": bool(ok), "prove_ms": dt * 1e3, "gates_per_s": circ.gates / dt,
+               "verify_ms": tv * 1e3, "paper_gpu_prove_s": TABLE2_GPU_PROVE_S[name]}
+        if with_oracle:
+            sc, sx, ss = small()
+            O.build(force=False)
+            threads = max(1, min(16, os.cpu_count() or 1))
+            O.set_threads(threads)
+            t = time.perf_counter()
+            O.prove(sc, sx, ss)
+            to = time.perf_counter() - t
+            rec["oracle"] = {"gates_per_s": sc.gates / to, "cores": threads,
+                             "sample": f"{small_name} ({sc.gates} gates) in {to:.2f} s"}
+        out[name] = rec
+        del gc, xt, circ, x
+    return out
+
+
 def batch_leg(G, W, np, torch, reps, tune):
     """64 uneven proofs (F2 n log-uniform in [2^12, 2^20], PM text in
     [2^14, 2^18], seed 4): the plain path proves them one by one, the
@@ -326,6 +374,8 @@ def main():
     ap.add_argument("--cpu-log-n", type=int, default=22)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-table2", action="store_true",
+                    help="skip the F0, PM-F0 and MatMult-check circuits at Table 2's sizes")
     ap.add_argument("--autotune", choices=["auto", "off", "force"], default="auto",
                     help="auto: load the saved launch-shape table if it matches the kernel "
                          "sources, else tune on the benchmark circuit; off: default shapes; "
@@ -473,6 +523,8 @@ def main():
         k = max(1, args.serve_points)
         rates = [0.1 * 15.0 ** (j / (k - 1)) for j in range(k)] if k > 1 else [1.0]
         line["served"] = serve_leg(G, W, np, args.serve_requests, 200, rates)
+    if not args.no_table2:
+        line["table2_circuits"] = table2_leg(G, W, np, torch, 3, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_log_n)
     print(json.dumps(line), flush=True)

@@ -189,16 +189,47 @@ def test_outputs_equal_direct_computations():
     assert naive >= 1 and int((V[0][:n - q + 1] == 0).sum()) == naive
 
 
+def test_f0_circuits_equal_direct_computations():
+    # F0 (Sec. 5.2.1): the output is 2 |{i : a_i != 0}| by Fermat's little theorem
+    for n, seed in ((1, 1), (7, 2), (200, 3)):
+        x = W.f0_inputs(n, seed)
+        x[::5] = 0
+        V = O.evaluate(W.f0_circuit(n), x)
+        assert int(V[0][0]) == 2 * int(np.count_nonzero(x)), n
+        top = len(V) - 1 - 61  # the Fermat stage's last layer: 2 x^(p-1) per value
+        assert [int(v) for v in V[top][:n]] == [2 if v else 0 for v in x.tolist()]
+    # PM with the F0 count: twice the shifts where the pattern does not occur
+    n, q = 120, 8
+    inp, text, pat = W.pm_inputs(n, 22, q)
+    V = O.evaluate(W.pm_f0_circuit(n, q), inp)
+    t, pp = text.astype(np.int64), pat.astype(np.int64)
+    miss = sum(1 for i in range(n - q + 1) if any(t[i + j] != pp[j] for j in range(q)))
+    assert miss < n - q + 1 and int(V[0][0]) == 2 * miss
+    # MatMult check: zero iff C = AB, else twice the wrong entries
+    for N, bad in ((2, 0), (4, 0), (4, 3), (8, 5)):
+        inp, wrong = W.matmult_check_inputs(N, 9, bad)
+        V = O.evaluate(W.matmult_check_circuit(N), inp)
+        assert wrong == bad and int(V[0][0]) == 2 * wrong, (N, bad)
+
+
 def test_gate_counts_and_transcript_sizes():
     path = os.path.join(os.path.dirname(__file__), "golden", "table2_circuit_sizes.txt")
     for line in open(path):
         if line.startswith("#") or not line.strip():
             continue
         prob, logn, millions = line.split()
-        assert prob == "F2"
-        c = W.f2_circuit(1 << int(logn))
-        assert c.gates == 3 * (1 << int(logn)) - 1
-        assert round(c.gates / 1e6, 1) == float(millions)
+        if prob == "F2":
+            c = W.f2_circuit(1 << int(logn))
+            assert c.gates == 3 * (1 << int(logn)) - 1
+            assert round(c.gates / 1e6, 1) == float(millions)
+            continue
+        n = 1 << int(logn)
+        gates = {"F0": lambda: 122 * n - 1,  # the builder's count, checked below at small n
+                 "PM": lambda: W.pm_f0_circuit(n, 8).gates,
+                 "MM": lambda: W.matmult_check_circuit(n).gates}[prob]()
+        assert abs(gates / 1e6 - float(millions)) < 0.06, (prob, gates)
+    for n in (1, 2, 64, 1024):  # powers of two: a complete sum tree of n - 1 gates
+        assert W.f0_circuit(n).gates == 122 * n - 1
     assert W.matmult_circuit(256).gates == 2 * 256 ** 3 + 256 ** 2
     assert O.transcript_size(W.f2_circuit(1 << 10)) == (632, 196)
     assert O.transcript_size(W.f2_circuit(1 << 22)) == (2708, 826)

@@ -9,12 +9,17 @@ sizes of the workloads measured:
   PM:           text uniform in [0, 256), purpose 1; pattern = the q symbols
                 of the text at a position drawn from purpose 6, so at least
                 one occurrence exists
+  F0:           n frequencies uniform in [0, 16), purpose 1 (about one in
+                sixteen is zero)
+  MatMult-check: A, B as MatMult; C = AB, then `bad` entries (positions
+                from purpose 7) increased by one; inputs A, B, -C mod p
 """
 import math
 
 import numpy as np
 
-from .circuits import f2_circuit, matmult_circuit, pm_circuit
+from .circuits import (f2_circuit, matmult_circuit, pm_circuit, f0_circuit, pm_f0_circuit,
+                       matmult_check_circuit)
 from .prng import splitmix64, uniform_bits
 
 P = (1 << 61) - 1
@@ -82,3 +87,41 @@ def batch_mix(seed: int = 4, count: int = 64, f2_range=(12, 20), pm_range=(14, 1
             inp, _, _ = pm_inputs(n, pseed, q)
             out.append(("PM", pm_circuit(n, q), inp, pseed))
     return out
+
+
+def f0_inputs(n: int, seed: int, bits: int = 4) -> np.ndarray:
+    return uniform_bits(seed, 1, n, bits).astype(np.uint64)
+
+
+def matmult_check_inputs(N: int, seed: int, bad: int = 0):
+    """(input vector A, B, -C mod p; the number of entries where C != AB).
+    C = AB exactly (entries below 2^28), then `bad` distinct entries + 1."""
+    ab = matmult_inputs(N, seed)
+    A = ab[:N * N].reshape(N, N).astype(np.int64)
+    B = ab[N * N:].reshape(N, N).astype(np.int64)
+    C = (A @ B).reshape(-1)
+    wrong = 0
+    if bad:
+        pos = np.unique(splitmix64(seed, 7, 4 * bad) % np.uint64(N * N))[:bad].astype(np.int64)
+        C[pos] += 1
+        wrong = len(pos)
+    negC = (np.uint64(P) - C.astype(np.uint64)) % np.uint64(P)
+    return np.concatenate([ab, negC]).astype(np.uint64), wrong
+
+
+# Table 2's other three problems, built on the F0 (Fermat) stage.
+def f1_f0(log_n: int = 21):
+    """F0 GKR, n = 2^21 (Table 2: 2.1 million inputs), seed 6."""
+    n = 1 << log_n
+    return f0_circuit(n), f0_inputs(n, 6), 6
+
+
+def f1_pm_f0(log_n: int = 19, q: int = 8):
+    """Pattern matching with the F0 count, text 2^19 (Table 2: 524,288), q = 8, seed 7."""
+    n = 1 << log_n
+    return pm_f0_circuit(n, q), pm_inputs(n, 7, q)[0], 7
+
+
+def f1_matmult_check(N: int = 256):
+    """MatMult with the C = AB check, N = 256 (Table 2: 65,536 entries), seed 8."""
+    return matmult_check_circuit(N), matmult_check_inputs(N, 8)[0], 8

@@ -14,7 +14,7 @@ M1 = np.uint64(0xBF58476D1CE4E5B9)
 M2 = np.uint64(0x94D049BB133111EB)
 
 PURPOSE = {"data": 1, "gkr_chal": 2, "f2sc_data": 3, "f2sc_chal": 4,
-           "mix": 5, "pm_pos": 6}
+           "mix": 5, "pm_pos": 6, "bad_entries": 7}
 
 
 def splitmix64(seed: int, purpose: int, n: int, start: int = 0) -> np.ndarray:
