@@ -610,3 +610,115 @@ int or_f2sc_verify(const u32 *freq, u64 n, u64 seed, const u64 *msgs, u64 n_msgs
     *accepted = 1;
     return 0;
 }
+
+/* ------------------------------------- non-interactive F2 (Sec. 2.3, 3.2.2)
+ *
+ * The reading fixed for this build (the paper gives the protocol's outline
+ * only): the universe [n] is a v x h grid, v = ceil(n / h), cell (row y,
+ * column j) holding a_i for i = j v + y (zero for i >= n).  h divides
+ * (p - 1) / 2, so F_p has subgroups H of order h and G of order 2h, with
+ * generators w_h = g^((p-1)/h) and xi = g^((p-1)/(2h)), g = 37 a primitive
+ * root; xi^2 = w_h.  Row y is the polynomial f_y of degree < h with
+ * f_y(w_h^j) = a(j, y).  The proof is g(X) = sum_y f_y(X)^2 (degree
+ * <= 2h - 2) at the 2h points xi^k: even k are the data squared, odd k need
+ * f_y at the coset xi H.  The verifier's secret r (seed, purpose 9) gives
+ * f_y(r) for each row (v words while streaming); it accepts iff
+ * g(r) = sum_y f_y(r)^2, and F2 = sum_j g(w_h^j) = sum_j msgs[2j]. */
+
+#define NIF2_ROOT 37
+#define NIF2_PURPOSE 9
+
+static u64 nif2_root(u64 N) { return ((P - 1) % N) ? 0 : f_pow(NIF2_ROOT, (P - 1) / N); }
+u64 or_nif2_root(u64 N) { return nif2_root(N); }
+
+/* Lagrange basis of the subgroup {w^0, .., w^(N-1)} at x:
+ * L_j(x) = w^j (x^N - 1) / (N (x - w^j)); at x = w^m it is [j == m]. */
+static void subgroup_basis(u64 w, u64 N, u64 x, u64 *L) {
+    u64 xN = f_pow(x, N), wj = 1, hit = N;
+    for (u64 j = 0; j < N; j++, wj = f_mul(wj, w))
+        if (wj == x) hit = j;
+    if (hit < N) {
+        for (u64 j = 0; j < N; j++) L[j] = j == hit;
+        return;
+    }
+    wj = 1;
+    for (u64 j = 0; j < N; j++, wj = f_mul(wj, w))
+        L[j] = f_mul(f_mul(wj, f_sub(xN, 1)), f_inv(f_mul(N % P, f_sub(x, wj))));
+}
+
+static u64 cell(const u64 *a, u64 n, u64 v, u64 j, u64 y) {
+    const u64 i = j * v + y;
+    return i < n ? a[i] % P : 0;
+}
+
+typedef struct { const u64 *a; u64 n, h, v, xi; u64 *msgs; int t, T; } nif2_job;
+
+/* Odd message points k = 2m + 1, m = t, t + T, ...: f_y(xi^k) by the
+ * Lagrange formula, squared and summed over the rows. */
+static void *nif2_odd(void *p) {
+    nif2_job *J = (nif2_job *)p;
+    const u64 h = J->h, wh = nif2_root(h);
+    u64 *L = (u64 *)malloc(h * sizeof(u64));
+    for (u64 m = (u64)J->t; m < h; m += (u64)J->T) {
+        const u64 k = 2 * m + 1;
+        subgroup_basis(wh, h, f_pow(J->xi, k), L);
+        u64 g = 0;
+        for (u64 y = 0; y < J->v; y++) {
+            u64 fy = 0;
+            for (u64 j = 0; j < h; j++) fy = f_add(fy, f_mul(cell(J->a, J->n, J->v, j, y), L[j]));
+            g = f_add(g, f_mul(fy, fy));
+        }
+        J->msgs[k] = g;
+    }
+    free(L);
+    return NULL;
+}
+
+/* msgs[0 .. 2h): g(xi^k).  Returns -1 if h does not divide (p - 1) / 2. */
+int or_nif2_prove(const u64 *a, u64 n, u64 h, u64 *msgs) {
+    if (h < 1 || h % 2 == 0 || ((P - 1) / 2) % h) return -1;
+    const u64 v = (n + h - 1) / h, xi = nif2_root(2 * h);
+    for (u64 j = 0; j < h; j++) {  /* even points: the data */
+        u64 g = 0;
+        for (u64 y = 0; y < v; y++) g = f_add(g, f_mul(cell(a, n, v, j, y), cell(a, n, v, j, y)));
+        msgs[2 * j] = g;
+    }
+    int T = g_threads < 1 ? 1 : g_threads;
+    pthread_t th[256];
+    nif2_job jobs[256];
+    for (int t = 0; t < T; t++) {
+        jobs[t] = (nif2_job){a, n, h, v, xi, msgs, t, T};
+        pthread_create(&th[t], NULL, nif2_odd, &jobs[t]);
+    }
+    for (int t = 0; t < T; t++) pthread_join(th[t], NULL);
+    return 0;
+}
+
+/* The verifier: r from (seed, purpose 9); accepted iff g(r) (interpolated
+ * from the 2h points) equals sum_y f_y(r)^2.  f2 = sum_j msgs[2j]. */
+int or_nif2_verify(const u64 *a, u64 n, u64 h, u64 seed, const u64 *msgs, u64 n_msgs, int *accepted,
+                   u64 *f2) {
+    if (h < 1 || h % 2 == 0 || ((P - 1) / 2) % h) return -1;
+    *accepted = 0;
+    *f2 = 0;
+    if (n_msgs != 2 * h) return 0;
+    for (u64 k = 0; k < n_msgs; k++) if (msgs[k] >= P) return 0;
+    const u64 v = (n + h - 1) / h;
+    sm64 rng; sm_init(&rng, seed, NIF2_PURPOSE);
+    const u64 r = sm_field(&rng);
+    u64 *L = (u64 *)malloc(2 * h * sizeof(u64));
+    subgroup_basis(nif2_root(h), h, r, L);
+    u64 rhs = 0;
+    for (u64 y = 0; y < v; y++) {
+        u64 fy = 0;
+        for (u64 j = 0; j < h; j++) fy = f_add(fy, f_mul(cell(a, n, v, j, y), L[j]));
+        rhs = f_add(rhs, f_mul(fy, fy));
+    }
+    subgroup_basis(nif2_root(2 * h), 2 * h, r, L);
+    u64 gr = 0;
+    for (u64 k = 0; k < 2 * h; k++) gr = f_add(gr, f_mul(msgs[k], L[k]));
+    free(L);
+    for (u64 j = 0; j < h; j++) *f2 = f_add(*f2, msgs[2 * j]);
+    *accepted = gr == rhs;
+    return 0;
+}

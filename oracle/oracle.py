@@ -58,6 +58,11 @@ def lib():
         L.or_lagrange.argtypes = [u64p, C.c_uint32, C.c_uint64]
         L.or_transcript_size.argtypes = [C.c_uint32, u32p, C.POINTER(C.c_uint64),
                                          C.POINTER(C.c_uint64)]
+        L.or_nif2_root.restype = C.c_uint64
+        L.or_nif2_root.argtypes = [C.c_uint64]
+        L.or_nif2_prove.argtypes = [u64p, C.c_uint64, C.c_uint64, u64p]
+        L.or_nif2_verify.argtypes = [u64p, C.c_uint64, C.c_uint64, C.c_uint64, u64p, C.c_uint64,
+                                     C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
         _circ = [C.c_uint32, u32p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_check_circuit.argtypes = _circ
         L.or_evaluate.argtypes = _circ + [u64p, C.c_void_p]
@@ -215,3 +220,27 @@ def f2sc_verify(freq, seed, msgs):
     if rc:
         raise ValueError("n must be a power of two")
     return bool(acc.value), wr.value, wc.value
+
+
+# Non-interactive F2 (Sec. 2.3, 3.2.2): a v x h grid, proof g at 2h points.
+def nif2_root(N):
+    """Generator of the order-N subgroup of F_p^* (0 if N does not divide p - 1)."""
+    return int(lib().or_nif2_root(N))
+
+
+def nif2_prove(a, h):
+    a = np.ascontiguousarray(a, np.uint64)
+    msgs = np.zeros(2 * h, np.uint64)
+    if lib().or_nif2_prove(a, len(a), h, msgs) != 0:
+        raise ValueError("h must be odd and divide (p - 1) / 2")
+    return msgs
+
+
+def nif2_verify(a, h, seed, msgs):
+    """(accepted, F2 read from the proof)."""
+    a = np.ascontiguousarray(a, np.uint64)
+    m = np.ascontiguousarray(msgs, np.uint64)
+    acc, f2 = C.c_int(), C.c_uint64()
+    if lib().or_nif2_verify(a, len(a), h, seed, m, len(m), C.byref(acc), C.byref(f2)) != 0:
+        raise ValueError("h must be odd and divide (p - 1) / 2")
+    return bool(acc.value), int(f2.value)
