@@ -199,6 +199,53 @@ def table2_leg(G, W, np, torch, reps, with_oracle):
     return out
 
 
+# Table 3 (non-interactive F2, n = 25 million): the paper's (v space,
+# proof length, GPU prover seconds) per row; h here is the admissible row
+# length nearest the paper's (h must divide (p - 1) / 2).
+TABLE3 = [(5005, "39.1 KB / 78.1 KB", 2.901), (2475, "78.2 KB / 39.1 KB", 1.872),
+          (1287, "156.5 KB / 19.5 KB", 1.154), (585, "313.2 KB / 9.8 KB", 0.909),
+          (45, "1953.1 KB / 0.78 KB", 0.357)]
+
+
+def table3_leg(G, np, torch, reps, with_oracle):
+    """The non-interactive F2 protocol on n = 25 million values in [0, 2^16)
+    (seed 25) for Table 3's space / proof-length tradeoffs: prove and verify
+    times with the values resident in HBM, and the oracle on one grid."""
+    n = 25_000_000
+    rng = np.random.default_rng(25)
+    a = rng.integers(0, 1 << 16, n).astype(np.uint64)
+    at = torch.from_numpy(a.view(np.int64)).cuda().view(torch.uint64)
+    out = []
+    for h, tradeoff, paper_s in TABLE3:
+        m = G.nif2_prove(at, h)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            G.nif2_prove(at, h)
+        dt = (time.perf_counter() - t) / reps
+        t = time.perf_counter()
+        ok, _ = G.nif2_verify(at, h, 1, m)
+        tv = time.perf_counter() - t
+        v = -(-n // h)
+        out.append({"h": h, "v": v, "proof_words": 2 * h, "paper_tradeoff": tradeoff,
+                    "prove_ms": dt * 1e3, "values_per_s": n / dt, "verify_ms": tv * 1e3,
+                    "accepted": bool(ok), "paper_gpu_prove_s": paper_s})
+    res = {"n": n, "data": "uniform in [0, 2^16), seed 25", "rows": out}
+    if with_oracle:
+        from oracle import oracle as O
+        O.build(force=False)
+        threads = max(1, min(16, os.cpu_count() or 1))
+        O.set_threads(threads)
+        h, v = 1287, 64
+        t = time.perf_counter()
+        O.nif2_prove(a[:h * v], h)
+        to = time.perf_counter() - t
+        res["oracle"] = {"values_per_s": h * v / to, "cores": threads,
+                         "sample": f"the {h * v} first values on a {v} x {h} grid in {to:.2f} s "
+                                   "(direct Lagrange evaluation, O(h^2 v))"}
+    return res
+
+
 def batch_leg(G, W, np, torch, reps, tune):
     """64 uneven proofs (F2 n log-uniform in [2^12, 2^20], PM text in
     [2^14, 2^18], seed 4): the plain path proves them one by one, the
@@ -376,6 +423,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-table2", action="store_true",
                     help="skip the F0, PM-F0 and MatMult-check circuits at Table 2's sizes")
+    ap.add_argument("--no-table3", action="store_true",
+                    help="skip the non-interactive F2 protocol at Table 3's size")
     ap.add_argument("--autotune", choices=["auto", "off", "force"], default="auto",
                     help="auto: load the saved launch-shape table if it matches the kernel "
                          "sources, else tune on the benchmark circuit; off: default shapes; "
@@ -525,6 +574,8 @@ def main():
         line["served"] = serve_leg(G, W, np, args.serve_requests, 200, rates)
     if not args.no_table2:
         line["table2_circuits"] = table2_leg(G, W, np, torch, 3, not args.no_cpu_baseline)
+    if not args.no_table3:
+        line["table3_noninteractive_f2"] = table3_leg(G, np, torch, 5, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_log_n)
     print(json.dumps(line), flush=True)

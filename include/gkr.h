@@ -217,6 +217,30 @@ int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_device, uint64_t
                        const uint64_t *msgs, uint64_t n_msgs, int *accepted,
                        gkr_reject_info *why, void *hip_stream);
 
+/* Non-interactive F2 (Sec. 2.3 and 3.2.2; GPU version Sec. 4.2; Table 3):
+ * a streaming verifier keeping v field words, a proof of 2h words.  The n
+ * values a (each below p; host, or device if on_device) fill a v x h grid,
+ * v = ceil(n / h), cell (row y, column j) = a[j v + y] (zero past n).  h
+ * must be odd, divide (p - 1) / 2 and have prime factors among 3, 5, 7, 11,
+ * 13 with 3 and 5 at most squared (e.g. 45, 585, 1287, 2475, 5005).  Row y
+ * is the polynomial f_y of degree < h through the order-h subgroup of
+ * F_p^* (generator 37^((p-1)/h)); the proof msgs[k] = sum_y f_y(xi^k)^2,
+ * k < 2h, xi = 37^((p-1)/(2h)), so F2 = sum_j msgs[2j].  msgs: 2h words,
+ * caller-owned host memory.  Errors: GKR_ERR_INVALID (NULL, n = 0,
+ * unsupported h), GKR_ERR_RANGE (a value not below p), GKR_ERR_DEVICE. */
+int nif2_prove(const uint64_t *a, uint64_t n, uint32_t h, int on_device, uint64_t *msgs,
+               void *hip_stream);
+
+/* The verifier: its secret r is drawn from SplitMix64 (seed, purpose 9)
+ * before the stream is read; it keeps f_y(r) for every row and accepts iff
+ * the polynomial through the 2h proof values equals sum_y f_y(r)^2 at r.
+ * *f2 (may be NULL) receives sum_j msgs[2j].  A proof of the wrong length
+ * or with a value not below p is rejected (*accepted = 0, GKR_OK).
+ * Errors: as nif2_prove. */
+int nif2_verify(const uint64_t *a, uint64_t n, uint32_t h, int on_device, uint64_t seed,
+                const uint64_t *msgs, uint64_t n_msgs, int *accepted, uint64_t *f2,
+                void *hip_stream);
+
 /* F_p arithmetic on the device field module (Sec. 5.1), for checking it:
  * out[k] = a[k] op b[k], op 0 = add, 1 = sub, 2 = mul; op 3 = the sum of
  * the 64 products a[j] b[j], j = k, k+1, ..., k+63 (indices mod n),

@@ -51,6 +51,9 @@ _SIGS = [
     ("f2_sumcheck_verify", C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_uint64, C.c_void_p,
                                      C.c_uint64, C.POINTER(C.c_int), C.POINTER(RejectInfo),
                                      C.c_void_p]),
+    ("nif2_prove", C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int, C.c_void_p, C.c_void_p]),
+    ("nif2_verify", C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int, C.c_uint64, C.c_void_p,
+                              C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.c_void_p]),
     ("gkr_batch_prove", C.c_int, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                   C.c_void_p, C.c_int, C.c_void_p]),
     ("gkr_server_create", C.c_int, [C.c_uint64, C.c_uint32, C.POINTER(C.c_void_p)]),
@@ -317,6 +320,27 @@ def f2_sumcheck_verify(freq, seed: int, msgs, stream=None):
     _check(lib().f2_sumcheck_verify(p, n, dev, seed, m.ctypes.data if len(m) else None, len(m),
                                     C.byref(acc), C.byref(why), _stream(dev, stream)))
     return bool(acc.value), why.round, why.check
+
+
+def nif2_prove(a, h: int, stream=None):
+    """Proof (2h words) of the non-interactive F2 protocol for the values a
+    (uint64 array or device tensor, each below p) on a v x h grid."""
+    p, dev, keep = _ptr(a, np.uint64)
+    n = a.numel() if _is_torch(a) else len(keep)
+    msgs = np.zeros(2 * h, np.uint64)
+    _check(lib().nif2_prove(p, n, h, dev, msgs.ctypes.data, _stream(dev, stream)))
+    return msgs
+
+
+def nif2_verify(a, h: int, seed: int, msgs, stream=None):
+    """(accepted, F2 read from the proof)."""
+    p, dev, keep = _ptr(a, np.uint64)
+    n = a.numel() if _is_torch(a) else len(keep)
+    m = np.ascontiguousarray(msgs, np.uint64)
+    acc, f2 = C.c_int(), C.c_uint64()
+    _check(lib().nif2_verify(p, n, h, dev, seed, m.ctypes.data if len(m) else None, len(m),
+                             C.byref(acc), C.byref(f2), _stream(dev, stream)))
+    return bool(acc.value), int(f2.value)
 
 
 def gkr_field_op(op: int, a, b, out, stream=None):

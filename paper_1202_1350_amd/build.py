@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgkr.so")
-SOURCES = ["kernels.hip", "steps.hip", "gkr.hip"]
+SOURCES = ["kernels.hip", "steps.hip", "gkr.hip", "nif2.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions are generated anywhere in the library

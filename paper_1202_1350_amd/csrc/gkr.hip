@@ -28,6 +28,7 @@
 #include "fp61.hpp"
 #include "kernels.hpp"
 #include "steps.hpp"
+#include "nif2.hpp"
 
 using namespace gkr;
 
@@ -58,13 +59,13 @@ namespace {
 // then the verifier's and the F2 sum-check's kernels.
 enum ProfClass {
     PC_STEP = 0,  // + StepKind
-    PC_WIRING = 18, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_COUNT
+    PC_WIRING = 18, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {
     "step_eval", "step_start", "step_eq", "step_p", "step_w", "step_fold", "step_lt",
     "step_line", "step_sge", "step_end", "step_wagg", "step_wt0", "step_wt", "step_wtail",
     "step_ptail", "step_load", "step_wa0", "step_finish", "wiring", "mle", "eq_tables", "f2sc_round",
-    "f2sc_final", "misc", "batch_step"};
+    "f2sc_final", "misc", "batch_step", "nif2"};
 static_assert(ST_FINISH + 1 == PC_WIRING, "one profiling class per step kind");
 
 struct ProfRec {
@@ -2396,4 +2397,203 @@ extern "C" void gkr_server_destroy(gkr_server *s) {
     for (auto &e : s->ring) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(s->st);
     delete s;
+}
+
+// ------------------------------------------------- non-interactive F2
+
+namespace {
+
+struct Nif2Scratch {
+    std::mutex mu;
+    int device = -1;
+    void *mem = nullptr;
+    size_t cap = 0;
+    u64 *h = nullptr;  // pinned: the proof and two verifier values
+    size_t h_cap = 0;
+} g_nif2;
+
+int nif2_reserve(size_t bytes, size_t host_words) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (g_nif2.device != dev || g_nif2.cap < bytes) {
+        if (g_nif2.mem) (void)hipFree(g_nif2.mem);
+        g_nif2.mem = nullptr;
+        g_nif2.cap = 0;
+        HIP_TRY(hipMalloc(&g_nif2.mem, bytes));
+        g_nif2.cap = bytes;
+        g_nif2.device = dev;
+    }
+    if (g_nif2.h_cap < host_words) {
+        if (g_nif2.h) (void)hipHostFree(g_nif2.h);
+        g_nif2.h = nullptr;
+        g_nif2.h_cap = 0;
+        HIP_TRY(hipHostMalloc((void **)&g_nif2.h, host_words * 8));
+        g_nif2.h_cap = host_words;
+    }
+    return GKR_OK;
+}
+
+constexpr u64 NIF2_ROOT = 37;     // a primitive root of F_p
+constexpr u64 NIF2_PURPOSE = 9;   // SplitMix64 stream of the verifier's secret
+
+// h = product of coprime prime powers among 3, 9, 5, 25, 7, 11, 13 (each a
+// supported DFT length); w generates the order-h subgroup.
+int nif2_plan(u32 h, PfaPlan &pl) {
+    if (h < 3 || h % 2 == 0 || ((fp::P - 1) / 2) % h)
+        return fail(GKR_ERR_INVALID, "h must be odd, at least 3, and divide (p - 1) / 2");
+    memset(&pl, 0, sizeof pl);
+    pl.h = h;
+    u32 rest = h;
+    for (u32 q : {3u, 5u, 7u, 11u, 13u}) {
+        u32 f = 1;
+        while (rest % q == 0) {
+            rest /= q;
+            f *= q;
+        }
+        if (f > 1) pl.F[pl.nf++] = f;
+    }
+    if (rest != 1)
+        return fail(GKR_ERR_INVALID, "h's prime factors must be among 3, 5, 7, 11, 13 (3 and 5 at most squared)");
+    const u64 w = fp::pow(NIF2_ROOT, (fp::P - 1) / h);
+    u32 stride = 1;
+    for (u32 i = 0; i < pl.nf; i++) {
+        const u32 F = pl.F[i], g = h / F;
+        pl.stride[i] = stride;
+        stride *= F;
+        pl.gstep[i] = g;
+        u32 gi = 1;
+        while ((u64)g * gi % F != 1) gi++;
+        pl.ginv[i] = gi;
+        pl.cstep[i] = (u32)((u64)g * gi % h);  // 1 mod F, 0 mod the other factors
+        pl.wfwd[i] = fp::pow(w, g);
+        pl.winv[i] = fp::inv(pl.wfwd[i]);
+    }
+    return GKR_OK;
+}
+
+// Host inputs below p (checked here) copied to dst, or device inputs
+// range-checked into *flag.
+int nif2_inputs(const uint64_t *a, u64 n, int on_device, u64 *dst, u32 *flag, hipStream_t st,
+                const u64 **src) {
+    HIP_TRY(hipMemsetAsync(flag, 0, 4, st));
+    if (on_device) {
+        LAUNCH(PC_NIF2, n * 8.0, launch_nif2_range(st, a, n, flag));
+        *src = a;
+        return GKR_OK;
+    }
+    for (u64 i = 0; i < n; i++)
+        if (a[i] >= fp::P) return fail(GKR_ERR_RANGE, "input value not below p");
+    HIP_TRY(hipMemcpyAsync(dst, a, n * 8, hipMemcpyHostToDevice, st));
+    *src = dst;
+    return GKR_OK;
+}
+
+}  // namespace
+
+extern "C" int nif2_prove(const uint64_t *a, uint64_t n, uint32_t h, int on_device, uint64_t *msgs,
+                          void *hip_stream) {
+    if (!a || !msgs || n == 0) return fail(GKR_ERR_INVALID, "NULL argument or n = 0");
+    PfaPlan pl;
+    int rc = nif2_plan(h, pl);
+    if (rc) return rc;
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    const u64 v = (n + h - 1) / h;
+    std::lock_guard<std::mutex> lk(g_nif2.mu);
+    struct {
+        u64 *W, *tw, *in, *msgs, *part;
+        u32 *flag;
+    } b;
+    auto lay = [&](Arena &ar) {
+        b.W = ar.take<u64>((u64)h * v);
+        b.part = ar.take<u64>(2ull * h * nif2_colsum_split(h, v));
+        b.tw = ar.take<u64>(h);
+        b.in = ar.take<u64>(on_device ? 1 : n);
+        b.msgs = ar.take<u64>(2ull * h);
+        b.flag = ar.take<u32>(1);
+    };
+    Arena sz;
+    lay(sz);
+    rc = nif2_reserve(sz.used, 2ull * h + 1);
+    if (rc) return rc;
+    Arena ar;
+    ar.base = (char *)g_nif2.mem;
+    lay(ar);
+    const u64 *src = nullptr;
+    rc = nif2_inputs(a, n, on_device, b.in, b.flag, st, &src);
+    if (rc) return rc;
+    const u64 xi = fp::pow(NIF2_ROOT, (fp::P - 1) / (2ull * h));
+    LAUNCH(PC_NIF2, h * 8.0, launch_nif2_twist(st, h, xi, b.tw));
+    LAUNCH(PC_NIF2, (double)h * v * 8 * 2 * 2 * pl.nf, launch_nif2_transform(st, pl, src, n, v, b.tw, b.W));
+    LAUNCH(PC_NIF2, (double)h * v * 16, launch_nif2_colsum(st, pl, src, n, v, b.W, b.part, b.msgs));
+    HIP_TRY(hipMemcpyAsync(g_nif2.h, b.msgs, 2ull * h * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(g_nif2.h + 2ull * h, b.flag, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (*(const u32 *)(g_nif2.h + 2ull * h)) return fail(GKR_ERR_RANGE, "input value not below p");
+    memcpy(msgs, g_nif2.h, 2ull * h * 8);
+    return GKR_OK;
+}
+
+extern "C" int nif2_verify(const uint64_t *a, uint64_t n, uint32_t h, int on_device, uint64_t seed,
+                           const uint64_t *msgs, uint64_t n_msgs, int *accepted, uint64_t *f2,
+                           void *hip_stream) {
+    if (!a || !accepted || n == 0) return fail(GKR_ERR_INVALID, "NULL argument or n = 0");
+    PfaPlan pl;
+    int rc = nif2_plan(h, pl);
+    if (rc) return rc;
+    *accepted = 0;
+    if (f2) *f2 = 0;
+    if (n_msgs != 2ull * h || !msgs) return GKR_OK;
+    for (u64 k = 0; k < n_msgs; k++)
+        if (msgs[k] >= fp::P) return GKR_OK;
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    const u64 v = (n + h - 1) / h;
+    const u32 nch = (h + 31) / 32;
+    std::lock_guard<std::mutex> lk(g_nif2.mu);
+    struct {
+        u64 *L, *L2, *part, *blk, *out, *in, *msgs;
+        u32 *flag;
+    } b;
+    auto lay = [&](Arena &ar) {
+        b.L = ar.take<u64>(h);
+        b.L2 = ar.take<u64>(2ull * h);
+        b.part = ar.take<u64>((u64)nch * v);
+        b.blk = ar.take<u64>(1024);
+        b.out = ar.take<u64>(2);
+        b.in = ar.take<u64>(on_device ? 1 : n);
+        b.msgs = ar.take<u64>(2ull * h);
+        b.flag = ar.take<u32>(1);
+    };
+    Arena sz;
+    lay(sz);
+    rc = nif2_reserve(sz.used, 2ull * h + 3);
+    if (rc) return rc;
+    Arena ar;
+    ar.base = (char *)g_nif2.mem;
+    lay(ar);
+    const u64 *src = nullptr;
+    rc = nif2_inputs(a, n, on_device, b.in, b.flag, st, &src);
+    if (rc) return rc;
+    // the secret point, drawn before the stream is read
+    u64 rs = fp::sm_state(seed, NIF2_PURPOSE);
+    const u64 r = fp::sm_field(rs);
+    const u64 w = fp::pow(NIF2_ROOT, (fp::P - 1) / h), xi = fp::pow(NIF2_ROOT, (fp::P - 1) / (2ull * h));
+    memcpy(g_nif2.h, msgs, 2ull * h * 8);
+    HIP_TRY(hipMemcpyAsync(b.msgs, g_nif2.h, 2ull * h * 8, hipMemcpyHostToDevice, st));
+    LAUNCH(PC_NIF2, h * 8.0, launch_nif2_basis(st, w, h, r, b.L));
+    LAUNCH(PC_NIF2, n * 8.0 + (double)nch * v * 16, launch_nif2_rows(st, src, n, v, h, b.L, b.part, b.blk, b.out));
+    LAUNCH(PC_NIF2, 2.0 * h * 8, launch_nif2_basis(st, xi, 2ull * h, r, b.L2));
+    LAUNCH(PC_NIF2, 2.0 * h * 16, launch_nif2_dot(st, b.msgs, b.L2, 2ull * h, b.blk, b.out + 1));
+    HIP_TRY(hipMemcpyAsync(g_nif2.h, b.out, 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(g_nif2.h + 2, b.flag, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (*(const u32 *)(g_nif2.h + 2)) return fail(GKR_ERR_RANGE, "input value not below p");
+    *accepted = g_nif2.h[0] == g_nif2.h[1];
+    if (f2) {
+        u64 s = 0;
+        for (u64 j = 0; j < h; j++) s = fp::add(s, msgs[2 * j]);
+        *f2 = s;
+    }
+    return GKR_OK;
 }
