@@ -158,6 +158,14 @@ struct TailIn {
 
 __device__ __forceinline__ u64 fold1(u64 x0, u64 x1, u64 r) { return add(x0, mul(r, sub(x1, x0))); }
 
+// fold1(fold1(x0, x1, r0), fold1(x2, x3, r0), r1) = x0 + r0 (x1 - x0) +
+// r1 (x2 - x0) + r0 r1 ((x3 - x2) - (x1 - x0)), summed in 128 bits
+// (< 2^124) and reduced once; r01 = r0 r1.
+__device__ __forceinline__ u64 fold2(u64 x0, u64 x1, u64 x2, u64 x3, u64 r0, u64 r1, u64 r01) {
+    const u64 d1 = sub(x1, x0), d2 = sub(x2, x0), d3 = sub(sub(x3, x2), d1);
+    return fp::red128((u128)x0 + fp::wide(r0, d1) + fp::wide(r1, d2) + fp::wide(r01, d3));
+}
+
 // Value t of a p-phase message from the two sums: G(0) = C (1-z) S0,
 // G(1) = C z S1, G(2) = C (3z - 1)(2 S1 - S0); t is chosen per lane.
 __device__ __forceinline__ u64 p_value(u32 t, u64 C, u64 z, u64 S0, u64 S1) {
@@ -377,7 +385,7 @@ __device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
         return;
     }
     u64 x = 0, y = 0;  // this lane's sums (see p_quad)
-    const u64 r0 = c.r, r1 = c.r2;
+    const u64 r0 = c.r, r1 = c.r2, r01 = mul(r0, r1);
     // lanes g = 4u + j; the stride is a multiple of 4, so a quad's lanes
     // leave the loop together
     for (u64 g = c.gtid; (g >> 2) < a.nu; g += c.gstride) {
@@ -389,7 +397,7 @@ __device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
             bq = beta0(2 * u + (j >> 1));  // lanes 0, 1: B_0[2u]; lanes 2, 3: B_0[2u+1]
         } else {
             const u64x2 p = ld2(a.Vsrc, 4 * g), q = ld2(a.Vsrc, 4 * g + 2);
-            v = fold1(fold1(p.x, p.y, r0), fold1(q.x, q.y, r0), r1);
+            v = fold2(p.x, p.y, q.x, q.y, r0, r1, r01);
             if (a.Vout) a.Vout[g] = v;
             bq = a.Bprev[g];  // B_{j+1}[4u + j]
         }
@@ -678,15 +686,16 @@ __device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC
         C3 = quad_get<3>(C);
     }
     const u32 t = j < 3 ? j : 2;
-    // round k at t: pairs (X0, X1) and (X2, X3)
-    const u64 g = add(add(mul(at_t(A0, A1, t), at_t(F0, F1, t)), at_t(C0, C1, t)),
-                      add(mul(at_t(A2, A3, t), at_t(F2, F3, t)), at_t(C2, C3, t)));
+    // round k at t: pairs (X0, X1) and (X2, X3); products summed in 128 bits
+    // and reduced once per value
+    const u64 g = fp::red128(fp::wide(at_t(A0, A1, t), at_t(F0, F1, t)) +
+                             fp::wide(at_t(A2, A3, t), at_t(F2, F3, t)) + at_t(C0, C1, t) + at_t(C2, C3, t));
     // round k+1's coefficients at t
     const u64 aA = at_t(A0, A2, t), bA = at_t(sub(A1, A0), sub(A3, A2), t);
     const u64 aF = at_t(F0, F2, t), bF = at_t(sub(F1, F0), sub(F3, F2), t);
     const u64 aC = at_t(C0, C2, t), bC = at_t(sub(C1, C0), sub(C3, C2), t);
     const u64 q0 = add(mul(aA, aF), aC);
-    const u64 q1 = add(add(mul(aA, bF), mul(bA, aF)), bC);
+    const u64 q1 = fp::red128(fp::wide(aA, bF) + fp::wide(bA, aF) + bC);
     const u64 q2 = mul(bA, bF);
     const bool on = j < 3;
     acc.g = add(acc.g, on ? g : 0);
@@ -781,7 +790,7 @@ __device__ void step_wa0(const Wa0Args &a, const ProofPtrs &pp, const Ctx &c, u6
 }
 
 __device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
-    const u64 r0 = c.r, r1 = c.r2;
+    const u64 r0 = c.r, r1 = c.r2, r01 = mul(r0, r1);
     QuadAcc acc;
     const u32 pend = a.pend;
     auto foldp = [&](const u64 *X, u64 g) {  // level-(k+pend) entry g from level k
@@ -790,7 +799,7 @@ __device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
             return fold1(p.x, p.y, r0);
         }
         const u64x2 p = ld2(X, 4 * g), q = ld2(X, 4 * g + 2);
-        return fold1(fold1(p.x, p.y, r0), fold1(q.x, q.y, r0), r1);
+        return fold2(p.x, p.y, q.x, q.y, r0, r1, r01);
     };
     // lane g = entry 4u + j of level k+pend (the stride is a multiple of 4)
     for (u64 g = c.gtid; (g >> 2) < a.nu; g += c.gstride) {
@@ -880,7 +889,7 @@ __device__ __forceinline__ u64 tail_entry(const u64 *X, u32 e, u32 pend, const C
         return fold1(p.x, p.y, c.r);
     }
     const u64x2 p = ld2(X, 4 * e), q = ld2(X, 4 * e + 2);
-    return fold1(fold1(p.x, p.y, c.r), fold1(q.x, q.y, c.r), c.r2);
+    return fold2(p.x, p.y, q.x, q.y, c.r, c.r2, mul(c.r, c.r2));
 }
 
 // RNG state of the tail's first round: the prologue drew the pending
