@@ -229,9 +229,6 @@ void line_shape(u32 sp, u32 *L, u32 *M, u32 *H) {
 
 // ------------------------------------------------------------------ circuit
 
-// Scratch of one proof on a circuit: the layer tables, the per-round tables
-// of the sum-checks, the transcript, and the step program (descriptors and
-// one-job launch entries) with every pointer bound to this scratch.
 // ------------------------------------------------------------ launch shapes
 //
 // A grid step over `units` work items launches ceil(units / (SBLOCK q))
@@ -284,6 +281,9 @@ u32 grid_for(u32 kind, u64 units, u32 qdef) {
     return (u32)std::max<u64>(1, std::min<u64>(b, 1ull << caplog));
 }
 
+// Scratch of one proof on a circuit: the layer tables, the per-round tables
+// of the sum-checks, the transcript, and the step program (descriptors and
+// one-job launch entries) with every pointer bound to this scratch.
 struct Workspace {
     void *mem = nullptr;
     std::vector<u64 *> V;  // per layer, 2^{s_i} values

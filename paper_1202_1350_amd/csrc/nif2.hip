@@ -71,12 +71,41 @@ __global__ void __launch_bounds__(NT) k_pfa_pass(const PassArgs pa, const u64 *_
 #pragma unroll
             for (int m = 0; m < F; m++) x[m] = W[(base + m * s) * v + y];
         }
+        if constexpr (F == 25) {
+            // 25 = 5 x 5: n = 5 n1 + n2, k = k1 + 5 k2, w^{nk} = u^{n1 k1} w^{n2 k1} u^{n2 k2}
+            // with u = w^5: five 5-point DFTs over n1 (in place), twiddles w^{n2 k1},
+            // five 5-point DFTs over n2 written out
 #pragma unroll
-        for (int k = 0; k < F; k++) {
-            u128 acc = 0;
+            for (int n2 = 0; n2 < 5; n2++) {
+                u64 t[5];
 #pragma unroll
-            for (int m = 0; m < F; m++) acc += fp::wide(x[m], pa.wp[(m * k) % F]);  // F < 32 terms < 2^127
-            W[(base + k * s) * v + y] = fp::red128(acc);
+                for (int k1 = 0; k1 < 5; k1++) {
+                    u128 acc = 0;
+#pragma unroll
+                    for (int n1 = 0; n1 < 5; n1++) acc += fp::wide(x[5 * n1 + n2], pa.wp[(5 * n1 * k1) % 25]);
+                    t[k1] = fp::red128(acc);
+                }
+#pragma unroll
+                for (int k1 = 0; k1 < 5; k1++) x[5 * k1 + n2] = (n2 * k1) ? mul(t[k1], pa.wp[n2 * k1]) : t[k1];
+            }
+#pragma unroll
+            for (int k1 = 0; k1 < 5; k1++) {
+#pragma unroll
+                for (int k2 = 0; k2 < 5; k2++) {
+                    u128 acc = 0;
+#pragma unroll
+                    for (int n2 = 0; n2 < 5; n2++) acc += fp::wide(x[5 * k1 + n2], pa.wp[(5 * n2 * k2) % 25]);
+                    W[(base + (k1 + 5 * k2) * s) * v + y] = fp::red128(acc);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < F; k++) {
+                u128 acc = 0;
+#pragma unroll
+                for (int m = 0; m < F; m++) acc += fp::wide(x[m], pa.wp[(m * k) % F]);  // F < 32 terms < 2^127
+                W[(base + k * s) * v + y] = fp::red128(acc);
+            }
         }
     }
 }

@@ -38,16 +38,6 @@ __device__ __forceinline__ u64 dpp64(u64 v) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(u32)(v >> 32), CTRL, ROWS, 0xf, true);
     return ((u64)(u32)hi << 32) | (u64)(u32)lo;
 }
-__device__ __forceinline__ u64 down64(u64 v, u32 d) {
-    const int lo = __shfl_down((int)(u32)v, d), hi = __shfl_down((int)(u32)(v >> 32), d);
-    return ((u64)(u32)hi << 32) | (u64)(u32)lo;
-}
-__device__ __forceinline__ u64 lane63(u64 v) {
-    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, 63);
-    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(v >> 32), 63);
-    return ((u64)hi << 32) | lo;
-}
-
 // Value of lane Q of this lane's quad (lanes 4m..4m+3).
 template <int Q>
 __device__ __forceinline__ u64 quad_get(u64 v) {
