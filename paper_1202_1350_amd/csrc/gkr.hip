@@ -704,8 +704,26 @@ struct Planner {
             u64 *msg = w ? w->msgs + c->mo[i] : nullptr;
             u64 *chals = w ? w->chals : nullptr;
             u64 *vslot = w ? msg + 3ull * n : nullptr;  // v1, v2, then h(2..s')
+            // A p-phase whose table fits a tail runs whole in one workgroup:
+            // the tail starts at round 0 from V_i, forms the suffix weights
+            // B_0 from z itself and carries the previous layer's finish.
+            const bool ptail_only = s > 0 && (1ull << s) <= (u64)TAIL_LIM;
+            if (ptail_only) {
+                StepDesc &st = add(ST_PTAIL, 1, 8.0 * (1ull << s));
+                st.fin = layer_end;
+                PtailArgs pt;
+                memset(&pt, 0, sizeof pt);
+                pt.j0 = 0;
+                pt.s = s;
+                pt.pend = 0;
+                pt.V = V(i);
+                pt.B = nullptr;  // B_0 from z
+                pt.c0 = co;
+                pt.msg = msg;
+                st.u.ptail = pt;
+            }
             // ---- eq tables of z_i[1..s) for the p-phase's first round
-            {
+            if (!ptail_only) {
                 const u32 nz = s ? s - 1 : 0;
                 const u64 ne = (1ull << (nz / 2)) + (1ull << (nz - nz / 2));
                 StepDesc &e = addg(ST_EQ, ne, 1, 8.0 * ne);
@@ -716,7 +734,7 @@ struct Planner {
             // large, then the remaining rounds in one workgroup.  The first
             // step does round 0 (and round 1's coefficients); a step reading
             // V^(j) does rounds j+2, j+3; the tail starts at round j0.
-            if (s > 0) {
+            if (s > 0 && !ptail_only) {
                 const bool look = s >= 2;
                 u32 j0 = 1;
                 if (look) j0 = s > 12 ? ((s - 10 + 1) & ~1u) : 2;  // even, 2^(s - j0) <= TAIL_LIM

@@ -874,6 +874,7 @@ __device__ __forceinline__ u64 line_at(u64 x0, u64 x1) {
 // Entry e of the level a tail starts from, folded from memory by the
 // pending challenge(s) of the prologue.
 __device__ __forceinline__ u64 tail_entry(const u64 *X, u32 e, u32 pend, const Ctx &c) {
+    if (pend == 0) return X[e];
     if (pend == 1) {
         const u64x2 p = ld2(X, 2 * e);
         return fold1(p.x, p.y, c.r);
@@ -1096,12 +1097,22 @@ __device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx c,
     const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
     u32 n = 1u << (a.s - a.j0);  // entries of V^(j0), at most TAIL_LIM
     for (u32 e = tid; e < n; e += SBLOCK) tv[e] = tail_entry(a.V, e, a.pend, c);
-    for (u32 m = tid; m < n / 2; m += SBLOCK) {  // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1]
-        const u64x2 pb = ld2(a.B, 2 * m);
-        tb[m] = add(pb.x, pb.y);
-    }
     const u32 rounds = a.s - a.j0;
     const u64 zr = lane < rounds ? pp.zbuf[a.j0 + lane] : 0;  // z_{j0 + l} in lane l
+    if (a.B) {
+        for (u32 m = tid; m < n / 2; m += SBLOCK) {  // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1]
+            const u64x2 pb = ld2(a.B, 2 * m);
+            tb[m] = add(pb.x, pb.y);
+        }
+    } else {
+        // j0 = 0: B_0[m] = prod_{k=1}^{s-1} eq(bit k-1 of m, z_k), the weights of
+        // z's suffix (the p-phase's first round pairs V entries 2m, 2m+1)
+        for (u32 m = tid; m < n / 2; m += SBLOCK) {
+            u64 b = 1;
+            for (u32 k = 1; k < a.s; k++) b = mul(b, fp::eqbit((m >> (k - 1)) & 1, lane_value(zr, k)));
+            tb[m] = b;
+        }
+    }
     if (!have_c && tid == 0) s_c = pp.state[0];
     u64 st = tail_state(pp, a.c0, drew, st0);
     __syncthreads();
@@ -1237,6 +1248,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
             ti.have_c = 1;
             ti.C = s_c;
         }
+        if ((fin_mask(KIND) & (1u << FIN_LINE)) && f.kind == FIN_LINE) __syncthreads();  // z_{i+1} stored
     }
 
     // --- body

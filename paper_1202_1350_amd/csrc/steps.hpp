@@ -82,7 +82,7 @@ constexpr u32 KALL = 0xFFFF;  // kind resolved at run time (mixed batches)
 __host__ __device__ constexpr u32 fin_mask(u32 kind) {
     return kind == KALL                              ? 0xFFu
            : kind == ST_P                            ? 1u << FIN_P2
-           : kind == ST_PTAIL                        ? (1u << FIN_P) | (1u << FIN_P2)
+           : kind == ST_PTAIL                        ? (1u << FIN_P) | (1u << FIN_P2) | (1u << FIN_LINE)
            : kind == ST_WT                           ? (1u << FIN_T) | (1u << FIN_T2)
            : kind == ST_WTAIL                        ? (1u << FIN_T) | (1u << FIN_T2)
            : kind == ST_EQ                           ? (1u << FIN_LINE) | (1u << FIN_W)
@@ -281,8 +281,9 @@ struct WtailArgs {
 };
 struct PtailArgs {
     u32 j0, s;
-    u32 pend;                // challenges the prologue drew (1 or 2)
-    const u64 *V, *B;        // V^(j0-pend) (2^{s-j0+pend}) and B_{j0-1} (2^{s-j0})
+    u32 pend;                // challenges the prologue drew (1 or 2; 0 when j0 = 0)
+    const u64 *V, *B;        // V^(j0-pend) (2^{s-j0+pend}) and B_{j0-1} (2^{s-j0});
+                             // j0 = 0: V_i, and B NULL (B_0 is formed from z)
     u32 c0;                  // challenge index of round j0
     u64 *msg;                // message slot of round j0
 };
