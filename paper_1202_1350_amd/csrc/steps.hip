@@ -219,7 +219,7 @@ __device__ void fin_inline(const StepDesc &sd, const Ctx &c, const u64 *s_pt, u6
 // One item of ST_FINISH: a round's rows into its message, lanes t < 3 (and
 // 3..5 for a second message) writing one value each; operands that do not
 // depend on the rows are loaded before the row sums.
-__device__ void step_finish(const FinishArgs &a, const Ctx &c) {
+__device__ __forceinline__ void step_finish(const FinishArgs &a, const Ctx &c) {
     const FinItem &it = a.items[c.lb];
     const u32 tid = threadIdx.x;
     switch (it.kind) {
@@ -579,7 +579,7 @@ __device__ void line_sums(const LineArgs &a, const Ctx &c, u64 *row) {
     block_store<LINE_CHUNK>(acc, row);
 }
 
-__device__ void step_line(const LineArgs &a, const Ctx &c, u64 *row) {
+__device__ __forceinline__ void step_line(const LineArgs &a, const Ctx &c, u64 *row) {
     switch (a.ch) {
         case 4: line_sums<4>(a, c, row); break;
         case 8: line_sums<8>(a, c, row); break;
@@ -951,7 +951,7 @@ __device__ __forceinline__ void wtail_narrow(const u64 *X, u64 *Y, u32 half, u32
 // Remaining omega rounds k0..s'-1 over A, C, F.  The prologue drew the
 // pending challenge(s) up to r_{k0-1}; each round writes its message, then
 // records its challenge; after the last fold F holds v1 (or v2).
-__device__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0) {
+__device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0) {
     __shared__ u64 s_part[3][NWAVES];
     u64 *tab = tail_lds();
     const u32 tid = threadIdx.x, lane = tid & 63;
@@ -1087,7 +1087,7 @@ __device__ __forceinline__ void ptail_narrow(const u64 *V, const u64 *B, u64 *Vn
 // a-coordinates not yet reached (beta over z's suffix); pair m of V goes
 // with B[m].  Round j's message is G(t) = C eq_t(z_j) S_t with eq_t(z) the
 // line through (0, 1 - z), (1, z): 1 - z, z, 3z - 1 at t = 0, 1, 2.
-__device__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0, u32 have_c,
+__device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0, u32 have_c,
                            u64 C0) {
     __shared__ u64 s_c;
     __shared__ u64 s_part[3][NWAVES];
