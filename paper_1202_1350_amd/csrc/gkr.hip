@@ -59,14 +59,14 @@ namespace {
 // then the verifier's and the F2 sum-check's kernels.
 enum ProfClass {
     PC_STEP = 0,  // + StepKind
-    PC_WIRING = 18, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_COUNT
+    PC_WIRING = 19, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {
     "step_eval", "step_start", "step_eq", "step_p", "step_w", "step_fold", "step_lt",
     "step_line", "step_sge", "step_end", "step_wagg", "step_wt0", "step_wt", "step_wtail",
-    "step_ptail", "step_load", "step_wa0", "step_finish", "wiring", "mle", "eq_tables", "f2sc_round",
+    "step_ptail", "step_load", "step_wa0", "step_finish", "step_wsmall", "wiring", "mle", "eq_tables", "f2sc_round",
     "f2sc_final", "misc", "batch_step", "nif2"};
-static_assert(ST_FINISH + 1 == PC_WIRING, "one profiling class per step kind");
+static_assert(ST_WSMALL + 1 == PC_WIRING, "one profiling class per step kind");
 
 struct ProfRec {
     int cls;
@@ -797,8 +797,13 @@ struct Planner {
                 pt.msg = w ? msg + 3ull * j0 : nullptr;
                 st.u.ptail = pt;
             }
+            // A small layer whose wires each carry one chunk of gates runs each
+            // omega phase in one workgroup (ST_WSMALL), which also forms the
+            // eq table of the phase's point.
+            const bool wsmall = c->omega_algo == GKR_OMEGA_TABLES && sp >= 1 &&
+                                (1ull << sp) <= (u64)TAIL_LIM && c->grp[0][i].single && c->grp[1][i].single;
             // ---- eq tables of a* (the p-phase tail recorded every challenge)
-            {
+            if (!wsmall) {
                 const u32 La = s / 2;
                 const u64 ne = (1ull << La) + (1ull << (s - La));
                 StepDesc &e = addg(ST_EQ, ne, 1, 8.0 * ne);
@@ -828,6 +833,43 @@ struct Planner {
                 // starts at round 1; otherwise a step folding once gives round 1
                 // and round 2's coefficients, steps folding twice follow, and
                 // the tail starts at an odd round k0 >= 3 (2^(s' - k0) <= TAIL_LIM).
+                if (wsmall) {
+                    for (u32 ph = 1; ph <= 2; ph++) {
+                        const u32 rbase = s + (ph == 2 ? sp : 0);
+                        const gkr_circuit::Group *dg = &c->grp[ph - 1][i];
+                        WsmallArgs a;
+                        memset(&a, 0, sizeof a);
+                        a.w.kind = kind;
+                        a.w.ph = ph;
+                        a.w.hasC = kind != KIND_MUL;
+                        a.w.npairs = (1ull << sp) / 2;
+                        a.w.perm = dg->perm;
+                        a.w.rowptr = dg->rowptr;
+                        a.w.oths = dg->oths;
+                        a.w.types = dg->types;
+                        a.w.Vn = V(i + 1);
+                        a.w.alo = w ? w->alo : nullptr;
+                        a.w.ahi = w ? w->ahi : nullptr;
+                        a.w.La = s / 2;
+                        a.w.blo = w ? w->blo : nullptr;
+                        a.w.bhi = w ? w->bhi : nullptr;
+                        a.w.Lb = sp / 2;
+                        a.eqn = ph == 1 ? s : sp;
+                        a.eqL = ph == 1 ? s / 2 : sp / 2;
+                        a.eqbase = ph == 1 ? co : co + s;
+                        a.eqlo = ph == 1 ? (w ? w->alo : nullptr) : (w ? w->blo : nullptr);
+                        a.eqhi = ph == 1 ? (w ? w->ahi : nullptr) : (w ? w->bhi : nullptr);
+                        a.sp = sp;
+                        a.last = ph;
+                        a.c0 = co + rbase;
+                        a.msg = w ? msg + 3ull * rbase : nullptr;
+                        a.vout = vslot ? vslot + (ph - 1) : nullptr;
+                        // eq entries 8, per gate sorted index 4 + other 4 + operand 8, per wire F 8
+                        const u64 ne = (1ull << (a.eqn / 2)) + (1ull << (a.eqn - a.eqn / 2));
+                        StepDesc &st = add(ST_WSMALL, 1, 8.0 * ne + 16.0 * S + 16.0 * (1ull << sp));
+                        st.u.wsmall = a;
+                    }
+                } else {
                 const u64 N = 1ull << sp;
                 u32 k0 = 1;
                 if (sp > 11) k0 = std::max<u32>(3, (sp - 10) | 1u);
@@ -976,6 +1018,7 @@ struct Planner {
                         st.u.wtail = a;
                     }
                 }
+                }  // small layer or not
                 // ---- line step (a9): every omega challenge is recorded
                 StepDesc &e = addg(ST_LT, ntab, 1, 8.0 * ntab);
                 e.u.lt = LtArgs{sp >= 2 ? sp : 0, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,

@@ -179,7 +179,7 @@ __device__ __forceinline__ u64 pick(const u64 (&tot)[K], u32 k) {
 // at the end of an omega phase folds the last pair into v1 / v2; the line
 // finish stores z_{i+1}.
 template <u32 KIND>
-__device__ void fin_inline(const StepDesc &sd, const Ctx &c, const u64 *s_pt, u64 *s_c) {
+__device__ __forceinline__ void fin_inline(const StepDesc &sd, const Ctx &c, const u64 *s_pt, u64 *s_c) {
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
     constexpr u32 FM = fin_mask(KIND);
@@ -283,7 +283,7 @@ __device__ __forceinline__ void step_finish(const FinishArgs &a, const Ctx &c) {
 
 // ------------------------------------------------------------ step bodies
 
-__device__ void step_load(const LoadArgs &a, const ProofPtrs &pp, const Ctx &c) {
+__device__ __forceinline__ void step_load(const LoadArgs &a, const ProofPtrs &pp, const Ctx &c) {
     const u64 *src = reinterpret_cast<const u64 *>(pp.state[3]);
     u64 bad = 0;
     for (u64 g = c.gtid; g < a.npad; g += c.gstride) {
@@ -297,7 +297,7 @@ __device__ void step_load(const LoadArgs &a, const ProofPtrs &pp, const Ctx &c) 
     if (bad) atomicOr(reinterpret_cast<unsigned long long *>(pp.state + 4), 1ull);
 }
 
-__device__ void step_eval(const EvalArgs &a, const Ctx &c) {
+__device__ __forceinline__ void step_eval(const EvalArgs &a, const Ctx &c) {
     for (u64 g = c.gtid; g < a.npad; g += c.gstride) {
         u64 v = 0;
         if (g < a.S) {
@@ -309,7 +309,7 @@ __device__ void step_eval(const EvalArgs &a, const Ctx &c) {
     }
 }
 
-__device__ void step_start(const StartArgs &a, const ProofPtrs &pp, const Ctx &c) {
+__device__ __forceinline__ void step_start(const StartArgs &a, const ProofPtrs &pp, const Ctx &c) {
     if (c.lb == 0 && threadIdx.x == 0) {
         u64 st = fp::sm_state(pp.state[2], fp::PURPOSE_GKR);  // state[2] = seed
         pp.rngst[0] = st;
@@ -325,7 +325,7 @@ __device__ void step_start(const StartArgs &a, const ProofPtrs &pp, const Ctx &c
     for (u64 g = c.gtid; g < a.S0; g += c.gstride) pp.msgs[g] = a.V0[g];
 }
 
-__device__ void step_eq(const EqArgs &a, const Ctx &c, const u64 *pt) {
+__device__ __forceinline__ void step_eq(const EqArgs &a, const Ctx &c, const u64 *pt) {
     const u64 nlo = 1ull << a.L, nhi = 1ull << (a.n - a.L);
     for (u64 x = c.gtid; x < nlo + nhi; x += c.gstride) {
         if (x < nlo)
@@ -359,7 +359,7 @@ __device__ __forceinline__ void p_quad(u32 j, u64 v0, u64 v1, u64 v2, u64 v3, u6
     y = add(y, s ? 0 : p2);
 }
 
-__device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
+__device__ __forceinline__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
     const u64 mask = (1ull << a.L) - 1;
     auto beta0 = [&](u64 m) { return mul(a.zlo[m & mask], a.zhi[m >> a.L]); };  // B_0[m]
     if (a.first && !a.look) {
@@ -419,7 +419,7 @@ __device__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
 // bit 1 adds P1 at t=1 and 4 P1 - 2 P0 at t=2.  The row holds (E0, E1)
 // = sums of (P0, P1) over bit-0 gates and (O0, O1) over bit-1 gates.
 template <int KIND, int PH>
-__device__ void step_w(const WArgs &a, const Ctx &c, const ProofPtrs &pp, u64 *row) {
+__device__ __forceinline__ void step_w(const WArgs &a, const Ctx &c, const ProofPtrs &pp, u64 *row) {
     const bool init = a.init, inl = a.inline_fold, wr = a.write_w;
     u64 r = 0, omr = 0;
     if (!init) {
@@ -486,7 +486,7 @@ __device__ void step_w(const WArgs &a, const Ctx &c, const ProofPtrs &pp, u64 *r
     block_store<4>(acc, row);
 }
 
-__device__ void step_fold(const FoldArgs &a, const Ctx &c) {
+__device__ __forceinline__ void step_fold(const FoldArgs &a, const Ctx &c) {
     const u64 r = c.r;
     for (u64 m = c.gtid; m < a.nh; m += c.gstride) {
         const u64x2 p = ld2(a.src, 2 * m);
@@ -497,7 +497,7 @@ __device__ void step_fold(const FoldArgs &a, const Ctx &c) {
 // Line step (a9).  h(t) = ~V_{i+1}(l(t)) for t = 2..s', l(t) = b* + t (c* - b*).
 // x = (hh 2^M + mid) 2^L + lane: chi_x(l(t)) = Hh_t[hh] Hl_t[mid] lo_t[lane].
 // Tables: lo [T][2^L], hl [T][2^M], hh [2^H][T].
-__device__ void step_lt(const LtArgs &a, const Ctx &c, const u64 *bstar, const u64 *cstar) {
+__device__ __forceinline__ void step_lt(const LtArgs &a, const Ctx &c, const u64 *bstar, const u64 *cstar) {
     if (a.sp < 2) return;  // no line points
     const u32 T = a.sp - 1, H = a.sp - a.L - a.M;
     const u64 nlo = 1ull << a.L, nhl = 1ull << a.M, nhh = 1ull << H;
@@ -627,7 +627,7 @@ __device__ __forceinline__ void wire_sums(const Args &a, u64 beta, u32 p0, u32 p
     sC_out = sC;
 }
 
-__device__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp, const Ctx &c) {
+__device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp, const Ctx &c) {
     const u64 beta = pp.state[0];  // beta(z, a*)
     for (u64 ch = c.gtid; ch < a.nch; ch += c.gstride) {
         u64 sA, sC;
@@ -761,7 +761,7 @@ __device__ __forceinline__ void level0_round(u32 ph, u32 hasC, u64 npairs, const
     block_store<3>(acc, row);
 }
 
-__device__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
+__device__ __forceinline__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
     level0_round(a.ph, a.hasC, a.npairs, a.F, a.A, a.C, pp, c, row, [&](u64 x, u64 &sA, u64 &sC) {
         sA = 0;
         sC = 0;
@@ -772,14 +772,14 @@ __device__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, const Ctx &c, u6
     });
 }
 
-__device__ void step_wa0(const Wa0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
+__device__ __forceinline__ void step_wa0(const Wa0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
     const u64 beta = pp.state[0];
     level0_round(a.ph, a.hasC, a.npairs, a.Vn, a.A, a.C, pp, c, row, [&](u64 x, u64 &sA, u64 &sC) {
         wire_sums(a, beta, a.rowptr[x], a.rowptr[x + 1], sA, sC);
     });
 }
 
-__device__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
+__device__ __forceinline__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
     const u64 r0 = c.r, r1 = c.r2, r01 = mul(r0, r1);
     QuadAcc acc;
     const u32 pend = a.pend;
@@ -951,21 +951,15 @@ __device__ __forceinline__ void wtail_narrow(const u64 *X, u64 *Y, u32 half, u32
 // Remaining omega rounds k0..s'-1 over A, C, F.  The prologue drew the
 // pending challenge(s) up to r_{k0-1}; each round writes its message, then
 // records its challenge; after the last fold F holds v1 (or v2).
-__device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0) {
+// The rounds of an omega tail over tables in LDS (the first level in area
+// 0, n entries): messages to msg, challenges c0, c0 + 1, ... recorded with
+// the RNG states after them; F's last entry is v1 (last = 1) or v2.
+__device__ __forceinline__ void wtail_rounds(u64 *tab, u32 n, bool hc, u64 st, u64 *msgp, u32 c0, u32 last,
+                                             u64 *vout, const ProofPtrs &pp) {
     __shared__ u64 s_part[3][NWAVES];
-    u64 *tab = tail_lds();
     const u32 tid = threadIdx.x, lane = tid & 63;
     const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
-    const bool hc = a.hasC != 0;
-    u32 n = 1u << (a.sp - a.k0);  // entries of level k0, at most TAIL_LIM
-    for (u32 e = tid; e < n; e += SBLOCK) {
-        tab[e] = tail_entry(a.A, e, a.pend, c);
-        if (hc) tab[TAIL_TAB + e] = tail_entry(a.C, e, a.pend, c);
-        tab[2 * TAIL_TAB + e] = tail_entry(a.F, e, a.pend, c);
-    }
-    u64 st = tail_state(pp, a.c0, drew, st0);
-    __syncthreads();
-    u32 k = 0;  // rounds done; level k0 + k sits in area k & 1
+    u32 k = 0;  // rounds done; level k sits in area k & 1
     for (; n > 1; n >>= 1, k++) {
         const u64 *X = tab + ((k & 1) ? TAIL_LIM : 0);
         u64 *Y = tab + ((k & 1) ? 0 : TAIL_LIM);
@@ -986,11 +980,11 @@ __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &
                 for (int q = 0; q < 3; q++) s_part[q][w] = t[q];
             }
             __syncthreads();
-            if (w < 3 && lane == 0) a.msg[3 * k + w] = waves_total(s_part, (int)w);
+            if (w < 3 && lane == 0) msgp[3 * k + w] = waves_total(s_part, (int)w);
             const u64 r = fp::sm_field(st);
             if (tid == 0) {
-                pp.chals[a.c0 + k] = r;
-                pp.rngst[a.c0 + k + 1] = st;
+                pp.chals[c0 + k] = r;
+                pp.rngst[c0 + k + 1] = st;
             }
             if (tid < half) {
                 Y[tid] = fold1(pa.x, pa.y, r);
@@ -998,7 +992,7 @@ __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &
                 if (hc) Y[TAIL_TAB + tid] = fold1(pc.x, pc.y, r);
             }
         } else if (w < 3) {
-            u64 *msg = a.msg + 3 * k + w, *chal = pp.chals + a.c0 + k, *stn = pp.rngst + a.c0 + k + 1;
+            u64 *msg = msgp + 3 * k + w, *chal = pp.chals + c0 + k, *stn = pp.rngst + c0 + k + 1;
             if (w == 0) wtail_narrow<0>(X, Y, half, lane, hc, st, msg, chal, stn);
             else if (w == 1) wtail_narrow<1>(X, Y, half, lane, hc, st, msg, chal, stn);
             else wtail_narrow<2>(X, Y, half, lane, hc, st, msg, chal, stn);
@@ -1007,9 +1001,60 @@ __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &
     }
     if (tid == 0) {
         const u64 v = tab[2 * TAIL_TAB + ((k & 1) ? TAIL_LIM : 0)];
-        *a.vout = v;
-        if (a.last == 1) pp.state[1] = v;
+        *vout = v;
+        if (last == 1) pp.state[1] = v;
     }
+}
+
+__device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0) {
+    u64 *tab = tail_lds();
+    const u32 tid = threadIdx.x;
+    const bool hc = a.hasC != 0;
+    const u32 n = 1u << (a.sp - a.k0);  // entries of level k0, at most TAIL_LIM
+    for (u32 e = tid; e < n; e += SBLOCK) {
+        tab[e] = tail_entry(a.A, e, a.pend, c);
+        if (hc) tab[TAIL_TAB + e] = tail_entry(a.C, e, a.pend, c);
+        tab[2 * TAIL_TAB + e] = tail_entry(a.F, e, a.pend, c);
+    }
+    const u64 st = tail_state(pp, a.c0, drew, st0);
+    __syncthreads();
+    wtail_rounds(tab, n, hc, st, a.msg, a.c0, a.last, a.vout, pp);
+}
+
+// A whole omega phase of a small layer in one workgroup: the eq table of
+// the phase's point (a* in phase 1, b* in phase 2) into the workspace, the
+// level-0 tables from the wiring (as ST_WA0 forms them) into LDS, then
+// every round as a tail.
+__device__ __forceinline__ void step_wsmall(const WsmallArgs &a, const ProofPtrs &pp, const Ctx c) {
+    u64 *tab = tail_lds();
+    const u32 tid = threadIdx.x;
+    {
+        const u64 *pt = pp.chals + a.eqbase;
+        const u64 nlo = 1ull << a.eqL, nhi = 1ull << (a.eqn - a.eqL);
+        for (u64 x = tid; x < nlo + nhi; x += SBLOCK) {
+            if (x < nlo)
+                a.eqlo[x] = chi_bits(x, pt, a.eqL);
+            else
+                a.eqhi[x - nlo] = chi_bits(x - nlo, pt + a.eqL, a.eqn - a.eqL);
+        }
+    }
+    __syncthreads();  // the eq table is read back by this workgroup
+    const Wa0Args &w = a.w;
+    const bool hc = w.hasC != 0;
+    const u64 beta = pp.state[0], v1 = w.ph == 2 ? pp.state[1] : 0;
+    const u32 n = 1u << a.sp;
+    for (u32 x = tid; x < n; x += SBLOCK) {
+        u64 sA, sC, A, C;
+        wire_sums(w, beta, w.rowptr[x], w.rowptr[x + 1], sA, sC);
+        level0(w.ph, v1, sA, sC, A, C);
+        tab[x] = A;
+        if (hc) tab[TAIL_TAB + x] = C;
+        tab[2 * TAIL_TAB + x] = w.Vn[x];
+    }
+    const u64 st = tail_state(pp, a.c0, 0, 0);
+    __syncthreads();
+    wtail_rounds(tab, n, hc, st, a.msg, a.c0, a.last, a.vout, pp);
+    (void)c;
 }
 
 // eq_T(z): the line through (0, 1 - z), (1, z) at t = T.
@@ -1180,7 +1225,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
     const u32 kind = KIND == KALL ? sd.kind : KIND;
-    const bool tail = kind == ST_WTAIL || kind == ST_PTAIL;  // one workgroup does everything
+    const bool tail = kind == ST_WTAIL || kind == ST_PTAIL || kind == ST_WSMALL;  // one workgroup does everything
     const bool has_fin = f.kind != FIN_NONE;
     const bool split = has_fin && !tail;  // workgroup nblocks finishes, the others run the body
     const bool fin_block = split && lb == sd.nblocks;
@@ -1237,12 +1282,11 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         s_pt[threadIdx.x] = ci == f.draw ? c.r : pp.chals[ci];
     }
     __syncthreads();
-    if (fin_block) {
+    if (fin_block || (tail && has_fin)) {
         fin_inline<KIND>(sd, c, s_pt, &s_c);
-        return;
+        if (fin_block) return;
     }
     if (tail && has_fin) {
-        fin_inline<KIND>(sd, c, s_pt, &s_c);
         if (kind == ST_PTAIL && (f.kind == FIN_P || f.kind == FIN_P2)) {
             __syncthreads();
             ti.have_c = 1;
@@ -1286,6 +1330,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_WTAIL: step_wtail(sd.u.wtail, pp, c, ti.drew, ti.st); break;
         case ST_PTAIL: step_ptail(sd.u.ptail, pp, c, ti.drew, ti.st, ti.have_c, ti.C); break;
         case ST_FINISH: step_finish(sd.u.finish, c); break;
+        case ST_WSMALL: step_wsmall(sd.u.wsmall, pp, c); break;
         case ST_SGE:
             if (c.lb == 0 && threadIdx.x == 0) {
                 const u64 v = sd.u.sge.Vn[0];
@@ -1334,7 +1379,7 @@ hipError_t launch_step_table(hipStream_t st, const JobTable &t) {
 }
 
 u32 step_grid(const StepDesc &sd) {
-    if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL) return 1;
+    if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL || sd.kind == ST_WSMALL) return 1;
     return sd.nblocks + (sd.fin.kind != FIN_NONE ? 1 : 0);
 }
 
@@ -1367,6 +1412,7 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_WTAIL: L1(ST_WTAIL); break;
         case ST_PTAIL: L1(ST_PTAIL); break;
         case ST_FINISH: L1(ST_FINISH); break;
+        case ST_WSMALL: L1(ST_WSMALL); break;
         default: L1(ST_END); break;
     }
 #undef L1

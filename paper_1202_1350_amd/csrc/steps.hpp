@@ -55,6 +55,7 @@ enum StepKind : u32 {
     ST_WA0,        // omega phase, tables: ST_WAGG and ST_WT0 in one pass, for
                    // layers whose wires each carry at most one chunk of gates
     ST_FINISH,     // every round's rows into its message values
+    ST_WSMALL,     // omega phase of a small layer: eq table, level-0 tables, all rounds
 };
 
 enum FinKind : u32 {
@@ -288,6 +289,17 @@ struct PtailArgs {
     u64 *msg;                // message slot of round j0
 };
 
+// A small layer's whole omega phase in one workgroup: w as for ST_WA0
+// (its eq table pointers are where this step writes the table of the
+// phase's point), then rounds 0 .. sp-1 as a tail.
+struct WsmallArgs {
+    Wa0Args w;
+    u32 eqn, eqL, eqbase;  // the point: coordinates, lo-table coordinates, challenge index
+    u64 *eqlo, *eqhi;
+    u32 sp, last, c0;       // last = phase (1: v1 into state[1]); c0: challenge index of round 0
+    u64 *msg, *vout;
+};
+
 struct StepDesc {
     u32 kind;
     u32 nblocks;
@@ -314,6 +326,7 @@ struct StepDesc {
         LoadArgs load;
         Wa0Args wa0;
         FinishArgs finish;
+        WsmallArgs wsmall;
     } u;
 };
 
