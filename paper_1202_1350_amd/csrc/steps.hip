@@ -806,28 +806,42 @@ __device__ __forceinline__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row)
 
 // ------------------------------------------------------------------ tails
 //
-// A tail runs the last rounds of a phase in one workgroup.  The level the
-// tail starts from is folded from memory into LDS; each round reads level
-// l from one of two LDS areas and writes level l + 1 to the other (the
-// second area half as large), so a round costs one barrier.  Value t of a
-// round's message is a sum over pairs of a term taken at t, and wave t
-// computes it alone: three waves produce the three values side by side,
-// each with its own wave reduction, then each folds one table.  No value
-// crosses waves inside a round.  The challenge stream is uniform, so it
-// runs on the scalar unit of every wave; the message never depends on the
-// challenge, so the fold is computed alongside the message's reduction.
-// The other waves load and join the barriers.
+// A tail runs the last rounds of a phase in one workgroup, over tables in
+// LDS.  Every level of a table is kept, as a binary tree: with n = 2^L
+// entries in level 0, level k (n_k = n >> k entries) sits at
+// [2n - 2 n_k, 2n - n_k), so pair m of level k is the tail's pair
+// q = n - n_k + m, it holds entries 2q, 2q + 1 and it folds into entry
+// n + q.  The challenges never depend on the messages, so the folds run
+// ahead of them: while a level has more than TAIL_WIDE entries every thread
+// folds one pair of every table and adds its message terms into 64-pair
+// chunk sums (one barrier a round); the remaining levels are folded by one
+// wave per table with no barrier at all, since each lane reads only what
+// lanes of its own wave wrote.  Their messages are summed afterwards, for
+// all rounds at once: those pairs fill at most two waves, and a DPP
+// reduction over runs of lanes gives each round its own sum.  Another wave
+// draws the challenges again, records them and (p-phase) forms the beta
+// prefixes while the folds run.
 
-constexpr int TAIL_TAB = TAIL_LIM + TAIL_LIM / 2;  // LDS entries per table
-// Rounds with at least this many pairs run wide: thread m takes pair m of
-// every table and all three values, the waves' sums meet in LDS (a second
-// barrier), and the folds are spread the same way.
-constexpr u32 WIDE_HALF = 256;
+constexpr int TAIL_TAB = 2 * TAIL_LIM;           // LDS entries per table: all levels
+constexpr u32 TAIL_WIDE = 128;                   // larger levels fold with every thread
+constexpr int TAIL_LOG = 10;                     // log2(TAIL_LIM): rounds of a tail
+constexpr int TAIL_CHUNKS = TAIL_LIM / 64;       // 64-pair chunks of a tail
+constexpr int TAIL_SLOTS = TAIL_CHUNKS + TAIL_LOG;  // chunk sums, then the small rounds' sums
+static_assert((1 << TAIL_LOG) == TAIL_LIM, "TAIL_LOG");
 static_assert(TAIL_LIM / 2 <= SBLOCK, "a wide round gives every pair a thread");
+static_assert(NWAVES >= 4, "three folding waves and a challenge wave");
 
 __device__ __forceinline__ u64 *tail_lds() {
     __shared__ __align__(16) u64 t[3 * TAIL_TAB];
     return t;
+}
+
+// Partial message sums of a tail, per value t: chunk c's sum in slot c
+// (rounds of at least 64 pairs), round k's sum in slot TAIL_CHUNKS + k
+// (rounds of fewer).
+__device__ __forceinline__ u64 (*tail_parts())[TAIL_SLOTS] {
+    __shared__ u64 p[3][TAIL_SLOTS];
+    return p;
 }
 
 // A value every lane holds the same copy of, moved to scalar registers.
@@ -840,6 +854,15 @@ __device__ __forceinline__ u64 lane_value(u64 v, u32 l) {  // l uniform
     const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, l);
     const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(v >> 32), l);
     return ((u64)hi << 32) | lo;
+}
+
+// Orders this wave's LDS writes before its later LDS reads of them by other
+// lanes of the wave: a wave's LDS operations complete in order, and the
+// fences keep the compiler from moving them across.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Sum over the wave of field elements, left in lane 63: as wave_sum63, but
@@ -856,13 +879,68 @@ __device__ __forceinline__ u64 wave_sum63_lazy(u64 v) {
     return fp::canon(fp::fold64(v));
 }
 
-// Total of the k-th value over the workgroup's waves, from the partial sums
-// lane 63 of each wave left in part[k].
-__device__ __forceinline__ u64 waves_total(const u64 (*part)[NWAVES], int k) {
-    u64 t = part[k][0];
+// Sum of field elements over each aligned run of s lanes (s a power of two,
+// at most 32, the same on every lane of a run), left in the run's last
+// lane.  Steps below a lane's run length add its partner in the run: lane
+// l ^ 1, l ^ 2, then the mirrored lane in the 8-lane half row and in the
+// row (the partial sums are uniform over the aligned groups by then), then
+// lane 15 of the row below into rows 1 and 3.  Lazy as wave_sum63_lazy.
+__device__ __forceinline__ u64 run_sum(u64 v, u32 s) {
+    u64 x = dpp64<0xb1, 0xf>(v);  // quad_perm [1, 0, 3, 2]
+    if (s >= 2) v += x;
+    x = dpp64<0x4e, 0xf>(v);  // quad_perm [2, 3, 0, 1]
+    if (s >= 4) v += x;
+    x = dpp64<0x141, 0xf>(v);  // row_half_mirror
+    if (s >= 8) v += x;
+    v = fp::canon(fp::fold64(v));
+    x = dpp64<0x140, 0xf>(v);  // row_mirror
+    if (s >= 16) v += x;
+    x = dpp64<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+    if (s >= 32) v += x;
+    return fp::canon(fp::fold64(v));
+}
+
+// Round of the tail's pair q (q <= n - 2): the pairs of round k are
+// [n - n_k, n - n_k / 2), so n - 1 - q lies in [n_k / 2, n_k).
+__device__ __forceinline__ u32 round_of(u32 q, u32 n, u32 L) {
+    return L - 1 - (31 - (u32)__builtin_clz((n - 1 - q) | 1));
+}
+
+// Adds a wave's three message terms (pair q = 64 c + lane, zero beyond the
+// last pair) into the partial sums: a chunk inside one round as one sum per
+// value, the chunk of the rounds with fewer than 64 pairs as one sum per
+// round.  c is wave-uniform.
+__device__ __forceinline__ void chunk_sums(u64 (&t)[3], u32 c, u32 lane, u32 n, u32 L) {
+    u64 (*mp)[TAIL_SLOTS] = tail_parts();
+    if ((n >> (round_of(64 * c, n, L) + 1)) >= 64) {
 #pragma unroll
-    for (int w = 1; w < NWAVES; w++) t = add(t, part[k][w]);
-    return t;
+        for (int i = 0; i < 3; i++) t[i] = wave_sum63_lazy(t[i]);
+        if (lane == 63) {
+#pragma unroll
+            for (int i = 0; i < 3; i++) mp[i][c] = t[i];
+        }
+        return;
+    }
+    const u32 q = 64 * c + lane;
+    const bool on = q < n - 1;
+    const u32 k = on ? round_of(q, n, L) : 0;
+    const u32 s = on ? n >> (k + 1) : 1;
+#pragma unroll
+    for (int i = 0; i < 3; i++) t[i] = run_sum(t[i], s);
+    if (on && (q & (s - 1)) == s - 1) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) mp[i][TAIL_CHUNKS + k] = t[i];
+    }
+}
+
+// Value t of round k's message sum from the partials.
+__device__ __forceinline__ u64 tail_sum(u32 n, u32 k, u32 t) {
+    const u64 (*mp)[TAIL_SLOTS] = tail_parts();
+    const u32 half = n >> (k + 1);
+    if (half < 64) return mp[t][TAIL_CHUNKS + k];
+    u64 s = 0;
+    for (u32 c = (n - 2 * half) >> 6; c < (n - half) >> 6; c++) s = add(s, mp[t][c]);
+    return s;
 }
 
 // X at t = T on the line through (0, x0), (1, x1).
@@ -893,118 +971,90 @@ __device__ __forceinline__ u64 tail_state(const ProofPtrs &pp, u32 c0, u32 drew,
     return uniform(s_st);
 }
 
-// Narrow round of an omega tail, wave T: message value T and table T's
-// fold.  With at most 64 pairs a lane keeps its pair in registers.
-template <int T>
-__device__ __forceinline__ void wtail_narrow(const u64 *X, u64 *Y, u32 half, u32 lane, bool hc, u64 &st,
-                                             u64 *msg, u64 *chal, u64 *stn) {
-    if (half <= 64) {
-        const bool on = lane < half;
-        u64x2 pa = {0, 0}, pc = {0, 0}, pf = {0, 0};
-        if (on) {
-            pa = ld2(X, 2 * lane);
-            pf = ld2(X + 2 * TAIL_TAB, 2 * lane);
-            if (hc) pc = ld2(X + TAIL_TAB, 2 * lane);
-        }
-        const u64 term = add(mul(line_at<T>(pa.x, pa.y), line_at<T>(pf.x, pf.y)), line_at<T>(pc.x, pc.y));
+// Records the challenges of rounds 0..L-1 of a tail, drawn from the state
+// st before its first round, with the states after them.
+__device__ __forceinline__ void record_chals(u64 st, u32 L, u32 lane, u32 c0, const ProofPtrs &pp) {
+    for (u32 j = 0; j < L; j++) {
         const u64 r = fp::sm_field(st);
-        const u64x2 own = T == 0 ? pa : (T == 1 ? pc : pf);
-        const u64 fv = fold1(own.x, own.y, r);
-        const u64 s = wave_sum63_lazy(term);
-        if (lane == 63) {
-            *msg = s;
-            if (T == 0) {
-                *chal = r;
-                *stn = st;
-            }
-        }
-        if (on && (T != 1 || hc)) Y[T * TAIL_TAB + lane] = fv;
-        return;
-    }
-    u64 s = 0;
-    for (u32 m = lane; m < half; m += 64) {
-        const u64x2 pa = ld2(X, 2 * m), pf = ld2(X + 2 * TAIL_TAB, 2 * m);
-        u64 ct = 0;
-        if (hc) {
-            const u64x2 pc = ld2(X + TAIL_TAB, 2 * m);
-            ct = line_at<T>(pc.x, pc.y);
-        }
-        s = add(s, add(mul(line_at<T>(pa.x, pa.y), line_at<T>(pf.x, pf.y)), ct));
-    }
-    s = wave_sum63_lazy(s);
-    const u64 r = fp::sm_field(st);
-    if (lane == 63) {
-        *msg = s;
-        if (T == 0) {
-            *chal = r;
-            *stn = st;
-        }
-    }
-    if (T != 1 || hc) {
-        for (u32 m = lane; m < half; m += 64) {
-            const u64x2 p = ld2(X + T * TAIL_TAB, 2 * m);
-            Y[T * TAIL_TAB + m] = fold1(p.x, p.y, r);
+        if (lane == 0) {
+            pp.chals[c0 + j] = r;
+            pp.rngst[c0 + j + 1] = st;
         }
     }
 }
 
-// Remaining omega rounds k0..s'-1 over A, C, F.  The prologue drew the
-// pending challenge(s) up to r_{k0-1}; each round writes its message, then
-// records its challenge; after the last fold F holds v1 (or v2).
-// The rounds of an omega tail over tables in LDS (the first level in area
-// 0, n entries): messages to msg, challenges c0, c0 + 1, ... recorded with
-// the RNG states after them; F's last entry is v1 (last = 1) or v2.
+// The rounds of an omega tail over tables A, C, F in LDS (level 0 of each,
+// n entries, at the start of its area): messages to msgp, challenges c0,
+// c0 + 1, ... recorded with the RNG states after them; F's last entry is
+// v1 (last = 1) or v2.  Round k's message is, at t = 0, 1, 2, the sum over
+// its pairs of A_t F_t + C_t with X_t the line through the pair.
 __device__ __forceinline__ void wtail_rounds(u64 *tab, u32 n, bool hc, u64 st, u64 *msgp, u32 c0, u32 last,
                                              u64 *vout, const ProofPtrs &pp) {
-    __shared__ u64 s_part[3][NWAVES];
     const u32 tid = threadIdx.x, lane = tid & 63;
     const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
-    u32 k = 0;  // rounds done; level k sits in area k & 1
-    for (; n > 1; n >>= 1, k++) {
-        const u64 *X = tab + ((k & 1) ? TAIL_LIM : 0);
-        u64 *Y = tab + ((k & 1) ? 0 : TAIL_LIM);
-        const u32 half = n >> 1;
-        if (half >= WIDE_HALF) {
-            u64x2 pa = {0, 0}, pc = {0, 0}, pf = {0, 0};
+    const u32 L = 31 - (u32)__builtin_clz(n);
+    u64 *A = tab, *Ct = tab + TAIL_TAB, *F = tab + 2 * TAIL_TAB;
+    const u64 st0 = st;
+    u32 nk = n;  // entries of the current level
+    for (; nk > TAIL_WIDE; nk >>= 1) {
+        const u32 q = n - nk + tid;
+        const u64 r = fp::sm_field(st);
+        if (tid < (nk >> 1)) {  // whole waves
+            const u64x2 pa = ld2(A, 2 * q), pf = ld2(F, 2 * q);
+            u64x2 pc = {0, 0};
+            if (hc) pc = ld2(Ct, 2 * q);
             u64 t[3] = {0, 0, 0};
-            if (tid < half) {
-                pa = ld2(X, 2 * tid);
-                pf = ld2(X + 2 * TAIL_TAB, 2 * tid);
-                if (hc) pc = ld2(X + TAIL_TAB, 2 * tid);
-                table_terms(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
-            }
-#pragma unroll
-            for (int q = 0; q < 3; q++) t[q] = wave_sum63_lazy(t[q]);
-            if (lane == 63) {
-#pragma unroll
-                for (int q = 0; q < 3; q++) s_part[q][w] = t[q];
-            }
-            __syncthreads();
-            if (w < 3 && lane == 0) msgp[3 * k + w] = waves_total(s_part, (int)w);
-            const u64 r = fp::sm_field(st);
-            if (tid == 0) {
-                pp.chals[c0 + k] = r;
-                pp.rngst[c0 + k + 1] = st;
-            }
-            if (tid < half) {
-                Y[tid] = fold1(pa.x, pa.y, r);
-                Y[2 * TAIL_TAB + tid] = fold1(pf.x, pf.y, r);
-                if (hc) Y[TAIL_TAB + tid] = fold1(pc.x, pc.y, r);
-            }
-        } else if (w < 3) {
-            u64 *msg = msgp + 3 * k + w, *chal = pp.chals + c0 + k, *stn = pp.rngst + c0 + k + 1;
-            if (w == 0) wtail_narrow<0>(X, Y, half, lane, hc, st, msg, chal, stn);
-            else if (w == 1) wtail_narrow<1>(X, Y, half, lane, hc, st, msg, chal, stn);
-            else wtail_narrow<2>(X, Y, half, lane, hc, st, msg, chal, stn);
+            table_terms(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
+            A[n + q] = fold1(pa.x, pa.y, r);
+            F[n + q] = fold1(pf.x, pf.y, r);
+            if (hc) Ct[n + q] = fold1(pc.x, pc.y, r);
+            chunk_sums(t, q >> 6, lane, n, L);
         }
         __syncthreads();
     }
+    if (nk > 1) {
+        if (w < 3) {  // wave w folds table w (A, C, F) through the remaining levels
+            u64 *T = tab + w * TAIL_TAB;
+            if (w != 1 || hc) {
+                for (u32 m = nk; m > 1; m >>= 1) {
+                    const u64 r = fp::sm_field(st);
+                    const u32 q = n - m + lane;
+                    if (lane < (m >> 1)) {
+                        const u64x2 p = ld2(T, 2 * q);
+                        T[n + q] = fold1(p.x, p.y, r);
+                    }
+                    wave_lds_sync();
+                }
+            }
+        } else if (w == 3) {
+            record_chals(st0, L, lane, c0, pp);
+        }
+        __syncthreads();
+        const u32 qb = n - nk;  // the remaining rounds' nk - 1 pairs start here
+        if (w < ((nk + 62) >> 6)) {
+            const u32 q = qb + 64 * w + lane;
+            u64 t[3] = {0, 0, 0};
+            if (q < n - 1) {
+                const u64x2 pa = ld2(A, 2 * q), pf = ld2(F, 2 * q);
+                u64x2 pc = {0, 0};
+                if (hc) pc = ld2(Ct, 2 * q);
+                table_terms(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
+            }
+            chunk_sums(t, (qb >> 6) + w, lane, n, L);
+        }
+    }
+    __syncthreads();
+    if (tid < 3 * L) {
+        const u32 k = tid / 3, t = tid - 3 * k;
+        msgp[3 * k + t] = tail_sum(n, k, t);
+    }
     if (tid == 0) {
-        const u64 v = tab[2 * TAIL_TAB + ((k & 1) ? TAIL_LIM : 0)];
+        const u64 v = F[2 * n - 2];  // the root
         *vout = v;
         if (last == 1) pp.state[1] = v;
     }
 }
+
 
 __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0) {
     u64 *tab = tail_lds();
@@ -1057,97 +1107,31 @@ __device__ __forceinline__ void step_wsmall(const WsmallArgs &a, const ProofPtrs
     (void)c;
 }
 
-// eq_T(z): the line through (0, 1 - z), (1, z) at t = T.
-template <int T>
-__device__ __forceinline__ u64 eq_at(u64 z) {
-    return T == 0 ? sub(1, z) : (T == 1 ? z : sub(add(add(z, z), z), 1));
-}
-
-// Narrow round of the p-phase tail, wave T: message value T; wave 0 folds
-// V (waves 0 and 2 share it beyond 64 pairs), wave 1 sums B.
-template <int T>
-__device__ __forceinline__ void ptail_narrow(const u64 *V, const u64 *B, u64 *Vn, u64 *Bn, u32 half, u32 lane,
-                                             u64 &st, u64 &C, u64 z, u64 *msg, u64 *chal, u64 *stn) {
-    const u64 Ce = mul(C, eq_at<T>(z));
-    if (half <= 64) {
-        const bool on = lane < half;
-        u64x2 pv = {0, 0};
-        u64 b = 0;
-        if (on) {
-            pv = ld2(V, 2 * lane);
-            b = B[lane];
-        }
-        const u64 term = mul(b, line_at<T>(pv.x, pv.y));
-        const u64 r = fp::sm_field(st);
-        u64 nv = 0;
-        if (T == 0) nv = fold1(pv.x, pv.y, r);
-        if (T == 1 && lane < half / 2) {
-            const u64x2 pb = ld2(B, 2 * lane);
-            nv = add(pb.x, pb.y);
-        }
-        const u64 s = wave_sum63_lazy(term);
-        if (lane == 63) {
-            *msg = mul(Ce, s);
-            if (T == 0) {
-                *chal = r;
-                *stn = st;
-            }
-        }
-        if (T == 0 && on) Vn[lane] = nv;
-        if (T == 1 && lane < half / 2) Bn[lane] = nv;
-        C = mul(C, fp::eq(z, r));
-        return;
-    }
-    u64 s = 0;
-    for (u32 m = lane; m < half; m += 64) {
-        const u64x2 p = ld2(V, 2 * m);
-        s = add(s, mul(B[m], line_at<T>(p.x, p.y)));
-    }
-    s = wave_sum63_lazy(s);
-    const u64 r = fp::sm_field(st);
-    if (lane == 63) {
-        *msg = mul(Ce, s);
-        if (T == 0) {
-            *chal = r;
-            *stn = st;
-        }
-    }
-    C = mul(C, fp::eq(z, r));
-    if (T == 1) {  // B_{j+1}[m] = B_j[2m] + B_j[2m+1]
-        for (u32 m = lane; m < half / 2; m += 64) {
-            const u64x2 p = ld2(B, 2 * m);
-            Bn[m] = add(p.x, p.y);
-        }
-    } else {  // waves 0 and 2 fold V, alternating runs of 64 pairs
-        for (u32 m = lane + (T == 2 ? 64 : 0); m < half; m += 128) {
-            const u64x2 p = ld2(V, 2 * m);
-            Vn[m] = fold1(p.x, p.y, r);
-        }
-    }
-}
-
 // Remaining p-phase rounds j0..s-1.  The prologue drew the pending
 // challenge(s) up to r_{j0-1} and its finish of round j0-1 computed the
 // beta prefix C.  B is the table of sums of the eq weights of the
 // a-coordinates not yet reached (beta over z's suffix); pair m of V goes
-// with B[m].  Round j's message is G(t) = C eq_t(z_j) S_t with eq_t(z) the
-// line through (0, 1 - z), (1, z): 1 - z, z, 3z - 1 at t = 0, 1, 2.
-__device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0, u32 have_c,
-                           u64 C0) {
+// with B[m].  Round j's message is G(t) = C_j eq_t(z_j) S_t with
+// S_t = sum_m B[m] V_t over the pairs and eq_t(z) the line through
+// (0, 1 - z), (1, z): 1 - z, z, 3z - 1 at t = 0, 1, 2; C_{j+1} =
+// C_j eq(z_j, r_j).  V is a tree as the omega tables; B's level k sits
+// at the indexes q of the pairs it goes with, its entry q' of level k+1
+// being the sum of entries 2q' - n and 2q' - n + 1.
+__device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0,
+                                           u32 have_c, u64 C0) {
     __shared__ u64 s_c;
-    __shared__ u64 s_part[3][NWAVES];
+    __shared__ u64 s_cz[2][TAIL_LOG];  // C_j and z_j of each round
     u64 *tab = tail_lds();
-    u64 *tv = tab, *tb = tab + TAIL_TAB;  // V areas: TAIL_LIM, TAIL_LIM / 2; B: half of each
+    u64 *V = tab, *B = tab + TAIL_TAB;
     const u32 tid = threadIdx.x, lane = tid & 63;
     const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
-    u32 n = 1u << (a.s - a.j0);  // entries of V^(j0), at most TAIL_LIM
-    for (u32 e = tid; e < n; e += SBLOCK) tv[e] = tail_entry(a.V, e, a.pend, c);
-    const u32 rounds = a.s - a.j0;
-    const u64 zr = lane < rounds ? pp.zbuf[a.j0 + lane] : 0;  // z_{j0 + l} in lane l
+    const u32 L = a.s - a.j0, n = 1u << L;  // entries of V^(j0), at most TAIL_LIM
+    for (u32 e = tid; e < n; e += SBLOCK) V[e] = tail_entry(a.V, e, a.pend, c);
+    const u64 zr = lane < L ? pp.zbuf[a.j0 + lane] : 0;  // z_{j0 + l} in lane l
     if (a.B) {
         for (u32 m = tid; m < n / 2; m += SBLOCK) {  // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1]
             const u64x2 pb = ld2(a.B, 2 * m);
-            tb[m] = add(pb.x, pb.y);
+            B[m] = add(pb.x, pb.y);
         }
     } else {
         // j0 = 0: B_0[m] = prod_{k=1}^{s-1} eq(bit k-1 of m, z_k), the weights of
@@ -1155,61 +1139,88 @@ __device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &
         for (u32 m = tid; m < n / 2; m += SBLOCK) {
             u64 b = 1;
             for (u32 k = 1; k < a.s; k++) b = mul(b, fp::eqbit((m >> (k - 1)) & 1, lane_value(zr, k)));
-            tb[m] = b;
+            B[m] = b;
         }
     }
     if (!have_c && tid == 0) s_c = pp.state[0];
     u64 st = tail_state(pp, a.c0, drew, st0);
     __syncthreads();
-    u64 C = uniform(have_c ? C0 : s_c);
-    u32 k = 0;  // rounds done; V^(j0 + k) and B_{j0 + k} sit in area k & 1
-    for (; n > 1; n >>= 1, k++) {
-        const u32 off = (k & 1) ? TAIL_LIM : 0, noff = (k & 1) ? 0 : TAIL_LIM;
-        const u64 *V = tv + off, *B = tb + off;
-        u64 *Vn = tv + noff, *Bn = tb + noff;
-        const u32 half = n >> 1;
-        const u64 z = lane_value(zr, k);
-        if (half >= WIDE_HALF) {
-            u64x2 pv = {0, 0};
+    const u64 Cs = uniform(have_c ? C0 : s_c), stc = st;
+    u32 nk = n;  // entries of the current level of V
+    for (; nk > TAIL_WIDE; nk >>= 1) {
+        const u32 half = nk >> 1, q = n - nk + tid;
+        const u64 r = fp::sm_field(st);
+        if (tid < half) {  // whole waves
+            const u64x2 pv = ld2(V, 2 * q);
+            const u64 b = B[q];
+            u64 t[3] = {mul(b, pv.x), mul(b, pv.y), mul(b, sub(add(pv.y, pv.y), pv.x))};
+            V[n + q] = fold1(pv.x, pv.y, r);
+            if (tid < half / 2) {  // B at the pairs of the next level
+                const u32 q2 = n - half + tid;
+                const u64x2 pb = ld2(B, 2 * q2 - n);
+                B[q2] = add(pb.x, pb.y);
+            }
+            chunk_sums(t, q >> 6, lane, n, L);
+        }
+        __syncthreads();
+    }
+    if (nk > 1) {
+        if (w == 0) {  // V through the remaining levels
+            for (u32 m = nk; m > 1; m >>= 1) {
+                const u64 r = fp::sm_field(st);
+                const u32 q = n - m + lane;
+                if (lane < (m >> 1)) {
+                    const u64x2 p = ld2(V, 2 * q);
+                    V[n + q] = fold1(p.x, p.y, r);
+                }
+                wave_lds_sync();
+            }
+        } else if (w == 1) {  // B at the pairs of each remaining level
+            for (u32 m = nk; m > 2; m >>= 1) {
+                const u32 q2 = n - (m >> 1) + lane;
+                if (lane < (m >> 2)) {
+                    const u64x2 pb = ld2(B, 2 * q2 - n);
+                    B[q2] = add(pb.x, pb.y);
+                }
+                wave_lds_sync();
+            }
+        } else if (w == 2) {  // the challenges and the beta prefixes
+            u64 s = stc, C = Cs;
+            for (u32 j = 0; j < L; j++) {
+                const u64 r = fp::sm_field(s);
+                const u64 z = lane_value(zr, j);
+                if (lane == 0) {
+                    pp.chals[a.c0 + j] = r;
+                    pp.rngst[a.c0 + j + 1] = s;
+                    s_cz[0][j] = C;
+                    s_cz[1][j] = z;
+                }
+                C = mul(C, fp::eq(z, r));
+            }
+            if (lane == 0) pp.state[0] = C;  // beta(z, a*)
+        }
+        __syncthreads();
+        const u32 qb = n - nk;  // the remaining rounds' nk - 1 pairs start here
+        if (w < ((nk + 62) >> 6)) {
+            const u32 q = qb + 64 * w + lane;
             u64 t[3] = {0, 0, 0};
-            if (tid < half) {
-                pv = ld2(V, 2 * tid);
-                const u64 b = B[tid];
+            if (q < n - 1) {
+                const u64x2 pv = ld2(V, 2 * q);
+                const u64 b = B[q];
                 t[0] = mul(b, pv.x);
                 t[1] = mul(b, pv.y);
                 t[2] = mul(b, sub(add(pv.y, pv.y), pv.x));
             }
-#pragma unroll
-            for (int q = 0; q < 3; q++) t[q] = wave_sum63_lazy(t[q]);
-            if (lane == 63) {
-#pragma unroll
-                for (int q = 0; q < 3; q++) s_part[q][w] = t[q];
-            }
-            __syncthreads();
-            if (w < 3 && lane == 0) {
-                const u64 e = w == 0 ? eq_at<0>(z) : (w == 1 ? eq_at<1>(z) : eq_at<2>(z));
-                a.msg[3 * k + w] = mul(mul(C, e), waves_total(s_part, (int)w));
-            }
-            const u64 r = fp::sm_field(st);
-            if (tid == 0) {
-                pp.chals[a.c0 + k] = r;
-                pp.rngst[a.c0 + k + 1] = st;
-            }
-            C = mul(C, fp::eq(z, r));
-            if (tid < half) Vn[tid] = fold1(pv.x, pv.y, r);
-            if (tid < half / 2) {
-                const u64x2 pb = ld2(B, 2 * tid);
-                Bn[tid] = add(pb.x, pb.y);
-            }
-        } else if (w < 3) {
-            u64 *msg = a.msg + 3 * k + w, *chal = pp.chals + a.c0 + k, *stn = pp.rngst + a.c0 + k + 1;
-            if (w == 0) ptail_narrow<0>(V, B, Vn, Bn, half, lane, st, C, z, msg, chal, stn);
-            else if (w == 1) ptail_narrow<1>(V, B, Vn, Bn, half, lane, st, C, z, msg, chal, stn);
-            else ptail_narrow<2>(V, B, Vn, Bn, half, lane, st, C, z, msg, chal, stn);
+            chunk_sums(t, (qb >> 6) + w, lane, n, L);
         }
-        __syncthreads();
     }
-    if (tid == 0) pp.state[0] = C;  // beta(z, a*)
+    __syncthreads();
+    if (tid < 3 * L) {
+        const u32 k = tid / 3, t = tid - 3 * k;
+        const u64 z = s_cz[1][k];
+        const u64 e = t == 0 ? sub(1, z) : (t == 1 ? z : sub(add(add(z, z), z), 1));
+        a.msg[3 * k + t] = mul(mul(s_cz[0][k], e), tail_sum(n, k, t));
+    }
 }
 
 // ---------------------------------------------------------------- kernel
