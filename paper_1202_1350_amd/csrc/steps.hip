@@ -807,29 +807,25 @@ __device__ __forceinline__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row)
 // ------------------------------------------------------------------ tails
 //
 // A tail runs the last rounds of a phase in one workgroup, over tables in
-// LDS.  Every level of a table is kept, as a binary tree: with n = 2^L
-// entries in level 0, level k (n_k = n >> k entries) sits at
-// [2n - 2 n_k, 2n - n_k), so pair m of level k is the tail's pair
-// q = n - n_k + m, it holds entries 2q, 2q + 1 and it folds into entry
-// n + q.  The challenges never depend on the messages, so the folds run
-// ahead of them: while a level has more than TAIL_WIDE entries every thread
-// folds one pair of every table and adds its message terms into 64-pair
-// chunk sums (one barrier a round); the remaining levels are folded by one
-// wave per table with no barrier at all, since each lane reads only what
-// lanes of its own wave wrote.  Their messages are summed afterwards, for
-// all rounds at once: those pairs fill at most two waves, and a DPP
-// reduction over runs of lanes gives each round its own sum.  Another wave
-// draws the challenges again, records them and (p-phase) forms the beta
-// prefixes while the folds run.
+// LDS laid out as binary trees: with n = 2^L entries in level 0, level k
+// (n_k = n >> k entries) sits at [2n - 2 n_k, 2n - n_k), so pair m of
+// level k is the tail's pair q = n - n_k + m, it holds entries 2q, 2q + 1
+// and it folds into entry n + q.  Every round first sums its message over
+// the level's pairs into partial sums in LDS; a barrier completes them, and
+// only after it is the round's challenge used (folds, the p-phase's beta
+// prefix); a second barrier publishes the next level.  While a level has at
+// least 128 entries every thread takes one pair of every table, adds its
+// three terms into 64-pair chunk sums and then folds the pair it holds;
+// below that wave t sums value t of the message and then folds table t.
+// The partial sums of all rounds are added into the messages at the end.
 
-constexpr int TAIL_TAB = 2 * TAIL_LIM;           // LDS entries per table: all levels
-constexpr u32 TAIL_WIDE = 128;                   // larger levels fold with every thread
-constexpr int TAIL_LOG = 10;                     // log2(TAIL_LIM): rounds of a tail
-constexpr int TAIL_CHUNKS = TAIL_LIM / 64;       // 64-pair chunks of a tail
+constexpr int TAIL_TAB = 2 * TAIL_LIM;              // LDS entries per table: all levels
+constexpr int TAIL_LOG = 10;                        // log2(TAIL_LIM): rounds of a tail
+constexpr int TAIL_CHUNKS = TAIL_LIM / 64;          // 64-pair chunks of a tail
 constexpr int TAIL_SLOTS = TAIL_CHUNKS + TAIL_LOG;  // chunk sums, then the small rounds' sums
 static_assert((1 << TAIL_LOG) == TAIL_LIM, "TAIL_LOG");
 static_assert(TAIL_LIM / 2 <= SBLOCK, "a wide round gives every pair a thread");
-static_assert(NWAVES >= 4, "three folding waves and a challenge wave");
+static_assert(NWAVES >= 3, "one wave per message value");
 
 __device__ __forceinline__ u64 *tail_lds() {
     __shared__ __align__(16) u64 t[3 * TAIL_TAB];
@@ -856,15 +852,6 @@ __device__ __forceinline__ u64 lane_value(u64 v, u32 l) {  // l uniform
     return ((u64)hi << 32) | lo;
 }
 
-// Orders this wave's LDS writes before its later LDS reads of them by other
-// lanes of the wave: a wave's LDS operations complete in order, and the
-// fences keep the compiler from moving them across.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Sum over the wave of field elements, left in lane 63: as wave_sum63, but
 // the first three and the last three steps add without reducing (eight
 // values below p stay below 2^64), with one reduction after each three.
@@ -879,57 +866,15 @@ __device__ __forceinline__ u64 wave_sum63_lazy(u64 v) {
     return fp::canon(fp::fold64(v));
 }
 
-// Sum of field elements over each aligned run of s lanes (s a power of two,
-// at most 32, the same on every lane of a run), left in the run's last
-// lane.  Steps below a lane's run length add its partner in the run: lane
-// l ^ 1, l ^ 2, then the mirrored lane in the 8-lane half row and in the
-// row (the partial sums are uniform over the aligned groups by then), then
-// lane 15 of the row below into rows 1 and 3.  Lazy as wave_sum63_lazy.
-__device__ __forceinline__ u64 run_sum(u64 v, u32 s) {
-    u64 x = dpp64<0xb1, 0xf>(v);  // quad_perm [1, 0, 3, 2]
-    if (s >= 2) v += x;
-    x = dpp64<0x4e, 0xf>(v);  // quad_perm [2, 3, 0, 1]
-    if (s >= 4) v += x;
-    x = dpp64<0x141, 0xf>(v);  // row_half_mirror
-    if (s >= 8) v += x;
-    v = fp::canon(fp::fold64(v));
-    x = dpp64<0x140, 0xf>(v);  // row_mirror
-    if (s >= 16) v += x;
-    x = dpp64<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
-    if (s >= 32) v += x;
-    return fp::canon(fp::fold64(v));
-}
-
-// Round of the tail's pair q (q <= n - 2): the pairs of round k are
-// [n - n_k, n - n_k / 2), so n - 1 - q lies in [n_k / 2, n_k).
-__device__ __forceinline__ u32 round_of(u32 q, u32 n, u32 L) {
-    return L - 1 - (31 - (u32)__builtin_clz((n - 1 - q) | 1));
-}
-
-// Adds a wave's three message terms (pair q = 64 c + lane, zero beyond the
-// last pair) into the partial sums: a chunk inside one round as one sum per
-// value, the chunk of the rounds with fewer than 64 pairs as one sum per
-// round.  c is wave-uniform.
-__device__ __forceinline__ void chunk_sums(u64 (&t)[3], u32 c, u32 lane, u32 n, u32 L) {
+// A wave's three message terms of one 64-pair chunk c, summed into the
+// chunk's partial sums.
+__device__ __forceinline__ void chunk_sums(u64 (&t)[3], u32 c, u32 lane) {
     u64 (*mp)[TAIL_SLOTS] = tail_parts();
-    if ((n >> (round_of(64 * c, n, L) + 1)) >= 64) {
 #pragma unroll
-        for (int i = 0; i < 3; i++) t[i] = wave_sum63_lazy(t[i]);
-        if (lane == 63) {
+    for (int i = 0; i < 3; i++) t[i] = wave_sum63_lazy(t[i]);
+    if (lane == 63) {
 #pragma unroll
-            for (int i = 0; i < 3; i++) mp[i][c] = t[i];
-        }
-        return;
-    }
-    const u32 q = 64 * c + lane;
-    const bool on = q < n - 1;
-    const u32 k = on ? round_of(q, n, L) : 0;
-    const u32 s = on ? n >> (k + 1) : 1;
-#pragma unroll
-    for (int i = 0; i < 3; i++) t[i] = run_sum(t[i], s);
-    if (on && (q & (s - 1)) == s - 1) {
-#pragma unroll
-        for (int i = 0; i < 3; i++) mp[i][TAIL_CHUNKS + k] = t[i];
+        for (int i = 0; i < 3; i++) mp[i][c] = t[i];
     }
 }
 
@@ -971,18 +916,6 @@ __device__ __forceinline__ u64 tail_state(const ProofPtrs &pp, u32 c0, u32 drew,
     return uniform(s_st);
 }
 
-// Records the challenges of rounds 0..L-1 of a tail, drawn from the state
-// st before its first round, with the states after them.
-__device__ __forceinline__ void record_chals(u64 st, u32 L, u32 lane, u32 c0, const ProofPtrs &pp) {
-    for (u32 j = 0; j < L; j++) {
-        const u64 r = fp::sm_field(st);
-        if (lane == 0) {
-            pp.chals[c0 + j] = r;
-            pp.rngst[c0 + j + 1] = st;
-        }
-    }
-}
-
 // The rounds of an omega tail over tables A, C, F in LDS (level 0 of each,
 // n entries, at the start of its area): messages to msgp, challenges c0,
 // c0 + 1, ... recorded with the RNG states after them; F's last entry is
@@ -994,56 +927,55 @@ __device__ __forceinline__ void wtail_rounds(u64 *tab, u32 n, bool hc, u64 st, u
     const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
     const u32 L = 31 - (u32)__builtin_clz(n);
     u64 *A = tab, *Ct = tab + TAIL_TAB, *F = tab + 2 * TAIL_TAB;
-    const u64 st0 = st;
-    u32 nk = n;  // entries of the current level
-    for (; nk > TAIL_WIDE; nk >>= 1) {
-        const u32 q = n - nk + tid;
-        const u64 r = fp::sm_field(st);
-        if (tid < (nk >> 1)) {  // whole waves
-            const u64x2 pa = ld2(A, 2 * q), pf = ld2(F, 2 * q);
-            u64x2 pc = {0, 0};
-            if (hc) pc = ld2(Ct, 2 * q);
-            u64 t[3] = {0, 0, 0};
-            table_terms(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
-            A[n + q] = fold1(pa.x, pa.y, r);
-            F[n + q] = fold1(pf.x, pf.y, r);
-            if (hc) Ct[n + q] = fold1(pc.x, pc.y, r);
-            chunk_sums(t, q >> 6, lane, n, L);
-        }
-        __syncthreads();
-    }
-    if (nk > 1) {
-        if (w < 3) {  // wave w folds table w (A, C, F) through the remaining levels
-            u64 *T = tab + w * TAIL_TAB;
-            if (w != 1 || hc) {
-                for (u32 m = nk; m > 1; m >>= 1) {
-                    const u64 r = fp::sm_field(st);
-                    const u32 q = n - m + lane;
-                    if (lane < (m >> 1)) {
-                        const u64x2 p = ld2(T, 2 * q);
-                        T[n + q] = fold1(p.x, p.y, r);
-                    }
-                    wave_lds_sync();
-                }
-            }
-        } else if (w == 3) {
-            record_chals(st0, L, lane, c0, pp);
-        }
-        __syncthreads();
-        const u32 qb = n - nk;  // the remaining rounds' nk - 1 pairs start here
-        if (w < ((nk + 62) >> 6)) {
-            const u32 q = qb + 64 * w + lane;
-            u64 t[3] = {0, 0, 0};
-            if (q < n - 1) {
-                const u64x2 pa = ld2(A, 2 * q), pf = ld2(F, 2 * q);
-                u64x2 pc = {0, 0};
+    u64 (*mp)[TAIL_SLOTS] = tail_parts();
+    for (u32 k = 0, nk = n; nk > 1; nk >>= 1, k++) {
+        const u32 half = nk >> 1, qb = n - nk;
+        const u64 r = fp::sm_field(st);  // challenge k: used after message k's sums
+        if (half >= 64) {  // thread tid takes pair qb + tid (whole waves)
+            const u32 q = qb + tid;
+            u64x2 pa = {0, 0}, pc = {0, 0}, pf = {0, 0};
+            if (tid < half) {
+                pa = ld2(A, 2 * q);
+                pf = ld2(F, 2 * q);
                 if (hc) pc = ld2(Ct, 2 * q);
+                u64 t[3] = {0, 0, 0};
                 table_terms(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
+                chunk_sums(t, q >> 6, lane);
             }
-            chunk_sums(t, (qb >> 6) + w, lane, n, L);
+            __syncthreads();  // message k's sums are complete
+            if (tid < half) {
+                A[n + q] = fold1(pa.x, pa.y, r);
+                F[n + q] = fold1(pf.x, pf.y, r);
+                if (hc) Ct[n + q] = fold1(pc.x, pc.y, r);
+            }
+        } else {  // wave t < 3 sums value t over the pairs, lane m < half taking pair qb + m
+            const u32 q = qb + lane;
+            const bool on = lane < half;
+            u64x2 own = {0, 0};
+            if (w < 3) {
+                u64x2 pa = {0, 0}, pc = {0, 0}, pf = {0, 0};
+                if (on) {
+                    pa = ld2(A, 2 * q);
+                    pf = ld2(F, 2 * q);
+                    if (hc) pc = ld2(Ct, 2 * q);
+                }
+                u64 term;
+                if (w == 0) term = add(mul(pa.x, pf.x), pc.x);
+                else if (w == 1) term = add(mul(pa.y, pf.y), pc.y);
+                else term = add(mul(line_at<2>(pa.x, pa.y), line_at<2>(pf.x, pf.y)), line_at<2>(pc.x, pc.y));
+                own = w == 0 ? pa : (w == 1 ? pc : pf);
+                const u64 v = wave_sum63_lazy(term);
+                if (lane == 63) mp[w][TAIL_CHUNKS + k] = v;
+            }
+            __syncthreads();  // message k's sums are complete
+            if (w < 3 && (w != 1 || hc) && on) tab[w * TAIL_TAB + n + q] = fold1(own.x, own.y, r);
         }
+        if (tid == 0) {
+            pp.chals[c0 + k] = r;
+            pp.rngst[c0 + k + 1] = st;
+        }
+        __syncthreads();  // level k + 1 is complete
     }
-    __syncthreads();
     if (tid < 3 * L) {
         const u32 k = tid / 3, t = tid - 3 * k;
         msgp[3 * k + t] = tail_sum(n, k, t);
@@ -1054,7 +986,6 @@ __device__ __forceinline__ void wtail_rounds(u64 *tab, u32 n, bool hc, u64 st, u
         if (last == 1) pp.state[1] = v;
     }
 }
-
 
 __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0) {
     u64 *tab = tail_lds();
@@ -1145,76 +1076,62 @@ __device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &
     if (!have_c && tid == 0) s_c = pp.state[0];
     u64 st = tail_state(pp, a.c0, drew, st0);
     __syncthreads();
-    const u64 Cs = uniform(have_c ? C0 : s_c), stc = st;
-    u32 nk = n;  // entries of the current level of V
-    for (; nk > TAIL_WIDE; nk >>= 1) {
-        const u32 half = nk >> 1, q = n - nk + tid;
-        const u64 r = fp::sm_field(st);
-        if (tid < half) {  // whole waves
-            const u64x2 pv = ld2(V, 2 * q);
-            const u64 b = B[q];
-            u64 t[3] = {mul(b, pv.x), mul(b, pv.y), mul(b, sub(add(pv.y, pv.y), pv.x))};
-            V[n + q] = fold1(pv.x, pv.y, r);
-            if (tid < half / 2) {  // B at the pairs of the next level
-                const u32 q2 = n - half + tid;
-                const u64x2 pb = ld2(B, 2 * q2 - n);
-                B[q2] = add(pb.x, pb.y);
-            }
-            chunk_sums(t, q >> 6, lane, n, L);
+    u64 C = uniform(have_c ? C0 : s_c);
+    u64 (*mp)[TAIL_SLOTS] = tail_parts();
+    for (u32 k = 0, nk = n; nk > 1; nk >>= 1, k++) {
+        const u32 half = nk >> 1, qb = n - nk;
+        const u64 r = fp::sm_field(st);  // challenge k: used after message k's sums
+        const u64 z = lane_value(zr, k);
+        if (tid == 0) {
+            s_cz[0][k] = C;
+            s_cz[1][k] = z;
         }
-        __syncthreads();
-    }
-    if (nk > 1) {
-        if (w == 0) {  // V through the remaining levels
-            for (u32 m = nk; m > 1; m >>= 1) {
-                const u64 r = fp::sm_field(st);
-                const u32 q = n - m + lane;
-                if (lane < (m >> 1)) {
-                    const u64x2 p = ld2(V, 2 * q);
-                    V[n + q] = fold1(p.x, p.y, r);
-                }
-                wave_lds_sync();
-            }
-        } else if (w == 1) {  // B at the pairs of each remaining level
-            for (u32 m = nk; m > 2; m >>= 1) {
-                const u32 q2 = n - (m >> 1) + lane;
-                if (lane < (m >> 2)) {
+        if (half >= 64) {  // thread tid takes pair qb + tid (whole waves)
+            const u32 q = qb + tid;
+            u64x2 pv = {0, 0};
+            if (tid < half) {
+                pv = ld2(V, 2 * q);
+                const u64 b = B[q];
+                u64 t[3] = {mul(b, pv.x), mul(b, pv.y), mul(b, sub(add(pv.y, pv.y), pv.x))};
+                chunk_sums(t, q >> 6, lane);
+                if (tid < half / 2) {  // B at the pairs of the next level
+                    const u32 q2 = n - half + tid;
                     const u64x2 pb = ld2(B, 2 * q2 - n);
                     B[q2] = add(pb.x, pb.y);
                 }
-                wave_lds_sync();
             }
-        } else if (w == 2) {  // the challenges and the beta prefixes
-            u64 s = stc, C = Cs;
-            for (u32 j = 0; j < L; j++) {
-                const u64 r = fp::sm_field(s);
-                const u64 z = lane_value(zr, j);
-                if (lane == 0) {
-                    pp.chals[a.c0 + j] = r;
-                    pp.rngst[a.c0 + j + 1] = s;
-                    s_cz[0][j] = C;
-                    s_cz[1][j] = z;
+            __syncthreads();  // message k's sums are complete
+            if (tid < half) V[n + q] = fold1(pv.x, pv.y, r);
+        } else {  // wave t < 3 sums value t over the pairs, lane m < half taking pair qb + m
+            const u32 q = qb + lane;
+            const bool on = lane < half;
+            u64x2 pv = {0, 0};
+            if (w < 3) {
+                u64 b = 0;
+                if (on) {
+                    pv = ld2(V, 2 * q);
+                    b = B[q];
                 }
-                C = mul(C, fp::eq(z, r));
+                const u64 x = w == 0 ? pv.x : (w == 1 ? pv.y : sub(add(pv.y, pv.y), pv.x));
+                const u64 v = wave_sum63_lazy(mul(b, x));
+                if (lane == 63) mp[w][TAIL_CHUNKS + k] = v;
+                if (w == 1 && lane < half / 2) {  // B at the pairs of the next level
+                    const u32 q2 = n - half + lane;
+                    const u64x2 pb = ld2(B, 2 * q2 - n);
+                    B[q2] = add(pb.x, pb.y);
+                }
             }
-            if (lane == 0) pp.state[0] = C;  // beta(z, a*)
+            __syncthreads();  // message k's sums are complete
+            if (w == 0 && on) V[n + q] = fold1(pv.x, pv.y, r);
         }
-        __syncthreads();
-        const u32 qb = n - nk;  // the remaining rounds' nk - 1 pairs start here
-        if (w < ((nk + 62) >> 6)) {
-            const u32 q = qb + 64 * w + lane;
-            u64 t[3] = {0, 0, 0};
-            if (q < n - 1) {
-                const u64x2 pv = ld2(V, 2 * q);
-                const u64 b = B[q];
-                t[0] = mul(b, pv.x);
-                t[1] = mul(b, pv.y);
-                t[2] = mul(b, sub(add(pv.y, pv.y), pv.x));
-            }
-            chunk_sums(t, (qb >> 6) + w, lane, n, L);
+        C = mul(C, fp::eq(z, r));  // the beta prefix of round k + 1
+        if (tid == 0) {
+            pp.chals[a.c0 + k] = r;
+            pp.rngst[a.c0 + k + 1] = st;
         }
+        __syncthreads();  // level k + 1 is complete
     }
-    __syncthreads();
+    if (tid == 0) pp.state[0] = C;  // beta(z, a*)
     if (tid < 3 * L) {
         const u32 k = tid / 3, t = tid - 3 * k;
         const u64 z = s_cz[1][k];
