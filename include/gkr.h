@@ -124,9 +124,11 @@ int gkr_prove(const gkr_circuit *c, const uint64_t *inputs, int inputs_on_device
               uint64_t *msgs, uint64_t *chals, void *hip_stream);
 
 /* Verify (Sec. 2.2, 4.1.2): replay every round check, the per-layer wiring
- * identity (add~ and mult~ evaluated on the device from the circuit), the
- * line step, and compare the last claim with the inputs' multilinear
- * extension, computed on the device in one pass over the inputs.
+ * identity, the line step, and compare the last claim with the inputs'
+ * multilinear extension, computed on the device in one pass over the
+ * inputs.  add~ and mult~ come from a closed form on the host where the
+ * layer has one (gkr_circuit_wiring), else from one pass over the layer's
+ * gates on the device.
  *   msgs/n_msgs   host transcript.  accepted: 1 or 0.  why: NULL or filled
  *   on rejection (layer/round/check as in gkr_reject_info).
  * Errors: GKR_ERR_INVALID, GKR_ERR_RANGE (an input >= p), GKR_ERR_NOMEM,
@@ -135,6 +137,25 @@ int gkr_prove(const gkr_circuit *c, const uint64_t *inputs, int inputs_on_device
 int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inputs_on_device, uint64_t seed,
                const uint64_t *msgs, uint64_t n_msgs, int *accepted, gkr_reject_info *why,
                void *hip_stream);
+
+/* Wiring shapes (Sec. 3.1's add~ and mult~ at a point (a, b, c)).  At
+ * creation every layer whose gates are all ADD or all MUL is matched against
+ * shapes whose predicate W(a, b, c) = sum_g chi_g(a) chi_in1(g)(b)
+ * chi_in2(g)(c) is a product over the bits of g; the verifier evaluates
+ * those in O(s_i + s_{i+1}) field operations on the host:
+ *   GKR_WIRING_TREE     gate g reads 2g and 2g + 1 (the binary sum trees);
+ *   GKR_WIRING_SQUARE   gate g reads g twice (F2's squares, F0's squaring);
+ *   GKR_WIRING_MATMULT  S = N^3 (N a power of two), gate (iN + j)N + k
+ *                       reads iN + k and N^2 + kN + j (A then B row-major).
+ * Any other layer is GKR_WIRING_GATES (one pass over its gates).
+ * gkr_circuit_wiring: the shape of layer `layer` (0 <= layer < d).
+ * Errors: GKR_ERR_INVALID. */
+enum { GKR_WIRING_GATES = 0, GKR_WIRING_TREE = 1, GKR_WIRING_SQUARE = 2, GKR_WIRING_MATMULT = 3 };
+int gkr_circuit_wiring(const gkr_circuit *c, uint32_t layer, int *form);
+/* Use the closed forms in later gkr_verify calls of this process (enable 1,
+ * the default) or pass over every layer's gates (0); returns the previous
+ * setting.  Verdicts do not depend on it. */
+int gkr_verify_closed_forms(int enable);
 
 /* Launch shapes.  A grid step over U work items (gates, wires, table
  * entries or quads of them) launches ceil(U / (512 q)) workgroups of 512

@@ -46,6 +46,8 @@ _SIGS = [
                             C.c_void_p]),
     ("gkr_verify", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_uint64, C.c_void_p, C.c_uint64,
                              C.POINTER(C.c_int), C.POINTER(RejectInfo), C.c_void_p]),
+    ("gkr_circuit_wiring", C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(C.c_int)]),
+    ("gkr_verify_closed_forms", C.c_int, [C.c_int]),
     ("f2_sumcheck_prove", C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_uint64, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
     ("f2_sumcheck_verify", C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_uint64, C.c_void_p,
@@ -197,6 +199,21 @@ def gkr_verify(circ: Circuit, inputs, seed: int, msgs, stream=None):
     _check(lib().gkr_verify(circ.handle, p, dev, seed, m.ctypes.data if len(m) else None, len(m),
                             C.byref(acc), C.byref(why), _stream(dev, stream)))
     return bool(acc.value), why.layer, why.round, why.check
+
+
+GKR_WIRING_GATES, GKR_WIRING_TREE, GKR_WIRING_SQUARE, GKR_WIRING_MATMULT = 0, 1, 2, 3
+
+
+def gkr_circuit_wiring(circ: Circuit, layer: int) -> int:
+    """Wiring shape of a layer (GKR_WIRING_*)."""
+    f = C.c_int()
+    _check(lib().gkr_circuit_wiring(circ.handle, layer, C.byref(f)))
+    return f.value
+
+
+def gkr_verify_closed_forms(enable: bool) -> bool:
+    """Closed-form wiring in gkr_verify on or off; returns the previous setting."""
+    return bool(lib().gkr_verify_closed_forms(1 if enable else 0))
 
 
 def gkr_batch_prove(circs, inputs, seeds, graph: bool = True, stream=None):

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -319,6 +320,7 @@ struct gkr_circuit {
     u32 L = 0;  // layers incl. input
     std::vector<u32> S, s;
     std::vector<int> kind;
+    std::vector<int> form;  // GKR_WIRING_* per layer
     std::vector<u8 *> type;
     std::vector<u32 *> in1, in2;
     void *soa = nullptr;
@@ -346,6 +348,98 @@ struct gkr_circuit {
     void *gmem = nullptr;       // device memory of the groups
 };
 
+// ---------------------------------------------------------------------------
+// Wiring predicates in closed form (the verifier's add~ and mult~ at a point,
+// Sec. 3.1).  For the layer shapes below the predicate
+//   W(a, b, c) = sum_{g < S} chi_g(a) chi_{in1(g)}(b) chi_{in2(g)}(c)
+// is a product over the bits of g, so the verifier evaluates it with
+// O(s_i + s_{i+1}) field operations instead of a pass over the gates.
+
+// The shape of a layer's wiring (all gates of one type), from one pass.
+static int wiring_form(u32 S, const uint32_t *in1, const uint32_t *in2) {
+    bool tree = true, square = true;
+    for (u32 g = 0; g < S && (tree || square); g++) {
+        tree = tree && in1[g] == 2ull * g && in2[g] == 2ull * g + 1;
+        square = square && in1[g] == g && in2[g] == g;
+    }
+    if (tree) return GKR_WIRING_TREE;
+    if (square) return GKR_WIRING_SQUARE;
+    const u32 n = log2ceil(S) / 3;  // S = N^3, N = 2^n
+    if (S != 1u << (3 * n) || n > 10) return GKR_WIRING_GATES;
+    const u64 N = 1ull << n;
+    for (u64 g = 0; g < S; g++) {
+        const u64 i = g >> (2 * n), j = (g >> n) & (N - 1), k = g & (N - 1);
+        if (in1[g] != i * N + k || in2[g] != N * N + k * N + j) return GKR_WIRING_GATES;
+    }
+    return GKR_WIRING_MATMULT;
+}
+
+// sum over g in [0, S) of prod_{k < K} f[k][bit k of g], for S <= 2^K: the
+// g below S share S's bits above some bit j where S has a 1 and g a 0, and
+// range freely below it.
+static u64 bits_sum(const std::vector<std::array<u64, 2>> &f, u64 S) {
+    using namespace fp;
+    const u32 K = (u32)f.size();
+    std::vector<u64> low(K + 1);  // low[j] = prod_{k < j} (f[k][0] + f[k][1])
+    low[0] = 1;
+    for (u32 k = 0; k < K; k++) low[k + 1] = mul(low[k], add(f[k][0], f[k][1]));
+    if (S == 1ull << K) return low[K];
+    u64 tot = 0, pre = 1;
+    for (int j = (int)K - 1; j >= 0; j--) {
+        if ((S >> j) & 1) {
+            tot = add(tot, mul(pre, mul(f[j][0], low[j])));
+            pre = mul(pre, f[j][1]);
+        } else {
+            pre = mul(pre, f[j][0]);
+        }
+    }
+    return tot;
+}
+
+// W(a, b, c) for a layer of S gates in closed form; a has s coordinates, b
+// and c sp each.  Wire bits beyond a point's coordinates are zero.
+static u64 wiring_closed(int form, u32 S, u32 s, u32 sp, const u64 *a, const u64 *b, const u64 *c) {
+    using namespace fp;
+    auto side = [](const u64 *v, u32 m, u32 len, u32 x) -> u64 { return m < len ? eqbit(x, v[m]) : (x ? 0 : 1); };
+    auto E3 = [](u64 x, u64 y, u64 w) {  // sum over t in {0,1} of eq(x,t) eq(y,t) eq(w,t)
+        return add(mul(mul(x, y), w), mul(mul(sub(1, x), sub(1, y)), sub(1, w)));
+    };
+    u64 v = 1;
+    u32 top = 0;  // b, c coordinates from here on take bit 0
+    if (form == GKR_WIRING_TREE || form == GKR_WIRING_SQUARE) {
+        const u32 sh = form == GKR_WIRING_TREE ? 1 : 0;  // g's bit k is bit k + sh of both wires
+        std::vector<std::array<u64, 2>> f(s);
+        for (u32 k = 0; k < s; k++)
+            for (u32 x = 0; x < 2; x++)
+                f[k][x] = mul(eqbit(x, a[k]), mul(side(b, k + sh, sp, x), side(c, k + sh, sp, x)));
+        v = bits_sum(f, S);
+        if (sh) v = mul(v, mul(sub(1, b[0]), c[0]));  // in1 even, in2 odd
+        top = s + sh;
+    } else {  // MatMult: g = (iN + j)N + k, in1 = iN + k, in2 = N^2 + kN + j
+        const u32 n = s / 3;
+        for (u32 t = 0; t < n; t++) {
+            v = mul(v, E3(a[t], b[t], c[n + t]));          // k
+            v = mul(v, eq(a[n + t], c[t]));                // j
+            v = mul(v, eq(a[2 * n + t], b[n + t]));        // i
+        }
+        v = mul(v, mul(sub(1, b[2 * n]), c[2 * n]));       // A's half, B's half
+        top = 2 * n + 1;
+    }
+    for (u32 m = top; m < sp; m++) v = mul(v, mul(sub(1, b[m]), sub(1, c[m])));
+    return v;
+}
+
+static std::atomic<int> g_closed_forms{1};
+
+extern "C" int gkr_circuit_wiring(const gkr_circuit *c, uint32_t layer, int *form) {
+    if (!c || !form) return fail(GKR_ERR_INVALID, "NULL argument");
+    if (layer + 1 >= c->L) return fail(GKR_ERR_INVALID, "layer out of range");
+    *form = c->form[layer];
+    return GKR_OK;
+}
+
+extern "C" int gkr_verify_closed_forms(int enable) { return g_closed_forms.exchange(enable ? 1 : 0); }
+
 extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_sizes,
                                   const uint8_t *const *gate_type, const uint32_t *const *in1,
                                   const uint32_t *const *in2, gkr_circuit **out) {
@@ -370,6 +464,7 @@ extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_siz
     }
     const u32 d = num_layers - 1;
     c->kind.resize(d);
+    c->form.resize(d);
     size_t soa_bytes = 0;
     for (u32 i = 0; i < d; i++) {
         if (!gate_type[i] || !in1[i] || !in2[i]) return fail(GKR_ERR_INVALID, "NULL layer array");
@@ -382,6 +477,7 @@ extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_siz
             (gate_type[i][g] ? any_mul : any_add) = true;
         }
         c->kind[i] = any_add && any_mul ? KIND_MIXED : (any_mul ? KIND_MUL : KIND_ADD);
+        c->form[i] = c->kind[i] == KIND_MIXED ? GKR_WIRING_GATES : wiring_form(c->S[i], in1[i], in2[i]);
         size_t n = c->S[i];
         soa_bytes += ((n * 4 + 255) & ~size_t(255)) * 2;
         if (c->kind[i] == KIND_MIXED) soa_bytes += (n + 255) & ~size_t(255);
@@ -1885,7 +1981,9 @@ extern "C" int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inpu
     }
     u64 *T = v.tab;
     int nb = 0;
+    const bool closed = g_closed_forms.load() != 0;
     for (u32 i = 0; i < d; i++) {
+        if (closed && c->form[i] != GKR_WIRING_GATES) continue;  // on the host below
         const u32 s = c->s[i], sp = c->s[i + 1];
         const u64 *r = v.pts + c->co[i];
         u32 La, Lb;
@@ -1949,7 +2047,12 @@ extern "C" int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inpu
         const u64 v1 = msgs[mi++], v2 = msgs[mi++];
         u64 beta = 1;
         for (u32 k = 0; k < s; k++) beta = mul(beta, eq(z[i][k], r[k]));
-        const u64 addv = res[2 * i], mulv = res[2 * i + 1];
+        u64 addv = res[2 * i], mulv = res[2 * i + 1];
+        if (closed && c->form[i] != GKR_WIRING_GATES) {
+            const u64 w = wiring_closed(c->form[i], c->S[i], s, sp, r, r + s, r + s + sp);
+            addv = c->kind[i] == KIND_ADD ? w : 0;
+            mulv = c->kind[i] == KIND_MUL ? w : 0;
+        }
         const u64 rhs = mul(beta, add(mul(addv, add(v1, v2)), mul(mulv, mul(v1, v2))));
         if (rhs != claim) {
             reject(accepted, why, (int)i, (int)n, GKR_CHECK_WIRING);
