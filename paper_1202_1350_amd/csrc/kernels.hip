@@ -185,9 +185,29 @@ __global__ void __launch_bounds__(BLOCK) k_mle(u64 n, const u64 *T64, const u32 
                                                const u64 *hi, u32 L, u64 *partials) {
     const u64 mask = (1ull << L) - 1;
     u64 acc[1] = {0};
-    for (u64 x = GTID; x < n; x += GSTRIDE) {
-        const u64 v = WIDE ? T64[x] : (u64)T32[x];
-        acc[0] = add(acc[0], mul(mul(lo[x & mask], hi[x >> L]), v));
+    if ((GSTRIDE & mask) == 0) {
+        // every x of this thread has the same low bits: chi_x = lo[x & mask]
+        // hi[x >> L], so the thread sums hi[x >> L] v_x exactly in 128 bits
+        // (reduced every 32 terms: 32 products below 2^122 fit) and
+        // multiplies by its lo once
+        u64 s = 0;
+        fp::u128 w = 0;
+        u32 k = 0;
+        for (u64 x = GTID; x < n; x += GSTRIDE) {
+            w += WIDE ? fp::wide(hi[x >> L], T64[x]) : fp::wide(hi[x >> L], (u64)T32[x]);
+            if (++k == 32) {
+                s = add(s, fp::red128(w));
+                w = 0;
+                k = 0;
+            }
+        }
+        s = add(s, fp::red128(w));
+        acc[0] = GTID < n ? mul(s, lo[GTID & mask]) : 0;
+    } else {
+        for (u64 x = GTID; x < n; x += GSTRIDE) {
+            const u64 v = WIDE ? T64[x] : (u64)T32[x];
+            acc[0] = add(acc[0], mul(mul(lo[x & mask], hi[x >> L]), v));
+        }
     }
     block_store<1>(acc, partials + (u64)blockIdx.x);
 }
