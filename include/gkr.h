@@ -126,9 +126,10 @@ int gkr_prove(const gkr_circuit *c, const uint64_t *inputs, int inputs_on_device
 /* Verify (Sec. 2.2, 4.1.2): replay every round check, the per-layer wiring
  * identity, the line step, and compare the last claim with the inputs'
  * multilinear extension, computed on the device in one pass over the
- * inputs.  add~ and mult~ come from a closed form on the host where the
- * layer has one (gkr_circuit_wiring), else from one pass over the layer's
- * gates on the device.
+ * inputs (host inputs stream through it in chunks of 2^23 values, so the
+ * verifier holds two chunks on the device).  add~ and mult~ come from a
+ * closed form on the host where the layer has one (gkr_circuit_wiring),
+ * else from one pass over the layer's gates on the device.
  *   msgs/n_msgs   host transcript.  accepted: 1 or 0.  why: NULL or filled
  *   on rejection (layer/round/check as in gkr_reject_info).
  * Errors: GKR_ERR_INVALID, GKR_ERR_RANGE (an input >= p), GKR_ERR_NOMEM,

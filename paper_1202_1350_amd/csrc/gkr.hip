@@ -1895,6 +1895,58 @@ int vs_reserve(size_t bytes, size_t host_words) {
     return GKR_OK;
 }
 
+// Streamed input extension for host inputs (the verifier's one pass over
+// the inputs, Sec. 4.1.2).  Chunks of VCHUNK values are copied from the
+// caller's memory into two device buffers on a copy stream, chunk k into
+// buffer k & 1 once the kernels that read that buffer before have finished;
+// the caller's stream checks the chunk against p (u64 values, into *bad_dev)
+// and adds its extension terms into the same per-workgroup rows while chunk
+// k + 1 is copied.  Chunks start at multiples of VCHUNK, a multiple of 2^L
+// for every table here (L <= 16).
+constexpr u64 VCHUNK = 1ull << 23;
+
+struct InputStream {
+    std::mutex mu;
+    int device = -1;
+    hipStream_t cs = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
+};
+InputStream g_is;
+
+// dbuf: device room for 2 min(n, VCHUNK) values.
+template <typename T>
+static int stream_mle(hipStream_t st, const T *in, u64 n, T *dbuf, const u64 *lo, const u64 *hi, u32 L,
+                      u64 *partials, int *nb, u32 *bad_dev) {
+    std::lock_guard<std::mutex> lk(g_is.mu);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (g_is.device != dev) {  // stream and events belong to one device
+        HIP_TRY(hipStreamCreateWithFlags(&g_is.cs, hipStreamNonBlocking));
+        for (int b = 0; b < 2; b++) {
+            HIP_TRY(hipEventCreateWithFlags(&g_is.copied[b], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&g_is.used[b], hipEventDisableTiming));
+        }
+        g_is.device = dev;
+    }
+    const u64 C = std::min<u64>(n, VCHUNK);
+    const int nbf = blocks_for(C, 8);
+    u64 k = 0;
+    for (u64 x0 = 0; x0 < n; x0 += C, k++) {
+        const int b = (int)(k & 1);
+        const u64 m = std::min<u64>(C, n - x0);
+        if (k >= 2) HIP_TRY(hipStreamWaitEvent(g_is.cs, g_is.used[b], 0));
+        HIP_TRY(hipMemcpyAsync(dbuf + b * C, in + x0, m * sizeof(T), hipMemcpyHostToDevice, g_is.cs));
+        HIP_TRY(hipEventRecord(g_is.copied[b], g_is.cs));
+        HIP_TRY(hipStreamWaitEvent(st, g_is.copied[b], 0));
+        const u64 *t64 = sizeof(T) == 8 ? (const u64 *)(dbuf + b * C) : nullptr;
+        const u32 *t32 = sizeof(T) == 4 ? (const u32 *)(dbuf + b * C) : nullptr;
+        if (t64) HIP_TRY(launch_check_range(st, t64, m, bad_dev));
+        HIP_TRY(launch_mle(st, m, t64, t32, lo, hi + (x0 >> L), L, partials, nb, k > 0, nbf));
+        HIP_TRY(hipEventRecord(g_is.used[b], st));
+    }
+    return GKR_OK;
+}
+
 void reject(int *accepted, gkr_reject_info *why, int layer, int round, int check) {
     *accepted = 0;
     if (why) {
@@ -1917,10 +1969,6 @@ extern "C" int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inpu
     if (why) *why = {-1, -1, 0};
     const u32 d = c->L - 1;
     const u64 Sd = c->S[d];
-    if (!inputs_on_device) {
-        for (u64 g = 0; g < Sd; g++)
-            if (inputs[g] >= P) return fail(GKR_ERR_RANGE, "input value not below p");
-    }
     if (n_msgs != c->n_msgs) {
         reject(accepted, why, -1, -1, GKR_CHECK_MALFORMED);
         return GKR_OK;
@@ -1957,7 +2005,7 @@ extern "C" int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inpu
         v.tab = a.take<u64>(6ull * HALF_MAX);
         v.partials = a.take<u64>((u64)MAX_BLOCKS * 4);
         v.res = a.take<u64>(2ull * d + 2);
-        v.in = a.take<u64>(inputs_on_device ? 1 : Sd);
+        v.in = a.take<u64>(inputs_on_device ? 1 : 2 * std::min<u64>(Sd, VCHUNK));
         v.flag = a.take<u32>(1);
     };
     lay(sz);
@@ -1971,14 +2019,8 @@ extern "C" int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inpu
     std::copy(ch.begin(), ch.end(), pts.begin());
     std::copy(z[d].begin(), z[d].end(), pts.begin() + c->n_chals);
     HIP_TRY(hipMemcpyAsync(v.pts, pts.data(), npts * 8, hipMemcpyHostToDevice, st));
-    const u64 *in_dev = inputs;
-    if (!inputs_on_device) {
-        HIP_TRY(hipMemcpyAsync(v.in, inputs, Sd * 8, hipMemcpyHostToDevice, st));
-        in_dev = v.in;
-    } else {
-        HIP_TRY(hipMemsetAsync(v.flag, 0, 4, st));
-        LAUNCH(PC_MISC, Sd * 8.0, launch_check_range(st, inputs, Sd, v.flag));
-    }
+    HIP_TRY(hipMemsetAsync(v.flag, 0, 4, st));
+    if (inputs_on_device) LAUNCH(PC_MISC, Sd * 8.0, launch_check_range(st, inputs, Sd, v.flag));
     u64 *T = v.tab;
     int nb = 0;
     const bool closed = g_closed_forms.load() != 0;
@@ -2017,14 +2059,19 @@ extern "C" int gkr_verify(const gkr_circuit *c, const uint64_t *inputs, int inpu
         u32 Ld;
         split_half(sd, &Ld);
         LAUNCH(PC_TABLES, 0, launch_eq_halves(st, v.pts + c->n_chals, sd, Ld, T, T + HALF_MAX));
-        LAUNCH(PC_MLE, Sd * 8.0, launch_mle(st, Sd, in_dev, nullptr, T, T + HALF_MAX, Ld, v.partials, &nb));
+        if (inputs_on_device) {
+            LAUNCH(PC_MLE, Sd * 8.0, launch_mle(st, Sd, inputs, nullptr, T, T + HALF_MAX, Ld, v.partials, &nb));
+        } else {
+            rc = stream_mle<u64>(st, inputs, Sd, v.in, T, T + HALF_MAX, Ld, v.partials, &nb, v.flag);
+            if (rc) return rc;
+        }
         LAUNCH(PC_MISC, 0, launch_reduce_rows(st, nb, 1, v.partials, v.res + 2 * d));
     }
     HIP_TRY(hipMemcpyAsync(g_vs.h_res, v.res, (2ull * d + 1) * 8, hipMemcpyDeviceToHost, st));
-    if (inputs_on_device)
-        HIP_TRY(hipMemcpyAsync(g_vs.h_res + 2ull * d + 1, v.flag, 4, hipMemcpyDeviceToHost, st));
+    g_vs.h_res[2ull * d + 1] = 0;
+    HIP_TRY(hipMemcpyAsync(g_vs.h_res + 2ull * d + 1, v.flag, 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (inputs_on_device && (uint32_t)g_vs.h_res[2ull * d + 1])
+    if ((uint32_t)g_vs.h_res[2ull * d + 1])
         return fail(GKR_ERR_RANGE, "input value not below p");
     const u64 *res = g_vs.h_res;
     // Host replay of the protocol (a10).
@@ -2219,7 +2266,7 @@ extern "C" int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_devic
         v.tab = a.take<u64>(2ull * HALF_MAX);
         v.partials = a.take<u64>((u64)MAX_BLOCKS);
         v.res = a.take<u64>(1);
-        v.in = a.take<u32>(on_device ? 1 : n);
+        v.in = a.take<u32>(on_device ? 1 : 2 * std::min<u64>(n, VCHUNK));
     };
     Arena sz;
     lay(sz);
@@ -2228,17 +2275,17 @@ extern "C" int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_devic
     Arena a;
     a.base = (char *)g_f2.mem;
     lay(a);
-    const u32 *a32 = freq;
-    if (!on_device) {
-        HIP_TRY(hipMemcpyAsync(v.in, freq, n * 4, hipMemcpyHostToDevice, st));
-        a32 = v.in;
-    }
     if (l) HIP_TRY(hipMemcpyAsync(v.pts, r.data(), l * 8ull, hipMemcpyHostToDevice, st));
     u32 L;
     split_half(l, &L);
     int nb = 0;
     LAUNCH(PC_TABLES, 0, launch_eq_halves(st, v.pts, l, L, v.tab, v.tab + HALF_MAX));
-    LAUNCH(PC_MLE, n * 4.0, launch_mle(st, n, nullptr, a32, v.tab, v.tab + HALF_MAX, L, v.partials, &nb));
+    if (on_device) {
+        LAUNCH(PC_MLE, n * 4.0, launch_mle(st, n, nullptr, freq, v.tab, v.tab + HALF_MAX, L, v.partials, &nb));
+    } else {
+        rc = stream_mle<u32>(st, freq, n, v.in, v.tab, v.tab + HALF_MAX, L, v.partials, &nb, nullptr);
+        if (rc) return rc;
+    }
     LAUNCH(PC_MISC, 0, launch_reduce_rows(st, nb, 1, v.partials, v.res));
     HIP_TRY(hipMemcpyAsync(g_f2.h, v.res, 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

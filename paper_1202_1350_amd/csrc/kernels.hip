@@ -182,7 +182,7 @@ hipError_t launch_wiring(hipStream_t st, const WiringArgs &a, int *nblocks) {
 
 template <bool WIDE>
 __global__ void __launch_bounds__(BLOCK) k_mle(u64 n, const u64 *T64, const u32 *T32, const u64 *lo,
-                                               const u64 *hi, u32 L, u64 *partials) {
+                                               const u64 *hi, u32 L, u64 *partials, int accumulate) {
     const u64 mask = (1ull << L) - 1;
     u64 acc[1] = {0};
     if ((GSTRIDE & mask) == 0) {
@@ -209,18 +209,22 @@ __global__ void __launch_bounds__(BLOCK) k_mle(u64 n, const u64 *T64, const u32 
             acc[0] = add(acc[0], mul(mul(lo[x & mask], hi[x >> L]), v));
         }
     }
-    block_store<1>(acc, partials + (u64)blockIdx.x);
+    __shared__ u64 tot[1];
+    block_store<1>(acc, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = accumulate ? add(partials[blockIdx.x], tot[0]) : tot[0];
 }
 
 hipError_t launch_mle(hipStream_t st, u64 n, const u64 *T64, const u32 *T32, const u64 *lo,
-                      const u64 *hi, u32 L, u64 *partials, int *nblocks) {
-    int nb = blocks_for(n, 8);
+                      const u64 *hi, u32 L, u64 *partials, int *nblocks, int accumulate, int nb_fixed) {
+    const int nb = nb_fixed > 0 ? nb_fixed : blocks_for(n, 8);
     *nblocks = nb;
     if (T64)
-        hipLaunchKernelGGL(k_mle<true>, dim3(nb), dim3(BLOCK), 0, st, n, T64, T32, lo, hi, L, partials);
+        hipLaunchKernelGGL(k_mle<true>, dim3(nb), dim3(BLOCK), 0, st, n, T64, T32, lo, hi, L, partials,
+                           accumulate);
     else
         hipLaunchKernelGGL(k_mle<false>, dim3(nb), dim3(BLOCK), 0, st, n, T64, T32, lo, hi, L,
-                           partials);
+                           partials, accumulate);
     return hipGetLastError();
 }
 

@@ -64,10 +64,14 @@ struct WiringArgs {
     u64 *partials;
 };
 hipError_t launch_wiring(hipStream_t st, const WiringArgs &a, int *nblocks);
-// Multilinear extension of T (n = 2^s values, u64 or u32) at the point with
-// half tables lo / hi: per-workgroup partial sums.
+// Multilinear extension of T (n values, u64 or u32) at the point with half
+// tables lo / hi (entry x weighs lo[x mod 2^L] hi[x >> L]): per-workgroup
+// partial sums, stored, or added to the rows already there (accumulate), on
+// nb_fixed workgroups (0: sized for n).  A chunk of a longer table starting
+// at a multiple of 2^L passes hi advanced by its start >> L.
 hipError_t launch_mle(hipStream_t st, u64 n, const u64 *T64, const u32 *T32, const u64 *lo,
-                      const u64 *hi, u32 L, u64 *partials, int *nblocks);
+                      const u64 *hi, u32 L, u64 *partials, int *nblocks, int accumulate = 0,
+                      int nb_fixed = 0);
 // Fold nparts rows of K partial sums into out[0..K).
 hipError_t launch_reduce_rows(hipStream_t st, int nparts, int K, const u64 *partials, u64 *out);
 
