@@ -2177,7 +2177,7 @@ extern "C" int f2_sumcheck_prove(const uint32_t *freq, uint64_t n, int on_device
     auto lay = [&](Arena &a) {
         v.A0 = a.take<u64>(std::max<u64>(n / 2, 2));
         v.A1 = a.take<u64>(std::max<u64>(n / 4, 2));
-        v.partials = a.take<u64>((u64)MAX_BLOCKS * 3);
+        v.partials = a.take<u64>((u64)MAX_BLOCKS * 6);  // two rounds' rows
         v.msgs = a.take<u64>(nm);
         v.chals = a.take<u64>(std::max<u32>(l, 1));
         v.ps = a.take<ProofState>(1);
@@ -2202,18 +2202,23 @@ extern "C" int f2_sumcheck_prove(const uint32_t *freq, uint64_t n, int on_device
         LAUNCH(PC_MISC, 0, launch_f2sc_init(st, v.ps, seed));
         u64 *bufs[2] = {v.A0, v.A1};
         const u64 *src = nullptr;
+        // round j's launch also finishes round j - 1 (its message and
+        // challenge), so the challenge is drawn one launch after its sums
+        int prev = 0;
         for (u32 j = 0; j < l; j++) {
             const u64 pairs = n >> (j + 1);
             u64 *dst = j == 0 ? nullptr : bufs[(j + 1) & 1];
             const double bytes = j == 0 ? pairs * 8.0 : (j == 1 ? pairs * 32.0 : pairs * 48.0);
+            u64 *pmsg = j ? v.msgs + 1 + 3 * (j - 1) : nullptr, *pchal = j ? v.chals + j - 1 : nullptr;
             LAUNCH(PC_F2SC, bytes,
-                   launch_f2sc_round(st, (int)std::min<u32>(j, 2), pairs, a32, src, dst,
-                                     j ? v.chals + j - 1 : nullptr, v.partials, &nb));
-            LAUNCH(PC_FINAL, nb * 24.0,
-                   launch_f2sc_final(st, nb, v.partials, v.ps, v.msgs + 1 + 3 * j, v.chals + j,
-                                     j == 0 ? v.msgs : nullptr));
+                   launch_f2sc_round(st, (int)j, pairs, a32, src, dst, v.ps, v.partials, prev, pmsg, pchal,
+                                     j == 1 ? v.msgs : nullptr, &nb));
+            prev = nb;
             if (j > 0) src = dst;
         }
+        LAUNCH(PC_FINAL, prev * 24.0,
+               launch_f2sc_final(st, (int)(l - 1), prev, v.partials, v.ps, v.msgs + 1 + 3 * (l - 1),
+                                 v.chals + l - 1, l == 1 ? v.msgs : nullptr));
     }
     HIP_TRY(hipMemcpyAsync(g_f2.h, v.msgs, nm * 8, hipMemcpyDeviceToHost, st));
     if (chals && l) HIP_TRY(hipMemcpyAsync(g_f2.h + nm, v.chals, l * 8ull, hipMemcpyDeviceToHost, st));

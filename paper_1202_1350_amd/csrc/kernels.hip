@@ -83,11 +83,28 @@ __device__ __forceinline__ void rows_total(int nparts, const u64 *partials, u64 
     for (int k = 0; k < K; k++) tot[k] = res[k];
 }
 
-__device__ __forceinline__ u64 draw(ProofState *ps) {
-    u64 s = ps->rng;
-    u64 r = fp::sm_field(s);
-    ps->rng = s;
+// Challenge d of the F2 sum-check, drawn from the state before it; the
+// state after it goes to *next when not NULL.
+__device__ __forceinline__ u64 draw(const ProofState *ps, int d, u64 *next) {
+    u64 s = ps->rng[d & 1];
+    const u64 r = fp::sm_field(s);
+    if (next) *next = s;
     return r;
+}
+
+// Message of F2 sum-check round d from its partial rows, challenge r_d, and
+// the state after it (one workgroup).
+__device__ __forceinline__ void f2sc_finish(int d, int nparts, const u64 *part, ProofState *ps, u64 *msg,
+                                            u64 *chal, u64 *f2) {
+    u64 t[3];
+    rows_total<3>(nparts, part, t);
+    if (threadIdx.x == 0) {
+        msg[0] = t[0];
+        msg[1] = t[1];
+        msg[2] = t[2];
+        if (f2) *f2 = add(t[0], t[1]);
+        *chal = draw(ps, d, &ps->rng[(d + 1) & 1]);
+    }
 }
 
 // ----------------------------------------------------------- evaluation (a3)
@@ -246,12 +263,19 @@ hipError_t launch_reduce_rows(hipStream_t st, int nparts, int K, const u64 *part
 // ------------------------------------------------------- F2 sum-check (a11)
 
 template <int J>  // 0: first round, 1: second round (u32 source), 2: later rounds
-__global__ void __launch_bounds__(BLOCK) k_f2sc_round(u64 nm, const u32 *a32, const u64 *Asrc,
-                                                      u64 *Aout, const u64 *rptr, u64 *partials) {
+__global__ void __launch_bounds__(BLOCK) k_f2sc_round(int j, u64 nm, const u32 *a32, const u64 *Asrc,
+                                                      u64 *Aout, ProofState *ps, u64 *part, int prev_parts,
+                                                      u64 *prev_msg, u64 *prev_chal, u64 *f2) {
+    const u32 nb = gridDim.x - (J > 0 ? 1 : 0);  // body workgroups
+    if (J > 0 && blockIdx.x == nb) {  // finishes round j - 1 beside the body
+        f2sc_finish(j - 1, prev_parts, part + 3ull * MAX_BLOCKS * ((j - 1) & 1), ps, prev_msg, prev_chal, f2);
+        return;
+    }
     u64 r = 0;
-    if (J > 0) r = *rptr;
+    if (J > 0) r = draw(ps, j - 1, nullptr);  // r_{j-1}: round j-1's sums are complete
+    const u64 stride = (u64)nb * BLOCK;
     u64 acc[3] = {0, 0, 0};
-    for (u64 m = GTID; m < nm; m += GSTRIDE) {
+    for (u64 m = GTID; m < nm; m += stride) {
         u64 v0, v1;
         if (J == 0) {
             const uint2 p = *reinterpret_cast<const uint2 *>(a32 + 2 * m);
@@ -273,42 +297,41 @@ __global__ void __launch_bounds__(BLOCK) k_f2sc_round(u64 nm, const u32 *a32, co
         acc[1] = add(acc[1], mul(v1, v1));
         acc[2] = add(acc[2], mul(d, d));
     }
-    block_store<3>(acc, partials + 3 * (u64)blockIdx.x);
+    block_store<3>(acc, part + 3ull * MAX_BLOCKS * (j & 1) + 3 * (u64)blockIdx.x);
 }
 
 hipError_t launch_f2sc_round(hipStream_t st, int j, u64 nm, const u32 *a32, const u64 *Asrc,
-                             u64 *Aout, const u64 *rptr, u64 *partials, int *nblocks) {
-    int nb = blocks_for(nm, 4);
+                             u64 *Aout, ProofState *ps, u64 *part, int prev_parts, u64 *prev_msg,
+                             u64 *prev_chal, u64 *f2, int *nblocks) {
+    const int nb = blocks_for(nm, 4);
     *nblocks = nb;
-    dim3 g(nb), b(BLOCK);
-    if (j == 0) hipLaunchKernelGGL(k_f2sc_round<0>, g, b, 0, st, nm, a32, Asrc, Aout, rptr, partials);
-    else if (j == 1) hipLaunchKernelGGL(k_f2sc_round<1>, g, b, 0, st, nm, a32, Asrc, Aout, rptr, partials);
-    else hipLaunchKernelGGL(k_f2sc_round<2>, g, b, 0, st, nm, a32, Asrc, Aout, rptr, partials);
+    const dim3 b(BLOCK);
+    if (j == 0)
+        hipLaunchKernelGGL(k_f2sc_round<0>, dim3(nb), b, 0, st, j, nm, a32, Asrc, Aout, ps, part, prev_parts,
+                           prev_msg, prev_chal, f2);
+    else if (j == 1)
+        hipLaunchKernelGGL(k_f2sc_round<1>, dim3(nb + 1), b, 0, st, j, nm, a32, Asrc, Aout, ps, part,
+                           prev_parts, prev_msg, prev_chal, f2);
+    else
+        hipLaunchKernelGGL(k_f2sc_round<2>, dim3(nb + 1), b, 0, st, j, nm, a32, Asrc, Aout, ps, part,
+                           prev_parts, prev_msg, prev_chal, f2);
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(BLOCK) k_f2sc_final(int nparts, const u64 *partials, ProofState *ps,
+__global__ void __launch_bounds__(BLOCK) k_f2sc_final(int j, int nparts, const u64 *part, ProofState *ps,
                                                       u64 *msg, u64 *chal, u64 *f2) {
-    u64 t[3];
-    rows_total<3>(nparts, partials, t);
-    if (threadIdx.x == 0) {
-        msg[0] = t[0];
-        msg[1] = t[1];
-        msg[2] = t[2];
-        if (f2) *f2 = add(t[0], t[1]);
-        *chal = draw(ps);
-    }
+    f2sc_finish(j, nparts, part + 3ull * MAX_BLOCKS * (j & 1), ps, msg, chal, f2);
 }
 
-hipError_t launch_f2sc_final(hipStream_t st, int nparts, const u64 *partials, ProofState *ps,
+hipError_t launch_f2sc_final(hipStream_t st, int j, int nparts, const u64 *part, ProofState *ps,
                              u64 *msg, u64 *chal, u64 *f2) {
-    hipLaunchKernelGGL(k_f2sc_final, dim3(1), dim3(BLOCK), 0, st, nparts, partials, ps, msg, chal, f2);
+    hipLaunchKernelGGL(k_f2sc_final, dim3(1), dim3(BLOCK), 0, st, j, nparts, part, ps, msg, chal, f2);
     return hipGetLastError();
 }
 
 __global__ void k_f2sc_init(ProofState *ps, u64 seed) {
     if (threadIdx.x == 0) {
-        ps->rng = fp::sm_state(seed, fp::PURPOSE_F2SC);
+        ps->rng[0] = fp::sm_state(seed, fp::PURPOSE_F2SC);
     }
 }
 

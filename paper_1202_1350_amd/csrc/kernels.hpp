@@ -20,8 +20,11 @@ enum Kind { KIND_ADD = 0, KIND_MUL = 1, KIND_MIXED = 2 };
 
 // Device state of an F2 sum-check.
 struct ProofState {
-    u64 rng;  // SplitMix64 state of the challenge stream
-    u64 pad[3];
+    // SplitMix64 states of the challenge stream: the state before draw d
+    // sits in rng[d & 1], so a launch reads one slot while its recorder
+    // writes the other
+    u64 rng[2];
+    u64 pad[2];
 };
 
 // Workgroup size of every reduction kernel, and the cap on workgroups per
@@ -77,13 +80,17 @@ hipError_t launch_reduce_rows(hipStream_t st, int nparts, int K, const u64 *part
 
 // ---- F2 sum-check (a11) -------------------------------------------------------
 // Round j over nm = n / 2^{j+1} pairs.  j = 0: pairs from the u32 vector.
-// j = 1: fold the u32 vector by r into Aout; j >= 2: fold Asrc (u64).
-// Partials: (sum A0^2, sum A1^2, sum (2 A1 - A0)^2).
+// j = 1: fold the u32 vector by r_0 into Aout; j >= 2: fold Asrc (u64) by
+// r_{j-1}, which every workgroup draws from the state round j-1 completed.
+// Partials of round j: rows (sum A0^2, sum A1^2, sum (2 A1 - A0)^2) at
+// part + 3 MAX_BLOCKS (j & 1).  For j >= 1 one more workgroup finishes round
+// j-1: its message (G(0), G(1), G(2)) into prev_msg (and F2 = G(0) + G(1)
+// into *f2 when not NULL), r_{j-1} into *prev_chal, and the state after it.
 hipError_t launch_f2sc_round(hipStream_t st, int j, u64 nm, const u32 *a32, const u64 *Asrc,
-                             u64 *Aout, const u64 *rptr, u64 *partials, int *nblocks);
-// Message (G(0), G(1), G(2)) into msg (and F2 = G(0) + G(1) into *f2 when
-// not NULL), then r drawn into *chal.
-hipError_t launch_f2sc_final(hipStream_t st, int nparts, const u64 *partials, ProofState *ps,
+                             u64 *Aout, ProofState *ps, u64 *part, int prev_parts, u64 *prev_msg,
+                             u64 *prev_chal, u64 *f2, int *nblocks);
+// Finish of the last round j over its nparts partial rows, as above.
+hipError_t launch_f2sc_final(hipStream_t st, int j, int nparts, const u64 *part, ProofState *ps,
                              u64 *msg, u64 *chal, u64 *f2);
 hipError_t launch_f2sc_init(hipStream_t st, ProofState *ps, u64 seed);
 // n == 1: the transcript is just F2 = a[0]^2.
