@@ -2205,7 +2205,10 @@ extern "C" int f2_sumcheck_prove(const uint32_t *freq, uint64_t n, int on_device
         // round j's launch also finishes round j - 1 (its message and
         // challenge), so the challenge is drawn one launch after its sums
         int prev = 0;
-        for (u32 j = 0; j < l; j++) {
+        // rounds from j0 on run as one tail once level j0 fits it
+        u32 j0 = l;
+        if (l >= 3) j0 = std::max<u32>(2, l > 12 ? l - 12 : 2);
+        for (u32 j = 0; j < j0; j++) {
             const u64 pairs = n >> (j + 1);
             u64 *dst = j == 0 ? nullptr : bufs[(j + 1) & 1];
             const double bytes = j == 0 ? pairs * 8.0 : (j == 1 ? pairs * 32.0 : pairs * 48.0);
@@ -2216,9 +2219,13 @@ extern "C" int f2_sumcheck_prove(const uint32_t *freq, uint64_t n, int on_device
             prev = nb;
             if (j > 0) src = dst;
         }
-        LAUNCH(PC_FINAL, prev * 24.0,
-               launch_f2sc_final(st, (int)(l - 1), prev, v.partials, v.ps, v.msgs + 1 + 3 * (l - 1),
-                                 v.chals + l - 1, l == 1 ? v.msgs : nullptr));
+        if (j0 < l)
+            LAUNCH(PC_FINAL, (n >> (j0 - 1)) * 8.0,
+                   launch_f2sc_tail(st, (int)j0, (int)l, src, prev, v.partials, v.ps, v.msgs, v.chals));
+        else
+            LAUNCH(PC_FINAL, prev * 24.0,
+                   launch_f2sc_final(st, (int)(l - 1), prev, v.partials, v.ps, v.msgs + 1 + 3 * (l - 1),
+                                     v.chals + l - 1, l == 1 ? v.msgs : nullptr));
     }
     HIP_TRY(hipMemcpyAsync(g_f2.h, v.msgs, nm * 8, hipMemcpyDeviceToHost, st));
     if (chals && l) HIP_TRY(hipMemcpyAsync(g_f2.h + nm, v.chals, l * 8ull, hipMemcpyDeviceToHost, st));

@@ -323,6 +323,48 @@ __global__ void __launch_bounds__(BLOCK) k_f2sc_final(int j, int nparts, const u
     f2sc_finish(j, nparts, part + 3ull * MAX_BLOCKS * (j & 1), ps, msg, chal, f2);
 }
 
+__global__ void __launch_bounds__(BLOCK) k_f2sc_tail(int j0, int l, const u64 *Asrc, int prev_parts,
+                                                     const u64 *part, ProofState *ps, u64 *msgs, u64 *chals) {
+    __shared__ __align__(16) u64 T[2][F2SC_TAIL];
+    __shared__ u64 tot[3];
+    const int d = j0 - 1;
+    f2sc_finish(d, prev_parts, part + 3ull * MAX_BLOCKS * (d & 1), ps, msgs + 1 + 3 * d, chals + d, nullptr);
+    u64 st = ps->rng[d & 1];
+    const u64 r0 = fp::sm_field(st);  // r_{j0-1}: round j0-1's sums are complete
+    u32 nt = 1u << (l - j0);          // entries of level j0
+    for (u32 e = threadIdx.x; e < nt; e += BLOCK) {
+        const u64x2 p = ld2(Asrc, 2 * e);
+        T[0][e] = add(p.x, mul(r0, sub(p.y, p.x)));
+    }
+    __syncthreads();
+    for (int j = j0, b = 0; j < l; j++, b ^= 1, nt >>= 1) {
+        const u32 half = nt >> 1;
+        u64 acc[3] = {0, 0, 0};
+        for (u32 m = threadIdx.x; m < half; m += BLOCK) {
+            const u64 v0 = T[b][2 * m], v1 = T[b][2 * m + 1], dd = sub(add(v1, v1), v0);
+            acc[0] = add(acc[0], mul(v0, v0));
+            acc[1] = add(acc[1], mul(v1, v1));
+            acc[2] = add(acc[2], mul(dd, dd));
+        }
+        block_store<3>(acc, tot);
+        __syncthreads();  // round j's message is complete
+        if (threadIdx.x < 3) msgs[1 + 3 * j + threadIdx.x] = tot[threadIdx.x];
+        const u64 r = fp::sm_field(st);
+        if (threadIdx.x == 0) chals[j] = r;
+        for (u32 m = threadIdx.x; m < half; m += BLOCK) {
+            const u64 v0 = T[b][2 * m], v1 = T[b][2 * m + 1];
+            T[b ^ 1][m] = add(v0, mul(r, sub(v1, v0)));
+        }
+        __syncthreads();  // the next level is complete (and tot is read)
+    }
+}
+
+hipError_t launch_f2sc_tail(hipStream_t st, int j0, int l, const u64 *Asrc, int prev_parts, const u64 *part,
+                            ProofState *ps, u64 *msgs, u64 *chals) {
+    hipLaunchKernelGGL(k_f2sc_tail, dim3(1), dim3(BLOCK), 0, st, j0, l, Asrc, prev_parts, part, ps, msgs, chals);
+    return hipGetLastError();
+}
+
 hipError_t launch_f2sc_final(hipStream_t st, int j, int nparts, const u64 *part, ProofState *ps,
                              u64 *msg, u64 *chal, u64 *f2) {
     hipLaunchKernelGGL(k_f2sc_final, dim3(1), dim3(BLOCK), 0, st, j, nparts, part, ps, msg, chal, f2);

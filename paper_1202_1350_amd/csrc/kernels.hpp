@@ -89,6 +89,15 @@ hipError_t launch_reduce_rows(hipStream_t st, int nparts, int K, const u64 *part
 hipError_t launch_f2sc_round(hipStream_t st, int j, u64 nm, const u32 *a32, const u64 *Asrc,
                              u64 *Aout, ProofState *ps, u64 *part, int prev_parts, u64 *prev_msg,
                              u64 *prev_chal, u64 *f2, int *nblocks);
+// The last rounds j0..l-1 in one workgroup, from level j0-1 of the table
+// (u64, 2 F2SC_TAIL entries at most, stored by round j0-1's launch): it
+// finishes round j0-1 (prev_parts rows), folds that level by r_{j0-1} into
+// LDS, then per round sums the message, and only after a barrier that
+// completes it draws the round's challenge and folds.  msgs and chals are
+// the transcript's bases.  j0 >= 2.
+constexpr int F2SC_TAIL = 4096;
+hipError_t launch_f2sc_tail(hipStream_t st, int j0, int l, const u64 *Asrc, int prev_parts, const u64 *part,
+                            ProofState *ps, u64 *msgs, u64 *chals);
 // Finish of the last round j over its nparts partial rows, as above.
 hipError_t launch_f2sc_final(hipStream_t st, int j, int nparts, const u64 *part, ProofState *ps,
                              u64 *msg, u64 *chal, u64 *f2);
