@@ -275,13 +275,27 @@ __global__ void __launch_bounds__(BLOCK) k_f2sc_round(int j, u64 nm, const u32 *
     if (J > 0) r = draw(ps, j - 1, nullptr);  // r_{j-1}: round j-1's sums are complete
     const u64 stride = (u64)nb * BLOCK;
     u64 acc[3] = {0, 0, 0};
-    for (u64 m = GTID; m < nm; m += stride) {
-        u64 v0, v1;
-        if (J == 0) {
+    if (J == 0) {
+        // u32 pairs (a, b): a^2, b^2 and ab are exact in 64 bits; their sums
+        // stay exact in 128 bits (a thread adds far fewer than 2^64 terms), and
+        // (2b - a)^2 = a^2 + 4 b^2 - 4 ab, so the thread reduces mod p once
+        fp::u128 saa = 0, sbb = 0, sab = 0;
+        for (u64 m = GTID; m < nm; m += stride) {
             const uint2 p = *reinterpret_cast<const uint2 *>(a32 + 2 * m);
-            v0 = p.x;
-            v1 = p.y;
-        } else if (J == 1) {
+            const u64 a = p.x, b = p.y;
+            saa += a * a;
+            sbb += b * b;
+            sab += a * b;
+        }
+        const u64 ra = fp::red128(saa), rb = fp::red128(sbb), rab = fp::red128(sab);
+        const u64 rb4 = add(add(rb, rb), add(rb, rb)), rab4 = add(add(rab, rab), add(rab, rab));
+        acc[0] = ra;
+        acc[1] = rb;
+        acc[2] = sub(add(ra, rb4), rab4);
+    }
+    for (u64 m = GTID; J > 0 && m < nm; m += stride) {
+        u64 v0, v1;
+        if (J == 1) {
             const uint4 p = *reinterpret_cast<const uint4 *>(a32 + 4 * m);
             v0 = add(p.x, mul(r, sub(p.y, p.x)));
             v1 = add(p.z, mul(r, sub(p.w, p.z)));
