@@ -1905,28 +1905,29 @@ int vs_reserve(size_t bytes, size_t host_words) {
 // for every table here (L <= 16).
 constexpr u64 VCHUNK = 1ull << 23;
 
-struct InputStream {
-    std::mutex mu;
-    int device = -1;
+struct InputStream {  // one per device, created on first use, kept until exit
     hipStream_t cs = nullptr;
     hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
 };
-InputStream g_is;
+constexpr int IS_DEVICES = 64;
+std::mutex g_is_mu;
+InputStream g_is[IS_DEVICES];
 
 // dbuf: device room for 2 min(n, VCHUNK) values.
 template <typename T>
 static int stream_mle(hipStream_t st, const T *in, u64 n, T *dbuf, const u64 *lo, const u64 *hi, u32 L,
                       u64 *partials, int *nb, u32 *bad_dev) {
-    std::lock_guard<std::mutex> lk(g_is.mu);
+    std::lock_guard<std::mutex> lk(g_is_mu);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    if (g_is.device != dev) {  // stream and events belong to one device
-        HIP_TRY(hipStreamCreateWithFlags(&g_is.cs, hipStreamNonBlocking));
+    if (dev < 0 || dev >= IS_DEVICES) return fail(GKR_ERR_DEVICE, "device index beyond the input streams");
+    InputStream &is = g_is[dev];
+    if (!is.cs) {  // stream and events belong to this device
+        HIP_TRY(hipStreamCreateWithFlags(&is.cs, hipStreamNonBlocking));
         for (int b = 0; b < 2; b++) {
-            HIP_TRY(hipEventCreateWithFlags(&g_is.copied[b], hipEventDisableTiming));
-            HIP_TRY(hipEventCreateWithFlags(&g_is.used[b], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&is.copied[b], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&is.used[b], hipEventDisableTiming));
         }
-        g_is.device = dev;
     }
     const u64 C = std::min<u64>(n, VCHUNK);
     const int nbf = blocks_for(C, 8);
@@ -1934,15 +1935,15 @@ static int stream_mle(hipStream_t st, const T *in, u64 n, T *dbuf, const u64 *lo
     for (u64 x0 = 0; x0 < n; x0 += C, k++) {
         const int b = (int)(k & 1);
         const u64 m = std::min<u64>(C, n - x0);
-        if (k >= 2) HIP_TRY(hipStreamWaitEvent(g_is.cs, g_is.used[b], 0));
-        HIP_TRY(hipMemcpyAsync(dbuf + b * C, in + x0, m * sizeof(T), hipMemcpyHostToDevice, g_is.cs));
-        HIP_TRY(hipEventRecord(g_is.copied[b], g_is.cs));
-        HIP_TRY(hipStreamWaitEvent(st, g_is.copied[b], 0));
+        if (k >= 2) HIP_TRY(hipStreamWaitEvent(is.cs, is.used[b], 0));
+        HIP_TRY(hipMemcpyAsync(dbuf + b * C, in + x0, m * sizeof(T), hipMemcpyHostToDevice, is.cs));
+        HIP_TRY(hipEventRecord(is.copied[b], is.cs));
+        HIP_TRY(hipStreamWaitEvent(st, is.copied[b], 0));
         const u64 *t64 = sizeof(T) == 8 ? (const u64 *)(dbuf + b * C) : nullptr;
         const u32 *t32 = sizeof(T) == 4 ? (const u32 *)(dbuf + b * C) : nullptr;
         if (t64) HIP_TRY(launch_check_range(st, t64, m, bad_dev));
         HIP_TRY(launch_mle(st, m, t64, t32, lo, hi + (x0 >> L), L, partials, nb, k > 0, nbf));
-        HIP_TRY(hipEventRecord(g_is.used[b], st));
+        HIP_TRY(hipEventRecord(is.used[b], st));
     }
     return GKR_OK;
 }
