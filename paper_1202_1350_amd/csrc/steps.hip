@@ -58,6 +58,18 @@ __device__ __forceinline__ u64 wave_sum63(u64 v) {
     return v;
 }
 
+// A value every lane holds the same copy of, moved to scalar registers.
+__device__ __forceinline__ u64 uniform(u64 v) {
+    const u32 lo = (u32)__builtin_amdgcn_readfirstlane((int)(u32)v);
+    const u32 hi = (u32)__builtin_amdgcn_readfirstlane((int)(u32)(v >> 32));
+    return ((u64)hi << 32) | lo;
+}
+__device__ __forceinline__ u64 lane_value(u64 v, u32 l) {  // l uniform
+    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, l);
+    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(v >> 32), l);
+    return ((u64)hi << 32) | lo;
+}
+
 // Workgroup sum of v; thread k < K writes total k to out[k].
 template <int K>
 __device__ __forceinline__ void block_store(u64 (&v)[K], u64 *out) {
@@ -761,15 +773,63 @@ __device__ __forceinline__ void level0_round(u32 ph, u32 hasC, u64 npairs, const
     block_store<3>(acc, row);
 }
 
+// Round 0 from the chunk sums: wire x's sums add its chunks
+// [xch[x], xch[x+1]).  A lane adds the chunks of its own wire when they are
+// few; a wire with more (the pattern entries of pattern matching feed up to
+// 2^18 gates) is summed by the whole wave, lanes striding over its chunks,
+// one such wire after another.  Whole waves iterate together, so the wave
+// reductions see every lane.
+constexpr u32 WT0_LANE_CHUNKS = 64;
 __device__ __forceinline__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
-    level0_round(a.ph, a.hasC, a.npairs, a.F, a.A, a.C, pp, c, row, [&](u64 x, u64 &sA, u64 &sC) {
-        sA = 0;
-        sC = 0;
-        for (u32 ch = a.xch[x]; ch < a.xch[x + 1]; ch++) {
-            sA = add(sA, a.partA[ch]);
-            sC = add(sC, a.partC[ch]);
+    const u64 v1 = a.ph == 2 ? pp.state[1] : 0;
+    const u32 lane = threadIdx.x & 63;
+    u64 acc[3] = {0, 0, 0};
+    for (u64 base = c.gtid - lane; base < a.npairs; base += c.gstride) {  // wave-uniform
+        const u64 m = base + lane;
+        const bool on = m < a.npairs;
+        u64 A[2], C[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            u32 c0 = 0, c1 = 0;
+            if (on) {
+                c0 = a.xch[2 * m + h];
+                c1 = a.xch[2 * m + h + 1];
+            }
+            const bool many = c1 - c0 > WT0_LANE_CHUNKS;
+            u64 sA = 0, sC = 0;
+            if (!many) {
+                for (u32 ch = c0; ch < c1; ch++) {
+                    sA = add(sA, a.partA[ch]);
+                    sC = add(sC, a.partC[ch]);
+                }
+            }
+            for (u64 hm = __ballot(many); hm; hm &= hm - 1) {
+                const u32 l = (u32)__ffsll((long long)hm) - 1;  // uniform
+                const u32 b0 = (u32)__builtin_amdgcn_readlane((int)c0, l);
+                const u32 b1 = (u32)__builtin_amdgcn_readlane((int)c1, l);
+                u64 wA = 0, wC = 0;
+                for (u32 ch = b0 + lane; ch < b1; ch += 64) {
+                    wA = add(wA, a.partA[ch]);
+                    wC = add(wC, a.partC[ch]);
+                }
+                wA = lane_value(wave_sum63(wA), 63);
+                wC = lane_value(wave_sum63(wC), 63);
+                if (lane == l) {
+                    sA = wA;
+                    sC = wC;
+                }
+            }
+            level0(a.ph, v1, sA, sC, A[h], C[h]);
+            if (!a.hasC) C[h] = 0;
         }
-    });
+        if (on) {
+            st2(a.A, 2 * m, A[0], A[1]);
+            if (a.hasC) st2(a.C, 2 * m, C[0], C[1]);
+            const u64x2 f = ld2(a.F, 2 * m);
+            table_terms(A[0], A[1], C[0], C[1], f.x, f.y, acc);
+        }
+    }
+    block_store<3>(acc, row);
 }
 
 __device__ __forceinline__ void step_wa0(const Wa0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
@@ -840,17 +900,6 @@ __device__ __forceinline__ u64 (*tail_parts())[TAIL_SLOTS] {
     return p;
 }
 
-// A value every lane holds the same copy of, moved to scalar registers.
-__device__ __forceinline__ u64 uniform(u64 v) {
-    const u32 lo = (u32)__builtin_amdgcn_readfirstlane((int)(u32)v);
-    const u32 hi = (u32)__builtin_amdgcn_readfirstlane((int)(u32)(v >> 32));
-    return ((u64)hi << 32) | lo;
-}
-__device__ __forceinline__ u64 lane_value(u64 v, u32 l) {  // l uniform
-    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, l);
-    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(v >> 32), l);
-    return ((u64)hi << 32) | lo;
-}
 
 // Sum over the wave of field elements, left in lane 63: as wave_sum63, but
 // the first three and the last three steps add without reducing (eight
