@@ -209,6 +209,18 @@ def test_c2_f2_4m_full_bit_exact():
     assert int(m[0]) == int((x.astype(object) ** 2).sum()) % P
     say("C2 verify")
     assert G().gkr_verify(gc, device_tensor(x), seed, m) == (True, -1, -1, 0)
+    # again in the launch shapes bench.py times: its committed table when it
+    # matches the kernel sources, else tuned on this proof as bench.py does
+    import bench
+    say("C2 in the launch shapes of bench.py")
+    xt = device_tensor(x)
+    try:
+        if not bench.load_tune_table(G(), bench.TUNE_FILE):
+            G().gkr_autotune([gc], [xt], reps=1)
+        m2, _ = G().gkr_prove(gc, xt, seed)
+        assert np.array_equal(m2, m)
+    finally:
+        G().gkr_tune_set(None)
 
 
 def test_c3_matmult_256_full_bit_exact():
