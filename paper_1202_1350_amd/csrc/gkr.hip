@@ -312,6 +312,7 @@ struct Workspace {
     u32 gepoch = 0;
     u64 *instage;  // host inputs land here
     size_t bytes = 0;  // device memory held
+    u32 gen = 0;       // the circuit's generation when the workspace was made
     u64 *h_msgs = nullptr, *h_chals = nullptr, *h_setup = nullptr;  // pinned staging
 };
 
@@ -334,6 +335,7 @@ struct gkr_circuit {
     std::mutex mu;
     Workspace *ws = nullptr;
     int omega_algo = GKR_OMEGA_TABLES;
+    u32 gen = 1;  // bumped when its workspaces go stale (algorithm change)
     std::vector<std::vector<u32>> h_in1, h_in2;  // host copies of the wires (grouping)
     std::vector<std::vector<u8>> h_type;         // host gate types of mixed layers (else empty)
     struct Group {  // gates of a layer grouped by the wire a phase binds
@@ -544,10 +546,12 @@ static void free_workspace(Workspace *ws) {
 }
 
 static void drop_batches_of(const gkr_circuit *c);
+static void drop_served_scratch_of(const gkr_circuit *c);
 
 extern "C" void gkr_circuit_destroy(gkr_circuit *c) {
     if (!c) return;
     drop_batches_of(c);
+    drop_served_scratch_of(c);
     free_workspace(c->ws);
     if (c->gmem) (void)hipFree(c->gmem);
     if (c->soa) (void)hipFree(c->soa);
@@ -558,12 +562,21 @@ extern "C" int gkr_circuit_set_algorithm(gkr_circuit *c, int omega_algo) {
     if (!c) return fail(GKR_ERR_INVALID, "circuit is NULL");
     if (omega_algo != GKR_OMEGA_GATES && omega_algo != GKR_OMEGA_TABLES)
         return fail(GKR_ERR_INVALID, "unknown omega-phase algorithm");
-    std::lock_guard<std::mutex> lk(c->mu);
-    if (c->omega_algo != omega_algo) {
-        free_workspace(c->ws);  // the step program is rebuilt on the next proof
-        c->ws = nullptr;
-        c->omega_algo = omega_algo;
-        c->ws_bytes = 0;
+    bool changed = false;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (c->omega_algo != omega_algo) {
+            free_workspace(c->ws);  // the step program is rebuilt on the next proof
+            c->ws = nullptr;
+            c->omega_algo = omega_algo;
+            c->ws_bytes = 0;
+            c->gen++;  // pooled server scratch of the old program is discarded
+            changed = true;
+        }
+    }
+    if (changed) {  // (a server takes its own lock before the circuit's)
+        drop_batches_of(c);
+        drop_served_scratch_of(c);
     }
     return GKR_OK;
 }
@@ -1367,6 +1380,7 @@ static int make_workspace(gkr_circuit *c, Workspace **out) {
     HIP_TRY(hipHostMalloc((void **)&ws->h_msgs, c->n_msgs * 8));
     HIP_TRY(hipHostMalloc((void **)&ws->h_chals, std::max<u64>(c->n_chals, 1) * 8));
     HIP_TRY(hipHostMalloc((void **)&ws->h_setup, 3 * 8));
+    ws->gen = c->gen;
     *out = ws.release();
     return GKR_OK;
 }
@@ -2347,6 +2361,7 @@ struct ServeReq {
     std::chrono::steady_clock::time_point t_submit, t_done;
     int state = 0;            // 0 queued, 1 running, 2 finishing, 3 done
     int err = GKR_OK;
+    std::string msg;          // what failed, when err != GKR_OK
 };
 
 size_t workspace_bytes(const Workspace *w) { return w ? w->bytes : 0; }
@@ -2371,36 +2386,51 @@ struct gkr_server {
     size_t ring_pos = 0;
     std::string err;
 
+    // Frees one workspace this server accounts for.
+    void drop(Workspace *w) {
+        used -= std::min<u64>(used, w->bytes);
+        free_workspace(w);
+    }
+
     // Scratch for r: pooled, or new if the budget allows (idle pooled scratch
     // of other circuits is released first).  1: got it; 0: wait for running
-    // proofs to return scratch; < 0: error (the request fails).
+    // proofs to return scratch; < 0: error (the request fails, r->msg says
+    // why).  Pooled scratch made before the circuit's program changed
+    // (another omega algorithm) is discarded.
     int acquire(ServeReq *r) {
         auto &v = pool[r->c];
-        if (!v.empty()) {
-            r->ws = v.back();
+        while (!v.empty()) {
+            Workspace *w = v.back();
             v.pop_back();
-            std::lock_guard<std::mutex> lk(r->c->mu);
-            const int rc = refresh_plan(r->c, *r->ws);
-            if (rc) {
-                pool[r->c].push_back(r->ws);
-                r->ws = nullptr;
-                return rc;
+            int rc;
+            {
+                std::lock_guard<std::mutex> lk(r->c->mu);
+                rc = w->gen != r->c->gen ? 1 : refresh_plan(r->c, *w);
             }
-            return 1;
+            if (rc == GKR_OK) {
+                r->ws = w;
+                return 1;
+            }
+            drop(w);  // stale or not re-plannable: make a fresh one below
         }
         size_t need = 0;
         {
             std::lock_guard<std::mutex> lk(r->c->mu);
             const int rc = workspace_size(r->c, &need);
-            if (rc) return rc;
+            if (rc) {
+                r->msg = g_err;
+                return rc;
+            }
         }
-        if (need > budget) return fail(GKR_ERR_NOMEM, "a proof's scratch exceeds the server's HBM budget");
+        if (need > budget) {
+            r->msg = "a proof's scratch exceeds the server's HBM budget";
+            return GKR_ERR_NOMEM;
+        }
         while (used + need > budget) {
             bool freed = false;
             for (auto &kv : pool)
                 if (!kv.second.empty()) {
-                    used -= kv.second.back()->bytes;
-                    free_workspace(kv.second.back());
+                    drop(kv.second.back());
                     kv.second.pop_back();
                     freed = true;
                     break;
@@ -2412,7 +2442,10 @@ struct gkr_server {
         {
             std::lock_guard<std::mutex> lk(r->c->mu);
             const int rc = make_workspace(r->c, &w);
-            if (rc) return rc;
+            if (rc) {
+                r->msg = g_err;
+                return rc;
+            }
         }
         used += w->bytes;
         r->ws = w;
@@ -2422,6 +2455,14 @@ struct gkr_server {
     void release(ServeReq *r) {
         if (r->ws) pool[r->c].push_back(r->ws);
         r->ws = nullptr;
+    }
+
+    // Idle scratch of circuit c (being destroyed, or its program changed).
+    void forget(const gkr_circuit *c) {
+        auto it = pool.find(const_cast<gkr_circuit *>(c));
+        if (it == pool.end()) return;
+        for (Workspace *w : it->second) drop(w);
+        pool.erase(it);
     }
 
     int start(ServeReq *r) {
@@ -2447,6 +2488,7 @@ struct gkr_server {
                 queued.pop_front();
                 r->err = got < 0 ? got : start(r);
                 if (r->err) {
+                    if (got > 0) r->msg = g_err;  // start() failed
                     r->state = 3;
                     release(r);
                     cv.notify_all();
@@ -2462,7 +2504,10 @@ struct gkr_server {
                 ServeReq *r = finishing[k];
                 if (hipEventQuery(r->done_ev) == hipSuccess) {
                     r->t_done = std::chrono::steady_clock::now();
-                    if (r->h_out[r->c->n_msgs]) r->err = GKR_ERR_RANGE;
+                    if (r->h_out[r->c->n_msgs]) {
+                        r->err = GKR_ERR_RANGE;
+                        r->msg = "input value not below p";
+                    }
                     r->state = 3;
                     release(r);
                     finishing.erase(finishing.begin() + k);
@@ -2501,10 +2546,15 @@ struct gkr_server {
             ring_pos = (ring_pos + 1) % ring.size();
             lk.lock();
             if (e != hipSuccess) {
-                err = hipGetErrorString(e);
+                // the proofs of the failed launch end with an error; their
+                // scratch may be mid-step, so it is freed rather than pooled
+                err = std::string("step launch failed: ") + hipGetErrorString(e);
                 for (ServeReq *r : running) {
                     r->err = GKR_ERR_DEVICE;
+                    r->msg = err;
                     r->state = 3;
+                    if (r->ws) drop(r->ws);
+                    r->ws = nullptr;
                 }
                 running.clear();
                 cv.notify_all();
@@ -2530,6 +2580,20 @@ struct gkr_server {
     }
 };
 
+// Live servers, so that a circuit's idle pooled scratch (whose step
+// programs point into the circuit's device arrays) is freed with the
+// circuit or when its program changes.
+static std::mutex g_servers_mu;
+static std::vector<gkr_server *> g_servers;
+
+static void drop_served_scratch_of(const gkr_circuit *c) {
+    std::lock_guard<std::mutex> lk(g_servers_mu);
+    for (gkr_server *s : g_servers) {
+        std::lock_guard<std::mutex> sl(s->mu);
+        s->forget(c);
+    }
+}
+
 extern "C" int gkr_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, gkr_server **out) {
     if (!out) return fail(GKR_ERR_INVALID, "out is NULL");
     *out = nullptr;
@@ -2544,6 +2608,10 @@ extern "C" int gkr_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, 
     for (auto &e : s->ring) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     gkr_server *raw = s.get();
     s->worker = std::thread([raw] { raw->loop(); });
+    {
+        std::lock_guard<std::mutex> lk(g_servers_mu);
+        g_servers.push_back(raw);
+    }
     *out = s.release();
     return GKR_OK;
 }
@@ -2580,14 +2648,15 @@ extern "C" int gkr_server_poll(gkr_server *s, uint64_t req_id, uint64_t *msgs, i
     ServeReq *r = it->second;
     *done = r->state == 3;
     if (!*done) return GKR_OK;
-    int err = r->err;
+    const int err = r->err;
+    const std::string msg = r->msg.empty() ? s->err : r->msg;
     if (!err && msgs) memcpy(msgs, r->h_out, r->c->n_msgs * 8);
     if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
     (void)hipEventDestroy(r->done_ev);
     (void)hipHostFree(r->h_out);
     s->reqs.erase(it);
     delete r;
-    if (err) return fail(err, err == GKR_ERR_RANGE ? "input value not below p" : s->err);
+    if (err) return fail(err, msg);
     return GKR_OK;
 }
 
@@ -2603,6 +2672,10 @@ extern "C" int gkr_server_stats(gkr_server *s, uint32_t *running, uint32_t *queu
 
 extern "C" void gkr_server_destroy(gkr_server *s) {
     if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(g_servers_mu);
+        g_servers.erase(std::remove(g_servers.begin(), g_servers.end(), s), g_servers.end());
+    }
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;

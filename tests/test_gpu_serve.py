@@ -123,3 +123,48 @@ def test_budget_limits_scratch_in_use():
             assert np.array_equal(res[ids[k]][0], want)
     finally:
         srv.close()
+
+
+def test_destroyed_circuit_releases_pooled_scratch():
+    """Idle pooled scratch refers to its circuit's device arrays: destroying
+    the circuit frees it, and a circuit created afterwards (possibly at the
+    same address) gets scratch of its own shape."""
+    import gc
+    O.set_threads(oracle_threads())
+    srv = G().Server(8 << 30, 4)
+    try:
+        ca = W.f2_circuit(1 << 12)
+        ga = G().Circuit.from_workload(ca)
+        say("serve: circuit A then destroy it")
+        wait_all(srv, [srv.submit(ga, W.f2_inputs(1 << 12, 1), 1)])
+        assert srv.stats()[2] > 0
+        del ga
+        gc.collect()
+        assert srv.stats()[2] == 0, "pooled scratch of a destroyed circuit kept"
+        cb = W.pm_circuit(1 << 10)
+        xb = W.pm_inputs(1 << 10, 3)[0]
+        for k in range(3):
+            gb = G().Circuit.from_workload(cb)
+            say("serve: circuit B after A was destroyed, round", k)
+            m = wait_all(srv, [rid := srv.submit(gb, xb, 9 + k)])[rid][0]
+            assert np.array_equal(m, O.prove(cb, xb, 9 + k)[0])
+            del gb
+            gc.collect()
+    finally:
+        srv.close()
+
+
+def test_algorithm_change_discards_pooled_scratch():
+    O.set_threads(oracle_threads())
+    c = W.matmult_circuit(8)
+    x = W.matmult_inputs(8, 4)
+    gc_ = G().Circuit.from_workload(c)
+    srv = G().Server(8 << 30, 4)
+    try:
+        for algo in (G().GKR_OMEGA_TABLES, G().GKR_OMEGA_GATES, G().GKR_OMEGA_TABLES):
+            gc_.set_algorithm(algo)
+            say("serve: omega algorithm", algo)
+            m = wait_all(srv, [rid := srv.submit(gc_, x, 5)])[rid][0]
+            assert np.array_equal(m, O.prove(c, x, 5)[0])
+    finally:
+        srv.close()
