@@ -6,6 +6,13 @@ paper's Table 2 family at n = 2^22 (GKR prove + verify of the F2 circuit,
 value = GKR prover gates/s = gates (inputs included, as Table 2 counts
 them) / mean time of gkr_prove, which includes device evaluation, every
 sum-check round and the transcript copy to the host.
+
+Further legs (each with its own flag to skip it): the F2 circuit at n = 2^10
+and MatMult at N = 256; a batch of 64 uneven proofs against the same proofs
+one by one; a proof server under Poisson arrivals against the same requests
+proved one by one; Table 2's F0-based circuits; the out-of-core memory
+strategies under device budgets; Table 3's non-interactive F2 protocol; and
+the CPU oracle on bounded samples at one thread and at every host thread.
 """
 import argparse
 import hashlib
@@ -18,6 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Modular products per second the chip can issue: 256 CUs x 4 SIMDs, one
+# wave64 VALU instruction per SIMD every 4 cycles at 2.4 GHz (3.93e13 32-bit
+# lane operations/s), 21 VALU instructions per product of the field module.
+ALU_PEAK_MULMOD = 256 * 4 * 64 / 4 * 2.4e9 / 21
 
 
 def kernel_source_hash():
@@ -135,39 +146,110 @@ def save_tune_table(G, path, note):
         f.write(f"table: {G.gkr_tune_get().hex()}\n")
 
 
-def cpu_baseline(log_n):
-    """The oracle (plain C, the tests' reference) on the host cores."""
+def cpu_info():
+    """Host CPU model (lscpu) and thread count."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def oracle_threads():
+    """Every host thread, at most 16 (the GPU machine's CPU share)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_baseline(W, np):
+    """The oracle (plain C, the tests' reference) on the host cores, on
+    bounded samples of the benchmark workloads: the F2 GKR circuit (C2a's
+    construction) at 2^20 inputs on every thread and 2^17 on one, the F2
+    sum-check (C2b's) at 2^24 and 2^21, and MatMult (C3's) at N = 64 and 32.
+    The headline sample is F2 at 2^20 on every thread."""
     from oracle import oracle as O
-    import workloads as W
-    threads = max(1, min(16, os.cpu_count() or 1))
     O.build(force=False)
-    O.set_threads(threads)
-    circ, x, seed = W.c2_f2(log_n)
+    T = oracle_threads()
+    res = {"host": cpu_info(), "samples": []}
+
+    def run(name, threads, gates, fn, unit="gates/s"):
+        O.set_threads(threads)
+        t = time.perf_counter()
+        fn()
+        dt = time.perf_counter() - t
+        res["samples"].append({"workload": name, "threads": threads, "seconds": dt,
+                               "value": gates / dt, "unit": unit})
+        return dt
+
+    circ20, x20, _ = W.c2_f2(20)
+    circ17, x17, _ = W.c2_f2(17)
+    head = run("F2 GKR prove, n=2^20, seed 2", T, circ20.gates, lambda: O.prove(circ20, x20, 2))
+    run("F2 GKR prove, n=2^17, seed 2", 1, circ17.gates, lambda: O.prove(circ17, x17, 2))
+    a24, a21 = W.f2sc_vector(1 << 24, 2), W.f2sc_vector(1 << 21, 2)
+    run("F2 sum-check prove, n=2^24, seed 2", T, 1 << 24, lambda: O.f2sc_prove(a24, 2), "values/s")
+    run("F2 sum-check prove, n=2^21, seed 2", 1, 1 << 21, lambda: O.f2sc_prove(a21, 2), "values/s")
+    for N, th in ((64, T), (32, 1)):
+        c, x = W.matmult_circuit(N), W.matmult_inputs(N, 3)
+        run(f"MatMult GKR prove, N={N}, seed 3", th, c.gates, lambda: O.prove(c, x, 3))
+    # the unverifiable computations the paper compares against (numpy, one pass)
     t = time.perf_counter()
-    O.prove(circ, x, seed)
-    dt = time.perf_counter() - t
-    return {"value": circ.gates / dt, "unit": "gates/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full oracle proof of the F2 circuit at n=2^{log_n} "
-                      f"({circ.gates} gates, seed 2) in {dt:.2f} s"}
+    _ = int((x20.astype(np.float64) ** 2).sum())
+    res["direct_f2_2p20_s"] = time.perf_counter() - t
+    res["headline"] = {"value": circ20.gates / head, "unit": "gates/s", "cores": T, "kind": "oracle",
+                       "sample": f"one full oracle proof of the F2 circuit at n=2^20 ({circ20.gates} gates, "
+                                 f"seed 2) in {head:.2f} s on {T} threads; the benchmark circuit is n=2^22",
+                       **cpu_info()}
+    return res
+
+
+def config_leg(G, W, np, torch, make, name, reps):
+    """One benchmark configuration proved and verified with its inputs
+    resident: mean prove time over reps after a warm-up proof, median of
+    five verifications."""
+    circ, x, seed = make()
+    gc = G.Circuit.from_workload(circ)
+    xt = torch.from_numpy(x.view(np.int64)).cuda().view(torch.uint64)
+    m, _ = G.gkr_prove(gc, xt, seed, want_chals=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        G.gkr_prove(gc, xt, seed, want_chals=False)
+    dt = (time.perf_counter() - t) / reps
+    tv = []
+    for _ in range(5):
+        t = time.perf_counter()
+        ok = G.gkr_verify(gc, xt, seed, m)[0]
+        tv.append(time.perf_counter() - t)
+        if not ok:
+            raise SystemExit(f"verifier rejected an honest transcript ({name})")
+    return {"workload": name, "gates": circ.gates, "rounds": gc.rounds, "msgs": gc.n_msgs,
+            "prove_ms": dt * 1e3, "gates_per_s": circ.gates / dt, "proofs_per_s": 1.0 / dt,
+            "verify_ms": 1e3 * sorted(tv)[2], "accepted": True}
 
 
 # Table 2's GPU prover times in seconds (the paper's GPU; context only).
 TABLE2_GPU_PROVE_S = {"F0": 128.5, "PM": 38.9, "MatMult": 39.6}
 
 
-def table2_leg(G, W, np, torch, reps, with_oracle):
+def table2_leg(G, W, np, torch, reps, with_oracle, keep=()):
     """Table 2's other three rows at its sizes, on circuits built on the F0
     (Fermat) stage: F0 of 2^21 values, pattern matching with the F0 count on
     a 2^19 text (q = 8), MatMult with the C = AB check (N = 256).  Prove and
     verify times with inputs resident; the oracle on a bounded sample of
-    each circuit family."""
+    each circuit family.  Returns the records and, for the names in keep,
+    (handle, inputs, seed, transcript) for the out-of-core leg."""
     from oracle import oracle as O
     fams = (("F0", W.f1_f0, lambda: (W.f0_circuit(1 << 12), W.f0_inputs(1 << 12, 6), 6), "F0 n=2^12"),
             ("PM", W.f1_pm_f0, lambda: (W.pm_f0_circuit(1 << 12, 8), W.pm_inputs(1 << 12, 7, 8)[0], 7),
              "PM-F0 text 2^12, q=8"),
             ("MatMult", W.f1_matmult_check,
              lambda: (W.matmult_check_circuit(16), W.matmult_check_inputs(16, 8)[0], 8), "MatMult-check N=16"))
-    out = {}
+    out, kept = {}, {}
     for name, make, small, small_name in fams:
         circ, x, seed = make()
         gc = G.Circuit.from_workload(circ)
@@ -187,7 +269,7 @@ def table2_leg(G, W, np, torch, reps, with_oracle):
         if with_oracle:
             sc, sx, ss = small()
             O.build(force=False)
-            threads = max(1, min(16, os.cpu_count() or 1))
+            threads = oracle_threads()
             O.set_threads(threads)
             t = time.perf_counter()
             O.prove(sc, sx, ss)
@@ -195,7 +277,51 @@ def table2_leg(G, W, np, torch, reps, with_oracle):
             rec["oracle"] = {"gates_per_s": sc.gates / to, "cores": threads,
                              "sample": f"{small_name} ({sc.gates} gates) in {to:.2f} s"}
         out[name] = rec
+        if name in keep:
+            kept[name] = (gc, circ.name, xt, seed, m, dt)
         del gc, xt, circ, x
+    return out, kept
+
+
+MEM_NAMES = {0: "resident (no copying)", 1: "copy once per layer", 2: "copy every message"}
+
+
+def ooc_leg(G, np, torch, kept, reps):
+    """Out-of-core proofs (Sec. 5.1.2, 5.1.3): each circuit proved under
+    device budgets of 1/4 and 1/8 of what its resident proof needs (the
+    first memory strategy that fits), and F0 in both strategies, against the
+    resident proof; transcripts must be bit-equal."""
+    out = {}
+    for name, (gc, cname, xt, seed, m_res, t_res) in kept.items():
+        need = {k: gc.memory_need(k) for k in (0, 1, 2)}
+        runs = []
+        plans = [("budget 1/4", G.GKR_MEM_AUTO, need[0][0] // 4), ("budget 1/8", G.GKR_MEM_AUTO, need[0][0] // 8)]
+        if name == "F0":
+            plans += [("forced", G.GKR_MEM_LAYER, 0), ("forced", G.GKR_MEM_MESSAGE, 0)]
+        for label, mode, budget in plans:
+            chosen = gc.set_memory(mode, budget)
+            m, _ = G.gkr_prove(gc, xt, seed, want_chals=False)  # scratch set up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                G.gkr_prove(gc, xt, seed, want_chals=False)
+            dt = (time.perf_counter() - t) / reps
+            runs.append({"what": label, "device_budget_bytes": budget, "mode": MEM_NAMES[chosen],
+                         "device_bytes": need[chosen][0], "host_bytes": need[chosen][1],
+                         "prove_ms": dt * 1e3, "slowdown_vs_resident": dt / t_res,
+                         "bit_exact_vs_resident": bool(np.array_equal(m, m_res))})
+            print(f"out of core {name} {label} {MEM_NAMES[chosen]}: {dt * 1e3:.1f} ms "
+                  f"({dt / t_res:.1f}x resident)", file=sys.stderr, flush=True)
+        gc.set_memory(G.GKR_MEM_RESIDENT)
+        rec = {"circuit": cname, "resident_prove_ms": t_res * 1e3,
+               "need_bytes": {MEM_NAMES[k]: {"device": v[0], "host": v[1]} for k, v in need.items()},
+               "runs": runs}
+        layer = [r for r in runs if r["mode"] == MEM_NAMES[1]]
+        msg = [r for r in runs if r["mode"] == MEM_NAMES[2]]
+        if layer and msg:
+            rec["message_vs_layer"] = msg[-1]["prove_ms"] / layer[-1]["prove_ms"]
+            rec["paper_message_vs_layer"] = "< 3x (preliminary, Sec. 5.1.3)"
+        out[name] = rec
     return out
 
 
@@ -246,93 +372,153 @@ def table3_leg(G, np, torch, reps, with_oracle):
     return res
 
 
-def batch_leg(G, W, np, torch, reps, tune):
+def launch_roofline(prof_entry, alu_peak, kernel):
+    """HBM and ALU fractions of a kernel class from its profiled launches
+    (total ms, launches, algorithmic bytes, algorithmic products)."""
+    ms, n, by, mo = prof_entry
+    if not n or ms <= 0:
+        return None
+    gbs = by / (ms * 1e-3) / 1e9
+    mps = mo / (ms * 1e-3)
+    fh, fa = gbs / HBM_PEAK_GBS, mps / alu_peak
+    return {"kernel": kernel, "launches": n, "avg_launch_us": ms * 1e3 / n,
+            "algorithmic_bytes_per_launch": by / n, "algorithmic_products_per_launch": mo / n,
+            "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fh},
+            "alu": {"achieved": mps / 1e9, "peak": alu_peak / 1e9, "unit": "Gmulmod/s", "frac": fa},
+            "bound": "alu" if fa > fh else "hbm"}
+
+
+def batch_leg(G, W, np, torch, reps, tune, alu_peak):
     """64 uneven proofs (F2 n log-uniform in [2^12, 2^20], PM text in
-    [2^14, 2^18], seed 4): the plain path proves them one by one, the
-    batched path in one launch per step (graph replay).  Both must give the
-    same transcripts.  Launch shapes are first tuned on these circuits."""
+    [2^14, 2^18], seed 4): the plain path proves them one by one (one
+    gkr_prove each, that proof's own launches replayed from its graph; no
+    launch fuses proofs), the batched path in one launch per step (graph
+    replay).  Both must give the same transcripts.  Launch shapes are tuned
+    on these circuits for this leg and restored afterwards."""
     mix = W.batch_mix(4, 64)
     circs = [G.Circuit.from_workload(c) for _, c, _, _ in mix]
     xs = [torch.from_numpy(x.view(np.int64)).cuda().view(torch.uint64) for _, _, x, _ in mix]
     seeds = [sd for _, _, _, sd in mix]
     gates = sum(c.gates for c in circs)
+    saved = G.gkr_tune_get()
     tune_s = None
-    if tune:
+    try:
+        if tune:
+            t = time.perf_counter()
+            G.gkr_autotune(circs, xs, reps=1)
+            tune_s = time.perf_counter() - t
+        plain = [G.gkr_prove(c, x, sd, want_chals=False)[0] for c, x, sd in zip(circs, xs, seeds)]
+        batched = G.gkr_batch_prove(circs, xs, seeds)
+        same = all(np.array_equal(a, b) for a, b in zip(plain, batched))
+        torch.cuda.synchronize()
         t = time.perf_counter()
-        G.gkr_autotune(circs, xs, reps=1)
-        tune_s = time.perf_counter() - t
-    plain = [G.gkr_prove(c, x, sd, want_chals=False)[0] for c, x, sd in zip(circs, xs, seeds)]
-    batched = G.gkr_batch_prove(circs, xs, seeds)
-    same = all(np.array_equal(a, b) for a, b in zip(plain, batched))
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(reps):
-        for c, x, sd in zip(circs, xs, seeds):
-            G.gkr_prove(c, x, sd, want_chals=False)
-    t_plain = (time.perf_counter() - t) / reps
-    t = time.perf_counter()
-    for _ in range(reps):
+        for _ in range(reps):
+            for c, x, sd in zip(circs, xs, seeds):
+                G.gkr_prove(c, x, sd, want_chals=False)
+        t_plain = (time.perf_counter() - t) / reps
+        t = time.perf_counter()
+        for _ in range(reps):
+            G.gkr_batch_prove(circs, xs, seeds)
+        t_batch = (time.perf_counter() - t) / reps
+        # the batched kernel's launches timed one by one (outside the timed region)
+        G.gkr_profile_read()
+        G.gkr_profile_enable(1)
         G.gkr_batch_prove(circs, xs, seeds)
-    t_batch = (time.perf_counter() - t) / reps
+        G.gkr_profile_enable(0)
+        prof = G.gkr_profile_read()
+    finally:
+        G.gkr_tune_set(saved)
     return {"workload": "64 uneven proofs: F2 n=2^[12,20], PM text 2^[14,18] (seed 4)",
             "proofs": len(circs), "gates": gates, "bit_exact_batched_vs_plain": same,
             "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
+            "plain_path": "one gkr_prove per proof, each replaying its own graph of launches",
             "plain_gates_per_s": gates / t_plain, "batched_gates_per_s": gates / t_batch,
             "batched_proofs_per_s": len(circs) / t_batch, "speedup": t_plain / t_batch,
-            "autotune_seconds": tune_s}
+            "launch_shapes": "tuned on this batch for this leg (then restored)" if tune else "defaults",
+            "autotune_seconds": tune_s,
+            "roofline": launch_roofline(prof.get("batch_step", (0, 0, 0, 0)), alu_peak,
+                                        "gkr::k_step_jobs(gkr::JobEntry const*, unsigned int)")}
 
 
-def serve_leg(G, W, np, n_req, n_sat, rates):
-    """Poisson proof requests (seed 5): type uniform over F2 (n = 2^u, u an
-    integer uniform in [14, 22]), MatMult (N in {64, 128, 256}) and PM (text
-    2^16, pattern 8).  Circuits are registered once per shape, as a service
-    would.  First the closed-loop saturation rate (n_sat requests submitted
-    at once), then open-loop arrivals at the given fractions of it, n_req
-    requests per point; the first 10% of each point are warm-up.  Latency
-    runs from the scheduled arrival to completion."""
-    total = n_sat + n_req * len(rates)
-    draws = W.splitmix64(5, 5, 4 * total)
-    shapes = {}
-
-    def shape(kind, size):
-        key = (kind, size)
-        if key not in shapes:
-            if kind == "F2":
-                c, x = W.f2_circuit(size), W.f2_inputs(size, 50 + size)
-            elif kind == "MM":
-                c, x = W.matmult_circuit(size), W.matmult_inputs(size, 50 + size)
-            else:
-                c, x = W.pm_circuit(size), W.pm_inputs(size, 50 + size)[0]
-            shapes[key] = (G.Circuit.from_workload(c), x, c.gates)
-        return shapes[key]
-
-    def request(k):
-        u = int(draws[4 * k] % np.uint64(3))
-        if u == 0:
-            kind, size = "F2", 1 << (14 + int(draws[4 * k + 1] % np.uint64(9)))
-        elif u == 1:
+def serve_requests(W, np, total, seed=5):
+    """Poisson proof requests (seed 5, purpose 5): type uniform over F2 (n =
+    2^u rounded up to 16 sizes per octave, u uniform in [14, 22]), MatMult
+    (N in {64, 128, 256}) and PM (text 2^16, pattern 8); per request (kind,
+    size, proof seed, unit exponential gap)."""
+    import math
+    draws = W.splitmix64(seed, 5, 4 * total)
+    reqs = []
+    for k in range(total):
+        kind = int(draws[4 * k] % np.uint64(3))
+        v01 = float(draws[4 * k + 1] >> np.uint64(11)) / float(1 << 53)
+        if kind == 0:
+            e = 14.0 + 8.0 * v01
+            g = 1 << (int(e) - 4)
+            n = min(1 << 22, int(math.ceil(2.0 ** e / g)) * g)
+            kind, size = "F2", n
+        elif kind == 1:
             kind, size = "MM", (64, 128, 256)[int(draws[4 * k + 1] % np.uint64(3))]
         else:
             kind, size = "PM", 1 << 16
-        gap = -np.log(1.0 - float(draws[4 * k + 2] >> np.uint64(11)) / float(1 << 53))
-        return kind, size, int(draws[4 * k + 3] >> np.uint64(8)), gap
+        gap = -math.log(1.0 - float(draws[4 * k + 2] >> np.uint64(11)) / float(1 << 53))
+        reqs.append((kind, size, int(draws[4 * k + 3] >> np.uint64(8)), gap))
+    return reqs
 
-    reqs = [request(k) for k in range(total)]
+
+def serve_leg(G, W, np, n_req, n_sat, rates, alu_peak):
+    """The Poisson request mix (serve_requests) on a continuous-batching
+    server (32 slots, 32 GiB budget).  The circuit of every distinct shape
+    is created before timing, as a service loads its circuits.  First the
+    closed-loop saturation rate (n_sat requests submitted at once), then the
+    same n_sat requests proved one by one with gkr_prove (the plain path;
+    transcripts must be bit-equal to the served ones), then open-loop
+    arrivals at the given fractions of saturation, n_req requests per point,
+    the first 10% of each point warm-up.  Latency runs from the scheduled
+    arrival to completion."""
+    total = n_sat + n_req * len(rates)
+    reqs = serve_requests(W, np, total)
+    shapes = {}
     for kind, size, _, _ in reqs:
-        shape(kind, size)
+        if (kind, size) in shapes:
+            continue
+        if kind == "F2":
+            c, x = W.f2_circuit(size), W.f2_inputs(size, 50 + size)
+        elif kind == "MM":
+            c, x = W.matmult_circuit(size), W.matmult_inputs(size, 50 + size)
+        else:
+            c, x = W.pm_circuit(size), W.pm_inputs(size, 50 + size)[0]
+        shapes[(kind, size)] = (G.Circuit.from_workload(c), x, c.gates)
+
+    def shape(kind, size):
+        return shapes[(kind, size)]
+
     srv = G.Server(32 << 30, 32)
     try:
-        # warm every shape's scratch pool
-        ids = [srv.submit(shape(k, sz)[0], shape(k, sz)[1], 1) for (k, sz) in list(shapes)]
+        ids = [srv.submit(c, x, 1) for c, x, _ in shapes.values()]  # every shape's scratch pool warmed
         while ids:
             ids = [r for r in ids if not srv.poll(r)[0]]
         # closed loop: all requests at once
+        sat_reqs = reqs[:n_sat]
+        sat_gates = sum(shape(k, sz)[2] for k, sz, _, _ in sat_reqs)
         t0 = time.perf_counter()
-        ids = [srv.submit(shape(k, sz)[0], shape(k, sz)[1], sd) for k, sz, sd, _ in reqs[:n_sat]]
-        pending = set(ids)
+        ids = [srv.submit(shape(k, sz)[0], shape(k, sz)[1], sd) for k, sz, sd, _ in sat_reqs]
+        served, pending = {}, set(ids)
         while pending:
-            pending = {r for r in pending if not srv.poll(r)[0]}
-        sat = n_sat / (time.perf_counter() - t0)
+            for r in list(pending):
+                done, m, _ = srv.poll(r)
+                if done:
+                    served[r] = m
+                    pending.discard(r)
+        t_sat = time.perf_counter() - t0
+        sat = n_sat / t_sat
+        # the same requests, one gkr_prove each (host inputs, as the server takes them)
+        for c, x, _ in shapes.values():
+            G.gkr_prove(c, x, 1, want_chals=False)  # each circuit's scratch and graph set up
+        t0 = time.perf_counter()
+        alone = [G.gkr_prove(shape(k, sz)[0], shape(k, sz)[1], sd, want_chals=False)[0]
+                 for k, sz, sd, _ in sat_reqs]
+        t_plain = time.perf_counter() - t0
+        exact = all(np.array_equal(served[r], a) for r, a in zip(ids, alone))
         points = []
         for pi, frac in enumerate(rates):
             rate = frac * sat
@@ -373,12 +559,32 @@ def serve_leg(G, W, np, n_req, n_sat, rates):
             print(f"serve point {frac:.2f}x: {points[-1]['proofs_per_s']:.1f} proofs/s, "
                   f"p50 {points[-1]['p50_ms']:.1f} ms, p99 {points[-1]['p99_ms']:.1f} ms",
                   file=sys.stderr, flush=True)
+        # the server's launches timed one by one (outside the timed region)
+        G.gkr_profile_read()
+        G.gkr_profile_enable(1)
+        ids = [srv.submit(shape(k, sz)[0], shape(k, sz)[1], sd) for k, sz, sd, _ in reqs[:min(100, n_sat)]]
+        while ids:
+            ids = [r for r in ids if not srv.poll(r)[0]]
+        G.gkr_profile_enable(0)
+        prof = G.gkr_profile_read()
     finally:
         srv.close()
-    return {"workload": "Poisson mix of F2 n=2^[14..22], MatMult N in {64,128,256}, "
-                        "PM text 2^16 (seed 5); 32 slots, 32 GiB budget",
+    kinds = {}
+    for kind, size in shapes:
+        kinds.setdefault(kind, set()).add(size)
+    return {"workload": "Poisson mix of F2 n=2^u (u uniform in [14,22], 16 sizes per octave), MatMult "
+                        "N in {64,128,256}, PM text 2^16 (seed 5); 32 slots, 32 GiB budget",
+            "distinct_shapes": {k: len(v) for k, v in kinds.items()},
             "requests_per_point": n_req, "warmup_fraction": 0.1,
-            "closed_loop_requests": n_sat, "closed_loop_proofs_per_s": sat, "points": points}
+            "closed_loop_requests": n_sat, "closed_loop_proofs_per_s": sat,
+            "closed_loop_gates_per_s": sat_gates / t_sat,
+            "plain_same_requests": {"path": "one gkr_prove per request, host inputs",
+                                    "proofs_per_s": n_sat / t_plain, "gates_per_s": sat_gates / t_plain},
+            "served_vs_plain_gates_per_s": t_plain / t_sat,
+            "bit_exact_served_vs_alone": exact,
+            "points": points,
+            "roofline": launch_roofline(prof.get("serve_step", (0, 0, 0, 0)), alu_peak,
+                                        "gkr::k_step_table(gkr::JobTable)")}
 
 
 def mulmod_rate(G, torch, dev):
@@ -418,7 +624,10 @@ def main():
     ap.add_argument("--log-n", type=int, default=22)
     ap.add_argument("--f2sc-log-n", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-log-n", type=int, default=22)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the F2 n=2^10 (seed 1) and MatMult N=256 (seed 3) legs")
+    ap.add_argument("--no-ooc", action="store_true",
+                    help="skip the out-of-core memory strategies (F0 2^21, MatMult check N=256)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-table2", action="store_true",
@@ -503,11 +712,13 @@ def main():
     # launch stream) cost CPU time per launch, so they run in a replay of the
     # same proofs after the timed region, leaving the timed steps clean.
     G.gkr_profile_read()
-    G.gkr_profile_enable(True)
+    G.gkr_profile_launches()
+    G.gkr_profile_enable(2)
     for _ in range(args.steps):
         G.gkr_prove(gc, xt, seed, want_chals=False)
-    G.gkr_profile_enable(False)
+    G.gkr_profile_enable(0)
     prof = G.gkr_profile_read()
+    per_launch = G.gkr_profile_launches()
 
     if args.copy_calibration_mib:
         src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
@@ -516,15 +727,51 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    peak_mm = mulmod_rate(G, torch, dev)
+    alu_peak = ALU_PEAK_MULMOD
     T = np.array(times)
     prove_s = float(T[:, 0].mean())
     value = circ.gates / prove_s
     # dominant prover kernel: the step kernel with the most device time
     prover_classes = [k for k in prof if prof[k][1] > 0 and k.startswith("step_") and k[5:] in STEP_KINDS]
     dom = max(prover_classes, key=lambda k: prof[k][0])
-    ms, launches, by = prof[dom]
+    ms, launches, by, mo = prof[dom]
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    alu_achieved = mo / (ms * 1e-3) if ms > 0 else 0.0
     traffic = measured_traffic(dom)
+    fh, fa = achieved / HBM_PEAK_GBS, alu_achieved / alu_peak
+    # both bounds per size class (ceil log2 of a launch's work items)
+    buckets = {}
+    for cls, sc, lms, lby, lmo in per_launch:
+        if cls != dom:
+            continue
+        b = buckets.setdefault(sc, [0, 0.0, 0.0, 0.0])
+        b[0] += 1
+        b[1] += lms
+        b[2] += lby
+        b[3] += lmo
+    by_size = []
+    for sc in sorted(buckets):
+        n_, t_, b_, m_ = buckets[sc]
+        gbs, mps = b_ / (t_ * 1e-3) / 1e9, m_ / (t_ * 1e-3)
+        by_size.append({"size_class_log2_items": sc, "launches_per_proof": n_ / args.steps,
+                        "avg_launch_us": t_ * 1e3 / n_, "bytes_per_launch": b_ / n_,
+                        "hbm_frac": gbs / HBM_PEAK_GBS, "alu_frac": mps / alu_peak,
+                        "bound": "alu" if mps / alu_peak > gbs / HBM_PEAK_GBS else "hbm"})
+    if fa > fh:
+        roof = {"bound": "alu", "achieved": alu_achieved / 1e9, "peak": alu_peak / 1e9,
+                "unit": "Gmulmod/s", "frac": fa}
+    else:
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fh}
+    roof.update({"traffic": traffic, "kernel": rocprof_kernel_name(dom), "class": dom,
+                 "avg_launch_us": ms * 1e3 / launches if launches else None,
+                 "algorithmic_bytes_per_launch": by / launches if launches else None,
+                 "algorithmic_products_per_launch": mo / launches if launches else None,
+                 "hbm_frac": fh, "alu_frac": fa, "by_size_class": by_size,
+                 "alu_peak_note": "21 VALU instructions per modular product (the field module's "
+                                  "compiled product), one wave64 instruction per SIMD per 4 cycles, "
+                                  "256 CUs x 4 SIMDs at 2.4 GHz; measured product probe "
+                                  f"{peak_mm / 1e9:.0f} Gmulmod/s"})
     line = {
         "metric": "GKR prover gates/s (batched vs plain, bit-exact); proofs/s + p50/p99 latency",
         "value": value,
@@ -547,37 +794,44 @@ def main():
                          "f2_sumcheck_prove": float(T[:, 2].mean()) * 1e3,
                          "f2_sumcheck_verify": float(T[:, 3].mean()) * 1e3},
         "kernels_per_proof": {k: {"ms": v[0] / args.steps, "launches": v[1] / args.steps,
-                        "GB_per_s": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None}
-                    for k, v in prof.items() if v[1]},
+                                  "GB_per_s": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None,
+                                  "Gmulmod_per_s": (v[3] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None}
+                              for k, v in prof.items() if v[1]},
         "autotune": tune,
-        "roofline": {"kernel": rocprof_kernel_name(dom), "class": dom, "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "avg_launch_us": ms * 1e3 / launches if launches else None,
-                     "algorithmic_bytes_per_launch": by / launches if launches else None,
-                     "traffic": traffic},
+        "roofline": roof,
     }
-    peak_mm = mulmod_rate(G, torch, dev)
     lm = line_mulmods(circ)
     if "step_line" in prof and prof["step_line"][0] > 0:
         line_rate = lm * args.steps / (prof["step_line"][0] * 1e-3)
-        line["alu"] = {"mulmod_peak_per_s": peak_mm,
+        line["alu"] = {"mulmod_peak_per_s": alu_peak, "mulmod_probe_per_s": peak_mm,
                        "peak_probe": "2^24 independent chains of 256 dependent products",
                        "line_kernel_mulmods_per_proof": lm,
                        "line_kernel_mulmods_per_s": line_rate,
-                       "line_kernel_frac_of_peak": line_rate / peak_mm}
+                       "line_kernel_frac_of_peak": line_rate / alu_peak}
+    if not args.no_configs:
+        line["configs"] = {
+            "F2 n=2^10": config_leg(G, W, np, torch, W.c1_f2, "F2 GKR n=2^10, seed 1", 50),
+            "MatMult N=256": config_leg(G, W, np, torch, W.c3_matmult, "MatMult GKR N=256, seed 3", 10)}
     if not args.no_batch:
-        line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2), args.autotune != "off")
+        line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2), args.autotune != "off",
+                                    alu_peak)
     if not args.no_serve:
         k = max(1, args.serve_points)
         rates = [0.1 * 15.0 ** (j / (k - 1)) for j in range(k)] if k > 1 else [1.0]
-        line["served"] = serve_leg(G, W, np, args.serve_requests, 200, rates)
+        line["served"] = serve_leg(G, W, np, args.serve_requests, 200, rates, alu_peak)
+    kept = {}
     if not args.no_table2:
-        line["table2_circuits"] = table2_leg(G, W, np, torch, 3, not args.no_cpu_baseline)
+        line["table2_circuits"], kept = table2_leg(G, W, np, torch, 3, not args.no_cpu_baseline,
+                                                   () if args.no_ooc else ("F0", "MatMult"))
+    if kept:
+        line["out_of_core"] = ooc_leg(G, np, torch, kept, 2)
+    kept = None
     if not args.no_table3:
         line["table3_noninteractive_f2"] = table3_leg(G, np, torch, 5, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_log_n)
+        cb = cpu_baseline(W, np)
+        line["cpu_baseline"] = cb["headline"]
+        line["cpu_oracle_samples"] = cb
     print(json.dumps(line), flush=True)
 
 

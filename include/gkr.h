@@ -3,7 +3,7 @@
  *
  * Method: Thaler, Roberts, Mitzenmacher, Pfister, "Verifiable Computation
  * with Massively Parallel Interactive Proofs" (GKR protocol, Sec. 3.1;
- * parallel prover, Sec. 4.1.1; verifier, Sec. 4.1.2; field, Sec. 5.1).
+ * parallel prover, Sec. 4.1.1; verifier, Sec. 4.1.2; field, Sec. 6.1).
  *
  * Conventions shared by every entry point
  *   - Field elements are uint64_t in canonical form, 0 <= x < p.
@@ -104,6 +104,47 @@ void gkr_circuit_destroy(gkr_circuit *c);
  * Must not be called while a proof on the circuit runs.
  * Errors: GKR_ERR_INVALID. */
 int gkr_circuit_set_algorithm(gkr_circuit *c, int omega_algo);
+
+/* Memory strategies for a circuit's proofs (Sec. 5.1.1 - 5.1.3).
+ *   GKR_MEM_RESIDENT  "no copying": the gate arrays and every layer's
+ *                     tables stay in device memory (the default).
+ *   GKR_MEM_LAYER     "copy once per layer": the gate arrays and the gate
+ *                     value tables V_i of all layers live in pinned host
+ *                     memory; the device holds three value-table slots and
+ *                     two gate-array slots sized for the widest layer, plus
+ *                     the round tables.  Evaluation copies each V_i out as
+ *                     it is written; layer i's sum-check reads V_i, V_{i+1}
+ *                     and its gate groups from the slots while V_{i+2} and
+ *                     layer i+1's groups are copied in on a second stream.
+ *   GKR_MEM_MESSAGE   "copy every message": the gate arrays, value tables
+ *                     and round tables all live in pinned host memory and
+ *                     every round's kernels read and write them in place
+ *                     through the host link, so each message moves its
+ *                     layer's data again; the device holds only the small
+ *                     per-proof state (eq half tables, partial rows,
+ *                     transcript, step program).
+ *   GKR_MEM_AUTO      the first of the three whose device bytes fit.
+ * Transcripts do not depend on the mode.  Proofs in GKR_MEM_LAYER are
+ * launched one by one (no graph replay) and cannot be batched; a server
+ * runs a circuit that is not resident, or whose resident scratch exceeds
+ * its budget, in GKR_MEM_MESSAGE. */
+enum { GKR_MEM_RESIDENT = 0, GKR_MEM_LAYER = 1, GKR_MEM_MESSAGE = 2, GKR_MEM_AUTO = 3 };
+
+/* Device and pinned host bytes one proof of c needs in a mode (RESIDENT,
+ * LAYER or MESSAGE), counting the circuit's gate arrays where the mode puts
+ * them; sized without allocating.  Errors: GKR_ERR_INVALID. */
+int gkr_memory_need(gkr_circuit *c, int mode, uint64_t *device_bytes, uint64_t *host_bytes);
+
+/* Choose how c's proofs place their data.  mode: one of GKR_MEM_*; with
+ * device_budget_bytes > 0 the chosen mode's device bytes (gkr_memory_need)
+ * must fit it (GKR_MEM_AUTO picks the first that does); 0 means no limit.
+ * The gate arrays move to pinned host memory for LAYER and MESSAGE and back
+ * to the device for RESIDENT; the circuit's proof scratch, cached batch plans
+ * and servers' idle scratch for it are released.  *chosen (may be NULL)
+ * receives the mode.  Must not be called while a proof on c runs.
+ * Errors: GKR_ERR_INVALID, GKR_ERR_NOMEM (nothing fits, or an allocation
+ * failed), GKR_ERR_DEVICE. */
+int gkr_circuit_set_memory(gkr_circuit *c, int mode, uint64_t device_budget_bytes, int *chosen);
 
 /* Transcript lengths for the layout above. */
 int gkr_transcript_size(const gkr_circuit *c, uint64_t *n_msgs, uint64_t *n_chals);
@@ -222,7 +263,7 @@ int gkr_server_stats(gkr_server *s, uint32_t *running, uint32_t *queued, uint64_
 void gkr_server_destroy(gkr_server *s);
 
 /* Sum-check for F2 = sum_x ~a(x)^2 over {0,1}^l, n = 2^l (the sum-check
- * primitive, Sec. 6, on the second frequency moment of Sec. 2.3).
+ * primitive, Sec. 7, on the second frequency moment of Sec. 3.2).
  *   freq   n uint32 values (device or host); n a power of two, n <= 2^32.
  *   msgs   host array of 1 + 3 l values: F2, then G_j(0), G_j(1), G_j(2)
  *          for rounds j = 1..l (G_j(t) = sum_m ((1-t) A[2m] + t A[2m+1])^2
@@ -239,7 +280,7 @@ int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_device, uint64_t
                        const uint64_t *msgs, uint64_t n_msgs, int *accepted,
                        gkr_reject_info *why, void *hip_stream);
 
-/* Non-interactive F2 (Sec. 2.3 and 3.2.2; GPU version Sec. 4.2; Table 3):
+/* Non-interactive F2 (Sec. 3.2; GPU version Sec. 4.2; Table 3):
  * a streaming verifier keeping v field words, a proof of 2h words.  The n
  * values a (each below p; host, or device if on_device) fill a v x h grid,
  * v = ceil(n / h), cell (row y, column j) = a[j v + y] (zero past n).  h
@@ -263,7 +304,7 @@ int nif2_verify(const uint64_t *a, uint64_t n, uint32_t h, int on_device, uint64
                 const uint64_t *msgs, uint64_t n_msgs, int *accepted, uint64_t *f2,
                 void *hip_stream);
 
-/* F_p arithmetic on the device field module (Sec. 5.1), for checking it:
+/* F_p arithmetic on the device field module (Sec. 6.1), for checking it:
  * out[k] = a[k] op b[k], op 0 = add, 1 = sub, 2 = mul; op 3 = the sum of
  * the 64 products a[j] b[j], j = k, k+1, ..., k+63 (indices mod n),
  * accumulated in 128 bits and reduced once (the lazy reduction the prover's
@@ -273,16 +314,26 @@ int nif2_verify(const uint64_t *a, uint64_t n, uint32_t h, int on_device, uint64
 int gkr_field_op(int op, const uint64_t *a, const uint64_t *b, uint64_t *out, uint64_t n,
                  void *hip_stream);
 
-/* Per-kernel timing.  While enabled (flag 1), every launch of the prover's
- * kernels is bracketed by HIP events on its stream.  gkr_profile_read
- * synchronises, then reports for each kernel class k < *n_classes: total
- * milliseconds, launch count and algorithmic bytes moved (the per-unit
- * figures of each kernel times the units processed), and resets the
- * totals.  names may be NULL; otherwise it receives static strings.
- * Errors: GKR_ERR_INVALID, GKR_ERR_DEVICE. */
+/* Per-kernel timing.  While enabled (flag 1, or 2 to also keep every
+ * launch's record), every launch of the prover's kernels is bracketed by
+ * HIP events on its stream (single proofs then run launch by launch, and
+ * batches without their graph).  gkr_profile_read synchronises, then
+ * reports for each kernel class k < *n_classes: total milliseconds, launch
+ * count, algorithmic bytes moved and algorithmic 64 x 64-bit modular
+ * products (the per-unit figures of each kernel times the units processed),
+ * and resets the totals.  names, ms, launches, bytes, mods may be NULL;
+ * names receives static strings.  Errors: GKR_ERR_INVALID, GKR_ERR_DEVICE. */
 int gkr_profile_enable(int flag);
 int gkr_profile_read(uint32_t *n_classes, const char **names, double *ms, uint64_t *launches,
-                     double *bytes);
+                     double *bytes, double *mods);
+/* The launches kept since the last call (flag 2): with every output NULL,
+ * *n receives their number; otherwise *n is the room and receives the
+ * number, and launch k's class, size class (ceil log2 of its work items,
+ * -1 for steps not sized by work items), milliseconds, bytes and products
+ * are written; the records are then dropped.  Errors: GKR_ERR_INVALID,
+ * GKR_ERR_DEVICE. */
+int gkr_profile_launches(uint64_t *n, int32_t *cls, int32_t *size_class, float *ms, double *bytes,
+                         double *mods);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char *gkr_last_error(void);

@@ -10,7 +10,7 @@
  *
  * What it follows (Thaler, Roberts, Mitzenmacher, Pfister, "Verifiable
  * Computation with Massively Parallel Interactive Proofs"):
- *   - Sec. 5.1: all arithmetic is exact in F_p with p = 2^61 - 1.  Here every
+ *   - Sec. 6.1: all arithmetic is exact in F_p with p = 2^61 - 1.  Here every
  *     product is reduced with a plain 128-bit remainder, not with the
  *     Mersenne shift trick, so the reduction is independent of the GPU's.
  *   - Sec. 3.1: the layered fan-in-2 circuit of ADD/MUL gates; one iteration
@@ -611,7 +611,7 @@ int or_f2sc_verify(const u32 *freq, u64 n, u64 seed, const u64 *msgs, u64 n_msgs
     return 0;
 }
 
-/* ------------------------------------- non-interactive F2 (Sec. 2.3, 3.2.2)
+/* ------------------------------------- non-interactive F2 (Sec. 3.2)
  *
  * The reading fixed for this build (the paper gives the protocol's outline
  * only): the universe [n] is a v x h grid, v = ceil(n / h), cell (row y,

@@ -222,7 +222,7 @@ def f2sc_verify(freq, seed, msgs):
     return bool(acc.value), wr.value, wc.value
 
 
-# Non-interactive F2 (Sec. 2.3, 3.2.2): a v x h grid, proof g at 2h points.
+# Non-interactive F2 (Sec. 3.2): a v x h grid, proof g at 2h points.
 def nif2_root(N):
     """Generator of the order-N subgroup of F_p^* (0 if N does not divide p - 1)."""
     return int(lib().or_nif2_root(N))

@@ -18,6 +18,7 @@ GKR_OK, GKR_ERR_INVALID, GKR_ERR_RANGE, GKR_ERR_NOMEM, GKR_ERR_DEVICE, GKR_ERR_B
     0, -1, -2, -3, -4, -5
 GKR_OMEGA_GATES, GKR_OMEGA_TABLES = 0, 1
 GKR_BATCH_GRAPH = 1
+GKR_MEM_RESIDENT, GKR_MEM_LAYER, GKR_MEM_MESSAGE, GKR_MEM_AUTO = 0, 1, 2, 3
 CHECKS = {1: "malformed", 2: "round", 3: "wiring", 4: "line", 5: "input"}
 
 
@@ -39,6 +40,8 @@ _SIGS = [
                                      C.POINTER(C.c_void_p)]),
     ("gkr_circuit_destroy", None, [C.c_void_p]),
     ("gkr_circuit_set_algorithm", C.c_int, [C.c_void_p, C.c_int]),
+    ("gkr_memory_need", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    ("gkr_circuit_set_memory", C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.POINTER(C.c_int)]),
     ("gkr_transcript_size", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     ("gkr_circuit_info", C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                    C.POINTER(C.c_uint32)]),
@@ -73,7 +76,9 @@ _SIGS = [
                                C.c_void_p]),
     ("gkr_profile_enable", C.c_int, [C.c_int]),
     ("gkr_profile_read", C.c_int, [C.POINTER(C.c_uint32), C.c_void_p, C.c_void_p, C.c_void_p,
-                                   C.c_void_p]),
+                                   C.c_void_p, C.c_void_p]),
+    ("gkr_profile_launches", C.c_int, [C.POINTER(C.c_uint64), C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]),
     ("gkr_last_error", C.c_char_p, []),
 ]
 EXPORTS = [s[0] for s in _SIGS]
@@ -168,6 +173,20 @@ class Circuit:
     def set_algorithm(self, omega_algo: int):
         """GKR_OMEGA_TABLES (default) or GKR_OMEGA_GATES; same transcript."""
         _check(lib().gkr_circuit_set_algorithm(self.handle, int(omega_algo)))
+
+    def memory_need(self, mode: int):
+        """(device bytes, pinned host bytes) of one proof in a GKR_MEM_* mode."""
+        d, h = C.c_uint64(), C.c_uint64()
+        _check(lib().gkr_memory_need(self.handle, int(mode), C.byref(d), C.byref(h)))
+        return d.value, h.value
+
+    def set_memory(self, mode: int, device_budget_bytes: int = 0) -> int:
+        """Place the proofs' data (GKR_MEM_RESIDENT, _LAYER, _MESSAGE or
+        _AUTO within the budget); returns the mode chosen."""
+        chosen = C.c_int(-1)
+        _check(lib().gkr_circuit_set_memory(self.handle, int(mode), int(device_budget_bytes),
+                                            C.byref(chosen)))
+        return chosen.value
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -369,17 +388,46 @@ def gkr_field_op(op: int, a, b, out, stream=None):
     _check(lib().gkr_field_op(op, pa, pb, po, out.numel(), _stream(dev, stream)))
 
 
-def gkr_profile_enable(flag: bool):
-    _check(lib().gkr_profile_enable(int(bool(flag))))
+def gkr_profile_enable(flag):
+    """0 off, 1 per-class totals, 2 totals and per-launch records."""
+    _check(lib().gkr_profile_enable(int(flag)))
 
 
 def gkr_profile_read():
-    """{kernel class: (ms, launches, algorithmic bytes)}; resets the totals."""
+    """{kernel class: (ms, launches, algorithmic bytes, algorithmic modular
+    products)}; resets the totals."""
     n = C.c_uint32(32)
     names = (C.c_char_p * 32)()
     ms = (C.c_double * 32)()
     cnt = (C.c_uint64 * 32)()
     by = (C.c_double * 32)()
+    mo = (C.c_double * 32)()
     _check(lib().gkr_profile_read(C.byref(n), C.cast(names, C.c_void_p), C.cast(ms, C.c_void_p),
-                                  C.cast(cnt, C.c_void_p), C.cast(by, C.c_void_p)))
-    return {names[k].decode(): (ms[k], cnt[k], by[k]) for k in range(n.value)}
+                                  C.cast(cnt, C.c_void_p), C.cast(by, C.c_void_p),
+                                  C.cast(mo, C.c_void_p)))
+    return {names[k].decode(): (ms[k], cnt[k], by[k], mo[k]) for k in range(n.value)}
+
+
+def gkr_profile_launches():
+    """Per-launch records kept under gkr_profile_enable(2): a list of
+    (class name, size class, ms, bytes, products); drops them."""
+    n = C.c_uint64(0)
+    _check(lib().gkr_profile_launches(C.byref(n), None, None, None, None, None))
+    k = n.value
+    cls = (C.c_int32 * max(k, 1))()
+    sc = (C.c_int32 * max(k, 1))()
+    ms = (C.c_float * max(k, 1))()
+    by = (C.c_double * max(k, 1))()
+    mo = (C.c_double * max(k, 1))()
+    _check(lib().gkr_profile_launches(C.byref(n), C.cast(cls, C.c_void_p), C.cast(sc, C.c_void_p),
+                                      C.cast(ms, C.c_void_p), C.cast(by, C.c_void_p),
+                                      C.cast(mo, C.c_void_p)))
+    names = list(gkr_profile_class_names())
+    return [(names[cls[i]], sc[i], ms[i], by[i], mo[i]) for i in range(min(k, n.value))]
+
+
+def gkr_profile_class_names():
+    n = C.c_uint32(64)
+    names = (C.c_char_p * 64)()
+    _check(lib().gkr_profile_read(C.byref(n), C.cast(names, C.c_void_p), None, None, None, None))
+    return [names[k].decode() for k in range(n.value)]

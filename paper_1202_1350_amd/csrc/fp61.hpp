@@ -1,4 +1,4 @@
-// fp61.hpp -- arithmetic in F_p, p = 2^61 - 1 (Sec. 5.1), for device and host.
+// fp61.hpp -- arithmetic in F_p, p = 2^61 - 1 (Sec. 6.1), for device and host.
 //
 // Values are kept canonical (0 <= x < p) in uint64_t.  A product is built
 // from the 64 x 64 -> 128-bit multiply (low word and mulhi) and reduced

@@ -6,7 +6,7 @@
 // line step.  Challenges are drawn on the device right after each message
 // is reduced, so the host never waits inside a proof; it copies the
 // transcript back once at the end.  Device scratch is allocated on the
-// first proof of a circuit and kept with it (Sec. 5.1 does not count
+// first proof of a circuit and kept with it (Sec. 6.1 does not count
 // scratch allocation in prover time).
 #include <hip/hip_runtime.h>
 
@@ -60,29 +60,40 @@ namespace {
 // then the verifier's and the F2 sum-check's kernels.
 enum ProfClass {
     PC_STEP = 0,  // + StepKind
-    PC_WIRING = 19, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_COUNT
+    PC_WIRING = 19, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_SERVE, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {
     "step_eval", "step_start", "step_eq", "step_p", "step_w", "step_fold", "step_lt",
     "step_line", "step_sge", "step_end", "step_wagg", "step_wt0", "step_wt", "step_wtail",
     "step_ptail", "step_load", "step_wa0", "step_finish", "step_wsmall", "wiring", "mle", "eq_tables", "f2sc_round",
-    "f2sc_final", "misc", "batch_step", "nif2"};
+    "f2sc_final", "misc", "batch_step", "nif2", "serve_step"};
 static_assert(ST_WSMALL + 1 == PC_WIRING, "one profiling class per step kind");
 
 struct ProfRec {
     int cls;
     hipEvent_t a, b;
-    double bytes;
+    double bytes, mods;
+    int sclass;  // size class of the launch (ceil log2 of its work items), -1 if none
+};
+
+// One timed launch, kept while per-launch records are asked for.
+struct LaunchRec {
+    int cls, sclass;
+    float ms;
+    double bytes, mods;
 };
 
 struct Profiler {
     std::mutex mu;
     bool on = false;
+    bool keep = false;  // keep per-launch records (gkr_profile_launches)
     std::vector<ProfRec> recs;
+    std::vector<LaunchRec> launches;
     std::vector<hipEvent_t> pool;
     double ms[PC_COUNT] = {0};
     uint64_t n[PC_COUNT] = {0};
     double bytes[PC_COUNT] = {0};
+    double mods[PC_COUNT] = {0};
 
     hipEvent_t get() {
         if (!pool.empty()) {
@@ -98,14 +109,14 @@ struct Profiler {
 
 // Events timing one dispatch when profiling is on (NULL otherwise); the
 // record is kept for gkr_profile_read.
-bool prof_pair(int cls, double bytes, hipEvent_t *a, hipEvent_t *b) {
+bool prof_pair(int cls, double bytes, hipEvent_t *a, hipEvent_t *b, double mods = 0, int sclass = -1) {
     *a = *b = nullptr;
     if (!g_prof.on) return false;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     *a = g_prof.get();
     *b = g_prof.get();
     if (!*a || !*b) return false;
-    g_prof.recs.push_back({cls, *a, *b, bytes});
+    g_prof.recs.push_back({cls, *a, *b, bytes, mods, sclass});
     return true;
 }
 
@@ -127,7 +138,7 @@ struct Scope {
         hipEvent_t b = g_prof.get();
         if (!b) return;
         (void)hipEventRecord(b, st);
-        g_prof.recs.push_back({cls, a, b, bytes});
+        g_prof.recs.push_back({cls, a, b, bytes, 0.0, -1});
     }
 };
 
@@ -136,13 +147,13 @@ struct Scope {
 extern "C" int gkr_profile_enable(int flag) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = flag != 0;
+    g_prof.keep = flag == 2;
     return GKR_OK;
 }
 
-extern "C" int gkr_profile_read(uint32_t *n_classes, const char **names, double *ms,
-                                uint64_t *launches, double *bytes) {
-    if (!n_classes) return fail(GKR_ERR_INVALID, "n_classes is NULL");
-    std::lock_guard<std::mutex> lk(g_prof.mu);
+// Timings of the recorded launches into the per-class totals (and the
+// per-launch list while it is kept).
+static int prof_collect() {
     for (auto &r : g_prof.recs) {
         HIP_TRY(hipEventSynchronize(r.b));
         float t = 0;
@@ -150,21 +161,57 @@ extern "C" int gkr_profile_read(uint32_t *n_classes, const char **names, double 
         g_prof.ms[r.cls] += t;
         g_prof.n[r.cls] += 1;
         g_prof.bytes[r.cls] += r.bytes;
+        g_prof.mods[r.cls] += r.mods;
+        if (g_prof.keep) g_prof.launches.push_back({r.cls, r.sclass, t, r.bytes, r.mods});
         g_prof.pool.push_back(r.a);
         g_prof.pool.push_back(r.b);
     }
     g_prof.recs.clear();
+    return GKR_OK;
+}
+
+extern "C" int gkr_profile_read(uint32_t *n_classes, const char **names, double *ms,
+                                uint64_t *launches, double *bytes, double *mods) {
+    if (!n_classes) return fail(GKR_ERR_INVALID, "n_classes is NULL");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    const int rc = prof_collect();
+    if (rc) return rc;
     uint32_t cap = *n_classes;
     *n_classes = PC_COUNT;
+    const bool totals = ms || launches || bytes || mods;  // names alone: nothing is reset
     for (uint32_t k = 0; k < PC_COUNT && k < cap; k++) {
         if (names) names[k] = kProfNames[k];
+        if (!totals) continue;
         if (ms) ms[k] = g_prof.ms[k];
         if (launches) launches[k] = g_prof.n[k];
         if (bytes) bytes[k] = g_prof.bytes[k];
+        if (mods) mods[k] = g_prof.mods[k];
         g_prof.ms[k] = 0;
         g_prof.n[k] = 0;
         g_prof.bytes[k] = 0;
+        g_prof.mods[k] = 0;
     }
+    return GKR_OK;
+}
+
+extern "C" int gkr_profile_launches(uint64_t *n, int32_t *cls, int32_t *size_class, float *ms,
+                                    double *bytes, double *mods) {
+    if (!n) return fail(GKR_ERR_INVALID, "n is NULL");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    const int rc = prof_collect();
+    if (rc) return rc;
+    const uint64_t cap = *n, have = g_prof.launches.size();
+    *n = have;
+    if (!cls && !size_class && !ms && !bytes && !mods) return GKR_OK;  // count only
+    for (uint64_t k = 0; k < have && k < cap; k++) {
+        const LaunchRec &r = g_prof.launches[k];
+        if (cls) cls[k] = r.cls;
+        if (size_class) size_class[k] = r.sclass;
+        if (ms) ms[k] = r.ms;
+        if (bytes) bytes[k] = r.bytes;
+        if (mods) mods[k] = r.mods;
+    }
+    g_prof.launches.clear();
     return GKR_OK;
 }
 
@@ -304,6 +351,7 @@ struct Workspace {
     std::vector<StepDesc> steps;  // host copy of the program
     std::vector<int> pclass;      // profiling class of each step
     std::vector<double> pbytes;   // algorithmic bytes of each step
+    std::vector<double> pmods;    // algorithmic modular products of each step
     std::vector<u64> punits;      // work items of each tunable step (0: not tunable)
     u32 epoch = 0;                // launch shapes the program was planned with
     u64 cap_rows = 0, cap_recs = 0, cap_items = 0;  // room carved for them
@@ -313,6 +361,31 @@ struct Workspace {
     u64 *instage;  // host inputs land here
     size_t bytes = 0;  // device memory held
     u32 gen = 0;       // the circuit's generation when the workspace was made
+    // Out-of-core proofs (Sec. 5.1.2, 5.1.3).  mode GKR_MEM_LAYER: V holds
+    // every layer's table in pinned host memory and the steps use three
+    // device slots (layer i's table in Vslot[i % 3]) and, for gate arrays in
+    // host memory, two gate slots (layer i's block in Gslot[i % 2]); xfers
+    // are the copies between them, on the copy stream cs.  GKR_MEM_MESSAGE:
+    // the layer and round tables are in pinned host memory, read and written
+    // in place by every message's kernels.
+    int mode = GKR_MEM_RESIDENT;
+    void *hmem = nullptr;  // pinned host part
+    size_t hbytes = 0;
+    u64 *Vslot[3] = {nullptr, nullptr, nullptr};
+    char *Gslot[2] = {nullptr, nullptr};
+    size_t gslot = 0;  // bytes of a gate slot
+    struct Xfer {
+        int after;   // step whose completion lets the copy start (-1: the proof's start)
+        int before;  // step that waits for the copy
+        void *dst;
+        const void *src;
+        size_t bytes;
+        hipMemcpyKind kind;
+    };
+    std::vector<Xfer> xfers;  // in order of `after`
+    hipStream_t cs = nullptr;
+    std::vector<hipEvent_t> xev;  // per transfer: step done (on the proof's stream), copy done (on cs)
+    hipEvent_t ev_begin = nullptr, ev_join = nullptr;
     u64 *h_msgs = nullptr, *h_chals = nullptr, *h_setup = nullptr;  // pinned staging
 };
 
@@ -331,7 +404,7 @@ struct gkr_circuit {
     u64 gmax = 0;
     u64 line_lo = 1, line_hl = 1, line_hh = 1;  // table sizes (entries)
     u64 nch_max = 1;  // most chunks of a phase grouping
-    size_t ws_bytes = 0;  // device bytes of one workspace (0: not yet sized)
+    size_t ws_bytes[3] = {0, 0, 0};  // device bytes of one workspace per memory mode (0: not yet sized)
     std::mutex mu;
     Workspace *ws = nullptr;
     int omega_algo = GKR_OMEGA_TABLES;
@@ -343,11 +416,19 @@ struct gkr_circuit {
         u32 *rowptr = nullptr;  // wire x's gates: sorted positions [rowptr[x], rowptr[x+1])
         u32 *oths = nullptr;    // other wire of each gate, in sorted order
         u8 *types = nullptr;    // gate types in sorted order (mixed layers)
-        u32 nch = 0;
+        u32 *tch = nullptr;     // tiles of whole chunks (at most TILE_POS positions each)
+        u32 nch = 0, ntiles = 0;
         bool single = false;    // every wire carries at most one chunk
     };
     std::vector<Group> grp[2];  // [phase - 1][layer], built with the first table workspace
-    void *gmem = nullptr;       // device memory of the groups
+    void *gmem = nullptr;       // memory of the groups (allocated with the first table workspace)
+    bool grouped = false;       // grp[][] sized (chunk counts, single flags)
+    // Where the gate arrays (soa, gmem) live: device memory, or pinned host
+    // memory when the circuit's proofs run out of core; and the byte ranges
+    // of each layer's block in them (layer i: [off[i], off[i+1])).
+    bool gates_host = false;
+    std::vector<size_t> soa_off, g_off;
+    int mem_mode = GKR_MEM_RESIDENT;  // how gkr_prove places a proof's tables
 };
 
 // ---------------------------------------------------------------------------
@@ -512,8 +593,10 @@ extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_siz
     c->type.assign(d, nullptr);
     c->in1.assign(d, nullptr);
     c->in2.assign(d, nullptr);
+    c->soa_off.assign(d + 1, 0);
     for (u32 i = 0; i < d; i++) {
         size_t n = c->S[i];
+        c->soa_off[i] = (size_t)(p - (char *)c->soa);
         c->in1[i] = (u32 *)p;
         p += (n * 4 + 255) & ~size_t(255);
         c->in2[i] = (u32 *)p;
@@ -530,15 +613,48 @@ extern "C" int gkr_circuit_create(uint32_t num_layers, const uint32_t *layer_siz
             HIP_TRY(hipMemcpy(c->type[i], gate_type[i], n, hipMemcpyHostToDevice));
         }
     }
+    c->soa_off[d] = (size_t)(p - (char *)c->soa);
     *out = c.release();
     return GKR_OK;
+}
+
+// Gate arrays and out-of-core tables: device memory, or pinned host memory
+// that kernels read and write in place through its device mapping.
+static hipError_t mem_alloc(bool host, size_t bytes, void **p) {
+    *p = nullptr;
+    if (!host) return hipMalloc(p, bytes);
+    void *h = nullptr;
+    hipError_t e = hipHostMalloc(&h, bytes, hipHostMallocMapped);
+    if (e != hipSuccess) return e;
+    void *d = nullptr;
+    e = hipHostGetDevicePointer(&d, h, 0);
+    if (e != hipSuccess || d != h) {  // kernels take the host address as is
+        (void)hipHostFree(h);
+        return e != hipSuccess ? e : hipErrorInvalidValue;
+    }
+    *p = h;
+    return hipSuccess;
+}
+
+static void gate_free(bool host, void *p) {
+    if (!p) return;
+    if (host)
+        (void)hipHostFree(p);
+    else
+        (void)hipFree(p);
 }
 
 static void free_workspace(Workspace *ws) {
     if (!ws) return;
     if (ws->gexec) (void)hipGraphExecDestroy(ws->gexec);
     if (ws->graph) (void)hipGraphDestroy(ws->graph);
+    if (ws->cs) (void)hipStreamSynchronize(ws->cs);
+    for (hipEvent_t e : ws->xev) (void)hipEventDestroy(e);
+    if (ws->ev_begin) (void)hipEventDestroy(ws->ev_begin);
+    if (ws->ev_join) (void)hipEventDestroy(ws->ev_join);
+    if (ws->cs) (void)hipStreamDestroy(ws->cs);
     if (ws->mem) (void)hipFree(ws->mem);
+    if (ws->hmem) (void)hipHostFree(ws->hmem);
     if (ws->h_msgs) (void)hipHostFree(ws->h_msgs);
     if (ws->h_chals) (void)hipHostFree(ws->h_chals);
     if (ws->h_setup) (void)hipHostFree(ws->h_setup);
@@ -553,8 +669,8 @@ extern "C" void gkr_circuit_destroy(gkr_circuit *c) {
     drop_batches_of(c);
     drop_served_scratch_of(c);
     free_workspace(c->ws);
-    if (c->gmem) (void)hipFree(c->gmem);
-    if (c->soa) (void)hipFree(c->soa);
+    gate_free(c->gates_host, c->gmem);
+    gate_free(c->gates_host, c->soa);
     delete c;
 }
 
@@ -569,7 +685,7 @@ extern "C" int gkr_circuit_set_algorithm(gkr_circuit *c, int omega_algo) {
             free_workspace(c->ws);  // the step program is rebuilt on the next proof
             c->ws = nullptr;
             c->omega_algo = omega_algo;
-            c->ws_bytes = 0;
+            for (size_t &b : c->ws_bytes) b = 0;
             c->gen++;  // pooled server scratch of the old program is discarded
             changed = true;
         }
@@ -602,9 +718,13 @@ extern "C" int gkr_circuit_info(const gkr_circuit *c, uint64_t *gates, uint64_t 
 // GROUP_CHUNK gates of one wire; chunks of wire x are [xch[x], xch[x+1]).
 constexpr u32 GROUP_CHUNK = 32;
 struct HostGroup {
-    std::vector<u32> perm, cstart, xch, rowptr, oths;
+    std::vector<u32> perm, cstart, xch, rowptr, oths, tch;
     std::vector<u8> types;
 };
+
+// Tiles of whole chunks spanning at most TILE_POS sorted positions (one
+// wave each in the per-chunk sums): tile t holds chunks [tch[t], tch[t+1]).
+constexpr u32 TILE_POS = 64;
 
 // Counting sort of the gates by their wire idx (stable): positions, the
 // other wire and the type in that order, chunks of <= GROUP_CHUNK gates of
@@ -634,6 +754,11 @@ static void build_group(const std::vector<u32> &idx, const std::vector<u32> &oth
     }
     G.xch[N] = (u32)G.cstart.size();
     G.cstart.push_back((u32)S);
+    G.tch.assign(1, 0);
+    const size_t nch = G.cstart.size() - 1;
+    for (size_t ch = 0; ch < nch; ch++)
+        if (G.cstart[ch + 1] - G.cstart[G.tch.back()] > TILE_POS) G.tch.push_back((u32)ch);
+    G.tch.push_back((u32)nch);
 }
 
 // Lay out (or size, when a.base is NULL) a proof's scratch.
@@ -644,20 +769,47 @@ struct PlanSizes {
     u64 rows, recs, items;
 };
 
-static void carve(const gkr_circuit *c, Arena &a, Workspace &w, const PlanSizes &ps) {
+// Bytes of the largest per-layer block a gate slot receives: the struct of
+// arrays for evaluation, and the groups (tables algorithm) or the struct of
+// arrays (per-gate rounds) for the layer's sum-check.
+static size_t gate_block_max(const gkr_circuit *c) {
+    size_t m = 0;
+    for (u32 i = 0; i + 1 < c->L; i++) {
+        m = std::max(m, c->soa_off[i + 1] - c->soa_off[i]);
+        if (c->omega_algo == GKR_OMEGA_TABLES) m = std::max(m, c->g_off[i + 1] - c->g_off[i]);
+    }
+    return m;
+}
+
+// Lay out (or size, when the arenas' bases are NULL) a proof's scratch in
+// device memory (a) and pinned host memory (h) as w.mode places it:
+// resident, every table on the device; per layer, the layer tables in host
+// memory with three device slots for them (and two for the gate arrays
+// when those are in host memory); per message, the layer and round tables
+// in host memory.  Small state (eq half tables, rows, transcript, step
+// program) is always on the device.
+static void carve(const gkr_circuit *c, Arena &a, Arena &h, Workspace &w, const PlanSizes &ps) {
     const size_t nsteps = ps.nsteps;
+    const int mode = w.mode;
+    Arena &vt = mode == GKR_MEM_RESIDENT ? a : h;  // layer value tables
+    Arena &rt = mode == GKR_MEM_MESSAGE ? h : a;   // round tables
     w.V.assign(c->L, nullptr);
-    for (u32 i = 0; i < c->L; i++) w.V[i] = a.take<u64>(1ull << c->s[i]);
+    for (u32 i = 0; i < c->L; i++) w.V[i] = vt.take<u64>(1ull << c->s[i]);
+    if (mode == GKR_MEM_LAYER) {
+        for (int k = 0; k < 3; k++) w.Vslot[k] = a.take<u64>(1ull << c->smax);
+        w.gslot = c->gates_host ? gate_block_max(c) : 0;
+        for (int k = 0; k < 2; k++) w.Gslot[k] = w.gslot ? a.take<char>(w.gslot) : nullptr;
+    }
     const u64 half = std::max<u64>(1ull << (c->smax ? c->smax - 1 : 0), 2);
-    w.pA = a.take<u64>(half);
-    w.pB = a.take<u64>(half);
-    w.bA = a.take<u64>(half);
-    w.bB = a.take<u64>(half);
-    w.fA = a.take<u64>(half);
-    w.fB = a.take<u64>(half);
+    w.pA = rt.take<u64>(half);
+    w.pB = rt.take<u64>(half);
+    w.bA = rt.take<u64>(half);
+    w.bB = rt.take<u64>(half);
+    w.fA = rt.take<u64>(half);
+    w.fB = rt.take<u64>(half);
     const bool gates = c->omega_algo == GKR_OMEGA_GATES;
-    w.w = a.take<u64>(gates ? c->gmax : 1);   // per-gate weights: per-gate rounds only
-    w.off = a.take<u64>(gates ? c->gmax : 1);
+    w.w = rt.take<u64>(gates ? c->gmax : 1);   // per-gate weights: per-gate rounds only
+    w.off = rt.take<u64>(gates ? c->gmax : 1);
     w.zlo = a.take<u64>(HALF_MAX);
     w.zhi = a.take<u64>(HALF_MAX);
     w.alo = a.take<u64>(HALF_MAX);
@@ -676,19 +828,19 @@ static void carve(const gkr_circuit *c, Arena &a, Workspace &w, const PlanSizes 
     w.zbuf = a.take<u64>(64);
     w.state = a.take<u64>(8);
     w.flag = a.take<u32>(1);
-    w.instage = a.take<u64>(c->S[c->L - 1]);
+    w.instage = vt.take<u64>(c->S[c->L - 1]);
     w.d_steps = a.take<StepDesc>(nsteps);
     w.d_jobs = a.take<JobEntry>(2 * nsteps);
     if (c->omega_algo == GKR_OMEGA_TABLES) {
         const u64 N = 1ull << c->spmax;
-        w.tA0 = a.take<u64>(N);
-        w.tC0 = a.take<u64>(N);
-        w.tA[0] = a.take<u64>(std::max<u64>(N / 2, 2));
-        w.tA[1] = a.take<u64>(std::max<u64>(N / 2, 2));
-        w.tC[0] = a.take<u64>(std::max<u64>(N / 2, 2));
-        w.tC[1] = a.take<u64>(std::max<u64>(N / 2, 2));
-        w.partA = a.take<u64>(c->nch_max);
-        w.partC = a.take<u64>(c->nch_max);
+        w.tA0 = rt.take<u64>(N);
+        w.tC0 = rt.take<u64>(N);
+        w.tA[0] = rt.take<u64>(std::max<u64>(N / 2, 2));
+        w.tA[1] = rt.take<u64>(std::max<u64>(N / 2, 2));
+        w.tC[0] = rt.take<u64>(std::max<u64>(N / 2, 2));
+        w.tC[1] = rt.take<u64>(std::max<u64>(N / 2, 2));
+        w.partA = rt.take<u64>(c->nch_max);
+        w.partC = rt.take<u64>(c->nch_max);
     }
 }
 
@@ -701,10 +853,37 @@ struct Planner {
     std::vector<StepDesc> out;
     std::vector<int> cls;
     std::vector<double> bytes;
+    std::vector<double> mods;   // algorithmic 64 x 64-bit modular products of each step
     std::vector<u64> units;
     std::vector<FinItem> items;
     u64 rows_used = 0, recs_used = 0;
     ProofPtrs pp{};
+    // step indices: evaluation of layer i, first and last step of its sum-check
+    std::vector<int> eval_at, sc_first, sc_last;
+
+    // Layer i's gate arrays as its steps see them: in place, or in gate
+    // slot i % 2 when the workspace stages host gate arrays layer by layer.
+    template <typename T>
+    T *soa_at(u32 i, T *p) const {
+        if (!w || !p || !w->gslot) return p;
+        return (T *)(w->Gslot[i % 2] + ((const char *)p - ((const char *)c->soa + c->soa_off[i])));
+    }
+    template <typename T>
+    T *grp_at(u32 i, T *p) const {
+        if (!w || !p || !w->gslot) return p;
+        return (T *)(w->Gslot[i % 2] + ((const char *)p - ((const char *)c->gmem + c->g_off[i])));
+    }
+    gkr_circuit::Group group(u32 ph, u32 i) const {
+        gkr_circuit::Group g = c->grp[ph - 1][i];
+        g.perm = grp_at(i, g.perm);
+        g.cstart = grp_at(i, g.cstart);
+        g.xch = grp_at(i, g.xch);
+        g.rowptr = grp_at(i, g.rowptr);
+        g.oths = grp_at(i, g.oths);
+        g.tch = grp_at(i, g.tch);
+        g.types = grp_at(i, g.types);
+        return g;
+    }
 
     PlanSizes sizes() const { return PlanSizes{out.size(), rows_used, recs_used, items.size()}; }
 
@@ -719,6 +898,7 @@ struct Planner {
         out.push_back(s);
         cls.push_back(PC_STEP + (int)kind);
         bytes.push_back(nbytes);
+        mods.push_back(0);
         units.push_back(0);
         return out.back();
     }
@@ -782,7 +962,13 @@ struct Planner {
     void build() {
         const u32 d = c->L - 1;
         if (w) pp = ProofPtrs{w->msgs, w->chals, w->rngst, w->zbuf, w->state};
-        auto V = [&](u32 i) -> u64 * { return w ? w->V[i] : nullptr; };
+        // layer i's value table: its own, or slot i % 3 (per-layer staging)
+        auto V = [&](u32 i) -> u64 * {
+            return w ? (w->mode == GKR_MEM_LAYER ? w->Vslot[i % 3] : w->V[i]) : nullptr;
+        };
+        eval_at.assign(d, -1);
+        sc_first.assign(d, -1);
+        sc_last.assign(d, -1);
         auto P_ = [&](u64 *p) -> u64 * { return w ? p : nullptr; };
         {
             const u64 Sd = c->S[d], npad = 1ull << c->s[d];
@@ -792,10 +978,12 @@ struct Planner {
         // circuit evaluation (a3), layer d-1 down to 0
         for (int i = (int)d - 1; i >= 0; i--) {
             const u64 S = c->S[i], npad = 1ull << c->s[i];
+            eval_at[i] = (int)out.size();
             StepDesc &s = addg(ST_EVAL, npad, 4,
                               S * (8.0 + 16 + 8 + (c->kind[i] == KIND_MIXED)) + (npad - S) * 8.0);
-            s.u.eval = EvalArgs{(u32)c->kind[i], c->S[i], npad, c->type[i], c->in1[i], c->in2[i],
-                                V(i + 1), V(i)};
+            mods.back() = c->kind[i] == KIND_ADD ? 0.0 : (double)S;  // one product a MUL gate
+            s.u.eval = EvalArgs{(u32)c->kind[i], c->S[i], npad, soa_at(i, c->type[i]), soa_at(i, c->in1[i]),
+                                soa_at(i, c->in2[i]), V(i + 1), V(i)};
         }
         {
             StepDesc &s = addg(ST_START, c->S[0], 1, c->S[0] * 16.0);
@@ -806,6 +994,8 @@ struct Planner {
         layer_end.kind = FIN_NONE;
         layer_end.draw = -1;
         for (u32 i = 0; i < d; i++) {
+            if (i > 0) sc_last[i - 1] = (int)out.size() - 1;
+            sc_first[i] = (int)out.size();
             const u32 s = c->s[i], sp = c->s[i + 1], S = c->S[i];
             const u32 n = s + 2 * sp;
             const int kind = c->kind[i];
@@ -836,6 +1026,7 @@ struct Planner {
                 const u32 nz = s ? s - 1 : 0;
                 const u64 ne = (1ull << (nz / 2)) + (1ull << (nz - nz / 2));
                 StepDesc &e = addg(ST_EQ, ne, 1, 8.0 * ne);
+                mods.back() = 0.5 * ne * nz;
                 e.fin = layer_end;
                 e.u.eq = EqArgs{PT_Z, nz, nz / 2, 1, P_(w ? w->zlo : nullptr), P_(w ? w->zhi : nullptr)};
             }
@@ -865,6 +1056,8 @@ struct Planner {
                     pa.L = nz / 2;
                     // V 8 per entry, eq halves 16 per pair, B_1 8 per quad
                     StepDesc &st = addg(ST_P, look ? 4 * pa.nu : pa.nu, 1, look ? pa.nu * (32.0 + 32 + 8) : 32.0);
+                    // per quad: a suffix weight and two products in each lane; per pair: 3
+                    mods.back() = look ? pa.nu * 12.0 : pa.nu * 3.0;
                     st.u.p = pa;
                     reduces(look ? 6 : 2);
                 }
@@ -882,6 +1075,7 @@ struct Planner {
                     pa.Bout = bbuf[bw ^ 1];
                     // per unit: V^(j) 16 read, V^(j+2) 4 written, B 4 read and 1 written
                     StepDesc &st = addg(ST_P, 4 * pa.nu, 1, pa.nu * 8.0 * (16 + 4 + 4 + 1));
+                    mods.back() = pa.nu * 20.0;  // per quad: four two-challenge folds (3 each), 8 products
                     st.fin = f;
                     st.u.p = pa;
                     reduces(6);
@@ -894,6 +1088,7 @@ struct Planner {
                 f.draw = (i32)(co + j0 - pend);
                 f.msg = w ? msg + 3ull * (j0 - pend) : nullptr;
                 StepDesc &st = add(ST_PTAIL, 1, 8.0 * (1ull << (s - j0 + pend)));
+                mods.back() = 4.0 * (1ull << (s - j0 + pend));
                 st.fin = f;
                 PtailArgs pt;
                 memset(&pt, 0, sizeof pt);
@@ -945,7 +1140,8 @@ struct Planner {
                 if (wsmall) {
                     for (u32 ph = 1; ph <= 2; ph++) {
                         const u32 rbase = s + (ph == 2 ? sp : 0);
-                        const gkr_circuit::Group *dg = &c->grp[ph - 1][i];
+                        const gkr_circuit::Group gd = group(ph, i);
+                        const gkr_circuit::Group *dg = &gd;
                         WsmallArgs a;
                         memset(&a, 0, sizeof a);
                         a.w.kind = kind;
@@ -976,6 +1172,7 @@ struct Planner {
                         // eq entries 8, per gate sorted index 4 + other 4 + operand 8, per wire F 8
                         const u64 ne = (1ull << (a.eqn / 2)) + (1ull << (a.eqn - a.eqn / 2));
                         StepDesc &st = add(ST_WSMALL, 1, 8.0 * ne + 16.0 * S + 16.0 * (1ull << sp));
+                        mods.back() = (ph == 1 ? 4.0 : 5.0) * S + 8.0 * (1ull << sp);
                         st.u.wsmall = a;
                     }
                 } else {
@@ -990,7 +1187,8 @@ struct Planner {
                         StepDesc &e = addg(ST_EQ, ne, 1, 8.0 * ne);
                         e.u.eq = EqArgs{PT_CHAL, sp, Lb, co + s, w ? w->blo : nullptr, w ? w->bhi : nullptr};
                     }
-                    const gkr_circuit::Group *dg = &c->grp[ph - 1][i];
+                    const gkr_circuit::Group gd = group(ph, i);
+                        const gkr_circuit::Group *dg = &gd;
                     const u32 nch = dg->nch;
                     const u32 hasC = kind != KIND_MUL;
                     if (dg->single) {
@@ -1019,6 +1217,9 @@ struct Planner {
                         StepDesc &st = addg(ST_WA0, N / 2, 1,
                                            S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) +
                                                N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 8.0 * nch);
+                        // per gate: chi_g(a*) (1), beta (1), the operand or chi_in1(b*) (1 or 2);
+                        // per wire (phase 2) v1 twice; per pair three term products
+                        mods.back() = S * (ph == 1 ? 3.0 : 4.0) + N * (ph == 2 ? 2.0 : 0.0) + 1.5 * N;
                         st.u.wa0 = a;
                         reduces(3);
                     } else {
@@ -1042,9 +1243,14 @@ struct Planner {
                             a.Lb = Lb;
                             a.partA = w ? w->partA : nullptr;
                             a.partC = w ? w->partC : nullptr;
-                            // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1
-                            StepDesc &st = addg(ST_WAGG, nch, 1,
-                                               S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) + 20.0 * nch);
+                            a.ntiles = dg->ntiles;
+                            a.tch = dg->tch;
+                            // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1;
+                            // per chunk: start 4, sums 16; per tile 4.  A lane per position of a tile.
+                            StepDesc &st = addg(ST_WAGG, (u64)dg->ntiles * TILE_POS, 1,
+                                               S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) + 20.0 * nch +
+                                                   4.0 * dg->ntiles);
+                            mods.back() = S * (ph == 1 ? 2.0 : 3.0) + 2.0 * nch;  // beta once per chunk
                             st.u.wagg = a;
                         }
                         {
@@ -1061,6 +1267,7 @@ struct Planner {
                             a.C = w ? w->tC0 : nullptr;
                             StepDesc &st = addg(ST_WT0, N / 2, 1,
                                                N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 16.0 * nch);
+                            mods.back() = N * (ph == 2 ? 2.0 : 0.0) + 1.5 * N;
                             st.u.wt0 = a;
                             reduces(3);
                         }
@@ -1100,6 +1307,9 @@ struct Planner {
                         // per unit and table: 4 << pend entries read, 4 written
                         const double tabs = hasC ? 3.0 : 2.0;
                         StepDesc &st = addg(ST_WT, 4 * a.nu, 1, a.nu * tabs * 8.0 * ((4u << pend) + 4));
+                        // per quad: each table's four entries folded (one product, or three for two
+                        // challenges), then six products in each of the three value lanes
+                        mods.back() = a.nu * (4.0 * tabs * (pend == 1 ? 1 : 3) + 18.0);
                         st.fin = f;
                         st.u.wt = a;
                         reduces(12);
@@ -1123,6 +1333,7 @@ struct Planner {
                         a.msg = w ? msg + 3ull * (rbase + k0) : nullptr;
                         a.vout = vslot ? vslot + (ph - 1) : nullptr;
                         StepDesc &st = add(ST_WTAIL, 1, 24.0 * (1ull << (sp - k0 + pend)));
+                        mods.back() = 8.0 * (1ull << (sp - k0 + pend));
                         st.fin = f;
                         st.u.wtail = a;
                     }
@@ -1163,9 +1374,9 @@ struct Planner {
                         a.S = S;
                         a.k = k;
                         a.nfold = 1ull << (sp - k);
-                        a.idx = ph == 1 ? c->in1[i] : c->in2[i];
-                        a.oth = ph == 1 ? c->in2[i] : c->in1[i];
-                        a.type = c->type[i];
+                        a.idx = soa_at(i, ph == 1 ? c->in1[i] : c->in2[i]);
+                        a.oth = soa_at(i, ph == 1 ? c->in2[i] : c->in1[i]);
+                        a.type = soa_at(i, c->type[i]);
                         a.Vn = V(i + 1);
                         a.alo = w ? w->alo : nullptr;
                         a.ahi = w ? w->ahi : nullptr;
@@ -1247,6 +1458,7 @@ struct Planner {
                     const u32 ch = ((T + chunks - 1) / chunks + 3) / 4 * 4;  // equal chunks, 4 | ch
                     const u32 cb = (u32)(((1ull << M) + (SBLOCK / 64) - 1) / (SBLOCK / 64));
                     StepDesc &ls = add(ST_LINE, chunks * cb, 8.0 * (1ull << sp) * chunks);
+                    mods.back() = (double)T * (1ull << sp);  // one product per line point and entry
                     ls.u.line = LineArgs{sp, Ll, M, T, cb, ch, V(i + 1), w ? w->llo : nullptr,
                                          w ? w->lhl : nullptr, w ? w->lhh : nullptr};
                     reduces(LINE_CHUNK);
@@ -1258,59 +1470,205 @@ struct Planner {
                 }
             }
         }
+        sc_last[d - 1] = (int)out.size() - 1;
         StepDesc &e = add(ST_END, 1, 0);
         e.fin = layer_end;
         add_finish();
     }
 };
 
-// Group every layer's gates by in1 and by in2 (once per circuit).
-static int ensure_groups(gkr_circuit *c) {
-    if (c->gmem) return GKR_OK;
+// Chunk counts, single-chunk flags and byte sizes of every layer's gate
+// groups, from the wire counts alone (what planning and sizing need; no
+// memory is allocated).
+static void size_groups(gkr_circuit *c) {
+    if (c->grouped) return;
     const u32 d = c->L - 1;
-    std::vector<HostGroup> hg(2 * d);
+    c->grp[0].assign(d, gkr_circuit::Group());
+    c->grp[1].assign(d, gkr_circuit::Group());
+    c->g_off.assign(d + 1, 0);
     c->nch_max = 1;
+    auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
     size_t bytes = 0;
+    std::vector<u32> cnt;
     for (u32 i = 0; i < d; i++) {
-        const u64 N = 1ull << c->s[i + 1];
-        build_group(c->h_in1[i], c->h_in2[i], c->h_type[i], N, hg[2 * i]);
-        build_group(c->h_in2[i], c->h_in1[i], c->h_type[i], N, hg[2 * i + 1]);
+        c->g_off[i] = bytes;
+        const u64 N = 1ull << c->s[i + 1], S = c->S[i];
         for (int ph = 0; ph < 2; ph++) {
-            const HostGroup &G = hg[2 * i + ph];
-            c->nch_max = std::max<u64>(c->nch_max, G.cstart.size());
-            for (size_t n : {G.perm.size() * 4, G.cstart.size() * 4, G.xch.size() * 4, G.rowptr.size() * 4,
-                             G.oths.size() * 4, G.types.size()})
-                bytes += (n + 255) & ~size_t(255);
+            const std::vector<u32> &idx = ph ? c->h_in2[i] : c->h_in1[i];
+            cnt.assign(N, 0);
+            for (u64 g = 0; g < S; g++) cnt[idx[g]]++;
+            u64 nch = 0, ntiles = 0, span = TILE_POS + 1;  // positions in the open tile
+            bool single = true;
+            for (u64 x = 0; x < N; x++) {
+                const u64 k = (cnt[x] + GROUP_CHUNK - 1) / GROUP_CHUNK;
+                nch += k;
+                single = single && k <= 1;
+                for (u64 q = 0; q < k; q++) {  // the chunks of wire x, in order (as build_group cuts them)
+                    const u64 len = std::min<u64>(GROUP_CHUNK, cnt[x] - q * GROUP_CHUNK);
+                    if (span + len > TILE_POS) {
+                        ntiles++;
+                        span = 0;
+                    }
+                    span += len;
+                }
+            }
+            if (!ntiles) ntiles = 1;  // no gates: one empty tile
+            gkr_circuit::Group &D = c->grp[ph][i];
+            D.nch = (u32)nch;
+            D.ntiles = (u32)ntiles;
+            D.single = single;
+            c->nch_max = std::max<u64>(c->nch_max, nch + 1);
+            // perm, cstart, xch, rowptr, oths, tch, types (mixed layers)
+            bytes += 2 * al(S * 4) + al((nch + 1) * 4) + 2 * al((N + 1) * 4) + al((ntiles + 1) * 4) +
+                     al(c->h_type[i].size());
         }
     }
-    HIP_TRY(hipMalloc(&c->gmem, std::max<size_t>(bytes, 256)));
-    char *p = (char *)c->gmem;
-    auto put = [&](const std::vector<u32> &v, u32 **dst) -> hipError_t {
-        *dst = (u32 *)p;
-        p += (v.size() * 4 + 255) & ~size_t(255);
-        return v.empty() ? hipSuccess : hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice);
+    c->g_off[d] = bytes;
+    c->grouped = true;
+}
+
+// Group every layer's gates by in1 and by in2 (once per circuit), one layer
+// at a time, into the memory the circuit's gate arrays live in.
+static int ensure_groups(gkr_circuit *c) {
+    if (c->gmem) return GKR_OK;
+    size_groups(c);
+    const u32 d = c->L - 1;
+    void *mem = nullptr;
+    HIP_TRY(mem_alloc(c->gates_host, std::max<size_t>(c->g_off[d], 256), &mem));
+    c->gmem = mem;
+    char *p = (char *)mem;
+    auto put = [&](const void *src, size_t bytes, void **dst) -> hipError_t {
+        *dst = p;
+        p += (bytes + 255) & ~size_t(255);
+        return bytes ? hipMemcpy(*dst, src, bytes, hipMemcpyDefault) : hipSuccess;
     };
-    c->grp[0].resize(d);
-    c->grp[1].resize(d);
-    for (u32 i = 0; i < d; i++)
+    for (u32 i = 0; i < d; i++) {
+        const u64 N = 1ull << c->s[i + 1];
         for (int ph = 0; ph < 2; ph++) {
-            const HostGroup &G = hg[2 * i + ph];
+            HostGroup G;
+            build_group(ph ? c->h_in2[i] : c->h_in1[i], ph ? c->h_in1[i] : c->h_in2[i], c->h_type[i], N, G);
             gkr_circuit::Group &D = c->grp[ph][i];
-            HIP_TRY(put(G.perm, &D.perm));
-            HIP_TRY(put(G.cstart, &D.cstart));
-            HIP_TRY(put(G.xch, &D.xch));
-            HIP_TRY(put(G.rowptr, &D.rowptr));
-            HIP_TRY(put(G.oths, &D.oths));
-            if (!G.types.empty()) {
-                D.types = (u8 *)p;
-                p += (G.types.size() + 255) & ~size_t(255);
-                HIP_TRY(hipMemcpy(D.types, G.types.data(), G.types.size(), hipMemcpyHostToDevice));
-            }
-            D.nch = (u32)G.cstart.size() - 1;
-            D.single = true;
-            for (size_t x = 0; x + 1 < G.xch.size() && D.single; x++)
-                D.single = G.xch[x + 1] - G.xch[x] <= 1;
+            if (G.cstart.size() != (size_t)D.nch + 1 || G.tch.size() != (size_t)D.ntiles + 1)
+                return fail(GKR_ERR_INVALID, "gate grouping changed size");
+            HIP_TRY(put(G.perm.data(), G.perm.size() * 4, (void **)&D.perm));
+            HIP_TRY(put(G.cstart.data(), G.cstart.size() * 4, (void **)&D.cstart));
+            HIP_TRY(put(G.xch.data(), G.xch.size() * 4, (void **)&D.xch));
+            HIP_TRY(put(G.rowptr.data(), G.rowptr.size() * 4, (void **)&D.rowptr));
+            HIP_TRY(put(G.oths.data(), G.oths.size() * 4, (void **)&D.oths));
+            HIP_TRY(put(G.tch.data(), G.tch.size() * 4, (void **)&D.tch));
+            D.types = nullptr;
+            if (!G.types.empty()) HIP_TRY(put(G.types.data(), G.types.size(), (void **)&D.types));
         }
+        if ((size_t)(p - (char *)mem) != c->g_off[i + 1]) return fail(GKR_ERR_INVALID, "gate groups misplaced");
+    }
+    return GKR_OK;
+}
+
+// Move the circuit's gate arrays (struct of arrays and groups) between
+// device memory and pinned host memory; pointers into them are rebased.
+// The caller invalidates every step program that holds the old pointers.
+static int move_gates(gkr_circuit *c, bool to_host) {
+    if (c->gates_host == to_host) return GKR_OK;
+    const u32 d = c->L - 1;
+    void *ns = nullptr, *ng = nullptr;
+    hipError_t e = mem_alloc(to_host, std::max<size_t>(c->soa_off[d], 256), &ns);
+    if (e == hipSuccess) e = hipMemcpy(ns, c->soa, c->soa_off[d], hipMemcpyDefault);
+    if (e == hipSuccess && c->gmem) {
+        e = mem_alloc(to_host, std::max<size_t>(c->g_off[d], 256), &ng);
+        if (e == hipSuccess) e = hipMemcpy(ng, c->gmem, c->g_off[d], hipMemcpyDefault);
+    }
+    if (e != hipSuccess) {
+        gate_free(to_host, ns);
+        gate_free(to_host, ng);
+        return fail(e == hipErrorOutOfMemory ? GKR_ERR_NOMEM : GKR_ERR_DEVICE,
+                    std::string("moving the gate arrays: ") + hipGetErrorString(e));
+    }
+    auto rb = [](auto *ptr, void *ob, void *nb) -> decltype(ptr) {
+        return ptr ? (decltype(ptr))((char *)nb + ((const char *)ptr - (const char *)ob)) : ptr;
+    };
+    for (u32 i = 0; i < d; i++) {
+        c->in1[i] = rb(c->in1[i], c->soa, ns);
+        c->in2[i] = rb(c->in2[i], c->soa, ns);
+        c->type[i] = rb(c->type[i], c->soa, ns);
+    }
+    if (c->gmem)
+        for (int ph = 0; ph < 2; ph++)
+            for (gkr_circuit::Group &D : c->grp[ph]) {
+                D.perm = rb(D.perm, c->gmem, ng);
+                D.cstart = rb(D.cstart, c->gmem, ng);
+                D.xch = rb(D.xch, c->gmem, ng);
+                D.rowptr = rb(D.rowptr, c->gmem, ng);
+                D.oths = rb(D.oths, c->gmem, ng);
+                D.tch = rb(D.tch, c->gmem, ng);
+                D.types = rb(D.types, c->gmem, ng);
+            }
+    gate_free(c->gates_host, c->soa);
+    gate_free(c->gates_host, c->gmem);
+    c->soa = ns;
+    c->gmem = ng;
+    c->gates_host = to_host;
+    return GKR_OK;
+}
+
+// (Re)build a workspace's step program with the current launch shapes and
+// upload it; the workspace must be idle.
+// Copies of a per-layer (copy-once-per-layer) proof, Sec. 5.1.2.  The
+// prover works on two layers at a time: layer i's sum-check reads V_i and
+// V_{i+1} (slots i % 3 and (i+1) % 3) and layer i's gate groups (gate slot
+// i % 2).  Evaluation runs from the inputs upward: each table V_j, j >= 3,
+// goes to host memory once written, before evaluation of layer j - 3
+// overwrites its slot; every layer's struct of arrays comes in while the
+// layer above the next one is evaluated.  The sum-check runs downward:
+// V_{i+2} and layer i+1's groups come in while layer i's rounds run, each
+// once the last step reading its slot's previous content has finished.
+static void plan_transfers(const gkr_circuit *c, Workspace &w, const Planner &pl) {
+    w.xfers.clear();
+    if (w.mode != GKR_MEM_LAYER) return;
+    const int d = (int)c->L - 1;
+    const int load = 0;  // the first step loads the inputs into V_d
+    auto writer = [&](int j) { return j == d ? load : pl.eval_at[j]; };
+    auto vbytes = [&](int j) { return (size_t)8 << c->s[j]; };
+    std::vector<Workspace::Xfer> x;
+    for (int j = d; j >= 3; j--)  // evaluation: V_j out before its slot is reused
+        x.push_back({writer(j), pl.eval_at[j - 3], w.V[j], w.Vslot[j % 3], vbytes(j), hipMemcpyDeviceToHost});
+    for (int j = 3; j <= d; j++)  // sum-check: V_j back for layers j - 1 and j
+        x.push_back({pl.sc_last[j - 3], pl.sc_first[j - 1], w.Vslot[j % 3], w.V[j], vbytes(j),
+                     hipMemcpyHostToDevice});
+    if (w.gslot) {
+        const bool tables = c->omega_algo == GKR_OMEGA_TABLES;
+        for (int i = d - 1; i >= 0; i--)  // evaluation of layer i: its struct of arrays
+            x.push_back({i + 2 <= d - 1 ? pl.eval_at[i + 2] : -1, pl.eval_at[i], w.Gslot[i % 2],
+                         (const char *)c->soa + c->soa_off[i], c->soa_off[i + 1] - c->soa_off[i],
+                         hipMemcpyHostToDevice});
+        for (int i = 0; i < d; i++) {  // sum-check of layer i: its groups (or struct of arrays)
+            const char *src = tables ? (const char *)c->gmem + c->g_off[i] : (const char *)c->soa + c->soa_off[i];
+            const size_t n = tables ? c->g_off[i + 1] - c->g_off[i] : c->soa_off[i + 1] - c->soa_off[i];
+            x.push_back({i <= 1 ? pl.eval_at[i] : pl.sc_last[i - 2], pl.sc_first[i], w.Gslot[i % 2], src, n,
+                         hipMemcpyHostToDevice});
+        }
+    }
+    std::stable_sort(x.begin(), x.end(), [](const Workspace::Xfer &a, const Workspace::Xfer &b) {
+        return a.after < b.after;
+    });
+    w.xfers = x;
+}
+
+// Every copy starts after the step it follows and ends before the step that
+// waits for it, and stays inside its slot.
+static int check_transfers(const gkr_circuit *c, const Workspace &w) {
+    const int nsteps = (int)w.steps.size();
+    const size_t vslot = (size_t)8 << c->smax;
+    for (const Workspace::Xfer &x : w.xfers) {
+        if (x.before < 0 || x.before >= nsteps || x.after >= x.before)
+            return fail(GKR_ERR_INVALID, "a transfer is ordered after the step that needs it");
+        const char *d = (const char *)(x.kind == hipMemcpyDeviceToHost ? x.src : x.dst);
+        bool inside = false;
+        for (int k = 0; k < 3; k++)
+            inside = inside || (d >= (const char *)w.Vslot[k] && d + x.bytes <= (const char *)w.Vslot[k] + vslot);
+        for (int k = 0; k < 2 && w.gslot; k++)
+            inside = inside || (d >= w.Gslot[k] && d + x.bytes <= w.Gslot[k] + w.gslot);
+        if (!inside) return fail(GKR_ERR_INVALID, "a transfer leaves its slot");
+    }
     return GKR_OK;
 }
 
@@ -1327,9 +1685,21 @@ static int plan_into(gkr_circuit *c, Workspace &ws) {
     for (const StepDesc &sd : plan.out)
         if (sd.fin.kind != FIN_NONE && !((fin_mask(sd.kind) >> sd.fin.kind) & 1))
             return fail(GKR_ERR_INVALID, "step program: a step carries a finish its kernel lacks");
+    plan_transfers(c, ws, plan);
+    {
+        ws.steps.resize(nsteps);  // (its length is all check_transfers reads)
+        const int rc = check_transfers(c, ws);
+        if (rc) return rc;
+    }
+    while (ws.xev.size() < 2 * ws.xfers.size()) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ws.xev.push_back(e);
+    }
     ws.steps = plan.out;
     ws.pclass = plan.cls;
     ws.pbytes = plan.bytes;
+    ws.pmods = plan.mods;
     ws.punits = plan.units;
     std::vector<JobEntry> jobs(2 * nsteps);
     for (size_t t = 0; t < nsteps; t++) {
@@ -1349,32 +1719,57 @@ static int refresh_plan(gkr_circuit *c, Workspace &ws) {
     return ws.epoch == g_tune_epoch.load() ? GKR_OK : plan_into(c, ws);
 }
 
+// Device and pinned host bytes of a workspace of c in the given mode
+// (sized without allocating).
+static PlanSizes plan_sizes(gkr_circuit *c) {
+    if (c->omega_algo == GKR_OMEGA_TABLES) size_groups(c);
+    Planner count{c, nullptr};
+    count.build();
+    return count.sizes();
+}
+
+static void size_workspace(gkr_circuit *c, int mode, const PlanSizes &ps, size_t *dev, size_t *host) {
+    Workspace probe;
+    probe.mode = mode;
+    Arena a, h;
+    carve(c, a, h, probe, ps);
+    *dev = a.used;
+    *host = h.used;
+}
+
 // A proof's scratch with its step program (for the circuit's own proofs, or
-// one entry of a batch).
-static int make_workspace(gkr_circuit *c, Workspace **out) {
+// one entry of a batch or server), its tables placed as `mode` says.
+static int make_workspace(gkr_circuit *c, int mode, Workspace **out) {
     *out = nullptr;
     if (c->omega_algo == GKR_OMEGA_TABLES) {
         int rc = ensure_groups(c);
         if (rc) return rc;
     }
-    Planner count{c, nullptr};
-    count.build();
-    const PlanSizes ps = count.sizes();
+    const PlanSizes ps = plan_sizes(c);
     const size_t nsteps = ps.nsteps;
-    Workspace probe;
-    Arena sz;
-    carve(c, sz, probe, ps);
+    size_t dbytes = 0, hbytes = 0;
+    size_workspace(c, mode, ps, &dbytes, &hbytes);
     std::unique_ptr<Workspace, void (*)(Workspace *)> ws(new Workspace(), free_workspace);
-    HIP_TRY(hipMalloc(&ws->mem, sz.used));
-    ws->bytes = sz.used;
-    Arena a;
+    ws->mode = mode;
+    HIP_TRY(hipMalloc(&ws->mem, dbytes));
+    ws->bytes = dbytes;
+    if (hbytes) HIP_TRY(mem_alloc(true, hbytes, &ws->hmem));
+    ws->hbytes = hbytes;
+    Arena a, h;
     a.base = (char *)ws->mem;
-    a.cap = sz.used;
-    carve(c, a, *ws, ps);
+    a.cap = dbytes;
+    h.base = (char *)ws->hmem;
+    h.cap = hbytes;
+    carve(c, a, h, *ws, ps);
     ws->cap_rows = ps.rows;
     ws->cap_recs = ps.recs;
     ws->cap_items = ps.items;
     ws->steps.resize(nsteps);
+    if (mode == GKR_MEM_LAYER) {
+        HIP_TRY(hipStreamCreateWithFlags(&ws->cs, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&ws->ev_begin, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&ws->ev_join, hipEventDisableTiming));
+    }
     int rc = plan_into(c, *ws);
     if (rc) return rc;
     HIP_TRY(hipHostMalloc((void **)&ws->h_msgs, c->n_msgs * 8));
@@ -1385,29 +1780,82 @@ static int make_workspace(gkr_circuit *c, Workspace **out) {
     return GKR_OK;
 }
 
-// Device bytes a workspace of c takes (sized without allocating; cached).
-static int workspace_size(gkr_circuit *c, size_t *bytes) {
-    if (c->ws_bytes) {
-        *bytes = c->ws_bytes;
-        return GKR_OK;
+// Device bytes of c's gate arrays (struct of arrays, and the groups the
+// tables algorithm reads).
+static size_t gate_bytes(gkr_circuit *c) {
+    if (c->omega_algo == GKR_OMEGA_TABLES) size_groups(c);
+    const u32 d = c->L - 1;
+    return c->soa_off[d] + (c->omega_algo == GKR_OMEGA_TABLES ? c->g_off[d] : 0);
+}
+
+// Device bytes a workspace of c takes in `mode` (sized without allocating;
+// cached per mode until the circuit's program changes).
+static int workspace_size(gkr_circuit *c, int mode, size_t *bytes) {
+    if (mode < 0 || mode > GKR_MEM_MESSAGE) return fail(GKR_ERR_INVALID, "unknown memory mode");
+    if (!c->ws_bytes[mode]) {
+        size_t host = 0;
+        size_workspace(c, mode, plan_sizes(c), &c->ws_bytes[mode], &host);
     }
-    if (c->omega_algo == GKR_OMEGA_TABLES) {
-        int rc = ensure_groups(c);
-        if (rc) return rc;
-    }
-    Planner count{c, nullptr};
-    count.build();
-    Workspace probe;
-    Arena sz;
-    carve(c, sz, probe, count.sizes());
-    c->ws_bytes = sz.used;
-    *bytes = sz.used;
+    *bytes = c->ws_bytes[mode];
     return GKR_OK;
 }
 
 static int ensure_workspace(gkr_circuit *c) {
     if (c->ws) return refresh_plan(c, *c->ws);
-    return make_workspace(c, &c->ws);
+    return make_workspace(c, c->mem_mode, &c->ws);
+}
+
+// Device and pinned host bytes of one proof of c in `mode`, gate arrays
+// included where the mode places them.
+static int memory_need(gkr_circuit *c, int mode, u64 *dev, u64 *host) {
+    if (mode < GKR_MEM_RESIDENT || mode > GKR_MEM_MESSAGE) return fail(GKR_ERR_INVALID, "unknown memory mode");
+    size_t d = 0, h = 0;
+    size_workspace(c, mode, plan_sizes(c), &d, &h);
+    const size_t g = gate_bytes(c);
+    *dev = d + (mode == GKR_MEM_RESIDENT ? g : 0);
+    *host = h + (mode == GKR_MEM_RESIDENT ? 0 : g);
+    return GKR_OK;
+}
+
+extern "C" int gkr_memory_need(gkr_circuit *c, int mode, uint64_t *device_bytes, uint64_t *host_bytes) {
+    if (!c) return fail(GKR_ERR_INVALID, "circuit is NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    u64 d = 0, h = 0;
+    const int rc = memory_need(c, mode, &d, &h);
+    if (rc) return rc;
+    if (device_bytes) *device_bytes = d;
+    if (host_bytes) *host_bytes = h;
+    return GKR_OK;
+}
+
+static void drop_batches_of(const gkr_circuit *c);
+static void drop_served_scratch_of(const gkr_circuit *c);
+
+extern "C" int gkr_circuit_set_memory(gkr_circuit *c, int mode, uint64_t device_budget_bytes, int *chosen) {
+    if (!c) return fail(GKR_ERR_INVALID, "circuit is NULL");
+    if (mode < GKR_MEM_RESIDENT || mode > GKR_MEM_AUTO) return fail(GKR_ERR_INVALID, "unknown memory mode");
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        int pick = -1;
+        for (int m = GKR_MEM_RESIDENT; m <= GKR_MEM_MESSAGE && pick < 0; m++) {
+            if (mode != GKR_MEM_AUTO && m != mode) continue;
+            u64 d = 0, h = 0;
+            const int rc = memory_need(c, m, &d, &h);
+            if (rc) return rc;
+            if (!device_budget_bytes || d <= device_budget_bytes) pick = m;
+        }
+        if (pick < 0) return fail(GKR_ERR_NOMEM, "no memory mode fits the device budget");
+        free_workspace(c->ws);  // every step program holds the old placement
+        c->ws = nullptr;
+        const int rc = move_gates(c, pick != GKR_MEM_RESIDENT);
+        c->mem_mode = pick;
+        c->gen++;
+        if (chosen) *chosen = pick;
+        if (rc) return rc;
+    }
+    drop_batches_of(c);
+    drop_served_scratch_of(c);
+    return GKR_OK;
 }
 
 // ------------------------------------------------------------------- prover
@@ -1418,14 +1866,44 @@ static int ensure_workspace(gkr_circuit *c) {
         HIP_TRY(expr);                                            \
     } while (0)
 
-// Enqueue one whole proof (inputs already in w.V[d], seed in w.state[2]):
-// one launch per step.
+// Enqueue one whole proof (inputs already staged, seed in w.state[2]): one
+// launch per step.  A per-layer proof's copies run on its copy stream: a
+// copy starts once the step named by its `after` has finished (an event on
+// st), and the step named by its `before` waits for it (an event on cs).
 static int enqueue_proof(Workspace &w, hipStream_t st) {
-    const size_t n = w.steps.size();
+    const size_t n = w.steps.size(), nx = w.xfers.size();
+    size_t xi = 0;
+    auto issue = [&](int after) -> int {  // copies that may start after step `after`
+        if (xi >= nx || w.xfers[xi].after != after) return GKR_OK;
+        hipEvent_t done = w.xev[2 * xi];
+        HIP_TRY(hipEventRecord(done, st));
+        HIP_TRY(hipStreamWaitEvent(w.cs, done, 0));
+        for (; xi < nx && w.xfers[xi].after == after; xi++) {
+            const Workspace::Xfer &x = w.xfers[xi];
+            HIP_TRY(hipMemcpyAsync(x.dst, x.src, x.bytes, x.kind, w.cs));
+            HIP_TRY(hipEventRecord(w.xev[2 * xi + 1], w.cs));
+        }
+        return GKR_OK;
+    };
+    if (nx) {
+        int rc = issue(-1);
+        if (rc) return rc;
+    }
     for (size_t t = 0; t < n; t++) {
+        for (size_t k = 0; k < nx; k++)
+            if (w.xfers[k].before == (int)t) HIP_TRY(hipStreamWaitEvent(st, w.xev[2 * k + 1], 0));
         hipEvent_t a, b;
-        prof_pair(w.pclass[t], w.pbytes[t], &a, &b);
+        prof_pair(w.pclass[t], w.pbytes[t], &a, &b, w.pmods[t], w.punits[t] ? (int)size_class(w.punits[t]) : -1);
         HIP_TRY(launch_step(st, w.steps[t], a, b));
+        if (nx) {
+            int rc = issue((int)t);
+            if (rc) return rc;
+        }
+    }
+    if (xi != nx) return fail(GKR_ERR_INVALID, "a transfer of the proof was not issued");
+    if (nx) {  // the copy stream's work ends before the proof does
+        HIP_TRY(hipEventRecord(w.ev_join, w.cs));
+        HIP_TRY(hipStreamWaitEvent(st, w.ev_join, 0));
     }
     return GKR_OK;
 }
@@ -1462,7 +1940,7 @@ static int proof_graph(Workspace &w) {
 // One proof's launches on st: replayed from its graph, or launched one by
 // one while per-launch profiling is on.
 static int run_proof(Workspace &w, hipStream_t st) {
-    if (g_prof.on) return enqueue_proof(w, st);
+    if (g_prof.on || w.mode == GKR_MEM_LAYER) return enqueue_proof(w, st);
     const int rc = proof_graph(w);
     if (rc) return rc;
     HIP_TRY(hipGraphLaunch(w.gexec, st));
@@ -1479,7 +1957,8 @@ static int stage_proof(gkr_circuit *c, Workspace &w, const uint64_t *inputs, int
     if (!inputs_on_device) {
         for (u64 g = 0; g < Sd; g++)
             if (inputs[g] >= fp::P) return fail(GKR_ERR_RANGE, "input value not below p");
-        HIP_TRY(hipMemcpyAsync(w.instage, inputs, Sd * 8, hipMemcpyHostToDevice, st));
+        // (into device memory, or into pinned host memory for out-of-core proofs)
+        HIP_TRY(hipMemcpyAsync(w.instage, inputs, Sd * 8, hipMemcpyDefault, st));
         src = w.instage;
     }
     w.h_setup[0] = seed;
@@ -1535,6 +2014,10 @@ extern "C" int gkr_autotune(uint32_t n, const gkr_circuit *const *circuits, cons
         for (u32 q = 0; q < n && !rc; q++) {
             gkr_circuit *c = const_cast<gkr_circuit *>(circuits[q]);
             std::lock_guard<std::mutex> lk(c->mu);
+            if (c->mem_mode == GKR_MEM_LAYER) {
+                rc = fail(GKR_ERR_INVALID, "launch shapes are tuned on resident or per-message circuits");
+                break;
+            }
             rc = ensure_workspace(c);
             if (rc) break;
             Workspace &w = *c->ws;
@@ -1640,6 +2123,7 @@ struct BatchPlan {
     u32 epoch = 0;  // launch shapes its programs were planned with
     std::vector<Workspace *> ws;
     std::vector<u32> l_off, l_njobs, l_blocks;  // per launch
+    std::vector<double> l_bytes, l_mods;         // algorithmic bytes and products per launch
     std::vector<u64> out_off;
     u64 out_words = 0;
     void *mem = nullptr;  // job tables, slots, gathered transcripts
@@ -1682,7 +2166,7 @@ int enqueue_batch(BatchPlan &B, hipStream_t st, bool profile) {
     HIP_TRY(launch_batch_setup(st, B.d_slots, n));
     for (size_t t = 0; t < B.l_off.size(); t++) {
         hipEvent_t a = nullptr, b = nullptr;
-        if (profile) prof_pair(PC_BATCH, 0, &a, &b);
+        if (profile) prof_pair(PC_BATCH, B.l_bytes[t], &a, &b, B.l_mods[t]);
         HIP_TRY(launch_steps(st, B.d_jobs + B.l_off[t], B.l_njobs[t], B.l_blocks[t], a, b));
     }
     HIP_TRY(launch_batch_gather(st, B.d_slots, n, B.d_out));
@@ -1698,7 +2182,9 @@ int build_batch(const std::vector<gkr_circuit *> &cs, int flags, std::unique_ptr
     for (gkr_circuit *c : cs) {
         Workspace *w = nullptr;
         std::lock_guard<std::mutex> lk(c->mu);
-        int rc = make_workspace(c, &w);
+        if (c->mem_mode == GKR_MEM_LAYER)
+            return fail(GKR_ERR_INVALID, "a copy-once-per-layer circuit is proved one proof at a time");
+        int rc = make_workspace(c, c->mem_mode, &w);
         if (rc) return rc;
         B->ws.push_back(w);
     }
@@ -1709,12 +2195,17 @@ int build_batch(const std::vector<gkr_circuit *> &cs, int flags, std::unique_ptr
     for (size_t t = 0; t < T; t++) {
         B->l_off.push_back((u32)jobs.size());
         u32 blocks = 0, nj = 0;
+        double lb = 0, lm = 0;
         for (Workspace *w : B->ws) {
             if (t >= w->steps.size()) continue;
             jobs.push_back(JobEntry{w->d_steps + t, blocks, 0});
             blocks += step_grid(w->steps[t]);
+            lb += w->pbytes[t];
+            lm += w->pmods[t];
             nj++;
         }
+        B->l_bytes.push_back(lb);
+        B->l_mods.push_back(lm);
         jobs.push_back(JobEntry{nullptr, blocks, 0});  // sentinel
         B->l_njobs.push_back(nj);
         B->l_blocks.push_back(blocks);
@@ -1822,7 +2313,7 @@ extern "C" int gkr_batch_prove(uint32_t n, const gkr_circuit *const *circuits,
         B->h_slots[q].input = (u64)(uintptr_t)inputs[q];
     }
     HIP_TRY(hipMemcpyAsync(B->d_slots, B->h_slots, n * sizeof(BatchSlot), hipMemcpyHostToDevice, st));
-    if (B->gexec) {
+    if (B->gexec && !g_prof.on) {
         HIP_TRY(hipGraphLaunch(B->gexec, st));
     } else {
         int rc = enqueue_batch(*B, st, g_prof.on);
@@ -1910,7 +2401,9 @@ int vs_reserve(size_t bytes, size_t host_words) {
 }
 
 // Streamed input extension for host inputs (the verifier's one pass over
-// the inputs, Sec. 4.1.2).  Chunks of VCHUNK values are copied from the
+// the inputs, Sec. 4.1.2, through two buffers, one filling while the other
+// is processed, as Sec. 4.2.2 suggests for a streaming verifier).  Chunks of
+// VCHUNK values are copied from the
 // caller's memory into two device buffers on a copy stream, chunk k into
 // buffer k & 1 once the kernels that read that buffer before have finished;
 // the caller's stream checks the chunk against p (u64 values, into *bad_dev)
@@ -2282,7 +2775,8 @@ extern "C" int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_devic
         }
         claim = quad_at(G, r[j]);
     }
-    // ~a(r) on the device, one pass over the vector (Sec. 4.1.2)
+    // ~a(r) on the device, one pass over the vector (the verifier's secret,
+    // Sec. 4.1.2; its pass parallel over the input symbols, Sec. 4.2.2)
     std::lock_guard<std::mutex> lk(g_f2.mu);
     struct {
         u64 *pts, *tab, *partials, *res;
@@ -2413,10 +2907,19 @@ struct gkr_server {
             }
             drop(w);  // stale or not re-plannable: make a fresh one below
         }
+        // resident scratch if the circuit is resident and it fits the
+        // budget, else the out-of-core placement whose rounds read their
+        // tables in place from host memory (Sec. 5.1.3)
         size_t need = 0;
+        int mode = GKR_MEM_RESIDENT;
         {
             std::lock_guard<std::mutex> lk(r->c->mu);
-            const int rc = workspace_size(r->c, &need);
+            int rc = GKR_OK;
+            if (r->c->mem_mode == GKR_MEM_RESIDENT) rc = workspace_size(r->c, GKR_MEM_RESIDENT, &need);
+            if (!rc && (r->c->mem_mode != GKR_MEM_RESIDENT || need > budget)) {
+                mode = GKR_MEM_MESSAGE;
+                rc = workspace_size(r->c, mode, &need);
+            }
             if (rc) {
                 r->msg = g_err;
                 return rc;
@@ -2441,7 +2944,7 @@ struct gkr_server {
         Workspace *w = nullptr;
         {
             std::lock_guard<std::mutex> lk(r->c->mu);
-            const int rc = make_workspace(r->c, &w);
+            const int rc = make_workspace(r->c, mode, &w);
             if (rc) {
                 r->msg = g_err;
                 return rc;
@@ -2468,7 +2971,7 @@ struct gkr_server {
     int start(ServeReq *r) {
         Workspace &w = *r->ws;
         const u64 Sd = r->inputs.size();
-        HIP_TRY(hipMemcpyAsync(w.instage, r->inputs.data(), Sd * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(w.instage, r->inputs.data(), Sd * 8, hipMemcpyDefault, st));
         w.h_setup[0] = r->seed;
         w.h_setup[1] = (u64)(uintptr_t)w.instage;
         w.h_setup[2] = 0;
@@ -2531,17 +3034,24 @@ struct gkr_server {
             JobTable t;
             t.n = 0;
             t.total = 0;
+            double lb = 0, lm = 0;
             for (ServeReq *r : running) {
                 const StepDesc &sd = r->ws->steps[r->next];
                 t.e[t.n++] = JobEntry{r->ws->d_steps + r->next, t.total, 0};
                 t.total += step_grid(sd);
+                lb += r->ws->pbytes[r->next];
+                lm += r->ws->pmods[r->next];
             }
             t.e[t.n] = JobEntry{nullptr, t.total, 0};
             lk.unlock();
             // keep at most ring.size() launches in flight
             hipEvent_t &slot = ring[ring_pos];
             (void)hipEventSynchronize(slot);
+            hipEvent_t pa = nullptr, pb = nullptr;
+            prof_pair(PC_SERVE, lb, &pa, &pb, lm);
+            if (pa) (void)hipEventRecord(pa, st);
             hipError_t e = launch_step_table(st, t);
+            if (pb) (void)hipEventRecord(pb, st);
             if (e == hipSuccess) e = hipEventRecord(slot, st);
             ring_pos = (ring_pos + 1) % ring.size();
             lk.lock();

@@ -7,7 +7,7 @@
 // writes one row of partial sums, and a one-workgroup *_final kernel folds
 // the rows, writes the message and only then draws the next challenge on
 // the device.  All arithmetic is exact modular integer arithmetic (no
-// floating point, Sec. 5.1), so any summation order gives identical bits.
+// floating point, Sec. 6.1), so any summation order gives identical bits.
 #include "fp61.hpp"
 #include "kernels.hpp"
 

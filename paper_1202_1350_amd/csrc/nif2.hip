@@ -1,11 +1,11 @@
-// nif2.hip -- the non-interactive F2 protocol (Sec. 2.3, 3.2.2, 4.2) on
+// nif2.hip -- the non-interactive F2 protocol (Sec. 3.2, 4.2) on
 // gfx950: the prover's prime factor transforms of the grid rows and the
 // column square-sums of its proof, and the verifier's row evaluations.
 //
 // The universe is a v x h grid, cell (row y, column j) = a_{j v + y}, so
 // element j of every row is one contiguous run of v words: a thread per
 // (row, line of a pass) reads and writes coalesced, the layout the paper
-// reaches by transposing the grid (Sec. 4.2.1).  Row y is the polynomial
+// reaches by transposing the grid (Sec. 6.2.1).  Row y is the polynomial
 // f_y of degree < h through the order-h subgroup H = <w>; the proof is
 // g = sum_y f_y^2 on the order-2h subgroup <xi> (xi^2 = w): the even points
 // are the data squared, the odd points are f_y on the coset xi H, obtained

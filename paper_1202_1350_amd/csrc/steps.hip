@@ -3,7 +3,7 @@
 // Sec. 4.1.1 of the paper: every gate (or table entry) contributes
 // independently to the prover's message, so a step is a grid-stride pass in
 // which each workgroup sums its share (wave64 shuffles, then LDS) into one
-// row of partial sums.  All arithmetic is exact in F_p (Sec. 5.1), so the
+// row of partial sums.  All arithmetic is exact in F_p (Sec. 6.1), so the
 // result does not depend on the summation order.
 #include <hip/hip_ext.h>
 
@@ -639,13 +639,56 @@ __device__ __forceinline__ void wire_sums(const Args &a, u64 beta, u32 p0, u32 p
     sC_out = sC;
 }
 
+// Value v of lane l (l uniform or not; every lane of the wave takes part).
+__device__ __forceinline__ u64 bperm64(u64 v, u32 l) {
+    const int lo = __builtin_amdgcn_ds_bpermute((int)(l << 2), (int)(u32)v);
+    const int hi = __builtin_amdgcn_ds_bpermute((int)(l << 2), (int)(u32)(v >> 32));
+    return ((u64)(u32)hi << 32) | (u64)(u32)lo;
+}
+
+// Per-chunk sums of the gates' terms (wires with more than one chunk).  A
+// wave takes a tile of whole chunks (at most 64 sorted positions) and lane
+// l the gate at the tile's position l, so the gate arrays are read in
+// coalesced runs; the inclusive scan of the terms over the wave gives each
+// chunk's sum as the scan at its last position minus the scan just before
+// its first.  beta(z, a*) multiplies every term, so it is applied once per
+// chunk.  Terms as in wire_sums.
 __device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp, const Ctx &c) {
     const u64 beta = pp.state[0];  // beta(z, a*)
-    for (u64 ch = c.gtid; ch < a.nch; ch += c.gstride) {
-        u64 sA, sC;
-        wire_sums(a, beta, a.cstart[ch], a.cstart[ch + 1], sA, sC);
-        a.partA[ch] = sA;
-        a.partC[ch] = sC;
+    const u32 lane = threadIdx.x & 63;
+    const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
+    const u64 nwaves = c.gstride >> 6;
+    for (u64 t = c.gtid >> 6; t < a.ntiles; t += nwaves) {  // wave-uniform
+        const u32 c0 = a.tch[t], nc = a.tch[t + 1] - c0;
+        if (nc == 0) continue;  // (a group without gates has one empty tile)
+        const u32 base = a.cstart[c0], end = a.cstart[c0 + nc];
+        const u32 p = base + lane;
+        u64 vA = 0, vC = 0;
+        if (p < end) {
+            const u32 g = a.perm[p], o = a.oths[p];
+            const bool ismul = a.kind == 1 || (a.kind == 2 && a.types[p]);
+            u64 w = mul(a.alo[g & amask], a.ahi[g >> a.La]);
+            if (a.ph == 1) {
+                const u64 wy = mul(w, a.Vn[o]);
+                vA = ismul ? wy : w;
+                vC = ismul ? 0 : wy;
+            } else {
+                w = mul(w, mul(a.blo[o & bmask], a.bhi[o >> a.Lb]));
+                vA = ismul ? 0 : w;
+                vC = ismul ? w : 0;
+            }
+        }
+        const u64 sA = wave_sum63(vA), sC = wave_sum63(vC);  // inclusive scans
+        const bool mine = lane < nc;  // lane k writes chunk c0 + k
+        const u32 k = mine ? lane : 0;
+        const u32 first = a.cstart[c0 + k] - base, last = a.cstart[c0 + k + 1] - base - 1;
+        const u32 before = first ? first - 1 : 0;
+        const u64 A1 = bperm64(sA, last), C1 = bperm64(sC, last);
+        const u64 A0 = bperm64(sA, before), C0 = bperm64(sC, before);
+        if (mine) {
+            a.partA[c0 + k] = mul(beta, first ? sub(A1, A0) : A1);
+            a.partC[c0 + k] = mul(beta, first ? sub(C1, C0) : C1);
+        }
     }
 }
 

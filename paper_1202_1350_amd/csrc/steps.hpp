@@ -238,6 +238,8 @@ struct WaggArgs {
     const u64 *blo, *bhi;
     u32 Lb;
     u64 *partA, *partC;      // per chunk (ph 2: sums over ADD / MUL gates)
+    u32 ntiles;              // tiles of whole chunks, at most 64 sorted positions each:
+    const u32 *tch;          // tile t holds chunks [tch[t], tch[t+1])
 };
 struct Wt0Args {
     u32 ph, hasC;

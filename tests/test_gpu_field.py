@@ -1,4 +1,4 @@
-"""Device field module (Sec. 5.1) against Python big integers."""
+"""Device field module (Sec. 6.1) against Python big integers."""
 import random
 
 import numpy as np

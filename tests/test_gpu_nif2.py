@@ -1,5 +1,5 @@
-"""GPU prover and verifier of the non-interactive F2 protocol (Sec. 2.3,
-3.2.2, 4.2): proofs bit-exact against the oracle on grids the oracle
+"""GPU prover and verifier of the non-interactive F2 protocol (Sec. 3.2,
+4.2): proofs bit-exact against the oracle on grids the oracle
 finishes quickly (every supported factor, ragged last rows); at Table 3's
 universe size (n = 25 million) the proof's F2 value, its degree bound and
 the oracle's verifier pin every value; errors and the verifier's rejections."""

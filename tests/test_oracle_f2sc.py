@@ -1,5 +1,5 @@
 """Pins of the oracle's sum-check for F2 = sum_x ~a(x)^2 (the sum-check
-primitive of Sec. 6 applied to the second frequency moment of Sec. 2.3)."""
+primitive of Sec. 7 applied to the second frequency moment of Sec. 3.2)."""
 import random
 
 import numpy as np

@@ -1,5 +1,5 @@
 """Oracle field and generator pins: F_p arithmetic against Python big
-integers (p = 2^61 - 1, Sec. 5.1) and SplitMix64 against its published
+integers (p = 2^61 - 1, Sec. 6.1) and SplitMix64 against its published
 known answers."""
 import os
 import random

@@ -5,7 +5,7 @@
 - any size: the sum-check invariants hold in every round, the honest
   transcript is accepted, single-element changes are rejected;
 - circuit outputs equal the directly computed F2, C = AB and pattern-match
-  distances (the unverifiable algorithms of Sec. 5.2.5);
+  distances (the unverifiable algorithms of Sec. 6.2.4);
 - gate counts match Table 2."""
 import os
 import random
@@ -164,7 +164,7 @@ def test_wrong_input_or_seed_rejected():
 
 
 def test_outputs_equal_direct_computations():
-    # F2 = sum a_i^2 (Sec. 5.2.5: the unverifiable algorithm sums squares)
+    # F2 = sum a_i^2 (Sec. 6.2.4: the unverifiable algorithm sums squares)
     circ, x, seed = W.c1_f2()
     V = O.evaluate(circ, x)
     assert int(V[0][0]) == sum(int(v) ** 2 for v in x) % P
@@ -190,7 +190,7 @@ def test_outputs_equal_direct_computations():
 
 
 def test_f0_circuits_equal_direct_computations():
-    # F0 (Sec. 5.2.1): the output is 2 |{i : a_i != 0}| by Fermat's little theorem
+    # F0 (Sec. 6.2.1): the output is 2 |{i : a_i != 0}| by Fermat's little theorem
     for n, seed in ((1, 1), (7, 2), (200, 3)):
         x = W.f0_inputs(n, seed)
         x[::5] = 0

@@ -1,4 +1,4 @@
-"""The oracle of the non-interactive F2 protocol (Sec. 2.3, 3.2.2), pinned
+"""The oracle of the non-interactive F2 protocol (Sec. 3.2), pinned
 to definitions computed here independently: the F2 value, the degree bound
 of the proof polynomial, a brute-force interpolation of every row on tiny
 grids, the subgroup orders, completeness and soundness."""

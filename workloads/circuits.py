@@ -1,4 +1,4 @@
-"""Wiring of the layered fan-in-2 circuits the paper benchmarks (Sec. 5.2.1).
+"""Wiring of the layered fan-in-2 circuits the paper benchmarks (Sec. 6.2.1).
 
 Layers are numbered 0 = output ... d = input.  Layer i < d has gate type
 (0 = ADD, 1 = MUL) and two wires into layer i+1 per gate; a wire may name a
@@ -46,7 +46,7 @@ def _sum_tree(sizes, types, in1, in2, width):
 
 def f2_circuit(n: int) -> Circuit:
     """F2 = sum_i a_i^2: a layer of MUL gates squaring each input, then a
-    binary ADD tree (the paper's single large-fan-in sum gate, Sec. 5.2.1,
+    binary ADD tree (the paper's single large-fan-in sum gate, Sec. 6.2.1,
     written as fan-in-2 adds).  n = 2^k gives 3n - 1 gates."""
     assert n >= 1
     g = np.arange(n, dtype=np.uint32)
@@ -101,7 +101,7 @@ def pm_circuit(n: int, q: int = 8) -> Circuit:
 
 
 # ----------------------------------------------------------------------
-# F0 (Sec. 5.2.1): Fermat's little theorem sends x to x^(p-1) = 1 for x != 0
+# F0 (Sec. 6.2.1): Fermat's little theorem sends x to x^(p-1) = 1 for x != 0
 # and 0 for x = 0, so summing x^(p-1) counts the non-zero values.  p - 1 =
 # 2^61 - 2 = 2 + 4 + ... + 2^60.  Two tracks of MUL gates per value: s_L =
 # x^(2^L) squares itself; the accumulator a starts one layer later as

@@ -1,6 +1,6 @@
 """Seeded synthetic workloads of the benchmark configurations.
 
-The paper generated its data at random (Sec. 5.2.5, unverifiable F2); these
+The paper generated its data at random (Sec. 6.2.4, unverifiable F2); these
 are uniform integers drawn from SplitMix64 streams (see prng.py), with the
 sizes of the workloads measured:
   F2 GKR:       n inputs uniform in [0, 2^20), seed s, purpose 1
