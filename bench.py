@@ -196,6 +196,21 @@ def cpu_baseline(W, np):
     for N, th in ((64, T), (32, 1)):
         c, x = W.matmult_circuit(N), W.matmult_inputs(N, 3)
         run(f"MatMult GKR prove, N={N}, seed 3", th, c.gates, lambda: O.prove(c, x, 3))
+    # batched workload: the first eight proofs of the 64-proof batch (seed 4),
+    # one after another; serving: one proof of each request type
+    mix = W.batch_mix(4, 64)[:8]
+    t = time.perf_counter()
+    O.set_threads(T)
+    for _, c, x, sd in mix:
+        O.prove(c, x, sd)
+    dt = time.perf_counter() - t
+    res["samples"].append({"workload": "first 8 proofs of the 64-proof batch (seed 4), summed", "threads": T,
+                           "seconds": dt, "value": sum(c.gates for _, c, _, _ in mix) / dt, "unit": "gates/s"})
+    for name, c, x in (("F2 n=2^14", W.f2_circuit(1 << 14), W.f2_inputs(1 << 14, 64)),
+                       ("F2 n=2^18", W.f2_circuit(1 << 18), W.f2_inputs(1 << 18, 68)),
+                       ("MatMult N=64", W.matmult_circuit(64), W.matmult_inputs(64, 64)),
+                       ("PM text 2^16", W.pm_circuit(1 << 16), W.pm_inputs(1 << 16, 66)[0])):
+        run(f"serving request type {name}, one proof", T, c.gates, lambda c=c, x=x: O.prove(c, x, 5))
     # the unverifiable computations the paper compares against (numpy, one pass)
     t = time.perf_counter()
     _ = int((x20.astype(np.float64) ** 2).sum())
@@ -230,6 +245,32 @@ def config_leg(G, W, np, torch, make, name, reps):
     return {"workload": name, "gates": circ.gates, "rounds": gc.rounds, "msgs": gc.n_msgs,
             "prove_ms": dt * 1e3, "gates_per_s": circ.gates / dt, "proofs_per_s": 1.0 / dt,
             "verify_ms": 1e3 * sorted(tv)[2], "accepted": True}
+
+
+def size_sweep(G, W, np, torch):
+    """Prover gates/s against input size (the analogue of the paper's
+    Fig. 5: speedups grow with the input as fixed costs amortise): F2 at
+    n = 2^10 .. 2^22 and MatMult at N = 16 .. 256, inputs resident, mean of
+    five proofs after a warm-up."""
+    out = []
+    cases = [("F2", n, lambda n=n: (W.f2_circuit(n), W.f2_inputs(n, 60 + n))) for n in
+             (1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22)]
+    cases += [("MatMult", N, lambda N=N: (W.matmult_circuit(N), W.matmult_inputs(N, 60 + N)))
+              for N in (16, 32, 64, 128, 256)]
+    for kind, size, make in cases:
+        circ, x = make()
+        gc = G.Circuit.from_workload(circ)
+        xt = torch.from_numpy(x.view(np.int64)).cuda().view(torch.uint64)
+        G.gkr_prove(gc, xt, 5, want_chals=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            G.gkr_prove(gc, xt, 5, want_chals=False)
+        dt = (time.perf_counter() - t) / 5
+        out.append({"circuit": kind, "size": size, "gates": circ.gates, "rounds": gc.rounds,
+                    "prove_ms": dt * 1e3, "gates_per_s": circ.gates / dt})
+        del gc, xt
+    return out
 
 
 # Table 2's GPU prover times in seconds (the paper's GPU; context only).
@@ -812,6 +853,8 @@ def main():
         line["configs"] = {
             "F2 n=2^10": config_leg(G, W, np, torch, W.c1_f2, "F2 GKR n=2^10, seed 1", 50),
             "MatMult N=256": config_leg(G, W, np, torch, W.c3_matmult, "MatMult GKR N=256, seed 3", 10)}
+    if not args.no_configs:
+        line["size_sweep"] = size_sweep(G, W, np, torch)
     if not args.no_batch:
         line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2), args.autotune != "off",
                                     alu_peak)
