@@ -146,6 +146,11 @@ def save_tune_table(G, path, note):
         f.write(f"table: {G.gkr_tune_get().hex()}\n")
 
 
+def note(*a):
+    """A progress line on stderr, one per leg of the benchmark."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def cpu_info():
     """Host CPU model (lscpu) and thread count."""
     import subprocess
@@ -178,6 +183,7 @@ def cpu_baseline(W, np):
     res = {"host": cpu_info(), "samples": []}
 
     def run(name, threads, gates, fn, unit="gates/s"):
+        note("oracle:", name, f"threads={threads}")
         O.set_threads(threads)
         t = time.perf_counter()
         fn()
@@ -849,29 +855,38 @@ def main():
                        "line_kernel_mulmods_per_proof": lm,
                        "line_kernel_mulmods_per_s": line_rate,
                        "line_kernel_frac_of_peak": line_rate / alu_peak}
+    note("plain leg done", f"{prove_s * 1e3:.3f} ms/proof")
     if not args.no_configs:
+        note("configuration legs")
         line["configs"] = {
             "F2 n=2^10": config_leg(G, W, np, torch, W.c1_f2, "F2 GKR n=2^10, seed 1", 50),
             "MatMult N=256": config_leg(G, W, np, torch, W.c3_matmult, "MatMult GKR N=256, seed 3", 10)}
     if not args.no_configs:
+        note("input-size sweep")
         line["size_sweep"] = size_sweep(G, W, np, torch)
     if not args.no_batch:
+        note("batch leg")
         line["batched"] = batch_leg(G, W, np, torch, max(1, args.steps // 2), args.autotune != "off",
                                     alu_peak)
     if not args.no_serve:
         k = max(1, args.serve_points)
         rates = [0.1 * 15.0 ** (j / (k - 1)) for j in range(k)] if k > 1 else [1.0]
+        note("serve leg")
         line["served"] = serve_leg(G, W, np, args.serve_requests, 200, rates, alu_peak)
     kept = {}
     if not args.no_table2:
+        note("Table 2 circuits")
         line["table2_circuits"], kept = table2_leg(G, W, np, torch, 3, not args.no_cpu_baseline,
                                                    () if args.no_ooc else ("F0", "MatMult"))
     if kept:
+        note("out-of-core leg")
         line["out_of_core"] = ooc_leg(G, np, torch, kept, 2)
     kept = None
     if not args.no_table3:
+        note("Table 3 leg")
         line["table3_noninteractive_f2"] = table3_leg(G, np, torch, 5, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
+        note("oracle on the host cores")
         cb = cpu_baseline(W, np)
         line["cpu_baseline"] = cb["headline"]
         line["cpu_oracle_samples"] = cb
