@@ -280,6 +280,21 @@ int f2_sumcheck_verify(const uint32_t *freq, uint64_t n, int on_device, uint64_t
                        const uint64_t *msgs, uint64_t n_msgs, int *accepted,
                        gkr_reject_info *why, void *hip_stream);
 
+/* f2_sumcheck_prove without any allocation, for callers that cannot
+ * allocate device or pinned memory during a call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, transcript and errors as f2_sumcheck_prove, with n <= 2^22:
+ * its scratch is one static 48 MiB device array per GPU (the two folded
+ * tables, the partial rows, the transcript and, for host inputs, their
+ * staging copy), held from the library's load on that GPU until the
+ * process ends; larger n returns GKR_ERR_NOMEM.  msgs and chals are copied
+ * straight into the caller's host arrays.  Calls on one GPU share the
+ * array: calls from this process are serialised by a lock, and calls that
+ * overlap on one GPU from elsewhere (another process's graph replaying
+ * it) race. */
+int f2_sumcheck_prove_noalloc(const uint32_t *freq, uint64_t n, int on_device, uint64_t seed,
+                              uint64_t *msgs, uint64_t *chals, void *hip_stream);
+
 /* Non-interactive F2 (Sec. 3.2; GPU version Sec. 4.2; Table 3):
  * a streaming verifier keeping v field words, a proof of 2h words.  The n
  * values a (each below p; host, or device if on_device) fill a v x h grid,

@@ -53,6 +53,8 @@ _SIGS = [
     ("gkr_verify_closed_forms", C.c_int, [C.c_int]),
     ("f2_sumcheck_prove", C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_uint64, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
+    ("f2_sumcheck_prove_noalloc", C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_uint64, C.c_void_p,
+                                            C.c_void_p, C.c_void_p]),
     ("f2_sumcheck_verify", C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_uint64, C.c_void_p,
                                      C.c_uint64, C.POINTER(C.c_int), C.POINTER(RejectInfo),
                                      C.c_void_p]),
@@ -344,6 +346,19 @@ def f2_sumcheck_prove(freq, seed: int, stream=None):
     chals = np.zeros(max(l, 1), np.uint64)
     _check(lib().f2_sumcheck_prove(p, n, dev, seed, msgs.ctypes.data, chals.ctypes.data,
                                    _stream(dev, stream)))
+    return msgs, chals[:l]
+
+
+def f2_sumcheck_prove_noalloc(freq, seed: int, stream=None):
+    """f2_sumcheck_prove with its scratch in the library's static device
+    array (no allocation inside the call; n <= 2^22)."""
+    p, dev, keep = _ptr(freq, np.uint32)
+    n = freq.numel() if _is_torch(freq) else len(keep)
+    l = int(n).bit_length() - 1
+    msgs = np.zeros(1 + 3 * l, np.uint64)
+    chals = np.zeros(max(l, 1), np.uint64)
+    _check(lib().f2_sumcheck_prove_noalloc(p, n, dev, seed, msgs.ctypes.data, chals.ctypes.data,
+                                           _stream(dev, stream)))
     return msgs, chals[:l]
 
 

@@ -2668,36 +2668,34 @@ bool pow2(u64 n) { return n && !(n & (n - 1)); }
 
 }  // namespace
 
-extern "C" int f2_sumcheck_prove(const uint32_t *freq, uint64_t n, int on_device, uint64_t seed,
-                                 uint64_t *msgs, uint64_t *chals, void *hip_stream) {
-    if (!freq || !msgs) return fail(GKR_ERR_INVALID, "NULL argument");
-    if (!pow2(n) || n > (1ull << 32)) return fail(GKR_ERR_INVALID, "n must be a power of two <= 2^32");
-    hipStream_t st = pick_stream(hip_stream);
-    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+// Scratch of one F2 sum-check proof at base (sized when base is NULL):
+// the two folded tables, two rounds' partial rows, the transcript and
+// challenges on the device, the challenge stream's state and, for host
+// inputs, their staging copy.
+struct F2scLayout {
+    u64 *A0, *A1, *partials, *msgs, *chals;
+    ProofState *ps;
+    u32 *in;
+};
+static size_t f2sc_layout(char *base, u64 n, int on_device, F2scLayout &v) {
     const u32 l = log2ceil(n);
-    const u64 nm = 1 + 3ull * l;
-    std::lock_guard<std::mutex> lk(g_f2.mu);
-    struct {
-        u64 *A0, *A1, *partials, *msgs, *chals;
-        ProofState *ps;
-        u32 *in;
-    } v;
-    auto lay = [&](Arena &a) {
-        v.A0 = a.take<u64>(std::max<u64>(n / 2, 2));
-        v.A1 = a.take<u64>(std::max<u64>(n / 4, 2));
-        v.partials = a.take<u64>((u64)MAX_BLOCKS * 6);  // two rounds' rows
-        v.msgs = a.take<u64>(nm);
-        v.chals = a.take<u64>(std::max<u32>(l, 1));
-        v.ps = a.take<ProofState>(1);
-        v.in = a.take<u32>(on_device ? 1 : n);
-    };
-    Arena sz;
-    lay(sz);
-    int rc = f2_reserve(sz.used, nm + l + 1);
-    if (rc) return rc;
     Arena a;
-    a.base = (char *)g_f2.mem;
-    lay(a);
+    a.base = base;
+    v.A0 = a.take<u64>(std::max<u64>(n / 2, 2));
+    v.A1 = a.take<u64>(std::max<u64>(n / 4, 2));
+    v.partials = a.take<u64>((u64)MAX_BLOCKS * 6);  // two rounds' rows
+    v.msgs = a.take<u64>(1 + 3ull * l);
+    v.chals = a.take<u64>(std::max<u32>(l, 1));
+    v.ps = a.take<ProofState>(1);
+    v.in = a.take<u32>(on_device ? 1 : n);
+    return a.used;
+}
+
+// Enqueue one F2 sum-check proof on st into the scratch v lays out (host
+// inputs are first copied into v.in); the transcript stays on the device.
+static int f2sc_enqueue(const uint32_t *freq, u64 n, int on_device, u64 seed, const F2scLayout &v,
+                        hipStream_t st) {
+    const u32 l = log2ceil(n);
     const u32 *a32 = freq;
     if (!on_device) {
         HIP_TRY(hipMemcpyAsync(v.in, freq, n * 4, hipMemcpyHostToDevice, st));
@@ -2706,40 +2704,110 @@ extern "C" int f2_sumcheck_prove(const uint32_t *freq, uint64_t n, int on_device
     int nb = 0;
     if (l == 0) {
         LAUNCH(PC_MISC, 4, launch_f2sc_single(st, a32, v.msgs));
-    } else {
-        LAUNCH(PC_MISC, 0, launch_f2sc_init(st, v.ps, seed));
-        u64 *bufs[2] = {v.A0, v.A1};
-        const u64 *src = nullptr;
-        // round j's launch also finishes round j - 1 (its message and
-        // challenge), so the challenge is drawn one launch after its sums
-        int prev = 0;
-        // rounds from j0 on run as one tail once level j0 fits it
-        u32 j0 = l;
-        if (l >= 3) j0 = std::max<u32>(2, l > 12 ? l - 12 : 2);
-        for (u32 j = 0; j < j0; j++) {
-            const u64 pairs = n >> (j + 1);
-            u64 *dst = j == 0 ? nullptr : bufs[(j + 1) & 1];
-            const double bytes = j == 0 ? pairs * 8.0 : (j == 1 ? pairs * 32.0 : pairs * 48.0);
-            u64 *pmsg = j ? v.msgs + 1 + 3 * (j - 1) : nullptr, *pchal = j ? v.chals + j - 1 : nullptr;
-            LAUNCH(PC_F2SC, bytes,
-                   launch_f2sc_round(st, (int)j, pairs, a32, src, dst, v.ps, v.partials, prev, pmsg, pchal,
-                                     j == 1 ? v.msgs : nullptr, &nb));
-            prev = nb;
-            if (j > 0) src = dst;
-        }
-        if (j0 < l)
-            LAUNCH(PC_FINAL, (n >> (j0 - 1)) * 8.0,
-                   launch_f2sc_tail(st, (int)j0, (int)l, src, prev, v.partials, v.ps, v.msgs, v.chals));
-        else
-            LAUNCH(PC_FINAL, prev * 24.0,
-                   launch_f2sc_final(st, (int)(l - 1), prev, v.partials, v.ps, v.msgs + 1 + 3 * (l - 1),
-                                     v.chals + l - 1, l == 1 ? v.msgs : nullptr));
+        return GKR_OK;
     }
+    LAUNCH(PC_MISC, 0, launch_f2sc_init(st, v.ps, seed));
+    u64 *bufs[2] = {v.A0, v.A1};
+    const u64 *src = nullptr;
+    // round j's launch also finishes round j - 1 (its message and
+    // challenge), so the challenge is drawn one launch after its sums
+    int prev = 0;
+    // rounds from j0 on run as one tail once level j0 fits it
+    u32 j0 = l;
+    if (l >= 3) j0 = std::max<u32>(2, l > 12 ? l - 12 : 2);
+    for (u32 j = 0; j < j0; j++) {
+        const u64 pairs = n >> (j + 1);
+        u64 *dst = j == 0 ? nullptr : bufs[(j + 1) & 1];
+        const double bytes = j == 0 ? pairs * 8.0 : (j == 1 ? pairs * 32.0 : pairs * 48.0);
+        u64 *pmsg = j ? v.msgs + 1 + 3 * (j - 1) : nullptr, *pchal = j ? v.chals + j - 1 : nullptr;
+        LAUNCH(PC_F2SC, bytes,
+               launch_f2sc_round(st, (int)j, pairs, a32, src, dst, v.ps, v.partials, prev, pmsg, pchal,
+                                 j == 1 ? v.msgs : nullptr, &nb));
+        prev = nb;
+        if (j > 0) src = dst;
+    }
+    if (j0 < l)
+        LAUNCH(PC_FINAL, (n >> (j0 - 1)) * 8.0,
+               launch_f2sc_tail(st, (int)j0, (int)l, src, prev, v.partials, v.ps, v.msgs, v.chals));
+    else
+        LAUNCH(PC_FINAL, prev * 24.0,
+               launch_f2sc_final(st, (int)(l - 1), prev, v.partials, v.ps, v.msgs + 1 + 3 * (l - 1),
+                                 v.chals + l - 1, l == 1 ? v.msgs : nullptr));
+    return GKR_OK;
+}
+
+static int f2sc_check(const uint32_t *freq, u64 n, const uint64_t *msgs) {
+    if (!freq || !msgs) return fail(GKR_ERR_INVALID, "NULL argument");
+    if (!pow2(n) || n > (1ull << 32)) return fail(GKR_ERR_INVALID, "n must be a power of two <= 2^32");
+    return GKR_OK;
+}
+
+extern "C" int f2_sumcheck_prove(const uint32_t *freq, uint64_t n, int on_device, uint64_t seed,
+                                 uint64_t *msgs, uint64_t *chals, void *hip_stream) {
+    int rc = f2sc_check(freq, n, msgs);
+    if (rc) return rc;
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    const u32 l = log2ceil(n);
+    const u64 nm = 1 + 3ull * l;
+    std::lock_guard<std::mutex> lk(g_f2.mu);
+    F2scLayout v;
+    rc = f2_reserve(f2sc_layout(nullptr, n, on_device, v), nm + l + 1);
+    if (rc) return rc;
+    f2sc_layout((char *)g_f2.mem, n, on_device, v);
+    rc = f2sc_enqueue(freq, n, on_device, seed, v, st);
+    if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(g_f2.h, v.msgs, nm * 8, hipMemcpyDeviceToHost, st));
     if (chals && l) HIP_TRY(hipMemcpyAsync(g_f2.h + nm, v.chals, l * 8ull, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     memcpy(msgs, g_f2.h, nm * 8);
     if (chals && l) memcpy(chals, g_f2.h + nm, l * 8ull);
+    return GKR_OK;
+}
+
+// ------------------------------------- F2 sum-check without allocation
+
+// The scratch of f2_sumcheck_prove_noalloc: one static array per device,
+// held from the module's load on that device until the process ends.
+constexpr u64 F2SC_NOALLOC_MAX_N = 1ull << 22;
+constexpr size_t F2SC_NOALLOC_BYTES = 48ull << 20;
+static __device__ __align__(256) char scratch[F2SC_NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+struct NoallocScratch {
+    std::mutex mu;                            // one proof at a time in this process
+    void *ptr[NOALLOC_MAX_DEVICES] = {};      // device address of `scratch` on each device
+} g_noalloc;
+}  // namespace
+
+extern "C" int f2_sumcheck_prove_noalloc(const uint32_t *freq, uint64_t n, int on_device, uint64_t seed,
+                                         uint64_t *msgs, uint64_t *chals, void *hip_stream) {
+    int rc = f2sc_check(freq, n, msgs);
+    if (rc) return rc;
+    if (n > F2SC_NOALLOC_MAX_N) return fail(GKR_ERR_NOMEM, "n above 2^22, the static scratch's limit");
+    F2scLayout v;
+    if (f2sc_layout(nullptr, n, on_device, v) > F2SC_NOALLOC_BYTES)
+        return fail(GKR_ERR_NOMEM, "the proof's scratch exceeds the static scratch array");
+    hipStream_t st = pick_stream(hip_stream);
+    if (!st) return fail(GKR_ERR_DEVICE, "no stream");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(GKR_ERR_DEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_noalloc.mu);
+    if (!g_noalloc.ptr[dev]) {  // once per device, with that device current
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(GKR_ERR_DEVICE, "no device address for the static scratch");
+        g_noalloc.ptr[dev] = p;
+    }
+    f2sc_layout((char *)g_noalloc.ptr[dev], n, on_device, v);
+    rc = f2sc_enqueue(freq, n, on_device, seed, v, st);
+    if (rc) return rc;
+    const u32 l = log2ceil(n);
+    HIP_TRY(hipMemcpyAsync(msgs, v.msgs, (1 + 3ull * l) * 8, hipMemcpyDeviceToHost, st));
+    if (chals && l) HIP_TRY(hipMemcpyAsync(chals, v.chals, l * 8ull, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return GKR_OK;
 }
 
