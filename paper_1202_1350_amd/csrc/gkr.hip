@@ -144,11 +144,15 @@ struct Scope {
 
 }  // namespace
 
+static int prof_collect();
+
 extern "C" int gkr_profile_enable(int flag) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
+    // launches recorded so far are kept (or not) as the setting they ran under says
+    const int rc = prof_collect();
     g_prof.on = flag != 0;
     g_prof.keep = flag == 2;
-    return GKR_OK;
+    return rc;
 }
 
 // Timings of the recorded launches into the per-class totals (and the
