@@ -59,8 +59,15 @@ enum { GKR_ADD = 0, GKR_MUL = 1 };
  *   GKR_OMEGA_TABLES  the gates' weights are summed once per phase into
  *                     tables indexed by the bound wire, and every round folds
  *                     those tables (which halve each round), O(S + 2^{s'}).
- * Both give the same transcript bit for bit. */
-enum { GKR_OMEGA_GATES = 0, GKR_OMEGA_TABLES = 1 };
+ *                     The circuit's first layers whose tables all fit one
+ *                     workgroup's LDS (2^{s_i}, 2^{s_{i+1}} <= 1024 values,
+ *                     at most 32 gates on a wire) run whole in one launch,
+ *                     their tables kept in LDS from one layer to the next
+ *                     (not for GKR_MEM_LAYER circuits);
+ *   GKR_OMEGA_TABLES_STEPWISE  the same tables, every layer in launches of
+ *                     its own.
+ * All give the same transcript bit for bit. */
+enum { GKR_OMEGA_GATES = 0, GKR_OMEGA_TABLES = 1, GKR_OMEGA_TABLES_STEPWISE = 2 };
 
 /* Reasons for rejection (gkr_reject_info.check). */
 enum {

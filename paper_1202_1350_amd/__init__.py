@@ -16,7 +16,7 @@ P = (1 << 61) - 1
 
 GKR_OK, GKR_ERR_INVALID, GKR_ERR_RANGE, GKR_ERR_NOMEM, GKR_ERR_DEVICE, GKR_ERR_BUFSIZE = \
     0, -1, -2, -3, -4, -5
-GKR_OMEGA_GATES, GKR_OMEGA_TABLES = 0, 1
+GKR_OMEGA_GATES, GKR_OMEGA_TABLES, GKR_OMEGA_TABLES_STEPWISE = 0, 1, 2
 GKR_BATCH_GRAPH = 1
 GKR_MEM_RESIDENT, GKR_MEM_LAYER, GKR_MEM_MESSAGE, GKR_MEM_AUTO = 0, 1, 2, 3
 CHECKS = {1: "malformed", 2: "round", 3: "wiring", 4: "line", 5: "input"}
@@ -173,7 +173,8 @@ class Circuit:
         return c
 
     def set_algorithm(self, omega_algo: int):
-        """GKR_OMEGA_TABLES (default) or GKR_OMEGA_GATES; same transcript."""
+        """GKR_OMEGA_TABLES (default), GKR_OMEGA_TABLES_STEPWISE or GKR_OMEGA_GATES;
+        same transcript."""
         _check(lib().gkr_circuit_set_algorithm(self.handle, int(omega_algo)))
 
     def memory_need(self, mode: int):

@@ -60,14 +60,14 @@ namespace {
 // then the verifier's and the F2 sum-check's kernels.
 enum ProfClass {
     PC_STEP = 0,  // + StepKind
-    PC_WIRING = 19, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_SERVE, PC_COUNT
+    PC_WIRING = 20, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_SERVE, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {
     "step_eval", "step_start", "step_eq", "step_p", "step_w", "step_fold", "step_lt",
     "step_line", "step_sge", "step_end", "step_wagg", "step_wt0", "step_wt", "step_wtail",
-    "step_ptail", "step_load", "step_wa0", "step_finish", "step_wsmall", "wiring", "mle", "eq_tables", "f2sc_round",
+    "step_ptail", "step_load", "step_wa0", "step_finish", "step_wsmall", "step_top", "wiring", "mle", "eq_tables", "f2sc_round",
     "f2sc_final", "misc", "batch_step", "nif2", "serve_step"};
-static_assert(ST_WSMALL + 1 == PC_WIRING, "one profiling class per step kind");
+static_assert(ST_TOP + 1 == PC_WIRING, "one profiling class per step kind");
 
 struct ProfRec {
     int cls;
@@ -346,6 +346,7 @@ struct Workspace {
     u64 *rowpool;        // every reducing step's rows, each at its own offset
     u64 *frec;           // records of p-phase finishes (C, z_j, z_{j+1})
     FinItem *d_items;    // the finish step's items
+    TopLayer *d_top;     // descriptors of the layers ST_TOP runs
     u64 *msgs, *chals, *rngst, *zbuf, *state;
     u32 *flag;
     // omega phases over tables
@@ -680,7 +681,7 @@ extern "C" void gkr_circuit_destroy(gkr_circuit *c) {
 
 extern "C" int gkr_circuit_set_algorithm(gkr_circuit *c, int omega_algo) {
     if (!c) return fail(GKR_ERR_INVALID, "circuit is NULL");
-    if (omega_algo != GKR_OMEGA_GATES && omega_algo != GKR_OMEGA_TABLES)
+    if (omega_algo != GKR_OMEGA_GATES && omega_algo != GKR_OMEGA_TABLES && omega_algo != GKR_OMEGA_TABLES_STEPWISE)
         return fail(GKR_ERR_INVALID, "unknown omega-phase algorithm");
     bool changed = false;
     {
@@ -780,7 +781,7 @@ static size_t gate_block_max(const gkr_circuit *c) {
     size_t m = 0;
     for (u32 i = 0; i + 1 < c->L; i++) {
         m = std::max(m, c->soa_off[i + 1] - c->soa_off[i]);
-        if (c->omega_algo == GKR_OMEGA_TABLES) m = std::max(m, c->g_off[i + 1] - c->g_off[i]);
+        if (c->omega_algo != GKR_OMEGA_GATES) m = std::max(m, c->g_off[i + 1] - c->g_off[i]);
     }
     return m;
 }
@@ -826,6 +827,7 @@ static void carve(const gkr_circuit *c, Arena &a, Arena &h, Workspace &w, const 
     w.rowpool = a.take<u64>(std::max<u64>(ps.rows, 1));
     w.frec = a.take<u64>(std::max<u64>(ps.recs, 1));
     w.d_items = a.take<FinItem>(std::max<u64>(ps.items, 1));
+    w.d_top = a.take<TopLayer>(c->L);
     w.msgs = a.take<u64>(c->n_msgs);
     w.chals = a.take<u64>(std::max<u64>(c->n_chals, 1));
     w.rngst = a.take<u64>(c->n_chals + 1);
@@ -835,7 +837,7 @@ static void carve(const gkr_circuit *c, Arena &a, Arena &h, Workspace &w, const 
     w.instage = vt.take<u64>(c->S[c->L - 1]);
     w.d_steps = a.take<StepDesc>(nsteps);
     w.d_jobs = a.take<JobEntry>(2 * nsteps);
-    if (c->omega_algo == GKR_OMEGA_TABLES) {
+    if (c->omega_algo != GKR_OMEGA_GATES) {
         const u64 N = 1ull << c->spmax;
         w.tA0 = rt.take<u64>(N);
         w.tC0 = rt.take<u64>(N);
@@ -850,6 +852,20 @@ static void carve(const gkr_circuit *c, Arena &a, Arena &h, Workspace &w, const 
 
 
 // Builds a proof's step program.  With `ws` NULL it only counts the steps.
+// Leading layers ST_TOP runs: layer i < K with 2^s_i and 2^s_{i+1} at most
+// TAIL_LIM entries, s_{i+1} >= 1 and one chunk of gates on every wire of
+// both omega phases (the tables algorithm; not with the per-layer copies of
+// GKR_MEM_LAYER, whose slots hold three value tables).
+static u32 top_layers(const gkr_circuit *c) {
+    if (c->omega_algo != GKR_OMEGA_TABLES || c->mem_mode == GKR_MEM_LAYER) return 0;
+    const u32 d = c->L - 1;
+    u32 K = 0;
+    while (K < d && (1ull << c->s[K]) <= (u64)TAIL_LIM && c->s[K + 1] >= 1 &&
+           (1ull << c->s[K + 1]) <= (u64)TAIL_LIM && c->grp[0][K].single && c->grp[1][K].single)
+        K++;
+    return K;
+}
+
 struct Planner {
     const gkr_circuit *c;
     Workspace *w;
@@ -860,6 +876,7 @@ struct Planner {
     std::vector<double> mods;   // algorithmic 64 x 64-bit modular products of each step
     std::vector<u64> units;
     std::vector<FinItem> items;
+    std::vector<TopLayer> top;  // the layers ST_TOP runs
     u64 rows_used = 0, recs_used = 0;
     ProofPtrs pp{};
     // step indices: evaluation of layer i, first and last step of its sum-check
@@ -997,7 +1014,51 @@ struct Planner {
         memset(&layer_end, 0, sizeof layer_end);
         layer_end.kind = FIN_NONE;
         layer_end.draw = -1;
-        for (u32 i = 0; i < d; i++) {
+        // The first K layers run whole in one workgroup (ST_TOP); the step
+        // after it draws the last one's tau.
+        const u32 K = top_layers(c);
+        if (K) {
+            top.clear();
+            double nbytes = 0, nmods = 0;
+            for (u32 i = 0; i < K; i++) {
+                const u32 s = c->s[i], sp = c->s[i + 1];
+                const u64 S = c->S[i], N = 1ull << sp;
+                TopLayer t;
+                memset(&t, 0, sizeof t);
+                t.s = s;
+                t.sp = sp;
+                t.kind = (u32)c->kind[i];
+                t.co = (u32)c->co[i];
+                t.msg = w ? w->msgs + c->mo[i] : nullptr;
+                t.Vn = V(i + 1);
+                for (u32 ph = 1; ph <= 2; ph++) {
+                    const gkr_circuit::Group &g = c->grp[ph - 1][i];
+                    t.rowptr[ph - 1] = g.rowptr;
+                    t.perm[ph - 1] = g.perm;
+                    t.oths[ph - 1] = g.oths;
+                    t.types[ph - 1] = g.types;
+                }
+                top.push_back(t);
+                sc_first[i] = sc_last[i] = (int)out.size();
+                // V_{i+1} 8 per entry; per phase: row pointers 4 per wire, sorted
+                // index and other wire 8 per gate (+1 type)
+                nbytes += 8.0 * N + 2 * (4.0 * (N + 1) + S * (8.0 + (c->kind[i] == KIND_MIXED)));
+                // p-phase ~4 per entry of V_i; per gate 4 (phase 1) and 5 (phase 2);
+                // per table entry 8 per phase; the line one product per point and entry
+                nmods += 4.0 * (1ull << s) + 9.0 * S + 16.0 * N + (sp >= 2 ? 1.5 * (sp - 1) * N : 0.0);
+            }
+            StepDesc &st = add(ST_TOP, 1, nbytes);
+            mods.back() = nmods;
+            st.u.top = TopArgs{K, w ? w->d_top : nullptr, V(0)};
+            const u32 i = K - 1, s = c->s[i], sp = c->s[i + 1], co = (u32)c->co[i];
+            layer_end.kind = FIN_LINE;
+            layer_end.draw = (i32)(co + s + 2 * sp);
+            layer_end.sp = sp;
+            layer_end.T = 0;  // h(2..sp) written by ST_TOP
+            layer_end.bstar = w ? w->chals + co + s : nullptr;
+            layer_end.cstar = w ? w->chals + co + s + sp : nullptr;
+        }
+        for (u32 i = K; i < d; i++) {
             if (i > 0) sc_last[i - 1] = (int)out.size() - 1;
             sc_first[i] = (int)out.size();
             const u32 s = c->s[i], sp = c->s[i + 1], S = c->S[i];
@@ -1108,7 +1169,7 @@ struct Planner {
             // A small layer whose wires each carry one chunk of gates runs each
             // omega phase in one workgroup (ST_WSMALL), which also forms the
             // eq table of the phase's point.
-            const bool wsmall = c->omega_algo == GKR_OMEGA_TABLES && sp >= 1 &&
+            const bool wsmall = c->omega_algo != GKR_OMEGA_GATES && sp >= 1 &&
                                 (1ull << sp) <= (u64)TAIL_LIM && c->grp[0][i].single && c->grp[1][i].single;
             // ---- eq tables of a* (the p-phase tail recorded every challenge)
             if (!wsmall) {
@@ -1132,7 +1193,7 @@ struct Planner {
             u32 Ll = 0, M = 0, H = 0;  // shape of the line step (a9)
             if (sp >= 2) line_shape(sp, &Ll, &M, &H);
             const u64 ntab = sp >= 2 ? (u64)(sp - 1) * ((1ull << Ll) + (1ull << M) + (1ull << H)) : 1;
-            if (c->omega_algo == GKR_OMEGA_TABLES) {
+            if (c->omega_algo != GKR_OMEGA_GATES) {
                 // ---- omega-phases over tables (a6, a7, a8): round 0 (and
                 // round 1's coefficients) with the level-0 tables, then grid
                 // steps of two rounds while the tables are large, then the
@@ -1639,7 +1700,7 @@ static void plan_transfers(const gkr_circuit *c, Workspace &w, const Planner &pl
         x.push_back({pl.sc_last[j - 3], pl.sc_first[j - 1], w.Vslot[j % 3], w.V[j], vbytes(j),
                      hipMemcpyHostToDevice});
     if (w.gslot) {
-        const bool tables = c->omega_algo == GKR_OMEGA_TABLES;
+        const bool tables = c->omega_algo != GKR_OMEGA_GATES;
         for (int i = d - 1; i >= 0; i--)  // evaluation of layer i: its struct of arrays
             x.push_back({i + 2 <= d - 1 ? pl.eval_at[i + 2] : -1, pl.eval_at[i], w.Gslot[i % 2],
                          (const char *)c->soa + c->soa_off[i], c->soa_off[i + 1] - c->soa_off[i],
@@ -1714,6 +1775,10 @@ static int plan_into(gkr_circuit *c, Workspace &ws) {
     HIP_TRY(hipMemcpy(ws.d_jobs, jobs.data(), jobs.size() * sizeof(JobEntry), hipMemcpyHostToDevice));
     if (!plan.items.empty())
         HIP_TRY(hipMemcpy(ws.d_items, plan.items.data(), plan.items.size() * sizeof(FinItem), hipMemcpyHostToDevice));
+    if (!plan.top.empty()) {
+        if (plan.top.size() >= c->L) return fail(GKR_ERR_INVALID, "top layers outgrew their descriptors");
+        HIP_TRY(hipMemcpy(ws.d_top, plan.top.data(), plan.top.size() * sizeof(TopLayer), hipMemcpyHostToDevice));
+    }
     ws.epoch = epoch;
     return GKR_OK;
 }
@@ -1726,7 +1791,7 @@ static int refresh_plan(gkr_circuit *c, Workspace &ws) {
 // Device and pinned host bytes of a workspace of c in the given mode
 // (sized without allocating).
 static PlanSizes plan_sizes(gkr_circuit *c) {
-    if (c->omega_algo == GKR_OMEGA_TABLES) size_groups(c);
+    if (c->omega_algo != GKR_OMEGA_GATES) size_groups(c);
     Planner count{c, nullptr};
     count.build();
     return count.sizes();
@@ -1745,7 +1810,7 @@ static void size_workspace(gkr_circuit *c, int mode, const PlanSizes &ps, size_t
 // one entry of a batch or server), its tables placed as `mode` says.
 static int make_workspace(gkr_circuit *c, int mode, Workspace **out) {
     *out = nullptr;
-    if (c->omega_algo == GKR_OMEGA_TABLES) {
+    if (c->omega_algo != GKR_OMEGA_GATES) {
         int rc = ensure_groups(c);
         if (rc) return rc;
     }
@@ -1787,9 +1852,9 @@ static int make_workspace(gkr_circuit *c, int mode, Workspace **out) {
 // Device bytes of c's gate arrays (struct of arrays, and the groups the
 // tables algorithm reads).
 static size_t gate_bytes(gkr_circuit *c) {
-    if (c->omega_algo == GKR_OMEGA_TABLES) size_groups(c);
+    if (c->omega_algo != GKR_OMEGA_GATES) size_groups(c);
     const u32 d = c->L - 1;
-    return c->soa_off[d] + (c->omega_algo == GKR_OMEGA_TABLES ? c->g_off[d] : 0);
+    return c->soa_off[d] + (c->omega_algo != GKR_OMEGA_GATES ? c->g_off[d] : 0);
 }
 
 // Device bytes a workspace of c takes in `mode` (sized without allocating;

@@ -1009,16 +1009,17 @@ __device__ __forceinline__ u64 tail_state(const ProofPtrs &pp, u32 c0, u32 drew,
 }
 
 // The rounds of an omega tail over tables A, C, F in LDS (level 0 of each,
-// n entries, at the start of its area): messages to msgp, challenges c0,
-// c0 + 1, ... recorded with the RNG states after them; F's last entry is
-// v1 (last = 1) or v2.  Round k's message is, at t = 0, 1, 2, the sum over
-// its pairs of A_t F_t + C_t with X_t the line through the pair.
-__device__ __forceinline__ void wtail_rounds(u64 *tab, u32 n, bool hc, u64 st, u64 *msgp, u32 c0, u32 last,
-                                             u64 *vout, const ProofPtrs &pp) {
+// n entries, at the start of its area of TAIL_TAB entries): messages to
+// msgp, challenges c0, c0 + 1, ... recorded with the RNG states after them
+// (and into rec[k], in LDS, when rec is not NULL); F's last entry is v1
+// (last = 1) or v2.  Round k's message is, at t = 0, 1, 2, the sum over its
+// pairs of A_t F_t + C_t with X_t the line through the pair.  Returns the
+// RNG state after the last round.
+__device__ __forceinline__ u64 wtail_rounds(u64 *A, u64 *Ct, u64 *F, u32 n, bool hc, u64 st, u64 *msgp, u32 c0,
+                                            u32 last, u64 *vout, const ProofPtrs &pp, u64 *rec = nullptr) {
     const u32 tid = threadIdx.x, lane = tid & 63;
     const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
     const u32 L = 31 - (u32)__builtin_clz(n);
-    u64 *A = tab, *Ct = tab + TAIL_TAB, *F = tab + 2 * TAIL_TAB;
     u64 (*mp)[TAIL_SLOTS] = tail_parts();
     for (u32 k = 0, nk = n; nk > 1; nk >>= 1, k++) {
         const u32 half = nk >> 1, qb = n - nk;
@@ -1060,11 +1061,12 @@ __device__ __forceinline__ void wtail_rounds(u64 *tab, u32 n, bool hc, u64 st, u
                 if (lane == 63) mp[w][TAIL_CHUNKS + k] = v;
             }
             __syncthreads();  // message k's sums are complete
-            if (w < 3 && (w != 1 || hc) && on) tab[w * TAIL_TAB + n + q] = fold1(own.x, own.y, r);
+            if (w < 3 && (w != 1 || hc) && on) (w == 0 ? A : (w == 1 ? Ct : F))[n + q] = fold1(own.x, own.y, r);
         }
         if (tid == 0) {
             pp.chals[c0 + k] = r;
             pp.rngst[c0 + k + 1] = st;
+            if (rec) rec[k] = r;
         }
         __syncthreads();  // level k + 1 is complete
     }
@@ -1077,6 +1079,7 @@ __device__ __forceinline__ void wtail_rounds(u64 *tab, u32 n, bool hc, u64 st, u
         *vout = v;
         if (last == 1) pp.state[1] = v;
     }
+    return st;
 }
 
 __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0) {
@@ -1091,7 +1094,7 @@ __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &
     }
     const u64 st = tail_state(pp, a.c0, drew, st0);
     __syncthreads();
-    wtail_rounds(tab, n, hc, st, a.msg, a.c0, a.last, a.vout, pp);
+    wtail_rounds(tab, tab + TAIL_TAB, tab + 2 * TAIL_TAB, n, hc, st, a.msg, a.c0, a.last, a.vout, pp);
 }
 
 // A whole omega phase of a small layer in one workgroup: the eq table of
@@ -1126,49 +1129,32 @@ __device__ __forceinline__ void step_wsmall(const WsmallArgs &a, const ProofPtrs
     }
     const u64 st = tail_state(pp, a.c0, 0, 0);
     __syncthreads();
-    wtail_rounds(tab, n, hc, st, a.msg, a.c0, a.last, a.vout, pp);
+    wtail_rounds(tab, tab + TAIL_TAB, tab + 2 * TAIL_TAB, n, hc, st, a.msg, a.c0, a.last, a.vout, pp);
     (void)c;
 }
 
-// Remaining p-phase rounds j0..s-1.  The prologue drew the pending
-// challenge(s) up to r_{j0-1} and its finish of round j0-1 computed the
-// beta prefix C.  B is the table of sums of the eq weights of the
-// a-coordinates not yet reached (beta over z's suffix); pair m of V goes
-// with B[m].  Round j's message is G(t) = C_j eq_t(z_j) S_t with
+// p-phase rounds in one workgroup.  B is the table of sums of the eq
+// weights of the a-coordinates not yet reached (beta over z's suffix); pair
+// m of V goes with B[m].  Round j's message is G(t) = C_j eq_t(z_j) S_t with
 // S_t = sum_m B[m] V_t over the pairs and eq_t(z) the line through
 // (0, 1 - z), (1, z): 1 - z, z, 3z - 1 at t = 0, 1, 2; C_{j+1} =
-// C_j eq(z_j, r_j).  V is a tree as the omega tables; B's level k sits
-// at the indexes q of the pairs it goes with, its entry q' of level k+1
-// being the sum of entries 2q' - n and 2q' - n + 1.
-__device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0,
-                                           u32 have_c, u64 C0) {
-    __shared__ u64 s_c;
+// C_j eq(z_j, r_j).  V is a tree as the omega tables; B's level k sits at
+// the indexes q of the pairs it goes with, its entry q' of level k+1 being
+// the sum of entries 2q' - n and 2q' - n + 1.
+//
+// ptail_rounds: the rounds over V (level 0: n = 2^L entries) and B (the
+// weights of its pairs, level 0: n / 2 entries), both in LDS as trees of
+// TAIL_TAB entries.  Lane l holds z_l of the tail's rounds in zr; C is the
+// beta prefix before round 0.  Messages go to msg, challenges c0, c0 + 1, ...
+// are recorded with the RNG states after them (and into rec[k], in LDS, when
+// rec is not NULL).  Returns beta over every round; st becomes the state
+// after the last challenge.
+__device__ __forceinline__ u64 ptail_rounds(u64 *V, u64 *B, u32 L, u64 zr, u64 C, u64 &st, u32 c0, u64 *msg,
+                                            const ProofPtrs &pp, u64 *rec = nullptr) {
     __shared__ u64 s_cz[2][TAIL_LOG];  // C_j and z_j of each round
-    u64 *tab = tail_lds();
-    u64 *V = tab, *B = tab + TAIL_TAB;
     const u32 tid = threadIdx.x, lane = tid & 63;
     const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
-    const u32 L = a.s - a.j0, n = 1u << L;  // entries of V^(j0), at most TAIL_LIM
-    for (u32 e = tid; e < n; e += SBLOCK) V[e] = tail_entry(a.V, e, a.pend, c);
-    const u64 zr = lane < L ? pp.zbuf[a.j0 + lane] : 0;  // z_{j0 + l} in lane l
-    if (a.B) {
-        for (u32 m = tid; m < n / 2; m += SBLOCK) {  // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1]
-            const u64x2 pb = ld2(a.B, 2 * m);
-            B[m] = add(pb.x, pb.y);
-        }
-    } else {
-        // j0 = 0: B_0[m] = prod_{k=1}^{s-1} eq(bit k-1 of m, z_k), the weights of
-        // z's suffix (the p-phase's first round pairs V entries 2m, 2m+1)
-        for (u32 m = tid; m < n / 2; m += SBLOCK) {
-            u64 b = 1;
-            for (u32 k = 1; k < a.s; k++) b = mul(b, fp::eqbit((m >> (k - 1)) & 1, lane_value(zr, k)));
-            B[m] = b;
-        }
-    }
-    if (!have_c && tid == 0) s_c = pp.state[0];
-    u64 st = tail_state(pp, a.c0, drew, st0);
-    __syncthreads();
-    u64 C = uniform(have_c ? C0 : s_c);
+    const u32 n = 1u << L;
     u64 (*mp)[TAIL_SLOTS] = tail_parts();
     for (u32 k = 0, nk = n; nk > 1; nk >>= 1, k++) {
         const u32 half = nk >> 1, qb = n - nk;
@@ -1218,17 +1204,228 @@ __device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &
         }
         C = mul(C, fp::eq(z, r));  // the beta prefix of round k + 1
         if (tid == 0) {
-            pp.chals[a.c0 + k] = r;
-            pp.rngst[a.c0 + k + 1] = st;
+            pp.chals[c0 + k] = r;
+            pp.rngst[c0 + k + 1] = st;
+            if (rec) rec[k] = r;
         }
         __syncthreads();  // level k + 1 is complete
     }
-    if (tid == 0) pp.state[0] = C;  // beta(z, a*)
     if (tid < 3 * L) {
         const u32 k = tid / 3, t = tid - 3 * k;
         const u64 z = s_cz[1][k];
         const u64 e = t == 0 ? sub(1, z) : (t == 1 ? z : sub(add(add(z, z), z), 1));
-        a.msg[3 * k + t] = mul(mul(s_cz[0][k], e), tail_sum(n, k, t));
+        msg[3 * k + t] = mul(mul(s_cz[0][k], e), tail_sum(n, k, t));
+    }
+    return C;
+}
+
+// B_0[m] = prod_{k=1}^{s-1} eq(bit k-1 of m, z_k) for m < 2^{s-1}, the
+// weights of z's suffix (the p-phase's first round pairs V entries 2m,
+// 2m+1); lane l holds z_l in zr.
+// The s - 1 factors are multiplied as a balanced tree (a chain of at most
+// four products instead of s - 1); tree levels no factor reaches are
+// skipped.
+__device__ __forceinline__ void suffix_weights(u64 *B, u32 s, u64 zr) {
+    const u32 nf = s ? s - 1 : 0;
+    for (u32 m = threadIdx.x; m < (1u << s) / 2; m += SBLOCK) {
+        u64 f[TAIL_LOG];
+#pragma unroll
+        for (u32 k = 0; k < TAIL_LOG; k++) f[k] = k < nf ? fp::eqbit((m >> k) & 1, lane_value(zr, k + 1)) : 1;
+#pragma unroll
+        for (u32 w = 1; w < TAIL_LOG; w *= 2) {
+            if (w < nf) {  // (uniform)
+#pragma unroll
+                for (u32 k = 0; k + w < TAIL_LOG; k += 2 * w) f[k] = mul(f[k], f[k + w]);
+            }
+        }
+        B[m] = f[0];
+    }
+}
+
+// Remaining p-phase rounds j0..s-1 (ST_PTAIL).  The prologue drew the
+// pending challenge(s) up to r_{j0-1} and its finish of round j0-1 computed
+// the beta prefix C.
+__device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0,
+                                           u32 have_c, u64 C0) {
+    __shared__ u64 s_c;
+    u64 *tab = tail_lds();
+    u64 *V = tab, *B = tab + TAIL_TAB;
+    const u32 tid = threadIdx.x, lane = tid & 63;
+    const u32 L = a.s - a.j0, n = 1u << L;  // entries of V^(j0), at most TAIL_LIM
+    for (u32 e = tid; e < n; e += SBLOCK) V[e] = tail_entry(a.V, e, a.pend, c);
+    const u64 zr = lane < L ? pp.zbuf[a.j0 + lane] : 0;  // z_{j0 + l} in lane l
+    if (a.B) {
+        for (u32 m = tid; m < n / 2; m += SBLOCK) {  // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1]
+            const u64x2 pb = ld2(a.B, 2 * m);
+            B[m] = add(pb.x, pb.y);
+        }
+    } else {
+        suffix_weights(B, a.s, zr);  // j0 = 0
+    }
+    if (!have_c && tid == 0) s_c = pp.state[0];
+    u64 st = tail_state(pp, a.c0, drew, st0);
+    __syncthreads();
+    const u64 C = ptail_rounds(V, B, L, zr, uniform(have_c ? C0 : s_c), st, a.c0, a.msg, pp);
+    if (tid == 0) pp.state[0] = C;  // beta(z, a*)
+}
+
+// ---------------------------------------------------------------- top layers
+//
+// ST_TOP runs the sum-check of the circuit's first layers in one
+// workgroup, one layer after the other, as the tails run a phase: the
+// p-phase over V_i, the two omega phases over A, C and F = V_{i+1}, and the
+// line through b* and c*.  The tables stay in LDS between layers: the
+// omega phases leave V_{i+1} as level 0 of F, which is the next layer's
+// V_i, so global memory is read only for each V_{i+1} and the wiring and
+// written only for messages, challenges and RNG states.  LDS areas (TAIL_TAB
+// entries each): X holds B (p-phase), A (omega phases) and the line's point
+// tables; Y holds C and, in its last 128 entries, the eq halves of a* and
+// b* while the level-0 tables are formed; Z holds V_i, then F.
+
+// lo[x] = chi_x(pt[0..L)) for x < 2^L and hi[x] = chi_x(pt[L..n)) for
+// x < 2^(n-L), L = n / 2, so chi_x(pt) = lo[x mod 2^L] hi[x >> L].
+__device__ __forceinline__ void eq_halves_lds(const u64 *pt, u32 n, u64 *lo, u64 *hi) {
+    const u32 L = n / 2, nlo = 1u << L, nhi = 1u << (n - L);
+    for (u32 x = threadIdx.x; x < nlo + nhi; x += SBLOCK) {
+        if (x < nlo)
+            lo[x] = chi_bits(x, pt, L);
+        else
+            hi[x - nlo] = chi_bits(x - nlo, pt + L, n - L);
+    }
+}
+
+// Level 0 of omega phase ph of a top layer: wire x's gates (one chunk)
+// summed as wire_sums sums them, with chi_g(a*) and (phase 2)
+// chi_in1(b*) from the eq halves in LDS and phase 1's operand V_{i+1}[in2]
+// from F in LDS.
+__device__ __forceinline__ void top_level0(const TopLayer &Ld, u32 ph, u64 beta, u64 v1, const u64 *ea, u32 La,
+                                           const u64 *eb, u32 Lb, const u64 *F, u64 *A, u64 *C, bool hc) {
+    const u32 N = 1u << Ld.sp, q = ph - 1;
+    const u32 *rowptr = Ld.rowptr[q], *perm = Ld.perm[q], *oths = Ld.oths[q];
+    const u8 *types = Ld.types[q];
+    const u32 amask = (1u << La) - 1, bmask = (1u << Lb) - 1;
+    const u64 *ea_hi = ea + 32, *eb_hi = eb + 32;
+    for (u32 x = threadIdx.x; x < N; x += SBLOCK) {
+        u64 sA = 0, sC = 0;
+        const u32 p0 = rowptr[x], p1 = rowptr[x + 1];
+        for (u32 p = p0; p < p1; p++) {
+            const u32 g = perm[p], o = oths[p];
+            const bool ismul = Ld.kind == 1 || (Ld.kind == 2 && types[p]);  // MUL, or a MUL gate of a mixed layer
+            u64 w = mul(beta, mul(ea[g & amask], ea_hi[g >> La]));
+            if (ph == 1) {
+                const u64 wy = mul(w, F[o]);
+                sA = add(sA, ismul ? wy : w);
+                sC = add(sC, ismul ? 0 : wy);
+            } else {
+                w = mul(w, mul(eb[o & bmask], eb_hi[o >> Lb]));
+                sA = add(sA, ismul ? 0 : w);
+                sC = add(sC, ismul ? w : 0);
+            }
+        }
+        u64 a, c;
+        level0(ph, v1, sA, sC, a, c);
+        A[x] = a;
+        if (hc) C[x] = c;
+    }
+}
+
+// The line of a top layer: h(t) = ~V_{i+1}(l(t)) for t = 2..sp, l(t) =
+// b* + t (c* - b*), over level 0 of F.  The eq halves of point t go to
+// tb + 64 (t - 2) (lo, 32 entries) and 32 past it (hi); wave w sums points
+// t - 2 = w, w + NWAVES, ..., each lane adding hi lo V over every 64th
+// entry in 128 bits, and lane 63 writes h(t) to out[t - 2].
+__device__ __forceinline__ void top_line(u32 sp, const u64 *bst, const u64 *cst, const u64 *F, u64 *tb, u64 *out) {
+    const u32 T = sp - 1, Ll = sp / 2, Lh = sp - Ll;
+    for (u32 e = threadIdx.x; e < T * 64; e += SBLOCK) {
+        const u32 tp = e >> 6, j = e & 63;
+        const u64 t = tp + 2;
+        const bool lo = j < 32;
+        const u32 x = lo ? j : j - 32, nb = lo ? Ll : Lh, base = lo ? 0 : Ll;
+        if (x < (1u << nb)) {
+            u64 v = 1;
+            for (u32 k = 0; k < nb; k++) {
+                const u64 b = bst[base + k], c = cst[base + k];
+                v = mul(v, fp::eqbit((x >> k) & 1, add(b, mul(t, sub(c, b)))));
+            }
+            tb[e] = v;
+        }
+    }
+    __syncthreads();
+    const u32 lane = threadIdx.x & 63;
+    const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
+    const u32 N = 1u << sp, m = (1u << Ll) - 1;
+    for (u32 tp = w; tp < T; tp += NWAVES) {
+        const u64 *lo = tb + 64 * tp, *hi = lo + 32;
+        u128 acc = 0;  // at most 16 products below 2^122
+        for (u32 x = lane; x < N; x += 64) acc += fp::wide(hi[x >> Ll], mul(lo[x & m], F[x]));
+        const u64 v = wave_sum63(fp::red128(acc));
+        if (lane == 63) out[tp] = v;
+    }
+}
+
+__device__ __forceinline__ void step_top(const TopArgs &a, const ProofPtrs &pp) {
+    __shared__ u64 s_r[3 * TAIL_LOG];  // the layer's challenges: a*, then b*, then c*
+    __shared__ u64 s_st;
+    u64 *tab = tail_lds();
+    u64 *X = tab, *Y = tab + TAIL_TAB, *Z = tab + 2 * TAIL_TAB;
+    u64 *eqa = Y + TAIL_TAB - 128, *eqb = eqa + 64;  // eq halves: lo in [0, 32), hi in [32, 64)
+    const u32 tid = threadIdx.x, lane = tid & 63;
+    // V_0, z_0 and the RNG state ST_START left
+    {
+        const TopLayer &L0 = a.L[0];
+        for (u32 e = tid; e < (1u << L0.s); e += SBLOCK) Z[e] = a.V0[e];
+        if (tid == 0) s_st = pp.rngst[L0.co];
+    }
+    u64 zr = lane < a.L[0].s ? pp.zbuf[lane] : 0;  // z_l of the layer in lane l
+    __syncthreads();
+    u64 st = uniform(s_st);
+    for (u32 i = 0; i < a.nl; i++) {
+        const TopLayer &Ld = a.L[i];
+        const u32 s = Ld.s, sp = Ld.sp, n = s + 2 * sp, N = 1u << sp;
+        const bool hc = Ld.kind != 1;  // a layer with ADD gates has a C table
+        // p-phase over V_i (level 0 of Z), B in X; beta starts at 1
+        u64 beta = 1;
+        if (s > 0) {
+            suffix_weights(X, s, zr);
+            __syncthreads();
+            beta = ptail_rounds(Z, X, s, zr, 1, st, Ld.co, Ld.msg, pp, s_r);
+        }
+        __syncthreads();  // the p-phase's reads of Z and of its partial sums are done
+        // phase 1: F = V_{i+1} into Z, A and C from the gates on in1
+        for (u32 e = tid; e < N; e += SBLOCK) Z[e] = Ld.Vn[e];
+        eq_halves_lds(s_r, s, eqa, eqa + 32);
+        __syncthreads();
+        top_level0(Ld, 1, beta, 0, eqa, s / 2, eqb, 0, Z, X, Y, hc);
+        __syncthreads();
+        st = wtail_rounds(X, Y, Z, N, hc, st, Ld.msg + 3 * s, Ld.co + s, 1, Ld.msg + 3 * n, pp, s_r + s);
+        const u64 v1 = Z[2 * N - 2];  // the root of F
+        __syncthreads();  // phase 1's partial sums are read; its tree in Y is no longer needed
+        // phase 2: the gates on in2, with v1
+        eq_halves_lds(s_r, s, eqa, eqa + 32);
+        eq_halves_lds(s_r + s, sp, eqb, eqb + 32);
+        __syncthreads();
+        top_level0(Ld, 2, beta, v1, eqa, s / 2, eqb, sp / 2, Z, X, Y, hc);
+        __syncthreads();
+        st = wtail_rounds(X, Y, Z, N, hc, st, Ld.msg + 3 * (s + sp), Ld.co + s + sp, 2, Ld.msg + 3 * n + 1, pp,
+                          s_r + s + sp);
+        __syncthreads();
+        // the line (level 0 of Z is still V_{i+1}); its point tables in X
+        if (sp >= 2) {
+            top_line(sp, s_r + s, s_r + s + sp, Z, X, Ld.msg + 3 * n + 2);
+            __syncthreads();
+        }
+        // tau and z_{i+1} = l(tau) for the next layer of this step (the
+        // step after it draws the last layer's tau)
+        if (i + 1 < a.nl) {
+            const u64 tau = fp::sm_field(st);
+            if (tid == 0) {
+                pp.chals[Ld.co + n] = tau;
+                pp.rngst[Ld.co + n + 1] = st;
+            }
+            const u64 b = lane < sp ? s_r[s + lane] : 0, c = lane < sp ? s_r[s + sp + lane] : 0;
+            zr = add(b, mul(tau, sub(c, b)));
+            __syncthreads();  // s_r is read before the next layer records into it
+        }
     }
 }
 
@@ -1245,7 +1442,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
     const u32 kind = KIND == KALL ? sd.kind : KIND;
-    const bool tail = kind == ST_WTAIL || kind == ST_PTAIL || kind == ST_WSMALL;  // one workgroup does everything
+    const bool tail = kind == ST_WTAIL || kind == ST_PTAIL || kind == ST_WSMALL || kind == ST_TOP;  // one workgroup does everything
     const bool has_fin = f.kind != FIN_NONE;
     const bool split = has_fin && !tail;  // workgroup nblocks finishes, the others run the body
     const bool fin_block = split && lb == sd.nblocks;
@@ -1351,6 +1548,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_PTAIL: step_ptail(sd.u.ptail, pp, c, ti.drew, ti.st, ti.have_c, ti.C); break;
         case ST_FINISH: step_finish(sd.u.finish, c); break;
         case ST_WSMALL: step_wsmall(sd.u.wsmall, pp, c); break;
+        case ST_TOP: step_top(sd.u.top, pp); break;
         case ST_SGE:
             if (c.lb == 0 && threadIdx.x == 0) {
                 const u64 v = sd.u.sge.Vn[0];
@@ -1399,7 +1597,7 @@ hipError_t launch_step_table(hipStream_t st, const JobTable &t) {
 }
 
 u32 step_grid(const StepDesc &sd) {
-    if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL || sd.kind == ST_WSMALL) return 1;
+    if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL || sd.kind == ST_WSMALL || sd.kind == ST_TOP) return 1;
     return sd.nblocks + (sd.fin.kind != FIN_NONE ? 1 : 0);
 }
 
@@ -1433,6 +1631,7 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_PTAIL: L1(ST_PTAIL); break;
         case ST_FINISH: L1(ST_FINISH); break;
         case ST_WSMALL: L1(ST_WSMALL); break;
+        case ST_TOP: L1(ST_TOP); break;
         default: L1(ST_END); break;
     }
 #undef L1

@@ -1,8 +1,9 @@
 // steps.hpp -- the prover as a program of steps, executed by one kernel.
 //
-// A proof is a fixed sequence of steps (evaluation of each layer, then per
-// layer: the eq table of z, the p-phase rounds, the eq table of a*, the two
-// omega-phases, the eq table of b*, the line tables and the line sums).
+// A proof is a fixed sequence of steps (evaluation of each layer, the
+// circuit's first small layers whole in one step, then per layer: the eq
+// table of z, the p-phase rounds, the eq table of a*, the two omega-phases,
+// the eq table of b*, the line tables and the line sums).
 // Every step is one grid pass; a step that ends a sum-check round leaves one
 // row of partial sums per workgroup.
 //
@@ -56,6 +57,7 @@ enum StepKind : u32 {
                    // layers whose wires each carry at most one chunk of gates
     ST_FINISH,     // every round's rows into its message values
     ST_WSMALL,     // omega phase of a small layer: eq table, level-0 tables, all rounds
+    ST_TOP,        // the first layers whose tables all fit a tail, whole, in one workgroup
 };
 
 enum FinKind : u32 {
@@ -302,6 +304,24 @@ struct WsmallArgs {
     u64 *msg, *vout;
 };
 
+// ST_TOP: the sum-check of layers 0 .. nl-1 in one workgroup.  Every one of
+// them has 2^s_i and 2^s_{i+1} (1 <= s_{i+1}) at most TAIL_LIM entries and
+// one chunk of gates per wire in both omega phases.  Its p-phase, omega
+// phases and line run as tails over tables kept in LDS from one layer to the
+// next (V_{i+1}, read for the omega phases, is the next layer's V_i).
+struct TopLayer {
+    u32 s, sp, kind, co;       // s_i, s_{i+1}, gate mix, challenge index of round 0
+    u64 *msg;                  // 3 n_i round values, v1, v2, h(2..s_{i+1})
+    const u64 *Vn;             // V_{i+1}
+    const u32 *rowptr[2], *perm[2], *oths[2];  // wire groups by in1 (phase 1) and in2 (phase 2)
+    const u8 *types[2];        // gate types in sorted order (mixed layers)
+};
+struct TopArgs {
+    u32 nl;
+    const TopLayer *L;         // nl descriptors (device memory)
+    const u64 *V0;             // V_0
+};
+
 struct StepDesc {
     u32 kind;
     u32 nblocks;
@@ -329,6 +349,7 @@ struct StepDesc {
         Wa0Args wa0;
         FinishArgs finish;
         WsmallArgs wsmall;
+        TopArgs top;
     } u;
 };
 

@@ -35,9 +35,10 @@ def random_circuit(rng, sizes, kinds=None):
     return Circuit(list(sizes), types, in1, in2, name=f"rand {sizes}")
 
 
-def check_same(circ, x, seed, name, device_inputs=False, algos=(1, 0)):
-    """Both omega-phase algorithms (tables, then per-gate rounds) against the
-    oracle; returns the circuit handle (tables) and its transcript."""
+def check_same(circ, x, seed, name, device_inputs=False, algos=(1, 2, 0)):
+    """The omega-phase algorithms (tables with the first small layers in one
+    launch, tables layer by layer, per-gate rounds) against the oracle;
+    returns the circuit handle (first algorithm) and its transcript."""
     say(name, "gates", circ.gates, "seed", seed)
     O.set_threads(oracle_threads())
     want_m, want_c = O.prove(circ, x, seed)
