@@ -721,15 +721,18 @@ extern "C" int gkr_circuit_info(const gkr_circuit *c, uint64_t *gates, uint64_t 
 // Gates of a layer grouped by the wire x a phase binds: perm lists the
 // gates in order of x (counting sort), cut into chunks of at most
 // GROUP_CHUNK gates of one wire; chunks of wire x are [xch[x], xch[x+1]).
+// A wire of more than HEAVY_WIRE gates (pattern matching's pattern values
+// feed 2^18) is cut into chunks of BIG_CHUNK gates instead, each summed by
+// a whole wave, so that the chunks of one wire stay few.
 constexpr u32 GROUP_CHUNK = 32;
+constexpr u32 HEAVY_WIRE = 64 * GROUP_CHUNK;
+constexpr u32 BIG_CHUNK = 512;
+__host__ __device__ constexpr u32 chunk_of(u64 gates) { return gates > HEAVY_WIRE ? BIG_CHUNK : GROUP_CHUNK; }
 struct HostGroup {
     std::vector<u32> perm, cstart, xch, rowptr, oths, tch;
     std::vector<u8> types;
 };
 
-// Tiles of whole chunks spanning at most TILE_POS sorted positions (one
-// wave each in the per-chunk sums): tile t holds chunks [tch[t], tch[t+1]).
-constexpr u32 TILE_POS = 64;
 
 // Counting sort of the gates by their wire idx (stable): positions, the
 // other wire and the type in that order, chunks of <= GROUP_CHUNK gates of
@@ -755,14 +758,17 @@ static void build_group(const std::vector<u32> &idx, const std::vector<u32> &oth
     G.cstart.clear();
     for (u64 x = 0; x < N; x++) {
         G.xch[x] = (u32)G.cstart.size();
-        for (u32 p = rowptr[x]; p < rowptr[x + 1]; p += GROUP_CHUNK) G.cstart.push_back(p);
+        const u32 csz = chunk_of(rowptr[x + 1] - rowptr[x]);
+        for (u32 p = rowptr[x]; p < rowptr[x + 1]; p += csz) G.cstart.push_back(p);
     }
     G.xch[N] = (u32)G.cstart.size();
     G.cstart.push_back((u32)S);
+    // a chunk that would carry the open tile past TILE_POS positions opens a
+    // tile of its own (a big chunk always stands alone in its tile)
     G.tch.assign(1, 0);
     const size_t nch = G.cstart.size() - 1;
     for (size_t ch = 0; ch < nch; ch++)
-        if (G.cstart[ch + 1] - G.cstart[G.tch.back()] > TILE_POS) G.tch.push_back((u32)ch);
+        if (ch > G.tch.back() && G.cstart[ch + 1] - G.cstart[G.tch.back()] > TILE_POS) G.tch.push_back((u32)ch);
     G.tch.push_back((u32)nch);
 }
 
@@ -1565,11 +1571,12 @@ static void size_groups(gkr_circuit *c) {
             u64 nch = 0, ntiles = 0, span = TILE_POS + 1;  // positions in the open tile
             bool single = true;
             for (u64 x = 0; x < N; x++) {
-                const u64 k = (cnt[x] + GROUP_CHUNK - 1) / GROUP_CHUNK;
+                const u64 csz = chunk_of(cnt[x]);
+                const u64 k = (cnt[x] + csz - 1) / csz;
                 nch += k;
                 single = single && k <= 1;
                 for (u64 q = 0; q < k; q++) {  // the chunks of wire x, in order (as build_group cuts them)
-                    const u64 len = std::min<u64>(GROUP_CHUNK, cnt[x] - q * GROUP_CHUNK);
+                    const u64 len = std::min<u64>(csz, cnt[x] - q * csz);
                     if (span + len > TILE_POS) {
                         ntiles++;
                         span = 0;

@@ -662,6 +662,31 @@ __device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp
         const u32 c0 = a.tch[t], nc = a.tch[t + 1] - c0;
         if (nc == 0) continue;  // (a group without gates has one empty tile)
         const u32 base = a.cstart[c0], end = a.cstart[c0 + nc];
+        if (end - base > TILE_POS) {  // one big chunk of a heavy wire: lanes stride over it
+            u64 sA = 0, sC = 0;
+#pragma unroll 4
+            for (u32 q = base + lane; q < end; q += 64) {
+                const u32 g = a.perm[q], o = a.oths[q];
+                const bool ismul = a.kind == 1 || (a.kind == 2 && a.types[q]);
+                u64 w = mul(a.alo[g & amask], a.ahi[g >> a.La]);
+                if (a.ph == 1) {
+                    const u64 wy = mul(w, a.Vn[o]);
+                    sA = add(sA, ismul ? wy : w);
+                    sC = add(sC, ismul ? 0 : wy);
+                } else {
+                    w = mul(w, mul(a.blo[o & bmask], a.bhi[o >> a.Lb]));
+                    sA = add(sA, ismul ? 0 : w);
+                    sC = add(sC, ismul ? w : 0);
+                }
+            }
+            sA = wave_sum63(sA);
+            sC = wave_sum63(sC);
+            if (lane == 63) {
+                a.partA[c0] = mul(beta, sA);
+                a.partC[c0] = mul(beta, sC);
+            }
+            continue;
+        }
         const u32 p = base + lane;
         u64 vA = 0, vC = 0;
         if (p < end) {
@@ -851,6 +876,7 @@ __device__ __forceinline__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, 
                 const u32 b0 = (u32)__builtin_amdgcn_readlane((int)c0, l);
                 const u32 b1 = (u32)__builtin_amdgcn_readlane((int)c1, l);
                 u64 wA = 0, wC = 0;
+#pragma unroll 4
                 for (u32 ch = b0 + lane; ch < b1; ch += 64) {
                     wA = add(wA, a.partA[ch]);
                     wC = add(wC, a.partC[ch]);

@@ -228,6 +228,10 @@ struct SgeArgs {
 // Tables of an omega phase: A[x] (weights) and C[x] (additive part) over
 // the bound wire x, with F the fold of V_{i+1}:
 //   G_k(t) = sum_m A_k(t, m) F_k(t, m) + C_k(t, m).
+// Tiles of whole chunks spanning at most TILE_POS sorted positions (one
+// wave each in the per-chunk sums), or a single big chunk of a heavy wire:
+// tile t holds chunks [tch[t], tch[t+1]).
+constexpr u32 TILE_POS = 64;
 struct WaggArgs {
     u32 kind, ph;
     u32 nch;                 // chunks: sorted positions [cstart[ch], cstart[ch+1]) share one wire x

@@ -115,6 +115,30 @@ def test_wire_fanout_around_chunk_size():
             check_same(circ, x, 31, f"fan-out kinds {kinds} swap {swap}")
 
 
+def test_heavy_wires_in_big_chunks():
+    """Wires read by 2047 .. 5000 gates: above 2048 gates a wire's gates are
+    cut into chunks of 512 summed by a whole wave; both phases, both kinds,
+    light wires beside them."""
+    rng = random.Random(23)
+    fan = [2047, 2048, 2049, 2560, 2561, 5000, 3, 0, 1, 700, 31, 33, 0, 2, 9, 64]
+    for kinds in (None, [1, 0], [0, 1]):
+        reads = [x for x, f in enumerate(fan) for _ in range(f)]
+        rng.shuffle(reads)
+        S0 = len(reads)
+        other = [rng.randrange(16) for _ in range(S0)]
+        small = [rng.randrange(16) for _ in range(16)]
+        t0 = [rng.randrange(2) if kinds is None else kinds[0] for _ in range(S0)]
+        t1 = [rng.randrange(2) if kinds is None else kinds[1] for _ in range(16)]
+        for swap in (False, True):
+            a, b = (other, reads) if swap else (reads, other)
+            circ = Circuit([S0, 16, 16], [np.array(t0, np.uint8), np.array(t1, np.uint8)],
+                           [np.array(a, np.uint32), np.array(small, np.uint32)],
+                           [np.array(b, np.uint32), np.array(small[::-1], np.uint32)],
+                           name="heavy wires")
+            x = np.array([rng.randrange(P) for _ in range(16)], np.uint64)
+            check_same(circ, x, 37, f"heavy wires kinds {kinds} swap {swap}")
+
+
 def test_c1_f2_1024():
     circ, x, seed = W.c1_f2()
     gc, m = check_same(circ, x, seed, "C1 F2 n=2^10")
