@@ -2264,21 +2264,43 @@ int build_batch(const std::vector<gkr_circuit *> &cs, int flags, std::unique_ptr
         if (rc) return rc;
         B->ws.push_back(w);
     }
-    // schedule: launch t holds step t of every proof with more than t steps
+    // schedule: launch t holds step t - start[q] of proof q.  A proof starts
+    // late enough that its ST_TOP step (the longest one-workgroup step) runs
+    // in the same launch as every other proof's, instead of lengthening
+    // launches of its own; proofs without one start at once.
+    std::vector<size_t> start(n, 0);
+    {
+        std::vector<long> top_at(n, -1);
+        long last_top = -1;
+        for (u32 q = 0; q < n; q++) {
+            const std::vector<StepDesc> &st = B->ws[q]->steps;
+            for (size_t t = 0; t < st.size() && top_at[q] < 0; t++)
+                if (st[t].kind == ST_TOP) top_at[q] = (long)t;
+            last_top = std::max(last_top, top_at[q]);
+        }
+        for (u32 q = 0; q < n; q++)
+            if (top_at[q] >= 0) start[q] = (size_t)(last_top - top_at[q]);
+    }
     size_t T = 0;
-    for (Workspace *w : B->ws) T = std::max(T, w->steps.size());
+    for (u32 q = 0; q < n; q++) T = std::max(T, start[q] + B->ws[q]->steps.size());
     std::vector<JobEntry> jobs;
     for (size_t t = 0; t < T; t++) {
         B->l_off.push_back((u32)jobs.size());
         u32 blocks = 0, nj = 0;
         double lb = 0, lm = 0;
-        for (Workspace *w : B->ws) {
-            if (t >= w->steps.size()) continue;
-            jobs.push_back(JobEntry{w->d_steps + t, blocks, 0});
-            blocks += step_grid(w->steps[t]);
-            lb += w->pbytes[t];
-            lm += w->pmods[t];
+        for (u32 q = 0; q < n; q++) {
+            Workspace *w = B->ws[q];
+            if (t < start[q] || t - start[q] >= w->steps.size()) continue;
+            const size_t k = t - start[q];
+            jobs.push_back(JobEntry{w->d_steps + k, blocks, 0});
+            blocks += step_grid(w->steps[k]);
+            lb += w->pbytes[k];
+            lm += w->pmods[k];
             nj++;
+        }
+        if (!nj) {  // (no proof in this launch: none is planned)
+            B->l_off.pop_back();
+            continue;
         }
         B->l_bytes.push_back(lb);
         B->l_mods.push_back(lm);
