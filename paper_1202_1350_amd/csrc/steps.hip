@@ -1463,7 +1463,7 @@ __device__ __forceinline__ void step_top(const TopArgs &a, const ProofPtrs &pp) 
 // beside the body instead of ahead of it) and records the drawn challenge.
 template <u32 KIND, int GK, int PH>
 __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
-    __shared__ u64 s_r, s_r2, s_st, s_c;
+    __shared__ u64 s_c;
     __shared__ u64 s_pt[64];  // a point (EQ), or b* and c* (LT), or z_{i+1} (FIN_LINE)
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
@@ -1479,52 +1479,52 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     c.gtid = (u64)c.lb * SBLOCK + threadIdx.x;
     c.gstride = (u64)c.nb * SBLOCK;
 
-    // --- prologue: the challenge (every workgroup draws the same value)
-    if (threadIdx.x == 0) {
-        u64 r = 0, r2 = 0;
-        if (f.draw >= 0) {
-            u64 st = pp.rngst[f.draw];
-            r = fp::sm_field(st);
-            if (recorder) {
-                pp.chals[f.draw] = r;
-                pp.rngst[f.draw + 1] = st;
+    // --- prologue: the challenge.  Every thread of every workgroup draws the
+    // same value from the state in memory (a uniform load), so nothing waits
+    // for a barrier before the body's first loads.
+    u64 st_after = 0;
+    c.r = 0;
+    c.r2 = 0;
+    if (f.draw >= 0) {
+        u64 st = pp.rngst[f.draw];
+        c.r = fp::sm_field(st);
+        const u64 st1 = st;
+        const bool two = f.kind == FIN_P2 || f.kind == FIN_T2;  // two rounds finish here
+        if (two) c.r2 = fp::sm_field(st);
+        if (recorder && threadIdx.x == 0) {
+            pp.chals[f.draw] = c.r;
+            pp.rngst[f.draw + 1] = st1;
+            if (two) {
+                pp.chals[f.draw + 1] = c.r2;
+                pp.rngst[f.draw + 2] = st;
             }
-            if (f.kind == FIN_P2 || f.kind == FIN_T2) {  // two rounds finish here
-                r2 = fp::sm_field(st);
-                if (recorder) {
-                    pp.chals[f.draw + 1] = r2;
-                    pp.rngst[f.draw + 2] = st;
-                }
-            }
-            s_st = st;  // the state after the drawn challenge(s)
         }
-        s_r = r;
-        s_r2 = r2;
+        st_after = st;  // the state after the drawn challenge(s)
     }
-    __syncthreads();
-    c.r = s_r;
-    c.r2 = s_r2;
-    TailIn ti = {f.draw >= 0 ? s_st : 0, 0, f.draw >= 0 ? 1u : 0u, 0u};
+    TailIn ti = {st_after, 0, f.draw >= 0 ? 1u : 0u, 0u};
     // points assembled in LDS (challenges drawn by earlier launches are in
     // chals; the one drawn just now is c.r)
-    if ((fin_mask(KIND) & (1u << FIN_LINE)) && f.kind == FIN_LINE && threadIdx.x < f.sp) {
-        const u64 bb = f.bstar[threadIdx.x], cc = f.cstar[threadIdx.x];
-        s_pt[threadIdx.x] = add(bb, mul(c.r, sub(cc, bb)));  // z_{i+1} = l(tau)
+    const bool line_fin = (fin_mask(KIND) & (1u << FIN_LINE)) && f.kind == FIN_LINE;
+    if (line_fin || kind == ST_EQ || kind == ST_LT) {  // (uniform)
+        if (line_fin && threadIdx.x < f.sp) {
+            const u64 bb = f.bstar[threadIdx.x], cc = f.cstar[threadIdx.x];
+            s_pt[threadIdx.x] = add(bb, mul(c.r, sub(cc, bb)));  // z_{i+1} = l(tau)
+        }
+        if (kind == ST_EQ && sd.u.eq.point == PT_Z && f.kind != FIN_LINE &&
+            threadIdx.x < sd.u.eq.base + sd.u.eq.n)
+            s_pt[threadIdx.x] = pp.zbuf[threadIdx.x];  // z of the layer, already recorded
+        if (kind == ST_EQ && sd.u.eq.point == PT_CHAL && threadIdx.x < sd.u.eq.n) {
+            const i32 ci = (i32)(sd.u.eq.base + threadIdx.x);
+            s_pt[threadIdx.x] = ci == f.draw ? c.r : pp.chals[ci];
+        }
+        if (kind == ST_LT && threadIdx.x < 2 * sd.u.lt.sp) {
+            const u32 sp = sd.u.lt.sp;
+            const i32 ci = (i32)(threadIdx.x < sp ? sd.u.lt.bbase + threadIdx.x
+                                                  : sd.u.lt.cbase + threadIdx.x - sp);
+            s_pt[threadIdx.x] = ci == f.draw ? c.r : pp.chals[ci];
+        }
+        __syncthreads();
     }
-    if (kind == ST_EQ && sd.u.eq.point == PT_Z && f.kind != FIN_LINE &&
-        threadIdx.x < sd.u.eq.base + sd.u.eq.n)
-        s_pt[threadIdx.x] = pp.zbuf[threadIdx.x];  // z of the layer, already recorded
-    if (kind == ST_EQ && sd.u.eq.point == PT_CHAL && threadIdx.x < sd.u.eq.n) {
-        const i32 ci = (i32)(sd.u.eq.base + threadIdx.x);
-        s_pt[threadIdx.x] = ci == f.draw ? c.r : pp.chals[ci];
-    }
-    if (kind == ST_LT && threadIdx.x < 2 * sd.u.lt.sp) {
-        const u32 sp = sd.u.lt.sp;
-        const i32 ci = (i32)(threadIdx.x < sp ? sd.u.lt.bbase + threadIdx.x
-                                              : sd.u.lt.cbase + threadIdx.x - sp);
-        s_pt[threadIdx.x] = ci == f.draw ? c.r : pp.chals[ci];
-    }
-    __syncthreads();
     if (fin_block || (tail && has_fin)) {
         fin_inline<KIND>(sd, c, s_pt, &s_c);
         if (fin_block) return;
