@@ -60,14 +60,14 @@ namespace {
 // then the verifier's and the F2 sum-check's kernels.
 enum ProfClass {
     PC_STEP = 0,  // + StepKind
-    PC_WIRING = 20, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_SERVE, PC_COUNT
+    PC_WIRING = 22, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_SERVE, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {
     "step_eval", "step_start", "step_eq", "step_p", "step_w", "step_fold", "step_lt",
     "step_line", "step_sge", "step_end", "step_wagg", "step_wt0", "step_wt", "step_wtail",
-    "step_ptail", "step_load", "step_wa0", "step_finish", "step_wsmall", "step_top", "wiring", "mle", "eq_tables", "f2sc_round",
+    "step_ptail", "step_load", "step_wa0", "step_finish", "step_wsmall", "step_top", "step_lfold", "step_ltail", "wiring", "mle", "eq_tables", "f2sc_round",
     "f2sc_final", "misc", "batch_step", "nif2", "serve_step"};
-static_assert(ST_TOP + 1 == PC_WIRING, "one profiling class per step kind");
+static_assert(ST_LTAIL + 1 == PC_WIRING, "one profiling class per step kind");
 
 struct ProfRec {
     int cls;
@@ -347,6 +347,7 @@ struct Workspace {
     u64 *frec;           // records of p-phase finishes (C, z_j, z_{j+1})
     FinItem *d_items;    // the finish step's items
     TopLayer *d_top;     // descriptors of the layers ST_TOP runs
+    u64 *lq;             // the line fold's workgroup polynomials (ST_LFOLD)
     u64 *msgs, *chals, *rngst, *zbuf, *state;
     u32 *flag;
     // omega phases over tables
@@ -834,6 +835,7 @@ static void carve(const gkr_circuit *c, Arena &a, Arena &h, Workspace &w, const 
     w.frec = a.take<u64>(std::max<u64>(ps.recs, 1));
     w.d_items = a.take<FinItem>(std::max<u64>(ps.items, 1));
     w.d_top = a.take<TopLayer>(c->L);
+    w.lq = a.take<u64>((u64)LF_ROW * LFOLD_MAX_WG);  // a row of h's terms per line-fold workgroup
     w.msgs = a.take<u64>(c->n_msgs);
     w.chals = a.take<u64>(std::max<u64>(c->n_chals, 1));
     w.rngst = a.take<u64>(c->n_chals + 1);
@@ -1198,6 +1200,18 @@ struct Planner {
             }
             u32 Ll = 0, M = 0, H = 0;  // shape of the line step (a9)
             if (sp >= 2) line_shape(sp, &Ll, &M, &H);
+            // A wide layer's line is V_{i+1} folded along it (ST_LFOLD, a
+            // workgroup per 2^(tb+9) entries, then ST_LTAIL) instead of sums
+            // over eq tables of the line points (ST_LT, ST_LINE).
+            const bool lfold = sp >= LFOLD_MIN && sp <= LFOLD_MAX;
+            const u32 ltb = lfold_tb(sp), lwg = lfold ? 1u << (sp - ltb - 9) : 0;
+            auto lfold_step = [&](const Fin &f) {
+                StepDesc &e = add(ST_LFOLD, lwg, 8.0 * (1ull << sp) + 8.0 * (sp - 1) * lwg);
+                // ~6 products an entry (two a fold coefficient), then the terms at 2..s'
+                mods.back() = 6.0 * (1ull << sp) + 2.0 * sp * (sp - 1) * lwg;
+                e.fin = f;
+                e.u.lfold = LfoldArgs{sp, ltb, co + s, co + s + sp, V(i + 1), w ? w->lq : nullptr, nullptr, chals};
+            };
             const u64 ntab = sp >= 2 ? (u64)(sp - 1) * ((1ull << Ll) + (1ull << M) + (1ull << H)) : 1;
             if (c->omega_algo != GKR_OMEGA_GATES) {
                 // ---- omega-phases over tables (a6, a7, a8): round 0 (and
@@ -1411,9 +1425,13 @@ struct Planner {
                 }
                 }  // small layer or not
                 // ---- line step (a9): every omega challenge is recorded
-                StepDesc &e = addg(ST_LT, ntab, 1, 8.0 * ntab);
-                e.u.lt = LtArgs{sp >= 2 ? sp : 0, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
-                                w ? w->lhl : nullptr, w ? w->lhh : nullptr};
+                if (lfold) {
+                    lfold_step(Fin{FIN_NONE, -1});
+                } else {
+                    StepDesc &e = addg(ST_LT, ntab, 1, 8.0 * ntab);
+                    e.u.lt = LtArgs{sp >= 2 ? sp : 0, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
+                                    w ? w->lhl : nullptr, w ? w->lhh : nullptr};
+                }
             } else {
                 // ---- omega-phases (a6, a7, a8)
                 const u64 *Fend = nullptr;  // table of the phase's last round
@@ -1508,11 +1526,15 @@ struct Planner {
                     f.last = 2;
                     f.F = Fend;
                     f.vout = vslot ? vslot + 1 : nullptr;
-                    StepDesc &e = addg(ST_LT, ntab, 1, 8.0 * ntab);
-                    e.fin = f;
-                    e.u.lt = LtArgs{sp >= 2 ? sp : 1, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
-                                    w ? w->lhl : nullptr, w ? w->lhh : nullptr};
-                    if (sp < 2) e.u.lt.sp = 0;  // nothing to tabulate
+                    if (lfold) {
+                        lfold_step(f);
+                    } else {
+                        StepDesc &e = addg(ST_LT, ntab, 1, 8.0 * ntab);
+                        e.fin = f;
+                        e.u.lt = LtArgs{sp >= 2 ? sp : 1, Ll, M, co + s, co + s + sp, w ? w->llo : nullptr,
+                                        w ? w->lhl : nullptr, w ? w->lhh : nullptr};
+                        if (sp < 2) e.u.lt.sp = 0;  // nothing to tabulate
+                    }
                 }
             }
             {
@@ -1523,7 +1545,12 @@ struct Planner {
                 layer_end.bstar = chals ? chals + co + s : nullptr;
                 layer_end.cstar = chals ? chals + co + s + sp : nullptr;
                 layer_end.msg = vslot ? vslot + 2 : nullptr;
-                if (sp >= 2) {
+                if (lfold) {  // the rest of the fold; it writes h(2..s') itself
+                    StepDesc &ls = add(ST_LTAIL, 1, 8.0 * (sp - 1) * lwg);
+                    mods.back() = 0;
+                    ls.u.lfold = LfoldArgs{sp, ltb, co + s, co + s + sp, V(i + 1), w ? w->lq : nullptr,
+                                           vslot ? vslot + 2 : nullptr, chals};
+                } else if (sp >= 2) {
                     const u32 T = sp - 1;
                     const u32 chunks = (T + LINE_CHUNK - 1) / LINE_CHUNK;
                     const u32 ch = ((T + chunks - 1) / chunks + 3) / 4 * 4;  // equal chunks, 4 | ch

@@ -1295,6 +1295,164 @@ __device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &
     if (tid == 0) pp.state[0] = C;  // beta(z, a*)
 }
 
+// ---------------------------------------------------------- line by folding
+//
+// h(t) = ~V_{i+1}(l(t)), l(t) = b* + t (c* - b*), is a polynomial of degree
+// s' in t.  Folding V along the line coordinate by coordinate (bit k of the
+// index, LSB first) turns each entry pair into a polynomial one degree
+// higher: with D = P1 - P0 and d_k = c_k - b_k, the fold is
+// P0(t) + (b_k + t d_k) D(t), whose coefficient j is P0_j + b_k D_j +
+// d_k D_{j-1}.  After all s' folds the one polynomial left is h.  About four
+// products an entry, against one per entry and line point for the sums over
+// eq tables (ST_LT, ST_LINE), so wide layers take this path.  A thread folds
+// 2^tb entries in registers (tb coordinates, 1 <= tb <= 5); the workgroup's 512
+// polynomials of degree tb take 9 more coordinates in LDS, one coefficient
+// per work item, leaving Q_g of degree D = tb + 9 for the workgroup's block
+// g of 2^D entries.  Since h(t) = sum_g Q_g(t) prod_{k >= D} (g_{k-D} ?
+// l_k(t) : 1 - l_k(t)), the workgroup then evaluates its term at t = 2..s'
+// and ST_LTAIL adds the terms up.
+constexpr u32 LF_LDS = 9;  // coordinates folded in LDS (SBLOCK = 2^9 polynomials)
+static_assert((1 << LF_LDS) == SBLOCK, "a workgroup's threads hold 2^9 polynomials");
+static_assert(LFOLD_MAX - 1 <= LF_ROW && SBLOCK % LF_ROW == 0, "a row holds h(2..s')");
+
+// The fold of a and b (degree D, in registers) into o (degree D + 1).
+template <int D>
+__device__ __forceinline__ void fold_poly(const u64 (&a)[D + 1], const u64 (&b)[D + 1], u64 bk, u64 dk,
+                                          u64 (&o)[D + 2]) {
+    u64 Dprev = 0;
+#pragma unroll
+    for (int j = 0; j <= D + 1; j++) {
+        const int jj = j <= D ? j : D;  // (in range for the unrolled loads)
+        const u64 Dj = j <= D ? sub(b[jj], a[jj]) : 0;
+        const u64 a0 = j <= D ? a[jj] : 0;
+        o[j] = fp::red128((u128)a0 + fp::wide(bk, Dj) + fp::wide(dk, Dprev));
+        Dprev = Dj;
+    }
+}
+
+template <int N, int D>
+__device__ __forceinline__ void fold_level_reg(const u64 (&p)[N][D + 1], u64 (&q)[N / 2][D + 2], u64 bk, u64 dk) {
+#pragma unroll
+    for (int m = 0; m < N / 2; m++) fold_poly<D>(p[2 * m], p[2 * m + 1], bk, dk, q[m]);
+}
+
+// L fold levels in LDS: M polynomials of degree d at src (d + 1 words each,
+// one after another) along coordinates k .. k + L - 1, one work item per
+// output coefficient, between src and dst in turn; returns the buffer with
+// the M >> L polynomials of degree d + L.  Ends with the workgroup in step.
+__device__ __forceinline__ u64 *lds_fold(u64 *src, u64 *dst, u32 M, u32 d, u32 k, u32 L, const u64 *bk,
+                                         const u64 *dk) {
+    for (u32 l = 0; l < L; l++, d++, M >>= 1, k++) {
+        const u32 nc = d + 2, items = (M >> 1) * nc;
+        const u64 b = bk[k], dl = dk[k];
+        for (u32 it = threadIdx.x; it < items; it += SBLOCK) {
+            const u32 m = it / nc, j = it - m * nc;
+            const u64 *P0 = src + (2 * m) * (d + 1), *P1 = P0 + (d + 1);
+            const u64 a0 = j <= d ? P0[j] : 0;
+            const u64 Dj = j <= d ? sub(P1[j], P0[j]) : 0;
+            const u64 Dm = j >= 1 ? sub(P1[j - 1], P0[j - 1]) : 0;
+            dst[it] = fp::red128((u128)a0 + fp::wide(b, Dj) + fp::wide(dl, Dm));  // (it = m nc + j)
+        }
+        __syncthreads();
+        u64 *t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
+// Register levels D .. TB-1 of N polynomials of degree D; the one left
+// (degree TB) goes to out.
+template <int N, int D, int TB>
+__device__ __forceinline__ void fold_regs(const u64 (&p)[N][D + 1], const u64 *bk, const u64 *dk, u64 *out) {
+    if constexpr (D == TB) {
+        static_assert(N == 1, "2^TB entries make one polynomial of degree TB");
+#pragma unroll
+        for (int j = 0; j <= TB; j++) out[j] = p[0][j];
+    } else {
+        u64 q[N / 2][D + 2];
+        fold_level_reg<N, D>(p, q, bk[D], dk[D]);
+        fold_regs<N / 2, D + 1, TB>(q, bk, dk, out);
+    }
+}
+
+template <int TB>
+__device__ __forceinline__ void lfold_body(const LfoldArgs &a, const Ctx &c, i32 draw) {
+    constexpr int E = 1 << TB;  // entries a thread folds
+    u64 *tab = tail_lds();
+    u64 *bk = tab, *dk = tab + 32;
+    u64 *buf0 = tab + 64, *buf1 = buf0 + SBLOCK * (TB + 1);  // 512 x (TB+1), then 256 x (TB+2) words
+    const u32 tid = threadIdx.x;
+    // the thread's entries (loaded before the line's coordinates are read)
+    const u64 *src = a.V + ((u64)c.lb << (TB + LF_LDS)) + ((u64)tid << TB);
+    u64 x[E][1];
+#pragma unroll
+    for (int e = 0; e < E; e += 2) {
+        const u64x2 v = ld2(src, e);
+        x[e][0] = v.x;
+        x[e + 1][0] = v.y;
+    }
+    if (tid < a.sp) {  // (the challenge drawn by this launch's prologue is c.r, not yet in chals)
+        const i32 bi = (i32)(a.bbase + tid), ci = (i32)(a.cbase + tid);
+        const u64 b = bi == draw ? c.r : a.chals[bi], cc = ci == draw ? c.r : a.chals[ci];
+        bk[tid] = b;
+        dk[tid] = sub(cc, b);
+    }
+    __syncthreads();
+    fold_regs<E, 0, TB>(x, bk, dk, buf0 + tid * (TB + 1));
+    __syncthreads();
+    constexpr u32 D = TB + LF_LDS;
+    const u64 *h = lds_fold(buf0, buf1, SBLOCK, TB, TB, LF_LDS, bk, dk);  // Q_g, degree D
+    // Q_g(t) times the weight of this workgroup's block along the remaining
+    // coordinates, prod_{k >= D} (g_{k-D} ? l_k(t) : 1 - l_k(t)), at t = 2..s'
+    if (tid + 2 <= a.sp) {
+        const u64 t = tid + 2;
+        u64 q = h[D];
+#pragma unroll
+        for (int j = D - 1; j >= 0; j--) q = add(mul(q, t), h[j]);
+        for (u32 k = D; k < a.sp; k++) {
+            const u64 l = add(bk[k], mul(t, dk[k]));
+            q = mul(q, (c.lb >> (k - D)) & 1 ? l : sub(1, l));
+        }
+        a.Q[(u64)c.lb * LF_ROW + tid] = q;
+    }
+}
+
+// draw: the challenge index drawn by the launch's prologue (one round's
+// finish at most: FIN_W or none), -1 if none.
+__device__ __forceinline__ void step_lfold(const LfoldArgs &a, const Ctx &c, i32 draw) {
+    switch (a.tb) {
+        case 1: lfold_body<1>(a, c, draw); break;
+        case 2: lfold_body<2>(a, c, draw); break;
+        case 3: lfold_body<3>(a, c, draw); break;
+        case 4: lfold_body<4>(a, c, draw); break;
+        default: lfold_body<5>(a, c, draw); break;
+    }
+}
+
+// h(t) = sum over the workgroups' weighted values at t = 2..s' (one row of
+// LF_ROW words a workgroup): 16 groups of 32 lanes each sum every 16th row,
+// then the 16 partial sums of each t.
+__device__ __forceinline__ void step_ltail(const LfoldArgs &a) {
+    constexpr u32 NG = SBLOCK / LF_ROW;
+    u64 *part = tail_lds();  // NG x LF_ROW partial sums
+    const u32 tid = threadIdx.x, l = tid % LF_ROW, q = tid / LF_ROW, T = a.sp - 1;
+    const u32 M = 1u << (a.sp - a.tb - LF_LDS);
+    u64 acc = 0;
+    if (l < T) {
+#pragma unroll 4
+        for (u32 g = q; g < M; g += NG) acc = add(acc, a.Q[(u64)g * LF_ROW + l]);
+    }
+    part[tid] = acc;  // (tid = q LF_ROW + l)
+    __syncthreads();
+    if (tid < T) {
+        u64 v = 0;
+#pragma unroll
+        for (u32 r = 0; r < NG; r++) v = add(v, part[r * LF_ROW + tid]);
+        a.msg[tid] = v;
+    }
+}
+
 // ---------------------------------------------------------------- top layers
 //
 // ST_TOP runs the sum-check of the circuit's first layers in one
@@ -1468,7 +1626,8 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
     const u32 kind = KIND == KALL ? sd.kind : KIND;
-    const bool tail = kind == ST_WTAIL || kind == ST_PTAIL || kind == ST_WSMALL || kind == ST_TOP;  // one workgroup does everything
+    const bool tail = kind == ST_WTAIL || kind == ST_PTAIL || kind == ST_WSMALL || kind == ST_TOP ||
+                      kind == ST_LTAIL;  // one workgroup does everything
     const bool has_fin = f.kind != FIN_NONE;
     const bool split = has_fin && !tail;  // workgroup nblocks finishes, the others run the body
     const bool fin_block = split && lb == sd.nblocks;
@@ -1575,6 +1734,8 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_FINISH: step_finish(sd.u.finish, c); break;
         case ST_WSMALL: step_wsmall(sd.u.wsmall, pp, c); break;
         case ST_TOP: step_top(sd.u.top, pp); break;
+        case ST_LFOLD: step_lfold(sd.u.lfold, c, f.draw); break;
+        case ST_LTAIL: step_ltail(sd.u.lfold); break;
         case ST_SGE:
             if (c.lb == 0 && threadIdx.x == 0) {
                 const u64 v = sd.u.sge.Vn[0];
@@ -1623,7 +1784,9 @@ hipError_t launch_step_table(hipStream_t st, const JobTable &t) {
 }
 
 u32 step_grid(const StepDesc &sd) {
-    if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL || sd.kind == ST_WSMALL || sd.kind == ST_TOP) return 1;
+    if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL || sd.kind == ST_WSMALL || sd.kind == ST_TOP ||
+        sd.kind == ST_LTAIL)
+        return 1;
     return sd.nblocks + (sd.fin.kind != FIN_NONE ? 1 : 0);
 }
 
@@ -1658,6 +1821,8 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_FINISH: L1(ST_FINISH); break;
         case ST_WSMALL: L1(ST_WSMALL); break;
         case ST_TOP: L1(ST_TOP); break;
+        case ST_LFOLD: L1(ST_LFOLD); break;
+        case ST_LTAIL: L1(ST_LTAIL); break;
         default: L1(ST_END); break;
     }
 #undef L1

@@ -139,6 +139,20 @@ def test_heavy_wires_in_big_chunks():
             check_same(circ, x, 37, f"heavy wires kinds {kinds} swap {swap}")
 
 
+def test_line_by_folding_on_wide_layers():
+    """Layers reading 2^17 .. 2^22 values take the line as a fold of V along
+    it (ST_LFOLD, ST_LTAIL): ragged sizes at both ends of that range, mixed
+    gates, every omega algorithm (the per-gate one finishes its last round
+    in the fold's first launch)."""
+    rng = random.Random(29)
+    for sizes in ([5, 70001, 131072 + 7], [3, (1 << 21) + 5], [1000, (1 << 22)]):
+        circ = random_circuit(rng, sizes)
+        x = np.array([rng.randrange(P) for _ in range(sizes[-1])], np.uint64)
+        check_same(circ, x, 41, f"line fold {sizes}", device_inputs=True)
+    n = (1 << 17) + 3
+    check_same(W.f2_circuit(n), W.f2_inputs(n, 43), 43, f"line fold F2 n={n}")
+
+
 def test_c1_f2_1024():
     circ, x, seed = W.c1_f2()
     gc, m = check_same(circ, x, seed, "C1 F2 n=2^10")
