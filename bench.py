@@ -652,17 +652,6 @@ def mulmod_rate(G, torch, dev):
     return n * 256 / best
 
 
-def line_mulmods(circ):
-    """Products of the line sums of one proof: (s'-1) per entry of V_{i+1}
-    for every layer with s' >= 2."""
-    tot = 0
-    for i in range(len(circ.sizes) - 1):
-        sp = (circ.sizes[i + 1] - 1).bit_length() if circ.sizes[i + 1] > 1 else 0
-        if sp >= 2:
-            tot += (sp - 1) << sp
-    return tot
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -847,14 +836,19 @@ def main():
         "autotune": tune,
         "roofline": roof,
     }
-    lm = line_mulmods(circ)
-    if "step_line" in prof and prof["step_line"][0] > 0:
-        line_rate = lm * args.steps / (prof["step_line"][0] * 1e-3)
-        line["alu"] = {"mulmod_peak_per_s": alu_peak, "mulmod_probe_per_s": peak_mm,
-                       "peak_probe": "2^24 independent chains of 256 dependent products",
-                       "line_kernel_mulmods_per_proof": lm,
-                       "line_kernel_mulmods_per_s": line_rate,
-                       "line_kernel_frac_of_peak": line_rate / alu_peak}
+    # The line's kernels, rated by the planner's count of their modular
+    # products: the sums over eq tables (step_line, one product per entry and
+    # line point) and the fold of wide layers (step_lfold, ~6 an entry).
+    line_k = {}
+    for cls in ("step_line", "step_lfold"):
+        if cls in prof and prof[cls][0] > 0 and prof[cls][3] > 0:
+            rate = prof[cls][3] / (prof[cls][0] * 1e-3)
+            line_k[cls] = {"mulmods_per_proof": prof[cls][3] / args.steps,
+                           "launches_per_proof": prof[cls][1] / args.steps,
+                           "mulmods_per_s": rate, "frac_of_peak": rate / alu_peak}
+    line["alu"] = {"mulmod_peak_per_s": alu_peak, "mulmod_probe_per_s": peak_mm,
+                   "peak_probe": "2^24 independent chains of 256 dependent products",
+                   "line_kernels": line_k}
     note("plain leg done", f"{prove_s * 1e3:.3f} ms/proof")
     if not args.no_configs:
         note("configuration legs")
