@@ -46,7 +46,7 @@ def kernel_source_hash():
 # Step kinds in the order of the StepKind enum: the profiling class
 # "step_<kind>" is the kernel k_step_one<kind index, ...>.
 STEP_KINDS = ["eval", "start", "eq", "p", "w", "fold", "lt", "line", "sge", "end", "wagg",
-              "wt0", "wt", "wtail", "ptail", "load", "wa0", "finish", "wsmall", "top", "lfold", "ltail"]
+              "wt0", "wt", "wtail", "ptail", "load", "wa0", "finish", "wsmall", "top", "lfold"]
 
 
 def rocprof_kernel_name(cls):

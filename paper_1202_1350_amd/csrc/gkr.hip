@@ -60,14 +60,14 @@ namespace {
 // then the verifier's and the F2 sum-check's kernels.
 enum ProfClass {
     PC_STEP = 0,  // + StepKind
-    PC_WIRING = 22, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_SERVE, PC_COUNT
+    PC_WIRING = 21, PC_MLE, PC_TABLES, PC_F2SC, PC_FINAL, PC_MISC, PC_BATCH, PC_NIF2, PC_SERVE, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {
     "step_eval", "step_start", "step_eq", "step_p", "step_w", "step_fold", "step_lt",
     "step_line", "step_sge", "step_end", "step_wagg", "step_wt0", "step_wt", "step_wtail",
-    "step_ptail", "step_load", "step_wa0", "step_finish", "step_wsmall", "step_top", "step_lfold", "step_ltail", "wiring", "mle", "eq_tables", "f2sc_round",
+    "step_ptail", "step_load", "step_wa0", "step_finish", "step_wsmall", "step_top", "step_lfold", "wiring", "mle", "eq_tables", "f2sc_round",
     "f2sc_final", "misc", "batch_step", "nif2", "serve_step"};
-static_assert(ST_LTAIL + 1 == PC_WIRING, "one profiling class per step kind");
+static_assert(ST_LFOLD + 1 == PC_WIRING, "one profiling class per step kind");
 
 struct ProfRec {
     int cls;
@@ -347,7 +347,6 @@ struct Workspace {
     u64 *frec;           // records of p-phase finishes (C, z_j, z_{j+1})
     FinItem *d_items;    // the finish step's items
     TopLayer *d_top;     // descriptors of the layers ST_TOP runs
-    u64 *lq;             // the line fold's workgroup polynomials (ST_LFOLD)
     u64 *msgs, *chals, *rngst, *zbuf, *state;
     u32 *flag;
     // omega phases over tables
@@ -835,7 +834,6 @@ static void carve(const gkr_circuit *c, Arena &a, Arena &h, Workspace &w, const 
     w.frec = a.take<u64>(std::max<u64>(ps.recs, 1));
     w.d_items = a.take<FinItem>(std::max<u64>(ps.items, 1));
     w.d_top = a.take<TopLayer>(c->L);
-    w.lq = a.take<u64>((u64)LF_ROW * LFOLD_MAX_WG);  // a row of h's terms per line-fold workgroup
     w.msgs = a.take<u64>(c->n_msgs);
     w.chals = a.take<u64>(std::max<u64>(c->n_chals, 1));
     w.rngst = a.take<u64>(c->n_chals + 1);
@@ -1201,16 +1199,20 @@ struct Planner {
             u32 Ll = 0, M = 0, H = 0;  // shape of the line step (a9)
             if (sp >= 2) line_shape(sp, &Ll, &M, &H);
             // A wide layer's line is V_{i+1} folded along it (ST_LFOLD, a
-            // workgroup per 2^(tb+9) entries, then ST_LTAIL) instead of sums
-            // over eq tables of the line points (ST_LT, ST_LINE).
+            // workgroup per 2^(tb+9) entries; ST_FINISH adds its rows into
+            // h(2..s')) instead of sums over eq tables of the line points
+            // (ST_LT, ST_LINE).
             const bool lfold = sp >= LFOLD_MIN && sp <= LFOLD_MAX;
-            const u32 ltb = lfold_tb(sp), lwg = lfold ? 1u << (sp - ltb - 9) : 0;
+            const u32 ltb = lfold_tb(sp), lwg = lfold ? lfold_wg(sp) : 0;
+            u64 *lrows = nullptr;
             auto lfold_step = [&](const Fin &f) {
                 StepDesc &e = add(ST_LFOLD, lwg, 8.0 * (1ull << sp) + 8.0 * (sp - 1) * lwg);
                 // ~6 products an entry (two a fold coefficient), then the terms at 2..s'
                 mods.back() = 6.0 * (1ull << sp) + 2.0 * sp * (sp - 1) * lwg;
                 e.fin = f;
-                e.u.lfold = LfoldArgs{sp, ltb, co + s, co + s + sp, V(i + 1), w ? w->lq : nullptr, nullptr, chals};
+                lrows = w ? w->rowpool + rows_used : nullptr;
+                rows_used += (u64)LFOLD_CHUNKS * lwg * ROW_STRIDE;
+                e.u.lfold = LfoldArgs{sp, ltb, co + s, co + s + sp, V(i + 1), lrows, chals};
             };
             const u64 ntab = sp >= 2 ? (u64)(sp - 1) * ((1ull << Ll) + (1ull << M) + (1ull << H)) : 1;
             if (c->omega_algo != GKR_OMEGA_GATES) {
@@ -1545,11 +1547,12 @@ struct Planner {
                 layer_end.bstar = chals ? chals + co + s : nullptr;
                 layer_end.cstar = chals ? chals + co + s + sp : nullptr;
                 layer_end.msg = vslot ? vslot + 2 : nullptr;
-                if (lfold) {  // the rest of the fold; it writes h(2..s') itself
-                    StepDesc &ls = add(ST_LTAIL, 1, 8.0 * (sp - 1) * lwg);
-                    mods.back() = 0;
-                    ls.u.lfold = LfoldArgs{sp, ltb, co + s, co + s + sp, V(i + 1), w ? w->lq : nullptr,
-                                           vslot ? vslot + 2 : nullptr, chals};
+                if (lfold) {  // the fold's rows, added up by ST_FINISH
+                    layer_end.T = sp - 1;
+                    layer_end.rows = lrows;
+                    layer_end.nrows = lwg;
+                    layer_end.chunk_blocks = lwg;
+                    layer_end.ch = ROW_STRIDE;
                 } else if (sp >= 2) {
                     const u32 T = sp - 1;
                     const u32 chunks = (T + LINE_CHUNK - 1) / LINE_CHUNK;

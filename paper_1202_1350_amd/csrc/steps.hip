@@ -1310,10 +1310,10 @@ __device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &
 // per work item, leaving Q_g of degree D = tb + 9 for the workgroup's block
 // g of 2^D entries.  Since h(t) = sum_g Q_g(t) prod_{k >= D} (g_{k-D} ?
 // l_k(t) : 1 - l_k(t)), the workgroup then evaluates its term at t = 2..s'
-// and ST_LTAIL adds the terms up.
+// and writes it as a row (two rows: 16 values a row); ST_FINISH adds the
+// rows up.
 constexpr u32 LF_LDS = 9;  // coordinates folded in LDS (SBLOCK = 2^9 polynomials)
 static_assert((1 << LF_LDS) == SBLOCK, "a workgroup's threads hold 2^9 polynomials");
-static_assert(LFOLD_MAX - 1 <= LF_ROW && SBLOCK % LF_ROW == 0, "a row holds h(2..s')");
 
 // The fold of a and b (degree D, in registers) into o (degree D + 1).
 template <int D>
@@ -1414,7 +1414,7 @@ __device__ __forceinline__ void lfold_body(const LfoldArgs &a, const Ctx &c, i32
             const u64 l = add(bk[k], mul(t, dk[k]));
             q = mul(q, (c.lb >> (k - D)) & 1 ? l : sub(1, l));
         }
-        a.Q[(u64)c.lb * LF_ROW + tid] = q;
+        a.rows[((u64)(tid / ROW_STRIDE) * c.nb + c.lb) * ROW_STRIDE + tid % ROW_STRIDE] = q;
     }
 }
 
@@ -1427,29 +1427,6 @@ __device__ __forceinline__ void step_lfold(const LfoldArgs &a, const Ctx &c, i32
         case 3: lfold_body<3>(a, c, draw); break;
         case 4: lfold_body<4>(a, c, draw); break;
         default: lfold_body<5>(a, c, draw); break;
-    }
-}
-
-// h(t) = sum over the workgroups' weighted values at t = 2..s' (one row of
-// LF_ROW words a workgroup): 16 groups of 32 lanes each sum every 16th row,
-// then the 16 partial sums of each t.
-__device__ __forceinline__ void step_ltail(const LfoldArgs &a) {
-    constexpr u32 NG = SBLOCK / LF_ROW;
-    u64 *part = tail_lds();  // NG x LF_ROW partial sums
-    const u32 tid = threadIdx.x, l = tid % LF_ROW, q = tid / LF_ROW, T = a.sp - 1;
-    const u32 M = 1u << (a.sp - a.tb - LF_LDS);
-    u64 acc = 0;
-    if (l < T) {
-#pragma unroll 4
-        for (u32 g = q; g < M; g += NG) acc = add(acc, a.Q[(u64)g * LF_ROW + l]);
-    }
-    part[tid] = acc;  // (tid = q LF_ROW + l)
-    __syncthreads();
-    if (tid < T) {
-        u64 v = 0;
-#pragma unroll
-        for (u32 r = 0; r < NG; r++) v = add(v, part[r * LF_ROW + tid]);
-        a.msg[tid] = v;
     }
 }
 
@@ -1626,8 +1603,8 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
     const Fin &f = sd.fin;
     const ProofPtrs &pp = sd.pp;
     const u32 kind = KIND == KALL ? sd.kind : KIND;
-    const bool tail = kind == ST_WTAIL || kind == ST_PTAIL || kind == ST_WSMALL || kind == ST_TOP ||
-                      kind == ST_LTAIL;  // one workgroup does everything
+    const bool tail = kind == ST_WTAIL || kind == ST_PTAIL || kind == ST_WSMALL ||
+                      kind == ST_TOP;  // one workgroup does everything
     const bool has_fin = f.kind != FIN_NONE;
     const bool split = has_fin && !tail;  // workgroup nblocks finishes, the others run the body
     const bool fin_block = split && lb == sd.nblocks;
@@ -1735,7 +1712,6 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_WSMALL: step_wsmall(sd.u.wsmall, pp, c); break;
         case ST_TOP: step_top(sd.u.top, pp); break;
         case ST_LFOLD: step_lfold(sd.u.lfold, c, f.draw); break;
-        case ST_LTAIL: step_ltail(sd.u.lfold); break;
         case ST_SGE:
             if (c.lb == 0 && threadIdx.x == 0) {
                 const u64 v = sd.u.sge.Vn[0];
@@ -1784,9 +1760,7 @@ hipError_t launch_step_table(hipStream_t st, const JobTable &t) {
 }
 
 u32 step_grid(const StepDesc &sd) {
-    if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL || sd.kind == ST_WSMALL || sd.kind == ST_TOP ||
-        sd.kind == ST_LTAIL)
-        return 1;
+    if (sd.kind == ST_WTAIL || sd.kind == ST_PTAIL || sd.kind == ST_WSMALL || sd.kind == ST_TOP) return 1;
     return sd.nblocks + (sd.fin.kind != FIN_NONE ? 1 : 0);
 }
 
@@ -1822,7 +1796,6 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_WSMALL: L1(ST_WSMALL); break;
         case ST_TOP: L1(ST_TOP); break;
         case ST_LFOLD: L1(ST_LFOLD); break;
-        case ST_LTAIL: L1(ST_LTAIL); break;
         default: L1(ST_END); break;
     }
 #undef L1

@@ -59,7 +59,6 @@ enum StepKind : u32 {
     ST_WSMALL,     // omega phase of a small layer: eq table, level-0 tables, all rounds
     ST_TOP,        // the first layers whose tables all fit a tail, whole, in one workgroup
     ST_LFOLD,      // line of a wide layer: V_{i+1} folded along the line, 2^(tb+9) entries a workgroup
-    ST_LTAIL,      // the workgroups' terms of h(2..s') added up in one workgroup
 };
 
 enum FinKind : u32 {
@@ -223,27 +222,26 @@ struct LineArgs {
     u32 sp, L, M, T, chunk_blocks, ch;
     const u64 *V, *lo, *hl, *hh;
 };
-// Line of a layer with 2^17 <= 2^s' <= 2^22 by folding (ST_LFOLD, ST_LTAIL):
+// Line of a layer with 2^17 <= 2^s' <= 2^22 by folding (ST_LFOLD):
 // h(t) = ~V_{i+1}(b* + t (c* - b*)) is a polynomial of degree s' in t; V is
 // folded coordinate by coordinate, each entry pair becoming a polynomial one
-// degree higher.  ST_LFOLD: with D = tb + 9, workgroup g folds entries
-// [g 2^D, (g+1) 2^D) along coordinates 0..D-1 into a polynomial of degree D
-// and writes its term of h(t), weighted along coordinates D..s'-1, for
-// t = 2..s' to Q + LF_ROW g; ST_LTAIL adds the 2^(s'-D) rows into msg.
-constexpr u32 LFOLD_MIN = 17, LFOLD_MAX = 22, LF_ROW = 32;
+// degree higher.  With D = tb + 9, workgroup g folds entries [g 2^D,
+// (g+1) 2^D) along coordinates 0..D-1 into a polynomial of degree D and
+// writes its term of h(t), weighted along coordinates D..s'-1, for
+// t = 2..s' as rows: value j in row (j / ROW_STRIDE) nwg + g, column
+// j % ROW_STRIDE (nwg workgroups).  ST_FINISH adds the rows up into h(2..s')
+// as it does for the line sums' rows.
+constexpr u32 LFOLD_MIN = 17, LFOLD_MAX = 22;
 // Entries a thread folds, 2^tb: 128 to 256 workgroups at every width (a
 // workgroup's time is set mostly by its LDS levels, not by tb).
 constexpr u32 lfold_tb(u32 sp) { return sp <= 17 ? 1 : sp == 18 ? 2 : sp <= 20 ? 3 : sp == 21 ? 4 : 5; }
-constexpr u32 LFOLD_MAX_WG = 1u << 8;  // rows of Q
-constexpr bool lfold_fits(u32 sp) {
-    return sp > LFOLD_MAX || ((1u << (sp - lfold_tb(sp) - 9)) <= LFOLD_MAX_WG && lfold_fits(sp + 1));
-}
-static_assert(lfold_fits(LFOLD_MIN), "the line fold's workgroups fit Q");
+constexpr u32 lfold_wg(u32 sp) { return 1u << (sp - lfold_tb(sp) - 9); }
+constexpr u32 LFOLD_CHUNKS = 2;  // rows a workgroup: h(2..s'), s' - 1 <= 2 ROW_STRIDE values
+static_assert(LFOLD_MAX - 1 <= LFOLD_CHUNKS * ROW_STRIDE, "h(2..s') fits a workgroup's rows");
 struct LfoldArgs {
     u32 sp, tb, bbase, cbase;  // coordinates; 2^tb entries a thread; challenge indices of b* and c*
     const u64 *V;              // V_{i+1}
-    u64 *Q;                    // LF_ROW words per workgroup
-    u64 *msg;                  // h(2..s')
+    u64 *rows;                 // LFOLD_CHUNKS x nwg rows of ROW_STRIDE words
     const u64 *chals;
 };
 struct SgeArgs {

@@ -141,9 +141,9 @@ def test_heavy_wires_in_big_chunks():
 
 def test_line_by_folding_on_wide_layers():
     """Layers reading 2^17 .. 2^22 values take the line as a fold of V along
-    it (ST_LFOLD, ST_LTAIL): ragged sizes at both ends of that range, mixed
-    gates, every omega algorithm (the per-gate one finishes its last round
-    in the fold's first launch)."""
+    it (ST_LFOLD, its rows added up by ST_FINISH): ragged sizes at both ends
+    of that range, mixed gates, every omega algorithm (the per-gate one
+    finishes its last round in the fold's launch)."""
     rng = random.Random(29)
     for sizes in ([5, 70001, 131072 + 7], [3, (1 << 21) + 5], [1000, (1 << 22)]):
         circ = random_circuit(rng, sizes)
