@@ -1182,7 +1182,7 @@ struct Planner {
                 const u32 La = s / 2;
                 const u64 ne = (1ull << La) + (1ull << (s - La));
                 StepDesc &e = addg(ST_EQ, ne, 1, 8.0 * ne);
-                e.u.eq = EqArgs{PT_CHAL, s, La, co, w ? w->alo : nullptr, w ? w->ahi : nullptr};
+                e.u.eq = EqArgs{PT_CHAL, s, La, co, w ? w->alo : nullptr, w ? w->ahi : nullptr, 1};
             }
             if (sp == 0) {
                 StepDesc &e = add(ST_SGE, 1, 8);

@@ -337,11 +337,12 @@ __device__ __forceinline__ void step_start(const StartArgs &a, const ProofPtrs &
     for (u64 g = c.gtid; g < a.S0; g += c.gstride) pp.msgs[g] = a.V0[g];
 }
 
-__device__ __forceinline__ void step_eq(const EqArgs &a, const Ctx &c, const u64 *pt) {
+__device__ __forceinline__ void step_eq(const EqArgs &a, const Ctx &c, const u64 *pt, const ProofPtrs &pp) {
     const u64 nlo = 1ull << a.L, nhi = 1ull << (a.n - a.L);
+    const u64 beta = a.beta_lo ? pp.state[0] : 1;
     for (u64 x = c.gtid; x < nlo + nhi; x += c.gstride) {
         if (x < nlo)
-            a.lo[x] = chi_bits(x, pt, a.L);
+            a.lo[x] = a.beta_lo ? mul(beta, chi_bits(x, pt, a.L)) : chi_bits(x, pt, a.L);
         else
             a.hi[x - nlo] = chi_bits(x - nlo, pt + a.L, a.n - a.L);
     }
@@ -438,7 +439,6 @@ __device__ __forceinline__ void step_w(const WArgs &a, const Ctx &c, const Proof
         r = inl ? c.r : pp.chals[a.rchal];
         omr = sub(1, r);
     }
-    const u64 wbase = init ? pp.state[0] : 0;  // beta(z, a*)
     const u64 v1 = PH == 2 ? pp.state[1] : 0;
     const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
     const u32 k = a.k;
@@ -455,7 +455,7 @@ __device__ __forceinline__ void step_w(const WArgs &a, const Ctx &c, const Proof
         const bool ismul = KIND == 1 || (KIND == 2 && a.type[g]);
         u64 wt, of;
         if (init) {
-            u64 wg = mul(wbase, mul(a.alo[g & amask], a.ahi[g >> a.La]));
+            u64 wg = mul(a.alo[g & amask], a.ahi[g >> a.La]);  // beta chi_g(a*): lo carries beta
             if (PH == 1) {
                 const u64 y = a.Vn[a.oth[g]];
                 wt = ismul ? mul(wg, y) : wg;
@@ -615,15 +615,14 @@ __device__ __forceinline__ void step_line(const LineArgs &a, const Ctx &c, u64 *
 // w V[in2] (sC).  Phase 2: sums of the weights over ADD gates (sA) and MUL
 // gates (sC); v1 enters when the level-0 tables are formed.
 template <typename Args>
-__device__ __forceinline__ void wire_sums(const Args &a, u64 beta, u32 p0, u32 p1, u64 &sA_out,
-                                          u64 &sC_out) {
+__device__ __forceinline__ void wire_sums(const Args &a, u32 p0, u32 p1, u64 &sA_out, u64 &sC_out) {
     const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
     // branch-free updates keep both sums in registers
     u64 sA = 0, sC = 0;
     for (u32 p = p0; p < p1; p++) {
         const u32 g = a.perm[p], o = a.oths[p];
         const bool ismul = a.kind == 1 || (a.kind == 2 && a.types[p]);
-        u64 w = mul(beta, mul(a.alo[g & amask], a.ahi[g >> a.La]));
+        u64 w = mul(a.alo[g & amask], a.ahi[g >> a.La]);  // beta chi_g(a*): lo carries beta
         if (a.ph == 1) {
             const u64 wy = mul(w, a.Vn[o]);
             sA = add(sA, ismul ? wy : w);
@@ -651,10 +650,10 @@ __device__ __forceinline__ u64 bperm64(u64 v, u32 l) {
 // l the gate at the tile's position l, so the gate arrays are read in
 // coalesced runs; the inclusive scan of the terms over the wave gives each
 // chunk's sum as the scan at its last position minus the scan just before
-// its first.  beta(z, a*) multiplies every term, so it is applied once per
-// chunk.  Terms as in wire_sums.
+// its first.  Terms as in wire_sums (beta(z, a*), which multiplies every
+// term, comes with the lo half of a*'s eq table).
 __device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp, const Ctx &c) {
-    const u64 beta = pp.state[0];  // beta(z, a*)
+    (void)pp;  // beta(z, a*) is in the lo half of a*'s eq table
     const u32 lane = threadIdx.x & 63;
     const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
     const u64 nwaves = c.gstride >> 6;
@@ -682,8 +681,8 @@ __device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp
             sA = wave_sum63(sA);
             sC = wave_sum63(sC);
             if (lane == 63) {
-                a.partA[c0] = mul(beta, sA);
-                a.partC[c0] = mul(beta, sC);
+                a.partA[c0] = sA;
+                a.partC[c0] = sC;
             }
             continue;
         }
@@ -711,8 +710,8 @@ __device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp
         const u64 A1 = bperm64(sA, last), C1 = bperm64(sC, last);
         const u64 A0 = bperm64(sA, before), C0 = bperm64(sC, before);
         if (mine) {
-            a.partA[c0 + k] = mul(beta, first ? sub(A1, A0) : A1);
-            a.partC[c0 + k] = mul(beta, first ? sub(C1, C0) : C1);
+            a.partA[c0 + k] = first ? sub(A1, A0) : A1;
+            a.partC[c0 + k] = first ? sub(C1, C0) : C1;
         }
     }
 }
@@ -902,9 +901,8 @@ __device__ __forceinline__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, 
 }
 
 __device__ __forceinline__ void step_wa0(const Wa0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
-    const u64 beta = pp.state[0];
     level0_round(a.ph, a.hasC, a.npairs, a.Vn, a.A, a.C, pp, c, row, [&](u64 x, u64 &sA, u64 &sC) {
-        wire_sums(a, beta, a.rowptr[x], a.rowptr[x + 1], sA, sC);
+        wire_sums(a, a.rowptr[x], a.rowptr[x + 1], sA, sC);
     });
 }
 
@@ -1133,9 +1131,10 @@ __device__ __forceinline__ void step_wsmall(const WsmallArgs &a, const ProofPtrs
     {
         const u64 *pt = pp.chals + a.eqbase;
         const u64 nlo = 1ull << a.eqL, nhi = 1ull << (a.eqn - a.eqL);
+        const u64 beta = pp.state[0];  // phase 1: a*'s lo half carries beta(z, a*)
         for (u64 x = tid; x < nlo + nhi; x += SBLOCK) {
             if (x < nlo)
-                a.eqlo[x] = chi_bits(x, pt, a.eqL);
+                a.eqlo[x] = a.w.ph == 1 ? mul(beta, chi_bits(x, pt, a.eqL)) : chi_bits(x, pt, a.eqL);
             else
                 a.eqhi[x - nlo] = chi_bits(x - nlo, pt + a.eqL, a.eqn - a.eqL);
         }
@@ -1143,11 +1142,11 @@ __device__ __forceinline__ void step_wsmall(const WsmallArgs &a, const ProofPtrs
     __syncthreads();  // the eq table is read back by this workgroup
     const Wa0Args &w = a.w;
     const bool hc = w.hasC != 0;
-    const u64 beta = pp.state[0], v1 = w.ph == 2 ? pp.state[1] : 0;
+    const u64 v1 = w.ph == 2 ? pp.state[1] : 0;
     const u32 n = 1u << a.sp;
     for (u32 x = tid; x < n; x += SBLOCK) {
         u64 sA, sC, A, C;
-        wire_sums(w, beta, w.rowptr[x], w.rowptr[x + 1], sA, sC);
+        wire_sums(w, w.rowptr[x], w.rowptr[x + 1], sA, sC);
         level0(w.ph, v1, sA, sC, A, C);
         tab[x] = A;
         if (hc) tab[TAIL_TAB + x] = C;
@@ -1681,7 +1680,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_EVAL: step_eval(sd.u.eval, c); break;
         case ST_START: step_start(sd.u.start, pp, c); break;
         case ST_EQ:
-            step_eq(sd.u.eq, c, sd.u.eq.point == PT_Z ? s_pt + sd.u.eq.base : s_pt);
+            step_eq(sd.u.eq, c, sd.u.eq.point == PT_Z ? s_pt + sd.u.eq.base : s_pt, pp);
             break;
         case ST_P: step_p(sd.u.p, c, row); break;
         case ST_W: {

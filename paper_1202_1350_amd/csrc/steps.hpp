@@ -174,6 +174,8 @@ struct EqArgs {
     u32 L;      // lo table covers coordinates [0, L)
     u32 base;   // PT_CHAL: first challenge index; PT_Z: first coordinate of z
     u64 *lo, *hi;
+    u32 beta_lo;  // a*: lo entries times beta(z, a*) (state[0]), so that a gate's
+                  // weight beta chi_g(a*) is lo[g mod 2^L] hi[g >> L]
 };
 // p-phase grid step.  first: round 0 (and 1) on V_i and the eq tables of
 // z_i[1..s); a unit is a quad of V_i (look) or a pair (s = 1); writes
