@@ -140,12 +140,12 @@ def test_heavy_wires_in_big_chunks():
 
 
 def test_line_by_folding_on_wide_layers():
-    """Layers reading 2^17 .. 2^22 values take the line as a fold of V along
+    """Layers reading 2^11 .. 2^22 values take the line as a fold of V along
     it (ST_LFOLD, its rows added up by ST_FINISH): ragged sizes at both ends
     of that range, mixed gates, every omega algorithm (the per-gate one
     finishes its last round in the fold's launch)."""
     rng = random.Random(29)
-    for sizes in ([5, 70001, 131072 + 7], [3, (1 << 21) + 5], [1000, (1 << 22)]):
+    for sizes in ([5, 70001, 131072 + 7], [3, (1 << 21) + 5], [1000, (1 << 22)], [7, 1025, 2048 + 3, 40000]):
         circ = random_circuit(rng, sizes)
         x = np.array([rng.randrange(P) for _ in range(sizes[-1])], np.uint64)
         check_same(circ, x, 41, f"line fold {sizes}", device_inputs=True)
