@@ -1002,8 +1002,11 @@ struct Planner {
             StepDesc &s = addg(ST_LOAD, npad, 4, Sd * 8.0 + npad * 8.0);
             s.u.load = LoadArgs{c->S[d], npad, V(d)};
         }
-        // circuit evaluation (a3), layer d-1 down to 0
-        for (int i = (int)d - 1; i >= 0; i--) {
+        // circuit evaluation (a3), layer d-1 down to 0; the first K layers
+        // (run by ST_TOP, which evaluates them and starts the proof itself)
+        // down to K
+        const u32 K = top_layers(c);
+        for (int i = (int)d - 1; i >= (int)K; i--) {
             const u64 S = c->S[i], npad = 1ull << c->s[i];
             eval_at[i] = (int)out.size();
             StepDesc &s = addg(ST_EVAL, npad, 4,
@@ -1012,7 +1015,7 @@ struct Planner {
             s.u.eval = EvalArgs{(u32)c->kind[i], c->S[i], npad, soa_at(i, c->type[i]), soa_at(i, c->in1[i]),
                                 soa_at(i, c->in2[i]), V(i + 1), V(i)};
         }
-        {
+        if (!K) {
             StepDesc &s = addg(ST_START, c->S[0], 1, c->S[0] * 16.0);
             s.u.start = StartArgs{c->s[0], c->S[0], V(0)};
         }
@@ -1022,7 +1025,6 @@ struct Planner {
         layer_end.draw = -1;
         // The first K layers run whole in one workgroup (ST_TOP); the step
         // after it draws the last one's tau.
-        const u32 K = top_layers(c);
         if (K) {
             top.clear();
             double nbytes = 0, nmods = 0;
@@ -1037,6 +1039,11 @@ struct Planner {
                 t.co = (u32)c->co[i];
                 t.msg = w ? w->msgs + c->mo[i] : nullptr;
                 t.Vn = V(i + 1);
+                t.S = (u32)S;
+                t.in1 = soa_at(i, c->in1[i]);
+                t.in2 = soa_at(i, c->in2[i]);
+                t.type = soa_at(i, c->type[i]);
+                t.V = V(i);
                 for (u32 ph = 1; ph <= 2; ph++) {
                     const gkr_circuit::Group &g = c->grp[ph - 1][i];
                     t.rowptr[ph - 1] = g.rowptr;
@@ -1049,6 +1056,9 @@ struct Planner {
                 // V_{i+1} 8 per entry; per phase: row pointers 4 per wire, sorted
                 // index and other wire 8 per gate (+1 type)
                 nbytes += 8.0 * N + 2 * (4.0 * (N + 1) + S * (8.0 + (c->kind[i] == KIND_MIXED)));
+                // its evaluation: wires 8 (+1 type) per gate, V_i written
+                nbytes += S * (8.0 + (c->kind[i] == KIND_MIXED)) + 8.0 * (1ull << s);
+                nmods += c->kind[i] == KIND_ADD ? 0.0 : (double)S;
                 // p-phase ~4 per entry of V_i; per gate 4 (phase 1) and 5 (phase 2);
                 // per table entry 8 per phase; the line one product per point and entry
                 nmods += 4.0 * (1ull << s) + 9.0 * S + 16.0 * N + (sp >= 2 ? 1.5 * (sp - 1) * N : 0.0);

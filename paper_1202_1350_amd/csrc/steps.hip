@@ -1530,7 +1530,50 @@ __device__ __forceinline__ void step_top(const TopArgs &a, const ProofPtrs &pp) 
     u64 *X = tab, *Y = tab + TAIL_TAB, *Z = tab + 2 * TAIL_TAB;
     u64 *eqa = Y + TAIL_TAB - 128, *eqb = eqa + 64;  // eq halves: lo in [0, 32), hi in [32, 64)
     const u32 tid = threadIdx.x, lane = tid & 63;
-    // V_0, z_0 and the RNG state ST_START left
+    // Evaluation of the layers, nl - 1 down to 0, each from the one below it
+    // in LDS (X and Y in turn; Z is not touched), every table also written
+    // to memory as ST_EVAL writes it.
+    {
+        const TopLayer &Lk = a.L[a.nl - 1];
+        u64 *src = X, *dst = Y;
+        for (u32 e = tid; e < (1u << Lk.sp); e += SBLOCK) src[e] = Lk.Vn[e];
+        __syncthreads();
+        for (u32 i = a.nl; i-- > 0;) {
+            const TopLayer &Ld = a.L[i];
+            for (u32 g = tid; g < (1u << Ld.s); g += SBLOCK) {
+                u64 v = 0;
+                if (g < Ld.S) {
+                    const u64 x = src[Ld.in1[g]], y = src[Ld.in2[g]];
+                    const bool ismul = Ld.kind == 1 || (Ld.kind == 2 && Ld.type[g]);
+                    v = ismul ? mul(x, y) : add(x, y);
+                }
+                dst[g] = v;
+                Ld.V[g] = v;
+            }
+            __syncthreads();
+            u64 *t = src;
+            src = dst;
+            dst = t;
+        }
+        // the start (as ST_START): z_0 from the seed's stream, the outputs
+        // (V_0, now in src) into the transcript
+        const TopLayer &L0 = a.L[0];
+        if (tid == 0) {
+            u64 st = fp::sm_state(pp.state[2], fp::PURPOSE_GKR);  // state[2] = seed
+            pp.rngst[0] = st;
+            for (u32 k = 0; k < L0.s; k++) {
+                const u64 z = fp::sm_field(st);
+                pp.chals[k] = z;
+                pp.zbuf[k] = z;
+                pp.rngst[k + 1] = st;
+            }
+            pp.state[0] = 1;
+            pp.state[1] = 0;
+        }
+        for (u32 g = tid; g < L0.S; g += SBLOCK) pp.msgs[g] = src[g];
+        __syncthreads();  // the tables, z_0 and the RNG state are read back below
+    }
+    // V_0, z_0 and the RNG state of the start
     {
         const TopLayer &L0 = a.L[0];
         for (u32 e = tid; e < (1u << L0.s); e += SBLOCK) Z[e] = a.V0[e];

@@ -346,7 +346,14 @@ struct TopLayer {
     const u64 *Vn;             // V_{i+1}
     const u32 *rowptr[2], *perm[2], *oths[2];  // wire groups by in1 (phase 1) and in2 (phase 2)
     const u8 *types[2];        // gate types in sorted order (mixed layers)
+    u32 S;                     // gates of layer i
+    const u32 *in1, *in2;      // its wiring (evaluation)
+    const u8 *type;            // its gate types (mixed layers)
+    u64 *V;                    // V_i, written by the evaluation
 };
+// ST_TOP also evaluates its layers, nl - 1 down to 0, from V_nl (the layer
+// below them, evaluated by ST_EVAL launches), and starts the proof as
+// ST_START does (the randomness of z_0 and the outputs into the transcript).
 struct TopArgs {
     u32 nl;
     const TopLayer *L;         // nl descriptors (device memory)
