@@ -50,11 +50,20 @@ STEP_KINDS = ["eval", "start", "eq", "p", "w", "fold", "lt", "line", "sge", "end
 
 
 def rocprof_kernel_name(cls):
-    """How rocprofv3 names the kernel of a profiling class (the
-    single-proof step kernels; other classes are returned unchanged)."""
-    if cls.startswith("step_") and cls[5:] in STEP_KINDS and cls != "step_w":
-        return f"void gkr::k_step_one<{STEP_KINDS.index(cls[5:])}u, -1, 0>(gkr::StepDesc)"
+    """How rocprofv3 names the kernels of a profiling class (the
+    single-proof step kernels, k_step_one<kind, *, *>: some kinds have one
+    kernel per gate mix and phase; other classes are returned unchanged)."""
+    if cls.startswith("step_") and cls[5:] in STEP_KINDS:
+        return f"void gkr::k_step_one<{STEP_KINDS.index(cls[5:])}u, *, *>(gkr::StepDesc)"
     return cls
+
+
+def kernel_matches(name, cls):
+    """Whether rocprofv3's kernel name is one of cls's kernels."""
+    pat = rocprof_kernel_name(cls)
+    if "*" not in pat:
+        return name == pat
+    return name.startswith(pat.split("*")[0])
 
 
 def traffic_path(cls):
@@ -107,7 +116,7 @@ def traffic_summary(fetch_dir, write_dir, cls, copy_bytes, command):
     for label, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = _pmc_rows(d, counter)
         copies = [v for k, v in rows if "copyBuffer" in k]
-        kern = [v for k, v in rows if k == name]
+        kern = [v for k, v in rows if kernel_matches(k, cls)]
         if not copies or not kern:
             raise SystemExit(f"{counter}: calibration copy or kernel {name} missing")
         cal = max(copies) * 1024.0

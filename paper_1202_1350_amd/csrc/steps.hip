@@ -614,24 +614,38 @@ __device__ __forceinline__ void step_line(const LineArgs &a, const Ctx &c, u64 *
 // put w V[in2] on x's value (sA), ADD gates put w on it (sA) and add
 // w V[in2] (sC).  Phase 2: sums of the weights over ADD gates (sA) and MUL
 // gates (sC); v1 enters when the level-0 tables are formed.
-template <typename Args>
+// GK, PH: the layer's gate mix (0 ADD, 1 MUL, 2 mixed) and the phase when
+// known at compile time, -1 and 0 to read them from a.
+template <int GK = -1, int PH = 0, typename Args>
 __device__ __forceinline__ void wire_sums(const Args &a, u32 p0, u32 p1, u64 &sA_out, u64 &sC_out) {
+    const u32 kind = GK >= 0 ? (u32)GK : a.kind, ph = PH > 0 ? (u32)PH : a.ph;
     const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
-    // branch-free updates keep both sums in registers
+    // branch-free updates keep both sums in registers; a sum that a gate
+    // mix leaves at zero is not updated
     u64 sA = 0, sC = 0;
     for (u32 p = p0; p < p1; p++) {
         const u32 g = a.perm[p], o = a.oths[p];
-        const bool ismul = a.kind == 1 || (a.kind == 2 && a.types[p]);
+        const bool ismul = kind == 1 || (kind == 2 && a.types[p]);
         u64 w = mul(a.alo[g & amask], a.ahi[g >> a.La]);  // beta chi_g(a*): lo carries beta
-        if (a.ph == 1) {
+        if (ph == 1) {
             const u64 wy = mul(w, a.Vn[o]);
-            sA = add(sA, ismul ? wy : w);
-            sC = add(sC, ismul ? 0 : wy);
+            if (kind == 1) {
+                sA = add(sA, wy);
+            } else {
+                sA = add(sA, ismul ? wy : w);
+                sC = add(sC, ismul ? 0 : wy);
+            }
         } else {
             const u32 i1 = o;
             w = mul(w, mul(a.blo[i1 & bmask], a.bhi[i1 >> a.Lb]));
-            sA = add(sA, ismul ? 0 : w);
-            sC = add(sC, ismul ? w : 0);
+            if (kind == 1) {
+                sC = add(sC, w);
+            } else if (kind == 0) {
+                sA = add(sA, w);
+            } else {
+                sA = add(sA, ismul ? 0 : w);
+                sC = add(sC, ismul ? w : 0);
+            }
         }
     }
     sA_out = sA;
@@ -716,13 +730,22 @@ __device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp
     }
 }
 
-// Message sums of one pair of a table round.
+// Message sums of one pair of a table round.  HC: whether the layer has a
+// C table, when known at compile time (without one C is zero and skipped).
+template <int HC = 1>
 __device__ __forceinline__ void table_terms(u64 A0, u64 A1, u64 C0, u64 C1, u64 F0, u64 F1,
                                             u64 (&acc)[3]) {
-    const u64 A2 = sub(add(A1, A1), A0), F2 = sub(add(F1, F1), F0), C2 = sub(add(C1, C1), C0);
-    acc[0] = add(acc[0], add(mul(A0, F0), C0));
-    acc[1] = add(acc[1], add(mul(A1, F1), C1));
-    acc[2] = add(acc[2], add(mul(A2, F2), C2));
+    const u64 A2 = sub(add(A1, A1), A0), F2 = sub(add(F1, F1), F0);
+    if (HC) {
+        const u64 C2 = sub(add(C1, C1), C0);
+        acc[0] = add(acc[0], add(mul(A0, F0), C0));
+        acc[1] = add(acc[1], add(mul(A1, F1), C1));
+        acc[2] = add(acc[2], add(mul(A2, F2), C2));
+    } else {
+        acc[0] = add(acc[0], mul(A0, F0));
+        acc[1] = add(acc[1], mul(A1, F1));
+        acc[2] = add(acc[2], mul(A2, F2));
+    }
 }
 
 // One quad of level-k tables, held one entry per lane by four adjacent
@@ -744,11 +767,14 @@ __device__ __forceinline__ u64 at_t(u64 x0, u64 x1, u32 t) {
     return t == 0 ? x0 : (t == 1 ? x1 : x2);
 }
 
+// HC: whether the layer has a C table (1, 0), or -1 to take hasC.
+template <int HC>
 __device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC, QuadAcc &acc) {
+    const bool hc = HC >= 0 ? HC != 0 : hasC;
     const u64 A0 = quad_get<0>(A), A1 = quad_get<1>(A), A2 = quad_get<2>(A), A3 = quad_get<3>(A);
     const u64 F0 = quad_get<0>(F), F1 = quad_get<1>(F), F2 = quad_get<2>(F), F3 = quad_get<3>(F);
     u64 C0 = 0, C1 = 0, C2 = 0, C3 = 0;
-    if (hasC) {
+    if (hc) {
         C0 = quad_get<0>(C);
         C1 = quad_get<1>(C);
         C2 = quad_get<2>(C);
@@ -757,14 +783,21 @@ __device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC
     const u32 t = j < 3 ? j : 2;
     // round k at t: pairs (X0, X1) and (X2, X3); products summed in 128 bits
     // and reduced once per value
-    const u64 g = fp::red128(fp::wide(at_t(A0, A1, t), at_t(F0, F1, t)) +
-                             fp::wide(at_t(A2, A3, t), at_t(F2, F3, t)) + at_t(C0, C1, t) + at_t(C2, C3, t));
+    u128 gs = fp::wide(at_t(A0, A1, t), at_t(F0, F1, t)) + fp::wide(at_t(A2, A3, t), at_t(F2, F3, t));
+    if (HC != 0) gs += (u128)(at_t(C0, C1, t) + at_t(C2, C3, t));  // (zero without a C table)
+    const u64 g = fp::red128(gs);
     // round k+1's coefficients at t
     const u64 aA = at_t(A0, A2, t), bA = at_t(sub(A1, A0), sub(A3, A2), t);
     const u64 aF = at_t(F0, F2, t), bF = at_t(sub(F1, F0), sub(F3, F2), t);
-    const u64 aC = at_t(C0, C2, t), bC = at_t(sub(C1, C0), sub(C3, C2), t);
-    const u64 q0 = add(mul(aA, aF), aC);
-    const u64 q1 = fp::red128(fp::wide(aA, bF) + fp::wide(bA, aF) + bC);
+    u64 q0, q1;
+    if (HC != 0) {
+        const u64 aC = at_t(C0, C2, t), bC = at_t(sub(C1, C0), sub(C3, C2), t);
+        q0 = add(mul(aA, aF), aC);
+        q1 = fp::red128(fp::wide(aA, bF) + fp::wide(bA, aF) + bC);
+    } else {
+        q0 = mul(aA, aF);
+        q1 = fp::red128(fp::wide(aA, bF) + fp::wide(bA, aF));
+    }
     const u64 q2 = mul(bA, bF);
     const bool on = j < 3;
     acc.g = add(acc.g, on ? g : 0);
@@ -817,10 +850,13 @@ __device__ __forceinline__ void level0(u32 ph, u64 v1, u64 sA, u64 sC, u64 &A, u
 }
 
 // Level-0 tables of an omega phase and round 0; a thread takes a pair of
-// wires.  wire(x, sA, sC) gives the sums of wire x's gates.
-template <typename Wire>
-__device__ __forceinline__ void level0_round(u32 ph, u32 hasC, u64 npairs, const u64 *F, u64 *At, u64 *Ct,
+// wires.  wire(x, sA, sC) gives the sums of wire x's gates.  GK, PH: the
+// gate mix and phase when known at compile time (-1, 0: ph and hasC).
+template <int GK, int PH, typename Wire>
+__device__ __forceinline__ void level0_round(u32 ph_rt, u32 hasC_rt, u64 npairs, const u64 *F, u64 *At, u64 *Ct,
                                              const ProofPtrs &pp, const Ctx &c, u64 *row, Wire wire) {
+    const u32 ph = PH > 0 ? (u32)PH : ph_rt;
+    const bool hasC = GK >= 0 ? GK != 1 : hasC_rt != 0;
     const u64 v1 = ph == 2 ? pp.state[1] : 0;
     u64 acc[3] = {0, 0, 0};
     for (u64 m = c.gtid; m < npairs; m += c.gstride) {
@@ -829,13 +865,21 @@ __device__ __forceinline__ void level0_round(u32 ph, u32 hasC, u64 npairs, const
         for (int h = 0; h < 2; h++) {
             u64 sA, sC;
             wire(2 * m + h, sA, sC);
-            level0(ph, v1, sA, sC, A[h], C[h]);
+            if (GK == 1 && ph == 2) {  // MUL gates only: sA is zero
+                A[h] = mul(v1, sC);
+                C[h] = 0;
+            } else {
+                level0(ph, v1, sA, sC, A[h], C[h]);
+            }
             if (!hasC) C[h] = 0;
         }
         st2(At, 2 * m, A[0], A[1]);
         if (hasC) st2(Ct, 2 * m, C[0], C[1]);
         const u64x2 f = ld2(F, 2 * m);
-        table_terms(A[0], A[1], C[0], C[1], f.x, f.y, acc);
+        if (GK == 1)
+            table_terms<0>(A[0], A[1], C[0], C[1], f.x, f.y, acc);
+        else
+            table_terms(A[0], A[1], C[0], C[1], f.x, f.y, acc);
     }
     block_store<3>(acc, row);
 }
@@ -900,13 +944,18 @@ __device__ __forceinline__ void step_wt0(const Wt0Args &a, const ProofPtrs &pp, 
     block_store<3>(acc, row);
 }
 
+// GK, PH: the gate mix and phase, compile-time (one kernel each) or -1, 0.
+template <int GK, int PH>
 __device__ __forceinline__ void step_wa0(const Wa0Args &a, const ProofPtrs &pp, const Ctx &c, u64 *row) {
-    level0_round(a.ph, a.hasC, a.npairs, a.Vn, a.A, a.C, pp, c, row, [&](u64 x, u64 &sA, u64 &sC) {
-        wire_sums(a, a.rowptr[x], a.rowptr[x + 1], sA, sC);
+    level0_round<GK, PH>(a.ph, a.hasC, a.npairs, a.Vn, a.A, a.C, pp, c, row, [&](u64 x, u64 &sA, u64 &sC) {
+        wire_sums<GK, PH>(a, a.rowptr[x], a.rowptr[x + 1], sA, sC);
     });
 }
 
+// HC: whether the layer has a C table, compile-time (one kernel each) or -1.
+template <int HC>
 __device__ __forceinline__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row) {
+    const bool hasC = HC >= 0 ? HC != 0 : a.hasC != 0;
     const u64 r0 = c.r, r1 = c.r2, r01 = mul(r0, r1);
     QuadAcc acc;
     const u32 pend = a.pend;
@@ -922,11 +971,11 @@ __device__ __forceinline__ void step_wt(const WtArgs &a, const Ctx &c, u64 *row)
     for (u64 g = c.gtid; (g >> 2) < a.nu; g += c.gstride) {
         const u32 j = (u32)(g & 3);
         const u64 A = foldp(a.A, g), F = foldp(a.F, g);
-        const u64 C = a.hasC ? foldp(a.C, g) : 0;
+        const u64 C = hasC ? foldp(a.C, g) : 0;
         a.An[g] = A;
         a.Fn[g] = F;
-        if (a.hasC) a.Cn[g] = C;
-        table_quad(j, A, C, F, a.hasC != 0, acc);
+        if (hasC) a.Cn[g] = C;
+        table_quad<HC>(j, A, C, F, hasC, acc);
     }
     table_quad_store((u32)(c.gtid & 3), acc, row);
 }
@@ -1746,8 +1795,8 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_LINE: step_line(sd.u.line, c, row); break;
         case ST_WAGG: step_wagg(sd.u.wagg, pp, c); break;
         case ST_WT0: step_wt0(sd.u.wt0, pp, c, row); break;
-        case ST_WA0: step_wa0(sd.u.wa0, pp, c, row); break;
-        case ST_WT: step_wt(sd.u.wt, c, row); break;
+        case ST_WA0: step_wa0<KIND == ST_WA0 ? GK : -1, KIND == ST_WA0 ? PH : 0>(sd.u.wa0, pp, c, row); break;
+        case ST_WT: step_wt<KIND == ST_WT ? GK : -1>(sd.u.wt, c, row); break;
         case ST_WTAIL: step_wtail(sd.u.wtail, pp, c, ti.drew, ti.st); break;
         case ST_PTAIL: step_ptail(sd.u.ptail, pp, c, ti.drew, ti.st, ti.have_c, ti.C); break;
         case ST_FINISH: step_finish(sd.u.finish, c); break;
@@ -1811,6 +1860,7 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
     // with events: the dispatch itself is timed (hipExtLaunchKernelGGL)
 #define L1(K) hipExtLaunchKernelGGL((k_step_one<K, -1, 0>), g, b, 0, st, ev0, ev1, 0, sd)
 #define LW(G, PH) hipExtLaunchKernelGGL((k_step_one<ST_W, G, PH>), g, b, 0, st, ev0, ev1, 0, sd)
+#define LK(K, G, PH) hipExtLaunchKernelGGL((k_step_one<K, G, PH>), g, b, 0, st, ev0, ev1, 0, sd)
     switch (sd.kind) {
         case ST_LOAD: L1(ST_LOAD); break;
         case ST_EVAL: L1(ST_EVAL); break;
@@ -1830,8 +1880,18 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_SGE: L1(ST_SGE); break;
         case ST_WAGG: L1(ST_WAGG); break;
         case ST_WT0: L1(ST_WT0); break;
-        case ST_WA0: L1(ST_WA0); break;
-        case ST_WT: L1(ST_WT); break;
+        case ST_WA0: {  // one kernel per gate mix and phase
+            const u32 k = sd.u.wa0.kind, ph = sd.u.wa0.ph;
+            if (ph == 1) {
+                if (k == 0) LK(ST_WA0, 0, 1); else if (k == 1) LK(ST_WA0, 1, 1); else LK(ST_WA0, 2, 1);
+            } else {
+                if (k == 0) LK(ST_WA0, 0, 2); else if (k == 1) LK(ST_WA0, 1, 2); else LK(ST_WA0, 2, 2);
+            }
+            break;
+        }
+        case ST_WT:  // one kernel with a C table, one without
+            if (sd.u.wt.hasC) LK(ST_WT, 1, 0); else LK(ST_WT, 0, 0);
+            break;
         case ST_WTAIL: L1(ST_WTAIL); break;
         case ST_PTAIL: L1(ST_PTAIL); break;
         case ST_FINISH: L1(ST_FINISH); break;
@@ -1842,6 +1902,7 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
     }
 #undef L1
 #undef LW
+#undef LK
     return hipGetLastError();
 }
 

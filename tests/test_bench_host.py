@@ -28,7 +28,12 @@ def test_step_kinds_follow_the_enum():
     body = body[body.index("{") + 1:body.index("};")]
     names = re.findall(r"^\s*ST_([A-Z0-9]+)", body, re.M)
     assert [n.lower() for n in names][:len(bench.STEP_KINDS)] == bench.STEP_KINDS
-    assert bench.rocprof_kernel_name("step_wt") == "void gkr::k_step_one<12u, -1, 0>(gkr::StepDesc)"
+    assert bench.rocprof_kernel_name("step_wt") == "void gkr::k_step_one<12u, *, *>(gkr::StepDesc)"
+    # every specialization of a kind is its kernel, no other kind's
+    assert bench.kernel_matches("void gkr::k_step_one<12u, 1, 0>(gkr::StepDesc)", "step_wt")
+    assert bench.kernel_matches("void gkr::k_step_one<12u, 0, 0>(gkr::StepDesc)", "step_wt")
+    assert not bench.kernel_matches("void gkr::k_step_one<1u, -1, 0>(gkr::StepDesc)", "step_wt")
+    assert not bench.kernel_matches("void gkr::k_step_one<12u, 1, 0>(gkr::StepDesc)", "step_start")
 
 
 def _counter_csv(path, counter, rows):
@@ -40,7 +45,7 @@ def _counter_csv(path, counter, rows):
 
 
 def test_traffic_summary_scales_each_counter_by_the_copy(tmp_path):
-    k = bench.rocprof_kernel_name("step_wt")
+    k = "void gkr::k_step_one<12u, 1, 0>(gkr::StepDesc)"
     cp = 1 << 30  # the calibration copy moves 1 GiB each way
     # FETCH_SIZE reads half of the copy (factor 2), WRITE_SIZE all of it
     _counter_csv(tmp_path / "f", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 512 * 1024), (k, 100.0), (k, 300.0)])
