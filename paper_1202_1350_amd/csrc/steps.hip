@@ -372,10 +372,14 @@ __device__ __forceinline__ void p_quad(u32 j, u64 v0, u64 v1, u64 v2, u64 v3, u6
     y = add(y, s ? 0 : p2);
 }
 
+// FIRST: whether this is the phase's first step, compile-time (1, 0; one
+// kernel each) or -1 to take a.first.
+template <int FIRST>
 __device__ __forceinline__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
+    const bool first = FIRST >= 0 ? FIRST != 0 : a.first != 0;
     const u64 mask = (1ull << a.L) - 1;
     auto beta0 = [&](u64 m) { return mul(a.zlo[m & mask], a.zhi[m >> a.L]); };  // B_0[m]
-    if (a.first && !a.look) {
+    if (first && !a.look) {
         // one round (s = 1)
         u64 acc[2] = {0, 0};
         for (u64 m = c.gtid; m < a.nu; m += c.gstride) {
@@ -395,7 +399,7 @@ __device__ __forceinline__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
         const u64 u = g >> 2;
         const u32 j = (u32)(g & 3);
         u64 v, bq;  // entry 4u + j of this step's level; B of that level at pair 2u + j/2
-        if (a.first) {
+        if (first) {
             v = a.Vsrc[g];
             bq = beta0(2 * u + (j >> 1));  // lanes 0, 1: B_0[2u]; lanes 2, 3: B_0[2u+1]
         } else {
@@ -406,7 +410,7 @@ __device__ __forceinline__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
         }
         const u64 v0 = quad_get<0>(v), v1 = quad_get<1>(v), v2 = quad_get<2>(v), v3 = quad_get<3>(v);
         u64 b0, b1;
-        if (a.first) {
+        if (first) {
             b0 = quad_get<0>(bq);
             b1 = quad_get<2>(bq);
         } else {
@@ -666,8 +670,11 @@ __device__ __forceinline__ u64 bperm64(u64 v, u32 l) {
 // chunk's sum as the scan at its last position minus the scan just before
 // its first.  Terms as in wire_sums (beta(z, a*), which multiplies every
 // term, comes with the lo half of a*'s eq table).
+// GK, PH: the gate mix and phase, compile-time (one kernel each) or -1, 0.
+template <int GK, int PH>
 __device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp, const Ctx &c) {
     (void)pp;  // beta(z, a*) is in the lo half of a*'s eq table
+    const u32 kind = GK >= 0 ? (u32)GK : a.kind, ph = PH > 0 ? (u32)PH : a.ph;
     const u32 lane = threadIdx.x & 63;
     const u64 amask = (1ull << a.La) - 1, bmask = (1ull << a.Lb) - 1;
     const u64 nwaves = c.gstride >> 6;
@@ -680,9 +687,9 @@ __device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp
 #pragma unroll 4
             for (u32 q = base + lane; q < end; q += 64) {
                 const u32 g = a.perm[q], o = a.oths[q];
-                const bool ismul = a.kind == 1 || (a.kind == 2 && a.types[q]);
+                const bool ismul = kind == 1 || (kind == 2 && a.types[q]);
                 u64 w = mul(a.alo[g & amask], a.ahi[g >> a.La]);
-                if (a.ph == 1) {
+                if (ph == 1) {
                     const u64 wy = mul(w, a.Vn[o]);
                     sA = add(sA, ismul ? wy : w);
                     sC = add(sC, ismul ? 0 : wy);
@@ -704,9 +711,9 @@ __device__ __forceinline__ void step_wagg(const WaggArgs &a, const ProofPtrs &pp
         u64 vA = 0, vC = 0;
         if (p < end) {
             const u32 g = a.perm[p], o = a.oths[p];
-            const bool ismul = a.kind == 1 || (a.kind == 2 && a.types[p]);
+            const bool ismul = kind == 1 || (kind == 2 && a.types[p]);
             u64 w = mul(a.alo[g & amask], a.ahi[g >> a.La]);
-            if (a.ph == 1) {
+            if (ph == 1) {
                 const u64 wy = mul(w, a.Vn[o]);
                 vA = ismul ? wy : w;
                 vC = ismul ? 0 : wy;
@@ -1088,8 +1095,11 @@ __device__ __forceinline__ u64 tail_state(const ProofPtrs &pp, u32 c0, u32 drew,
 // (last = 1) or v2.  Round k's message is, at t = 0, 1, 2, the sum over its
 // pairs of A_t F_t + C_t with X_t the line through the pair.  Returns the
 // RNG state after the last round.
-__device__ __forceinline__ u64 wtail_rounds(u64 *A, u64 *Ct, u64 *F, u32 n, bool hc, u64 st, u64 *msgp, u32 c0,
+// HC: whether the phase has a C table, compile-time (1, 0) or -1 to take hc_rt.
+template <int HC = -1>
+__device__ __forceinline__ u64 wtail_rounds(u64 *A, u64 *Ct, u64 *F, u32 n, bool hc_rt, u64 st, u64 *msgp, u32 c0,
                                             u32 last, u64 *vout, const ProofPtrs &pp, u64 *rec = nullptr) {
+    const bool hc = HC >= 0 ? HC != 0 : hc_rt;
     const u32 tid = threadIdx.x, lane = tid & 63;
     const u32 w = (u32)__builtin_amdgcn_readfirstlane((int)(tid >> 6));  // wave-uniform
     const u32 L = 31 - (u32)__builtin_clz(n);
@@ -1105,7 +1115,7 @@ __device__ __forceinline__ u64 wtail_rounds(u64 *A, u64 *Ct, u64 *F, u32 n, bool
                 pf = ld2(F, 2 * q);
                 if (hc) pc = ld2(Ct, 2 * q);
                 u64 t[3] = {0, 0, 0};
-                table_terms(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
+                table_terms<HC == 0 ? 0 : 1>(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
                 chunk_sums(t, q >> 6, lane);
             }
             __syncthreads();  // message k's sums are complete
@@ -1126,9 +1136,15 @@ __device__ __forceinline__ u64 wtail_rounds(u64 *A, u64 *Ct, u64 *F, u32 n, bool
                     if (hc) pc = ld2(Ct, 2 * q);
                 }
                 u64 term;
-                if (w == 0) term = add(mul(pa.x, pf.x), pc.x);
-                else if (w == 1) term = add(mul(pa.y, pf.y), pc.y);
-                else term = add(mul(line_at<2>(pa.x, pa.y), line_at<2>(pf.x, pf.y)), line_at<2>(pc.x, pc.y));
+                if (HC == 0) {
+                    if (w == 0) term = mul(pa.x, pf.x);
+                    else if (w == 1) term = mul(pa.y, pf.y);
+                    else term = mul(line_at<2>(pa.x, pa.y), line_at<2>(pf.x, pf.y));
+                } else {
+                    if (w == 0) term = add(mul(pa.x, pf.x), pc.x);
+                    else if (w == 1) term = add(mul(pa.y, pf.y), pc.y);
+                    else term = add(mul(line_at<2>(pa.x, pa.y), line_at<2>(pf.x, pf.y)), line_at<2>(pc.x, pc.y));
+                }
                 own = w == 0 ? pa : (w == 1 ? pc : pf);
                 const u64 v = wave_sum63_lazy(term);
                 if (lane == 63) mp[w][TAIL_CHUNKS + k] = v;
@@ -1155,10 +1171,12 @@ __device__ __forceinline__ u64 wtail_rounds(u64 *A, u64 *Ct, u64 *F, u32 n, bool
     return st;
 }
 
+// HC: whether the phase has a C table, compile-time (one kernel each) or -1.
+template <int HC>
 __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &pp, const Ctx c, u32 drew, u64 st0) {
     u64 *tab = tail_lds();
     const u32 tid = threadIdx.x;
-    const bool hc = a.hasC != 0;
+    const bool hc = HC >= 0 ? HC != 0 : a.hasC != 0;
     const u32 n = 1u << (a.sp - a.k0);  // entries of level k0, at most TAIL_LIM
     for (u32 e = tid; e < n; e += SBLOCK) {
         tab[e] = tail_entry(a.A, e, a.pend, c);
@@ -1167,7 +1185,7 @@ __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &
     }
     const u64 st = tail_state(pp, a.c0, drew, st0);
     __syncthreads();
-    wtail_rounds(tab, tab + TAIL_TAB, tab + 2 * TAIL_TAB, n, hc, st, a.msg, a.c0, a.last, a.vout, pp);
+    wtail_rounds<HC>(tab, tab + TAIL_TAB, tab + 2 * TAIL_TAB, n, hc, st, a.msg, a.c0, a.last, a.vout, pp);
 }
 
 // A whole omega phase of a small layer in one workgroup: the eq table of
@@ -1774,7 +1792,7 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_EQ:
             step_eq(sd.u.eq, c, sd.u.eq.point == PT_Z ? s_pt + sd.u.eq.base : s_pt, pp);
             break;
-        case ST_P: step_p(sd.u.p, c, row); break;
+        case ST_P: step_p<KIND == ST_P ? GK : -1>(sd.u.p, c, row); break;
         case ST_W: {
             const WArgs &a = sd.u.w;
             if (GK >= 0) {
@@ -1793,11 +1811,11 @@ __device__ __forceinline__ void run_step(const StepDesc &sd, u32 lb) {
         case ST_FOLD: step_fold(sd.u.fold, c); break;
         case ST_LT: step_lt(sd.u.lt, c, s_pt, s_pt + sd.u.lt.sp); break;
         case ST_LINE: step_line(sd.u.line, c, row); break;
-        case ST_WAGG: step_wagg(sd.u.wagg, pp, c); break;
+        case ST_WAGG: step_wagg<KIND == ST_WAGG ? GK : -1, KIND == ST_WAGG ? PH : 0>(sd.u.wagg, pp, c); break;
         case ST_WT0: step_wt0(sd.u.wt0, pp, c, row); break;
         case ST_WA0: step_wa0<KIND == ST_WA0 ? GK : -1, KIND == ST_WA0 ? PH : 0>(sd.u.wa0, pp, c, row); break;
         case ST_WT: step_wt<KIND == ST_WT ? GK : -1>(sd.u.wt, c, row); break;
-        case ST_WTAIL: step_wtail(sd.u.wtail, pp, c, ti.drew, ti.st); break;
+        case ST_WTAIL: step_wtail<KIND == ST_WTAIL ? GK : -1>(sd.u.wtail, pp, c, ti.drew, ti.st); break;
         case ST_PTAIL: step_ptail(sd.u.ptail, pp, c, ti.drew, ti.st, ti.have_c, ti.C); break;
         case ST_FINISH: step_finish(sd.u.finish, c); break;
         case ST_WSMALL: step_wsmall(sd.u.wsmall, pp, c); break;
@@ -1866,7 +1884,9 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_EVAL: L1(ST_EVAL); break;
         case ST_START: L1(ST_START); break;
         case ST_EQ: L1(ST_EQ); break;
-        case ST_P: L1(ST_P); break;
+        case ST_P:  // one kernel for the phase's first step, one for the others
+            if (sd.u.p.first) LK(ST_P, 1, 0); else LK(ST_P, 0, 0);
+            break;
         case ST_W:
             if (sd.u.w.ph == 1) {
                 if (sd.u.w.kind == 0) LW(0, 1); else if (sd.u.w.kind == 1) LW(1, 1); else LW(2, 1);
@@ -1878,7 +1898,15 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_LT: L1(ST_LT); break;
         case ST_LINE: L1(ST_LINE); break;
         case ST_SGE: L1(ST_SGE); break;
-        case ST_WAGG: L1(ST_WAGG); break;
+        case ST_WAGG: {  // one kernel per gate mix and phase
+            const u32 k = sd.u.wagg.kind, ph = sd.u.wagg.ph;
+            if (ph == 1) {
+                if (k == 0) LK(ST_WAGG, 0, 1); else if (k == 1) LK(ST_WAGG, 1, 1); else LK(ST_WAGG, 2, 1);
+            } else {
+                if (k == 0) LK(ST_WAGG, 0, 2); else if (k == 1) LK(ST_WAGG, 1, 2); else LK(ST_WAGG, 2, 2);
+            }
+            break;
+        }
         case ST_WT0: L1(ST_WT0); break;
         case ST_WA0: {  // one kernel per gate mix and phase
             const u32 k = sd.u.wa0.kind, ph = sd.u.wa0.ph;
@@ -1892,7 +1920,9 @@ hipError_t launch_step(hipStream_t st, const StepDesc &sd, hipEvent_t ev0, hipEv
         case ST_WT:  // one kernel with a C table, one without
             if (sd.u.wt.hasC) LK(ST_WT, 1, 0); else LK(ST_WT, 0, 0);
             break;
-        case ST_WTAIL: L1(ST_WTAIL); break;
+        case ST_WTAIL:  // one kernel with a C table, one without
+            if (sd.u.wtail.hasC) LK(ST_WTAIL, 1, 0); else LK(ST_WTAIL, 0, 0);
+            break;
         case ST_PTAIL: L1(ST_PTAIL); break;
         case ST_FINISH: L1(ST_FINISH); break;
         case ST_WSMALL: L1(ST_WSMALL); break;
