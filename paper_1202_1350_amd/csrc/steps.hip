@@ -158,13 +158,17 @@ struct TailIn {
     u32 drew, have_c;
 };
 
-__device__ __forceinline__ u64 fold1(u64 x0, u64 x1, u64 r) { return add(x0, mul(r, sub(x1, x0))); }
+__device__ __forceinline__ u64 fold1(u64 x0, u64 x1, u64 r) {
+    return fp::red128((u128)x0 + fp::wide(r, x1 + (fp::P - x0)));  // x1 - x0 + p < 2 p, unreduced
+}
 
 // fold1(fold1(x0, x1, r0), fold1(x2, x3, r0), r1) = x0 + r0 (x1 - x0) +
 // r1 (x2 - x0) + r0 r1 ((x3 - x2) - (x1 - x0)), summed in 128 bits
-// (< 2^124) and reduced once; r01 = r0 r1.
+// and reduced once; r01 = r0 r1.  Inputs canonical.
 __device__ __forceinline__ u64 fold2(u64 x0, u64 x1, u64 x2, u64 x3, u64 r0, u64 r1, u64 r01) {
-    const u64 d1 = sub(x1, x0), d2 = sub(x2, x0), d3 = sub(sub(x3, x2), d1);
+    // the differences unreduced: d1, d2 = x1 - x0 + p, x2 - x0 + p < 2 p and
+    // d3 = x3 - x2 - x1 + x0 + 2 p < 4 p, so the sum stays below 8 p^2 + p < 2^125
+    const u64 d1 = x1 + (fp::P - x0), d2 = x2 + (fp::P - x0), d3 = (x3 + x0) + (2 * fp::P - x1 - x2);
     return fp::red128((u128)x0 + fp::wide(r0, d1) + fp::wide(r1, d2) + fp::wide(r01, d3));
 }
 
@@ -348,6 +352,17 @@ __device__ __forceinline__ void step_eq(const EqArgs &a, const Ctx &c, const u64
     }
 }
 
+// x1 - x0 + p, not reduced (canonical x0, x1: below 2 p).
+__device__ __forceinline__ u64 diff_lz(u64 x1, u64 x0) { return x1 + (fp::P - x0); }
+
+// x mod p as red128 computes it, without the final subtraction: a value
+// below p + 4 that is congruent to x.
+__device__ __forceinline__ u64 red128_lz(u128 x) {
+    const u64 lo = (u64)x, hi = (u64)(x >> 64);
+    u64 s = (lo & fp::P) + (lo >> 61) + ((hi << 3) & fp::P) + (hi >> 58);  // < 2^63
+    return (s & fp::P) + (s >> 61);
+}
+
 // Two-round steps give each quad (four consecutive entries of the level
 // they sum over) to four adjacent lanes: lane j of the quad holds entry j,
 // loads and stores stay coalesced, the quad's values are exchanged with DPP
@@ -360,16 +375,19 @@ __device__ __forceinline__ void step_eq(const EqArgs &a, const Ctx &c, const u64
 // (1), U0 and U1 (2), W0 and W1 (3): two products each, operands chosen by
 // j so that all lanes run the same instructions.  x: its first (or only)
 // sum, y: its second.
+// bb and the differences stay unreduced (below 2 p), each product is
+// reduced to below p + 4, and x, y are kept below p + 4 (canonical only
+// when the step stores them).
 __device__ __forceinline__ void p_quad(u32 j, u64 v0, u64 v1, u64 v2, u64 v3, u64 b0, u64 b1,
                                        u64 &x, u64 &y) {
-    const u64 bb = add(b0, b1);
+    const u64 bb = b0 + b1;
     const bool s = j < 2;
     const u64 m1 = s ? b0 : bb, m2 = s ? b1 : bb;
     const u64 o1 = j == 0 ? v0 : (j == 1 ? v1 : (j == 2 ? v0 : v2));
-    const u64 o2 = j == 0 ? v2 : (j == 1 ? v3 : (j == 2 ? sub(v1, v0) : sub(v3, v2)));
-    const u64 p1 = mul(m1, o1), p2 = mul(m2, o2);
-    x = add(x, s ? add(p1, p2) : p1);
-    y = add(y, s ? 0 : p2);
+    const u64 o2 = j == 0 ? v2 : (j == 1 ? v3 : (j == 2 ? diff_lz(v1, v0) : diff_lz(v3, v2)));
+    const u64 p1 = red128_lz(fp::wide(m1, o1)), p2 = red128_lz(fp::wide(m2, o2));
+    x = fp::fold64(x + (s ? p1 + p2 : p1));
+    y = fp::fold64(y + (s ? 0 : p2));
 }
 
 // FIRST: whether this is the phase's first step, compile-time (1, 0; one
@@ -421,6 +439,8 @@ __device__ __forceinline__ void step_p(const PArgs &a, const Ctx &c, u64 *row) {
         p_quad(j, v0, v1, v2, v3, b0, b1, x, y);
     }
     // rows: S0, S1, U0, U1, W0, W1
+    x = fp::canon(x);
+    y = fp::canon(y);
     const u32 j = (u32)(c.gtid & 3);
     u64 acc[6] = {j == 0 ? x : 0, j == 1 ? x : 0, j == 2 ? x : 0, j == 2 ? y : 0, j == 3 ? x : 0,
                   j == 3 ? y : 0};
@@ -757,7 +777,7 @@ __device__ __forceinline__ void table_terms(u64 A0, u64 A1, u64 C0, u64 C1, u64 
 
 // One quad of level-k tables, held one entry per lane by four adjacent
 // lanes.  Lane t < 3 adds, for its t, round k's value over the quad's two
-// pairs and round k+1's three coefficients (lane 3 adds nothing): the quad
+// pairs and round k+1's three coefficients (lane 3's sums are dropped): the quad
 // folds to the pair (X0 + r dX0, X2 + r dX2), dX0 = X1 - X0, dX2 = X3 - X2,
 // whose value at t is a_t + r b_t with a = (X0, X2, 2 X2 - X0),
 // b = (dX0, dX2, 2 dX2 - dX0):
@@ -768,13 +788,21 @@ struct QuadAcc {
     u64 g = 0, q0 = 0, q1 = 0, q2 = 0;
 };
 
-// x at t in {0, 1, 2} on the line through (0, x0), (1, x1)
-__device__ __forceinline__ u64 at_t(u64 x0, u64 x1, u32 t) {
-    const u64 x2 = sub(add(x1, x1), x0);
+
+// x at t in {0, 1, 2} on the line through (0, x0), (1, x1), not reduced:
+// with x0, x1 < K p the value is below 3 K p (K <= 2: below 2^64).  It only
+// feeds 128-bit product sums, which red128 reduces whatever their size.
+template <int K>
+__device__ __forceinline__ u64 at_t_lz(u64 x0, u64 x1, u32 t) {
+    static_assert(K == 1 || K == 2, "3 K p < 2^64");
+    const u64 x2 = 2 * x1 + ((u64)K * fp::P - x0);
     return t == 0 ? x0 : (t == 1 ? x1 : x2);
 }
 
-// HC: whether the layer has a C table (1, 0), or -1 to take hasC.
+// HC: whether the layer has a C table (1, 0), or -1 to take hasC.  The line
+// values and differences stay unreduced (below 6 p); each of g, q0, q1, q2
+// is one 128-bit sum of at most two products and two such values, reduced
+// once (below 2^128: 2 (3p)(6p) + 9p < 2^127.3).
 template <int HC>
 __device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC, QuadAcc &acc) {
     const bool hc = HC >= 0 ? HC != 0 : hasC;
@@ -788,29 +816,24 @@ __device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC
         C3 = quad_get<3>(C);
     }
     const u32 t = j < 3 ? j : 2;
-    // round k at t: pairs (X0, X1) and (X2, X3); products summed in 128 bits
-    // and reduced once per value
-    u128 gs = fp::wide(at_t(A0, A1, t), at_t(F0, F1, t)) + fp::wide(at_t(A2, A3, t), at_t(F2, F3, t));
-    if (HC != 0) gs += (u128)(at_t(C0, C1, t) + at_t(C2, C3, t));  // (zero without a C table)
-    const u64 g = fp::red128(gs);
+    // round k at t: pairs (X0, X1) and (X2, X3)
+    u128 gs = fp::wide(at_t_lz<1>(A0, A1, t), at_t_lz<1>(F0, F1, t)) +
+              fp::wide(at_t_lz<1>(A2, A3, t), at_t_lz<1>(F2, F3, t));
+    if (HC != 0) gs += (u128)at_t_lz<1>(C0, C1, t) + at_t_lz<1>(C2, C3, t);  // (zero without a C table)
     // round k+1's coefficients at t
-    const u64 aA = at_t(A0, A2, t), bA = at_t(sub(A1, A0), sub(A3, A2), t);
-    const u64 aF = at_t(F0, F2, t), bF = at_t(sub(F1, F0), sub(F3, F2), t);
-    u64 q0, q1;
+    const u64 aA = at_t_lz<1>(A0, A2, t), bA = at_t_lz<2>(diff_lz(A1, A0), diff_lz(A3, A2), t);
+    const u64 aF = at_t_lz<1>(F0, F2, t), bF = at_t_lz<2>(diff_lz(F1, F0), diff_lz(F3, F2), t);
+    u128 s0 = fp::wide(aA, aF), s1 = fp::wide(aA, bF) + fp::wide(bA, aF);
     if (HC != 0) {
-        const u64 aC = at_t(C0, C2, t), bC = at_t(sub(C1, C0), sub(C3, C2), t);
-        q0 = add(mul(aA, aF), aC);
-        q1 = fp::red128(fp::wide(aA, bF) + fp::wide(bA, aF) + bC);
-    } else {
-        q0 = mul(aA, aF);
-        q1 = fp::red128(fp::wide(aA, bF) + fp::wide(bA, aF));
+        s0 += at_t_lz<1>(C0, C2, t);
+        s1 += at_t_lz<2>(diff_lz(C1, C0), diff_lz(C3, C2), t);
     }
-    const u64 q2 = mul(bA, bF);
-    const bool on = j < 3;
-    acc.g = add(acc.g, on ? g : 0);
-    acc.q0 = add(acc.q0, on ? q0 : 0);
-    acc.q1 = add(acc.q1, on ? q1 : 0);
-    acc.q2 = add(acc.q2, on ? q2 : 0);
+    const u64 g = red128_lz(gs), q0 = red128_lz(s0), q1 = red128_lz(s1), q2 = red128_lz(fp::wide(bA, bF));
+    // sums kept below p + 4 (lane 3's are never stored, see table_quad_store)
+    acc.g = fp::fold64(acc.g + g);
+    acc.q0 = fp::fold64(acc.q0 + q0);
+    acc.q1 = fp::fold64(acc.q1 + q1);
+    acc.q2 = fp::fold64(acc.q2 + q2);
 }
 
 // Rows of a two-round table step: G(0..2), Q0(0..2), Q1(0..2), Q2(0..2);
@@ -821,7 +844,7 @@ __device__ __forceinline__ void table_quad(u32 j, u64 A, u64 C, u64 F, bool hasC
 // four rows of the wave, LDS the waves.
 __device__ __forceinline__ void table_quad_store(u32 j, const QuadAcc &q, u64 *row) {
     __shared__ u64 sm[NWAVES][12];
-    u64 v[4] = {q.g, q.q0, q.q1, q.q2};
+    u64 v[4] = {fp::canon(q.g), fp::canon(q.q0), fp::canon(q.q1), fp::canon(q.q2)};  // (below p + 4)
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         v[k] = add(v[k], dpp64<0x114, 0xf>(v[k]));  // row_shr:4
