@@ -1412,7 +1412,7 @@ __device__ __forceinline__ void fold_poly(const u64 (&a)[D + 1], const u64 (&b)[
 #pragma unroll
     for (int j = 0; j <= D + 1; j++) {
         const int jj = j <= D ? j : D;  // (in range for the unrolled loads)
-        const u64 Dj = j <= D ? sub(b[jj], a[jj]) : 0;
+        const u64 Dj = j <= D ? diff_lz(b[jj], a[jj]) : 0;  // (< 2p: the sum stays below 2^125)
         const u64 a0 = j <= D ? a[jj] : 0;
         o[j] = fp::red128((u128)a0 + fp::wide(bk, Dj) + fp::wide(dk, Dprev));
         Dprev = Dj;
@@ -1438,8 +1438,8 @@ __device__ __forceinline__ u64 *lds_fold(u64 *src, u64 *dst, u32 M, u32 d, u32 k
             const u32 m = it / nc, j = it - m * nc;
             const u64 *P0 = src + (2 * m) * (d + 1), *P1 = P0 + (d + 1);
             const u64 a0 = j <= d ? P0[j] : 0;
-            const u64 Dj = j <= d ? sub(P1[j], P0[j]) : 0;
-            const u64 Dm = j >= 1 ? sub(P1[j - 1], P0[j - 1]) : 0;
+            const u64 Dj = j <= d ? diff_lz(P1[j], P0[j]) : 0;  // (< 2p: the sum stays below 2^125)
+            const u64 Dm = j >= 1 ? diff_lz(P1[j - 1], P0[j - 1]) : 0;
             dst[it] = fp::red128((u128)a0 + fp::wide(b, Dj) + fp::wide(dl, Dm));  // (it = m nc + j)
         }
         __syncthreads();
