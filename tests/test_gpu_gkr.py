@@ -153,6 +153,22 @@ def test_line_by_folding_on_wide_layers():
     check_same(W.f2_circuit(n), W.f2_inputs(n, 43), 43, f"line fold F2 n={n}")
 
 
+def test_extreme_values_through_every_kernel():
+    """Inputs at the ends of the field (all p - 1, all zero, p - 1 and 0 in
+    turn) through layers wide enough for the grid steps, the line fold and
+    the tails, on every omega algorithm: differences, line values and
+    running sums are kept unreduced below fixed multiples of p inside the
+    kernels, and these inputs put the first layers' values at those ends."""
+    n = (1 << 14) + 5
+    for name, x in (("p-1", np.full(n, P - 1, np.uint64)), ("zero", np.zeros(n, np.uint64)),
+                    ("alternating", np.array([P - 1 if i % 2 else 0 for i in range(n)], np.uint64))):
+        check_same(W.f2_circuit(n), x, 3, f"F2 n={n} inputs {name}")
+    rng = random.Random(61)
+    sizes = [3, 300, 5000, 20000]
+    circ = random_circuit(rng, sizes)
+    check_same(circ, np.full(sizes[-1], P - 1, np.uint64), 5, f"mixed {sizes} inputs p-1")
+
+
 def test_c1_f2_1024():
     circ, x, seed = W.c1_f2()
     gc, m = check_same(circ, x, seed, "C1 F2 n=2^10")
