@@ -1089,6 +1089,23 @@ __device__ __forceinline__ u64 line_at(u64 x0, u64 x1) {
     return T == 0 ? x0 : (T == 1 ? x1 : sub(add(x1, x1), x0));
 }
 
+// The three terms of one pair of a tail round, canonical: A(t) F(t) (+ C(t))
+// at t = 0, 1, 2, the values at t = 2 unreduced (below 3p) in one 128-bit
+// sum reduced once.
+template <int HC>
+__device__ __forceinline__ void tail_pair_terms(u64 A0, u64 A1, u64 C0, u64 C1, u64 F0, u64 F1, u64 (&t)[3]) {
+    u128 t0 = fp::wide(A0, F0), t1 = fp::wide(A1, F1);
+    u128 t2 = fp::wide(2 * A1 + (fp::P - A0), 2 * F1 + (fp::P - F0));
+    if (HC != 0) {
+        t0 += C0;
+        t1 += C1;
+        t2 += 2 * C1 + (fp::P - C0);
+    }
+    t[0] = fp::red128(t0);
+    t[1] = fp::red128(t1);
+    t[2] = fp::red128(t2);
+}
+
 // Entry e of the level a tail starts from, folded from memory by the
 // pending challenge(s) of the prologue.
 __device__ __forceinline__ u64 tail_entry(const u64 *X, u32 e, u32 pend, const Ctx &c) {
@@ -1137,8 +1154,8 @@ __device__ __forceinline__ u64 wtail_rounds(u64 *A, u64 *Ct, u64 *F, u32 n, bool
                 pa = ld2(A, 2 * q);
                 pf = ld2(F, 2 * q);
                 if (hc) pc = ld2(Ct, 2 * q);
-                u64 t[3] = {0, 0, 0};
-                table_terms<HC == 0 ? 0 : 1>(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
+                u64 t[3];
+                tail_pair_terms<HC == 0 ? 0 : 1>(pa.x, pa.y, pc.x, pc.y, pf.x, pf.y, t);
                 chunk_sums(t, q >> 6, lane);
             }
             __syncthreads();  // message k's sums are complete
@@ -1158,16 +1175,11 @@ __device__ __forceinline__ u64 wtail_rounds(u64 *A, u64 *Ct, u64 *F, u32 n, bool
                     pf = ld2(F, 2 * q);
                     if (hc) pc = ld2(Ct, 2 * q);
                 }
-                u64 term;
-                if (HC == 0) {
-                    if (w == 0) term = mul(pa.x, pf.x);
-                    else if (w == 1) term = mul(pa.y, pf.y);
-                    else term = mul(line_at<2>(pa.x, pa.y), line_at<2>(pf.x, pf.y));
-                } else {
-                    if (w == 0) term = add(mul(pa.x, pf.x), pc.x);
-                    else if (w == 1) term = add(mul(pa.y, pf.y), pc.y);
-                    else term = add(mul(line_at<2>(pa.x, pa.y), line_at<2>(pf.x, pf.y)), line_at<2>(pc.x, pc.y));
-                }
+                // value w's term; the values at t = 2 unreduced (below 3p), reduced once
+                const u64 a2 = 2 * pa.y + (fp::P - pa.x), f2 = 2 * pf.y + (fp::P - pf.x);
+                u128 tw = w == 0 ? fp::wide(pa.x, pf.x) : (w == 1 ? fp::wide(pa.y, pf.y) : fp::wide(a2, f2));
+                if (HC != 0) tw += w == 0 ? pc.x : (w == 1 ? pc.y : 2 * pc.y + (fp::P - pc.x));
+                const u64 term = fp::red128(tw);
                 own = w == 0 ? pa : (w == 1 ? pc : pf);
                 const u64 v = wave_sum63_lazy(term);
                 if (lane == 63) mp[w][TAIL_CHUNKS + k] = v;
@@ -1285,7 +1297,7 @@ __device__ __forceinline__ u64 ptail_rounds(u64 *V, u64 *B, u32 L, u64 zr, u64 C
             if (tid < half) {
                 pv = ld2(V, 2 * q);
                 const u64 b = B[q];
-                u64 t[3] = {mul(b, pv.x), mul(b, pv.y), mul(b, sub(add(pv.y, pv.y), pv.x))};
+                u64 t[3] = {mul(b, pv.x), mul(b, pv.y), fp::red128(fp::wide(b, 2 * pv.y + (fp::P - pv.x)))};
                 chunk_sums(t, q >> 6, lane);
                 if (tid < half / 2) {  // B at the pairs of the next level
                     const u32 q2 = n - half + tid;
@@ -1305,8 +1317,8 @@ __device__ __forceinline__ u64 ptail_rounds(u64 *V, u64 *B, u32 L, u64 zr, u64 C
                     pv = ld2(V, 2 * q);
                     b = B[q];
                 }
-                const u64 x = w == 0 ? pv.x : (w == 1 ? pv.y : sub(add(pv.y, pv.y), pv.x));
-                const u64 v = wave_sum63_lazy(mul(b, x));
+                const u64 x = w == 0 ? pv.x : (w == 1 ? pv.y : 2 * pv.y + (fp::P - pv.x));  // (t = 2: below 3p)
+                const u64 v = wave_sum63_lazy(fp::red128(fp::wide(b, x)));
                 if (lane == 63) mp[w][TAIL_CHUNKS + k] = v;
                 if (w == 1 && lane < half / 2) {  // B at the pairs of the next level
                     const u32 q2 = n - half + lane;
