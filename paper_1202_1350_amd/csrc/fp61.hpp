@@ -56,9 +56,10 @@ __host__ __device__ __forceinline__ u64 red128(u128 x) {
 // eq(bit, r) = r if bit else 1 - r
 __host__ __device__ __forceinline__ u64 eqbit(u32 bit, u64 r) { return bit ? r : sub(1, r); }
 
-// eq(x, y) = x y + (1 - x)(1 - y)
+// eq(x, y) = x y + (1 - x)(1 - y) = 2 x y + 1 - x - y: one product, the
+// rest added unreduced (2 p + 1 - x - y > 0) and reduced once.
 __host__ __device__ __forceinline__ u64 eq(u64 x, u64 y) {
-    return add(mul(x, y), mul(sub(1, x), sub(1, y)));
+    return red128((wide(x, y) << 1) + (2 * P + 1 - x - y));
 }
 
 __host__ __device__ __forceinline__ u64 pow(u64 a, u64 e) {

@@ -1176,8 +1176,9 @@ __device__ __forceinline__ u64 wtail_rounds(u64 *A, u64 *Ct, u64 *F, u32 n, bool
                     if (hc) pc = ld2(Ct, 2 * q);
                 }
                 // value w's term; the values at t = 2 unreduced (below 3p), reduced once
-                const u64 a2 = 2 * pa.y + (fp::P - pa.x), f2 = 2 * pf.y + (fp::P - pf.x);
-                u128 tw = w == 0 ? fp::wide(pa.x, pf.x) : (w == 1 ? fp::wide(pa.y, pf.y) : fp::wide(a2, f2));
+                const u64 xa = w == 0 ? pa.x : (w == 1 ? pa.y : 2 * pa.y + (fp::P - pa.x));
+                const u64 xf = w == 0 ? pf.x : (w == 1 ? pf.y : 2 * pf.y + (fp::P - pf.x));
+                u128 tw = fp::wide(xa, xf);
                 if (HC != 0) tw += w == 0 ? pc.x : (w == 1 ? pc.y : 2 * pc.y + (fp::P - pc.x));
                 const u64 term = fp::red128(tw);
                 own = w == 0 ? pa : (w == 1 ? pc : pf);
