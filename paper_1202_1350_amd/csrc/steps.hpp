@@ -1,11 +1,12 @@
 // steps.hpp -- the prover as a program of steps, executed by one kernel.
 //
 // A proof is a fixed sequence of steps (evaluation of each layer, the
-// circuit's first small layers whole in one step, then per layer: the eq
-// table of z, the p-phase rounds, the eq table of a*, the two omega-phases,
-// the eq table of b*, the line tables and the line sums).
-// Every step is one grid pass; a step that ends a sum-check round leaves one
-// row of partial sums per workgroup.
+// circuit's first small layers whole in one step that also evaluates them,
+// then per layer: the eq table of z, the p-phase rounds, the eq table of
+// a*, the two omega-phases, the eq table of b*, and the line: V_{i+1}
+// folded along it for layers of 2^11..2^22 entries, else the line points'
+// eq tables and the line sums).  Most steps are one grid pass; a step that
+// ends a sum-check round leaves one row of partial sums per workgroup.
 //
 // Every workgroup of the next step draws the round's challenge from the
 // same SplitMix64 state (the verifier's coins do not depend on the
