@@ -225,7 +225,7 @@ struct LineArgs {
     u32 sp, L, M, T, chunk_blocks, ch;
     const u64 *V, *lo, *hl, *hh;
 };
-// Line of a layer with 2^11 <= 2^s' <= 2^22 by folding (ST_LFOLD):
+// Line of a layer with 2^11 <= 2^s' <= 2^32 by folding (ST_LFOLD):
 // h(t) = ~V_{i+1}(b* + t (c* - b*)) is a polynomial of degree s' in t; V is
 // folded coordinate by coordinate, each entry pair becoming a polynomial one
 // degree higher.  With D = tb + 9, workgroup g folds entries [g 2^D,
@@ -234,15 +234,17 @@ struct LineArgs {
 // t = 2..s' as rows: value j in row (j / ROW_STRIDE) nwg + g, column
 // j % ROW_STRIDE (nwg workgroups).  ST_FINISH adds the rows up into h(2..s')
 // as it does for the line sums' rows.
-constexpr u32 LFOLD_MIN = 11, LFOLD_MAX = 22;
-// Entries a thread folds, 2^tb: 128 to 256 workgroups from 2^17 entries up
-// (a workgroup's time is set mostly by its LDS levels, not by tb), and as
-// many as there are below.
+constexpr u32 LFOLD_MIN = 11, LFOLD_MAX = 32;
+// Entries a thread folds, 2^tb: 128 to 256 workgroups from 2^17 to 2^22
+// entries (a workgroup's time is set mostly by its LDS levels, not by tb), as
+// many as there are below, and 2^(s' - 14) above (tb = 5 at most: more
+// polynomials in registers would spill).
 constexpr u32 lfold_tb(u32 sp) { return sp <= 17 ? 1 : sp == 18 ? 2 : sp <= 20 ? 3 : sp == 21 ? 4 : 5; }
 static_assert(LFOLD_MIN >= 1 + 9, "a workgroup folds at least 2^(1 + 9) entries");
 constexpr u32 lfold_wg(u32 sp) { return 1u << (sp - lfold_tb(sp) - 9); }
 constexpr u32 LFOLD_CHUNKS = 2;  // rows a workgroup: h(2..s'), s' - 1 <= 2 ROW_STRIDE values
 static_assert(LFOLD_MAX - 1 <= LFOLD_CHUNKS * ROW_STRIDE, "h(2..s') fits a workgroup's rows");
+static_assert(LFOLD_MAX <= 32, "b*_k and c*_k - b*_k of the line sit in 32 words of LDS each");
 struct LfoldArgs {
     u32 sp, tb, bbase, cbase;  // coordinates; 2^tb entries a thread; challenge indices of b* and c*
     const u64 *V;              // V_{i+1}

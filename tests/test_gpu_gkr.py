@@ -153,6 +153,17 @@ def test_line_by_folding_on_wide_layers():
     check_same(W.f2_circuit(n), W.f2_inputs(n, 43), 43, f"line fold F2 n={n}")
 
 
+def test_line_by_folding_above_2p22_entries():
+    """Input layers of 2^22 + 5 and 2^23 + 3 values (s' = 23, 24: 512 and
+    1,024 folding workgroups, whose rows ST_FINISH adds) read by a few gates,
+    so the oracle stays quick."""
+    rng = random.Random(31)
+    for sizes in ([3, 5, (1 << 22) + 5], [2, (1 << 23) + 3]):
+        circ = random_circuit(rng, sizes)
+        x = np.random.default_rng(sizes[-1]).integers(0, P, sizes[-1], dtype=np.uint64)
+        check_same(circ, x, 47, f"line fold {sizes}", device_inputs=True)
+
+
 def test_extreme_values_through_every_kernel():
     """Inputs at the ends of the field (all p - 1, all zero, p - 1 and 0 in
     turn) through layers wide enough for the grid steps, the line fold and
