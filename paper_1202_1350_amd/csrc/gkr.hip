@@ -428,6 +428,10 @@ struct gkr_circuit {
     std::vector<Group> grp[2];  // [phase - 1][layer], built with the first table workspace
     void *gmem = nullptr;       // memory of the groups (allocated with the first table workspace)
     bool grouped = false;       // grp[][] sized (chunk counts, single flags)
+    // Per layer i: entries of its omega phases' tables that can be nonzero,
+    // max(S_{i+1}, 1 + the largest wire read); entries above are zero at
+    // every level (no gate reads them and V_{i+1} is zero there).
+    std::vector<u64> wlive;
     // Where the gate arrays (soa, gmem) live: device memory, or pinned host
     // memory when the circuit's proofs run out of core; and the byte ranges
     // of each layer's block in them (layer i: [off[i], off[i+1])).
@@ -1276,6 +1280,12 @@ struct Planner {
                 const u64 N = 1ull << sp;
                 u32 k0 = 1;
                 if (sp > 11) k0 = std::max<u32>(3, (sp - 10) | 1u);
+                // Entries above c->wlive[i] stay zero at every level, so the
+                // grid steps take only the first NL entries of level 0 (NL
+                // a multiple of 2^k0: every step's range is then exact) and
+                // the tail zeroes its level's entries from NL >> k0 on.
+                const u64 wl = i < c->wlive.size() ? c->wlive[i] : N;
+                const u64 NL = std::min<u64>(N, (wl + (1ull << k0) - 1) >> k0 << k0);
                 for (u32 ph = 1; ph <= 2; ph++) {
                     const u32 rbase = s + (ph == 2 ? sp : 0);
                     const u32 Lb = sp / 2;
@@ -1295,7 +1305,7 @@ struct Planner {
                         a.kind = kind;
                         a.ph = ph;
                         a.hasC = hasC;
-                        a.npairs = N / 2;
+                        a.npairs = NL / 2;
                         a.perm = dg->perm;
                         a.rowptr = dg->rowptr;
                         a.oths = dg->oths;
@@ -1311,12 +1321,12 @@ struct Planner {
                         a.C = w ? w->tC0 : nullptr;
                         // per gate: perm 4, other wire 4, operand gather 8 (ph 1), type 1;
                         // per table entry: chunk index 4, F 8, A 8 (+ C 8)
-                        StepDesc &st = addg(ST_WA0, N / 2, 1,
+                        StepDesc &st = addg(ST_WA0, NL / 2, 1,
                                            S * (8.0 + (ph == 1 ? 8 : 0) + (kind == KIND_MIXED)) +
-                                               N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 8.0 * nch);
+                                               NL * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 8.0 * nch);
                         // per gate: chi_g(a*) (1), beta (1), the operand or chi_in1(b*) (1 or 2);
                         // per wire (phase 2) v1 twice; per pair three term products
-                        mods.back() = S * (ph == 1 ? 3.0 : 4.0) + N * (ph == 2 ? 2.0 : 0.0) + 1.5 * N;
+                        mods.back() = S * (ph == 1 ? 3.0 : 4.0) + NL * (ph == 2 ? 2.0 : 0.0) + 1.5 * NL;
                         st.u.wa0 = a;
                         reduces(3);
                     } else {
@@ -1355,16 +1365,16 @@ struct Planner {
                             memset(&a, 0, sizeof a);
                             a.ph = ph;
                             a.hasC = hasC;
-                            a.npairs = N / 2;
+                            a.npairs = NL / 2;
                             a.xch = dg->xch;
                             a.partA = w ? w->partA : nullptr;
                             a.partC = w ? w->partC : nullptr;
                             a.F = V(i + 1);
                             a.A = w ? w->tA0 : nullptr;
                             a.C = w ? w->tC0 : nullptr;
-                            StepDesc &st = addg(ST_WT0, N / 2, 1,
-                                               N * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 16.0 * nch);
-                            mods.back() = N * (ph == 2 ? 2.0 : 0.0) + 1.5 * N;
+                            StepDesc &st = addg(ST_WT0, NL / 2, 1,
+                                               NL * (4.0 + 8 + 8 + (hasC ? 8 : 0)) + 16.0 * nch);
+                            mods.back() = NL * (ph == 2 ? 2.0 : 0.0) + 1.5 * NL;
                             st.u.wt0 = a;
                             reduces(3);
                         }
@@ -1391,7 +1401,7 @@ struct Planner {
                         memset(&a, 0, sizeof a);
                         a.hasC = hasC;
                         a.pend = pend;
-                        a.nu = 1ull << (sp - k - pend - 2);  // quads of level k + pend
+                        a.nu = NL >> (k + pend + 2);  // quads of level k + pend (k + pend + 2 <= k0)
                         const u64 *A, *C, *F;
                         level(k, &A, &C, &F);
                         a.A = A;
@@ -1425,6 +1435,7 @@ struct Planner {
                         a.hasC = hasC;
                         a.last = ph;
                         a.pend = pend;
+                        a.live = (u32)(NL >> k0);
                         level(k0 - pend, &a.A, &a.C, &a.F);
                         a.c0 = co + rbase + k0;
                         a.msg = w ? msg + 3ull * (rbase + k0) : nullptr;
@@ -1601,13 +1612,18 @@ static void size_groups(gkr_circuit *c) {
     auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
     size_t bytes = 0;
     std::vector<u32> cnt;
+    c->wlive.assign(d, 0);
     for (u32 i = 0; i < d; i++) {
         c->g_off[i] = bytes;
         const u64 N = 1ull << c->s[i + 1], S = c->S[i];
+        u64 live = c->S[i + 1];
         for (int ph = 0; ph < 2; ph++) {
             const std::vector<u32> &idx = ph ? c->h_in2[i] : c->h_in1[i];
             cnt.assign(N, 0);
-            for (u64 g = 0; g < S; g++) cnt[idx[g]]++;
+            for (u64 g = 0; g < S; g++) {
+                cnt[idx[g]]++;
+                live = std::max<u64>(live, (u64)idx[g] + 1);
+            }
             u64 nch = 0, ntiles = 0, span = TILE_POS + 1;  // positions in the open tile
             bool single = true;
             for (u64 x = 0; x < N; x++) {
@@ -1630,6 +1646,7 @@ static void size_groups(gkr_circuit *c) {
             D.ntiles = (u32)ntiles;
             D.single = single;
             c->nch_max = std::max<u64>(c->nch_max, nch + 1);
+            c->wlive[i] = std::min<u64>(live, N);
             // perm, cstart, xch, rowptr, oths, tch, types (mixed layers)
             bytes += 2 * al(S * 4) + al((nch + 1) * 4) + 2 * al((N + 1) * 4) + al((ntiles + 1) * 4) +
                      al(c->h_type[i].size());

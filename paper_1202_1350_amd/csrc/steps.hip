@@ -1215,9 +1215,10 @@ __device__ __forceinline__ void step_wtail(const WtailArgs &a, const ProofPtrs &
     const bool hc = HC >= 0 ? HC != 0 : a.hasC != 0;
     const u32 n = 1u << (a.sp - a.k0);  // entries of level k0, at most TAIL_LIM
     for (u32 e = tid; e < n; e += SBLOCK) {
-        tab[e] = tail_entry(a.A, e, a.pend, c);
-        if (hc) tab[TAIL_TAB + e] = tail_entry(a.C, e, a.pend, c);
-        tab[2 * TAIL_TAB + e] = tail_entry(a.F, e, a.pend, c);
+        const bool on = e < a.live;  // (the grid steps wrote level k0 - pend below live << pend)
+        tab[e] = on ? tail_entry(a.A, e, a.pend, c) : 0;
+        if (hc) tab[TAIL_TAB + e] = on ? tail_entry(a.C, e, a.pend, c) : 0;
+        tab[2 * TAIL_TAB + e] = on ? tail_entry(a.F, e, a.pend, c) : 0;
     }
     const u64 st = tail_state(pp, a.c0, drew, st0);
     __syncthreads();

@@ -313,6 +313,7 @@ struct WtArgs {
 struct WtailArgs {
     u32 k0, sp, hasC, last;
     u32 pend;                // challenges the prologue drew (1 or 2): level k0 - pend is in memory
+    u32 live;                // level-k0 entries [live, 2^{sp-k0}) are zero (not read)
     const u64 *A, *C, *F;    // level k0-pend, 2^{sp-k0+pend} entries
     u32 c0;                  // challenge index of round k0
     u64 *msg;                // message slot of round k0

@@ -20,11 +20,15 @@ def G():
     return mod
 
 
-def random_circuit(rng, sizes, kinds=None):
+def random_circuit(rng, sizes, kinds=None, live_wires=False):
+    """Random gates; wires read any slot of the next layer's padded table,
+    or (live_wires) only its gates."""
     d = len(sizes) - 1
     types, in1, in2 = [], [], []
     for i in range(d):
         lim = 1 << (sizes[i + 1] - 1).bit_length() if sizes[i + 1] > 1 else 1
+        if live_wires:
+            lim = sizes[i + 1]
         if kinds is None:
             t = [rng.randrange(2) for _ in range(sizes[i])]
         else:
@@ -162,6 +166,20 @@ def test_line_by_folding_above_2p22_entries():
         circ = random_circuit(rng, sizes)
         x = np.random.default_rng(sizes[-1]).integers(0, P, sizes[-1], dtype=np.uint64)
         check_same(circ, x, 47, f"line fold {sizes}", device_inputs=True)
+
+
+def test_wires_below_the_padding():
+    """Layers whose gates read only the next layer's gates (not its zero
+    padding): the omega phases' grid steps take the tables' first entries
+    only, rounded up to 2^k0, and the tail zeroes the rest of its level.
+    Next-layer sizes just above a power of two, at a multiple of it plus one,
+    and tiny, for every omega algorithm."""
+    rng = random.Random(37)
+    for sizes in ([5, 70001, 131072 + 7], [3, 300, 1500, (1 << 20) + (1 << 16) + 5],
+                  [7, 1025, 2048 + 3, 40000], [2, 9, 17, 33, 300, 4097, 3 * 8192 + 1]):
+        circ = random_circuit(rng, sizes, live_wires=True)
+        x = np.random.default_rng(sizes[-1]).integers(0, P, sizes[-1], dtype=np.uint64)
+        check_same(circ, x, 53, f"live wires {sizes}", device_inputs=True)
 
 
 def test_extreme_values_through_every_kernel():
