@@ -1102,6 +1102,7 @@ struct Planner {
                 pt.pend = 0;
                 pt.V = V(i);
                 pt.B = nullptr;  // B_0 from z
+                pt.live = 1u << s;
                 pt.c0 = co;
                 pt.msg = msg;
                 st.u.ptail = pt;
@@ -1123,6 +1124,13 @@ struct Planner {
                 const bool look = s >= 2;
                 u32 j0 = 1;
                 if (look) j0 = s > 12 ? ((s - 10 + 1) & ~1u) : 2;  // even, 2^(s - j0) <= TAIL_LIM
+                // V_i is zero from S_i on, and so is every V^(j) from S_i >> j:
+                // the grid steps take the first NP entries of V_i (S_i rounded
+                // up to 2^j0, so every step's range is exact) and the tail
+                // zeroes V^(j0) from NP >> j0 on.  The suffix weights B are not
+                // zero there; the steps write them below the bound only, so a
+                // trimmed tail forms its B_{j0} from z.
+                const u64 NP = std::min<u64>(1ull << s, ((u64)c->S[i] + (1ull << j0) - 1) >> j0 << j0);
                 u64 *vbuf[2] = {w ? w->pA : nullptr, w ? w->pB : nullptr};
                 u64 *bbuf[2] = {w ? w->bA : nullptr, w ? w->bB : nullptr};
                 const u32 nz = s - 1;
@@ -1133,7 +1141,7 @@ struct Planner {
                     memset(&pa, 0, sizeof pa);
                     pa.first = 1;
                     pa.look = look;
-                    pa.nu = look ? 1ull << (s - 2) : 1;
+                    pa.nu = look ? NP >> 2 : 1;
                     pa.Vsrc = V(i);
                     pa.Bout = look ? bbuf[0] : nullptr;  // B_1
                     pa.zlo = w ? w->zlo : nullptr;
@@ -1153,7 +1161,7 @@ struct Planner {
                     f.msg = w ? msg + 3ull * j : nullptr;
                     PArgs pa;
                     memset(&pa, 0, sizeof pa);
-                    pa.nu = 1ull << (s - j - 4);
+                    pa.nu = NP >> (j + 4);  // (j + 4 <= j0)
                     pa.Vsrc = vlast;
                     pa.Vout = vbuf[(j / 2) & 1];
                     pa.Bprev = bbuf[bw];
@@ -1181,7 +1189,8 @@ struct Planner {
                 pt.s = s;
                 pt.pend = pend;
                 pt.V = vlast;       // V^(j0 - pend)
-                pt.B = bbuf[bw];    // B_{j0-1}
+                pt.B = NP == (1ull << s) ? bbuf[bw] : nullptr;  // B_{j0-1}, or B_{j0} from z
+                pt.live = (u32)(NP >> j0);
                 pt.c0 = co + j0;
                 pt.msg = w ? msg + 3ull * j0 : nullptr;
                 st.u.ptail = pt;

@@ -1381,7 +1381,7 @@ __device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &
     u64 *V = tab, *B = tab + TAIL_TAB;
     const u32 tid = threadIdx.x, lane = tid & 63;
     const u32 L = a.s - a.j0, n = 1u << L;  // entries of V^(j0), at most TAIL_LIM
-    for (u32 e = tid; e < n; e += SBLOCK) V[e] = tail_entry(a.V, e, a.pend, c);
+    for (u32 e = tid; e < n; e += SBLOCK) V[e] = e < a.live ? tail_entry(a.V, e, a.pend, c) : 0;
     const u64 zr = lane < L ? pp.zbuf[a.j0 + lane] : 0;  // z_{j0 + l} in lane l
     if (a.B) {
         for (u32 m = tid; m < n / 2; m += SBLOCK) {  // B_{j0}[m] = B_{j0-1}[2m] + B_{j0-1}[2m+1]
@@ -1389,7 +1389,7 @@ __device__ __forceinline__ void step_ptail(const PtailArgs &a, const ProofPtrs &
             B[m] = add(pb.x, pb.y);
         }
     } else {
-        suffix_weights(B, a.s, zr);  // j0 = 0
+        suffix_weights(B, L, zr);  // B_{j0}[m] = prod_{k >= 1} eq(bit k-1 of m, z_{j0+k})
     }
     if (!have_c && tid == 0) s_c = pp.state[0];
     u64 st = tail_state(pp, a.c0, drew, st0);

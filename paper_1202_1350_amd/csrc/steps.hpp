@@ -322,8 +322,10 @@ struct WtailArgs {
 struct PtailArgs {
     u32 j0, s;
     u32 pend;                // challenges the prologue drew (1 or 2; 0 when j0 = 0)
+    u32 live;                // entries [live, 2^{s-j0}) of V^(j0) are zero (not read)
     const u64 *V, *B;        // V^(j0-pend) (2^{s-j0+pend}) and B_{j0-1} (2^{s-j0});
-                             // j0 = 0: V_i, and B NULL (B_0 is formed from z)
+                             // B NULL: B_{j0} is formed from z (j0 = 0, or the grid
+                             // steps wrote B below the live entries only)
     u32 c0;                  // challenge index of round j0
     u64 *msg;                // message slot of round j0
 };
