@@ -1226,7 +1226,7 @@ struct Planner {
             // h(2..s')) instead of sums over eq tables of the line points
             // (ST_LT, ST_LINE).
             const bool lfold = sp >= LFOLD_MIN && sp <= LFOLD_MAX;
-            const u32 ltb = lfold_tb(sp), lwg = lfold ? lfold_wg(sp) : 0;
+            const u32 ltb = lfold_tb(sp), lwg = lfold ? lfold_wg_live(sp, c->S[i + 1]) : 0;
             u64 *lrows = nullptr;
             auto lfold_step = [&](const Fin &f) {
                 StepDesc &e = add(ST_LFOLD, lwg, 8.0 * (1ull << sp) + 8.0 * (sp - 1) * lwg);

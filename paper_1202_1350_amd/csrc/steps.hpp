@@ -228,12 +228,13 @@ struct LineArgs {
 // Line of a layer with 2^11 <= 2^s' <= 2^32 by folding (ST_LFOLD):
 // h(t) = ~V_{i+1}(b* + t (c* - b*)) is a polynomial of degree s' in t; V is
 // folded coordinate by coordinate, each entry pair becoming a polynomial one
-// degree higher.  With D = tb + 9, workgroup g folds entries [g 2^D,
-// (g+1) 2^D) along coordinates 0..D-1 into a polynomial of degree D and
-// writes its term of h(t), weighted along coordinates D..s'-1, for
-// t = 2..s' as rows: value j in row (j / ROW_STRIDE) nwg + g, column
-// j % ROW_STRIDE (nwg workgroups).  ST_FINISH adds the rows up into h(2..s')
-// as it does for the line sums' rows.
+// degree higher.  With D = tb + 9, workgroup g (one per 2^D entries below
+// S_{i+1}) folds entries [g 2^D, (g+1) 2^D) along coordinates 0..D-1 into
+// a polynomial of degree D and writes its term of h(t), weighted along
+// coordinates D..s'-1, for t = 2..s' as rows: value j in row
+// (j / ROW_STRIDE) nwg + g, column j % ROW_STRIDE (nwg workgroups).
+// ST_FINISH adds the rows up into h(2..s') as it does for the line sums'
+// rows.
 constexpr u32 LFOLD_MIN = 11, LFOLD_MAX = 32;
 // Entries a thread folds, 2^tb: 128 to 256 workgroups from 2^17 to 2^22
 // entries (a workgroup's time is set mostly by its LDS levels, not by tb), as
@@ -242,6 +243,12 @@ constexpr u32 LFOLD_MIN = 11, LFOLD_MAX = 32;
 constexpr u32 lfold_tb(u32 sp) { return sp <= 17 ? 1 : sp == 18 ? 2 : sp <= 20 ? 3 : sp == 21 ? 4 : 5; }
 static_assert(LFOLD_MIN >= 1 + 9, "a workgroup folds at least 2^(1 + 9) entries");
 constexpr u32 lfold_wg(u32 sp) { return 1u << (sp - lfold_tb(sp) - 9); }
+// Workgroups that cover the first n entries (V_{i+1} is zero from S_{i+1}
+// on, so the blocks above hold zero polynomials and write no rows).
+constexpr u32 lfold_wg_live(u32 sp, u64 n) {
+    const u64 need = (n + (1ull << (lfold_tb(sp) + 9)) - 1) >> (lfold_tb(sp) + 9);
+    return need < 1 ? 1u : need > lfold_wg(sp) ? lfold_wg(sp) : (u32)need;
+}
 constexpr u32 LFOLD_CHUNKS = 2;  // rows a workgroup: h(2..s'), s' - 1 <= 2 ROW_STRIDE values
 static_assert(LFOLD_MAX - 1 <= LFOLD_CHUNKS * ROW_STRIDE, "h(2..s') fits a workgroup's rows");
 static_assert(LFOLD_MAX <= 32, "b*_k and c*_k - b*_k of the line sit in 32 words of LDS each");
