@@ -158,9 +158,10 @@ def test_line_by_folding_on_wide_layers():
 
 
 def test_line_by_folding_above_2p22_entries():
-    """Input layers of 2^22 + 5 and 2^23 + 3 values (s' = 23, 24: 512 and
-    1,024 folding workgroups, whose rows ST_FINISH adds) read by a few gates,
-    so the oracle stays quick."""
+    """Input layers of 2^22 + 5 and 2^23 + 3 values (s' = 23, 24: 257 and
+    513 folding workgroups, one per 2^14 entries up to the layer's size,
+    whose rows ST_FINISH adds) read by a few gates, so the oracle stays
+    quick."""
     rng = random.Random(31)
     for sizes in ([3, 5, (1 << 22) + 5], [2, (1 << 23) + 3]):
         circ = random_circuit(rng, sizes)
