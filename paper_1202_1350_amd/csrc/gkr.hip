@@ -285,8 +285,9 @@ void line_shape(u32 sp, u32 *L, u32 *M, u32 *H) {
 //
 // A grid step over `units` work items launches ceil(units / (SBLOCK q))
 // workgroups, at most `cap`, with q (items per thread) and cap chosen per
-// step kind and size class (ceil log2 of the units) by gkr_autotune; kinds
-// and classes it has not measured keep their defaults.  A shape code packs
+// step kind and size class (ceil log2 of the units) by gkr_autotune; a class
+// above the largest one measured for its kind takes that one's shape, the
+// other classes it has not measured keep their defaults.  A shape code packs
 // log2 q (bits 0-1) and log2 cap - 8 (bits 2-3): 16 candidates.
 constexpr u32 CAP_MAX = 2048;
 constexpr int NKIND = ST_WA0 + 1;
@@ -324,6 +325,17 @@ u32 grid_for(u32 kind, u64 units, u32 qdef) {
     u32 caplog = 9;  // 512 workgroups: two per CU
     int code = SHAPE_DEFAULT;
     if (tunable(kind)) code = g_force >= 0 ? g_force : g_tune[kind][size_class(units)];
+    if (code == SHAPE_DEFAULT && g_force < 0 && tunable(kind)) {
+        // a class above every class tuned for this kind takes the shape of
+        // the largest tuned one (the wide launches of circuits larger than
+        // the one tuned on)
+        const u32 b = size_class(units);
+        for (int k = NCLASS - 1; k >= 0; k--)
+            if (g_tune[kind][k] != SHAPE_DEFAULT) {
+                if ((u32)k < b) code = g_tune[kind][k];
+                break;
+            }
+    }
     if (code != SHAPE_DEFAULT) {
         qlog = code & 3;
         caplog = 8 + ((code >> 2) & 3);
